@@ -1,0 +1,210 @@
+"""FP64 oracle for the S_N source-iteration path and the operator network.
+
+TEST INFRASTRUCTURE ONLY: this package is imported by the test suite, the
+smoke check and the benchmark's CPU-baseline leg, never by the library.  It
+shares no code with the HIP path.
+
+Contents
+  * ``si_oracle.c`` (loaded here through ctypes): diamond-difference sweeps and
+    source iteration in 1-D and 2-D, FP64 (section 5.1, Eq. 12; the iteration
+    M of Eq. 3a/4b);
+  * ``recast``: the equation-recast loop of Eq. 24 with a caller-given inner
+    solution operator (the exact transport operator at p* for the closed-form
+    check, or a network);
+  * ``fno``: FP64 forward/backward of the Fourier neural operator and Adam.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "si_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libsi_oracle.so")
+_lib = None
+_lock = threading.Lock()
+
+OK = 0
+NOT_CONVERGED = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile si_oracle.c with gcc into oracle/libsi_oracle.so."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB_PATH)
+            D = ctypes.POINTER(ctypes.c_double)
+            I = ctypes.POINTER(ctypes.c_int)
+            i, d = ctypes.c_int, ctypes.c_double
+            lib.or_sweep2d.argtypes = [i, i, d, d, i, D, D, D, D, D, I, D, D, D, D]
+            lib.or_si2d.argtypes = [i, i, d, d, i, D, D, D, D, D, D, I, D, d, i,
+                                    i, D, D, D]
+            lib.or_sweep1d.argtypes = [i, d, i, D, D, D, D, I, D, D, D, D]
+            lib.or_si1d.argtypes = [i, d, i, D, D, D, D, D, I, D, d, i, i, D, D, D]
+            for f in (lib.or_sweep2d, lib.or_si2d, lib.or_sweep1d, lib.or_si1d):
+                f.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _bc(bc) -> ctypes.Array:
+    return (ctypes.c_int * 4)(*[int(b) for b in (list(bc) + [0, 0, 0, 0])[:4]])
+
+
+class SolveResult:
+    def __init__(self, phi, status, iterations, residual, leak, dscatter,
+                 hist):
+        self.phi = phi
+        self.status = status
+        self.iterations = iterations
+        self.residual = residual
+        self.leakage = leak
+        self.dscatter = dscatter
+        self.history = hist
+
+
+def sweep2d(nx, ny, lx, ly, mu, eta, w, sigma_t, emission, bc=(0, 0, 0, 0),
+            face_prev=None, return_faces=False):
+    """One 2-D DD sweep of every direction for emission density Q.
+
+    Returns phi (ny, nx) [and the face array (4, max(nx,ny), M), leakage]."""
+    lib = _load()
+    mu, eta, w = _f64(mu), _f64(eta), _f64(w)
+    M = mu.shape[0]
+    nf = max(nx, ny)
+    st = _f64(sigma_t).reshape(-1)
+    Q = _f64(emission).reshape(-1)
+    phi = np.zeros(nx * ny)
+    fo = np.zeros(4 * nf * M)
+    fp = None if face_prev is None else _f64(face_prev).reshape(-1)
+    leak = ctypes.c_double(0.0)
+    rc = lib.or_sweep2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
+                        _dp(Q), _bc(bc), _dp(fp), _dp(fo), _dp(phi),
+                        ctypes.byref(leak))
+    if rc != OK:
+        raise ValueError(f"or_sweep2d failed ({rc})")
+    phi = phi.reshape(ny, nx)
+    if return_faces:
+        return phi, fo.reshape(4, nf, M), leak.value
+    return phi
+
+
+def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
+         phi0=None, tol=1e-6, max_iter=100000, norm="l2") -> SolveResult:
+    """2-D source iteration to tolerance (zero start unless phi0 is given)."""
+    lib = _load()
+    mu, eta, w = _f64(mu), _f64(eta), _f64(w)
+    M = mu.shape[0]
+    st = _f64(sigma_t).reshape(-1)
+    ss = _f64(sigma_s).reshape(-1)
+    qq = _f64(q).reshape(-1)
+    p0 = None if phi0 is None else _f64(phi0).reshape(-1)
+    phi = np.zeros(nx * ny)
+    stats = np.zeros(4)
+    hist = np.zeros(max_iter)
+    rc = lib.or_si2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
+                     _dp(ss), _dp(qq), _bc(bc), _dp(p0), float(tol),
+                     int(max_iter), 1 if norm == "max" else 0, _dp(phi),
+                     _dp(stats), _dp(hist))
+    if rc < 0:
+        raise ValueError(f"or_si2d failed ({rc})")
+    it = int(stats[0])
+    return SolveResult(phi.reshape(ny, nx), rc, it, stats[1], stats[2],
+                       stats[3], hist[:it].copy())
+
+
+def sweep1d(nx, lx, mu, w, sigma_t, emission, bc=(0, 0), face_prev=None,
+            return_faces=False):
+    lib = _load()
+    mu, w = _f64(mu), _f64(w)
+    M = mu.shape[0]
+    st = _f64(sigma_t).reshape(-1)
+    Q = _f64(emission).reshape(-1)
+    phi = np.zeros(nx)
+    fo = np.zeros(2 * M)
+    fp = None if face_prev is None else _f64(face_prev).reshape(-1)
+    leak = ctypes.c_double(0.0)
+    rc = lib.or_sweep1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(Q), _bc(bc),
+                        _dp(fp), _dp(fo), _dp(phi), ctypes.byref(leak))
+    if rc != OK:
+        raise ValueError(f"or_sweep1d failed ({rc})")
+    if return_faces:
+        return phi, fo.reshape(2, M), leak.value
+    return phi
+
+
+def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
+         max_iter=100000, norm="max") -> SolveResult:
+    lib = _load()
+    mu, w = _f64(mu), _f64(w)
+    M = mu.shape[0]
+    st = _f64(sigma_t).reshape(-1)
+    ss = _f64(sigma_s).reshape(-1)
+    qq = _f64(q).reshape(-1)
+    p0 = None if phi0 is None else _f64(phi0).reshape(-1)
+    phi = np.zeros(nx)
+    stats = np.zeros(4)
+    hist = np.zeros(max_iter)
+    rc = lib.or_si1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(ss), _dp(qq),
+                     _bc(bc), _dp(p0), float(tol), int(max_iter),
+                     1 if norm == "max" else 0, _dp(phi), _dp(stats),
+                     _dp(hist))
+    if rc < 0:
+        raise ValueError(f"or_si1d failed ({rc})")
+    it = int(stats[0])
+    return SolveResult(phi, rc, it, stats[1], stats[2], stats[3],
+                       hist[:it].copy())
+
+
+def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None):
+    """Solve one inputs.Instance with the oracle (dim from the instance)."""
+    if inst.dim == 1:
+        return si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
+                    inst.sigma_s, inst.source, bc=inst.bc[:2], phi0=phi0,
+                    tol=tol, max_iter=max_iter, norm=norm or "max")
+    return si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
+                inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
+                phi0=phi0, tol=tol, max_iter=max_iter, norm=norm or "l2")
+
+
+def solve_many(insts: Sequence, quad, tol, phi0s=None, threads: int = 1,
+               max_iter=100000):
+    """Solve several instances, one per worker thread (the C call releases
+    the interpreter lock).  Returns a list of SolveResult."""
+    phi0s = phi0s if phi0s is not None else [None] * len(insts)
+    if threads <= 1:
+        return [solve_instance(i, quad, tol, p, max_iter)
+                for i, p in zip(insts, phi0s)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(solve_instance, i, quad, tol, p, max_iter)
+                for i, p in zip(insts, phi0s)]
+        return [f.result() for f in futs]
