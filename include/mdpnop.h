@@ -1,0 +1,204 @@
+/*
+ * mdpnop.h -- C ABI of the MI355X (gfx950) S_N source-iteration library with
+ * an equation-recast neural-operator warm start (arXiv 2509.01416).
+ *
+ * General conventions
+ *   - Field pointers are DEVICE pointers owned by the caller: FP32, cell-major
+ *     with x fastest, nx*ny elements.  Quadrature arrays are HOST pointers.
+ *   - All work is enqueued on the context's HIP stream.  Every call returns
+ *     after its results and statistics are final (a stream synchronisation).
+ *   - The context owns its workspaces (allocated on first use, grown when a
+ *     larger problem arrives, reused otherwise).  A context is not
+ *     thread-safe; use one per host thread.
+ *   - No C++ exception crosses this interface.  On error a negative status is
+ *     returned and tr_last_error() describes it.
+ *   - Quadrature weights must sum to 1 (to 1e-12) and the set must be closed
+ *     under mu -> -mu (and eta -> -eta in 2-D).  With this normalisation the
+ *     emission density per unit weight is Q = sigma_s*phi + S and
+ *     phi = sum_m w_m psi_m, the scalar flux of section 5.1 (Eq. 12, 17); the
+ *     paper's weights sum to 2 with a factor 1/2 on the emission, which gives
+ *     the same phi.
+ */
+#ifndef MDPNOP_H
+#define MDPNOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TR_OK = 0,
+    TR_NOT_CONVERGED = 1,     /* max_iter reached; last iterate returned      */
+    TR_RECAST_DIVERGED = 2,   /* recast loop diverged; guess zeroed           */
+    TR_ERR_INVALID_ARG = -1,
+    TR_ERR_HIP = -2,
+    TR_ERR_OOM = -3,
+    TR_ERR_NONFINITE = -4
+} tr_status;
+
+typedef enum { TR_BC_VACUUM = 0, TR_BC_REFLECTIVE = 1 } tr_bc;
+
+typedef struct tr_context tr_context;
+typedef struct no_model no_model;
+
+/* One fixed-source problem: section 5.1 Eq. 12 (dim = 1) or its x-y analogue
+ * (dim = 2).  The parameter vector p of Eq. 1 is (sigma_t, sigma_s).
+ * Uniform cells: dx = lx/nx, dy = ly/ny (ny = 1, ly ignored when dim = 1).
+ * Requirements: sigma_t > 0, 0 <= sigma_s <= sigma_t, all values finite;
+ * sigma_a = sigma_t - sigma_s must not vanish everywhere unless some face is
+ * vacuum.  bc = {x-, x+, y-, y+} (tr_bc); only bc[0..1] are used in 1-D.   */
+typedef struct {
+    int32_t dim, nx, ny;
+    double lx, ly;
+    const float *sigma_t, *sigma_s, *source;
+    int32_t bc[4];
+} tr_problem;
+
+/* Discrete ordinates (section 5.1: S_N angular discretisation).  HOST
+ * arrays of n_dir entries; eta = NULL in 1-D.  sum(w) = 1.                 */
+typedef struct {
+    int32_t n_dir;
+    const double *mu, *eta, *w;
+} tr_quadrature;
+
+/* Per-instance results.  residual: last relative change norm (FP64);
+ * balance_rel: |sum q V - sum sigma_a phi V - leakage| / sum q V in FP64;
+ * seconds: wall time of the whole call (same value for every instance).   */
+typedef struct {
+    int32_t status, iterations;
+    double residual, balance_rel, seconds;
+} tr_stats;
+
+/* Create a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *ctx is set on success.        */
+tr_status tr_context_create(tr_context **ctx, void *hip_stream);
+void tr_context_destroy(tr_context *ctx);
+/* Message of the last failed call on ctx ("" if none); valid until the next
+ * call on ctx.                                                              */
+const char *tr_last_error(const tr_context *ctx);
+
+/*
+ * One transport sweep for each of n_inst problems (the operator Sweep of the
+ * source iteration, section 5.1 after Eq. 20): given the emission density
+ * emission[i] (= sigma_s*phi + S per unit weight), solve every direction in
+ * upwind order with diamond differencing and return
+ * phi_out[i] = sum_m w_m psi_m at cell centres.  sigma_s and source of the
+ * problems are not read.  Reflective faces receive zero incoming flux (there
+ * is no previous sweep); vacuum faces zero as always.
+ * Returns TR_OK or an error.                                                */
+tr_status tr_sweep(tr_context *ctx, int32_t n_inst, const tr_problem *p,
+                   const tr_quadrature *q, const float *const *emission,
+                   float *const *phi_out);
+
+/*
+ * Source iteration (the model-based operator M of Eq. 3a/4b; Eq. 9a/10b
+ * when phi_init is a neural-operator guess): repeat
+ *     phi <- Sweep(sigma_s*phi + S)
+ * until the FP64 change norm drops below tol, for n_inst independent
+ * problems of possibly different sizes in one batched launch sequence.
+ *   tol > 0: relative L2 change ||phi_new - phi_old|| / ||phi_new||;
+ *   tol < 0: max_i |phi_new - phi_old| / |phi_new| < -tol.
+ * phi_init == NULL or phi_init[i] == NULL -> zero start for instance i;
+ * otherwise phi_init[i] (device, may equal phi_out[i]) is the first iterate
+ * and reflective faces start isotropic at the adjacent cell's value.
+ * Reflective faces are lagged one iteration.  phi_out[i] receives the last
+ * iterate; stats[i] (may be NULL) the per-instance results.  Return value:
+ * the worst status over instances (errors < 0 take precedence).            */
+tr_status tr_solve(tr_context *ctx, int32_t n_inst, const tr_problem *p,
+                   const tr_quadrature *q, const float *const *phi_init,
+                   float *const *phi_out, double tol, int32_t max_iter,
+                   tr_stats *stats);
+
+/*
+ * Equation-recast guess (Eq. 24; Eq. 8 in general form): with the network
+ * m trained at (sigma_t_star, sigma_s_star), iterate
+ *     phi^(k+1) = NO[ S + (sigma_a* - sigma_a) phi^(k) ],  phi^(0) = 0,
+ * where NO(S) = s * net(S/s, x, y) / sigma_a*, s = mean|S| per instance,
+ * until ||phi^(k+1)-phi^(k)||/||phi^(k+1)|| < tol or max_iter updates.
+ * Problems must be 2-D.  A problem whose grid differs from the network's
+ * (a multiple of it) is block-averaged onto the network grid for the loop
+ * and the result is bilinearly interpolated back (cell-centred, edges
+ * clamped).  On divergence (non-finite change, or an absolute change that
+ * grew three times running past the first update's) phi_guess[i] is zeroed
+ * and status TR_RECAST_DIVERGED reported, so that a following tr_solve
+ * falls back to the zero start.                                            */
+tr_status no_recast_guess(tr_context *ctx, const no_model *m, int32_t n_inst,
+                          const tr_problem *p, double sigma_t_star,
+                          double sigma_s_star, double tol, int32_t max_iter,
+                          float *const *phi_guess, tr_stats *stats);
+
+/* ---------------------------------------------------------------------
+ * Fourier neural operator (section 4.2, Appendix A1; 2-D form): lift of
+ * (field, x, y) to `width` channels, `layers` Fourier layers (retained
+ * modes kx in [0,modes), ky in [0,modes) U [grid-modes, grid)), GELU after
+ * all but the last, projection width -> 128 -> 1.  Supported shape:
+ * width 32, modes 12, layers 4, grid 64.  Parameters are a flat FP32
+ * vector (master copy) in this order:
+ *   W0[3][w], b0[w]; per layer R[2][m][m][w][w][2], W[w][w], b[w];
+ *   P1[w][128], c1[128], P2[128], c2[1]
+ * (2,368,001 values for the supported shape).  The network computes in
+ * BF16 on the matrix cores with FP32 accumulation.
+ * ------------------------------------------------------------------- */
+tr_status no_model_create(tr_context *ctx, no_model **m, int32_t width,
+                          int32_t modes, int32_t layers, int32_t grid,
+                          const float *params_host);
+void no_model_destroy(no_model *m);
+int64_t no_model_param_count(const no_model *m);
+/* Copy the FP32 master parameters to host memory (param_count floats).   */
+tr_status no_model_get_params(tr_context *ctx, const no_model *m,
+                              float *params_host);
+tr_status no_model_set_params(tr_context *ctx, no_model *m,
+                              const float *params_host);
+
+/* Network forward for a batch: input[b] and output[b] are device
+ * grid*grid FP32 fields (the first input channel; the coordinate channels
+ * are generated inside).                                                   */
+tr_status no_forward(tr_context *ctx, const no_model *m, int32_t batch,
+                     const float *input, float *output);
+
+/* One training step on a batch (Appendix A1: Adam, MSE loss): forward,
+ * MSE against target, hand-written backward, Adam (b1 0.9, b2 0.999,
+ * eps 1e-8, bias-corrected) on the FP32 master parameters, BF16 copy
+ * refreshed.  input/target: device [batch][grid*grid].  *loss receives the
+ * batch MSE before the update.  grad_out (device, param_count floats, may
+ * be NULL) receives the gradient; with lr = 0 the parameters are unchanged
+ * and the call only evaluates the loss and gradient.                       */
+tr_status no_train_step(tr_context *ctx, no_model *m, int32_t batch,
+                        const float *input, const float *target, double lr,
+                        double *loss, float *grad_out);
+
+/* ---------------------------------------------------------------------
+ * Host-only helpers and tuning
+ * ------------------------------------------------------------------- */
+
+/* Run the host-side argument checks of tr_solve (problem shapes, extents,
+ * boundary codes, quadrature symmetry and normalisation, tol, max_iter)
+ * without touching a device; field values are not read.  msg (may be NULL)
+ * receives the reason for a failure, truncated to msg_len bytes.          */
+tr_status tr_check_args(int32_t n_inst, const tr_problem *p,
+                        const tr_quadrature *q, double tol, int32_t max_iter,
+                        char *msg, int32_t msg_len);
+
+/* Force the 2-D sweep's launch shape on this context (0 = automatic):
+ * D directions per lane (1,2,3,4,5,6,9,10), W waves per workgroup (1..16),
+ * S direction slices per octant, R rows per lane segment (a power of two
+ * <= 64; a problem narrower than R uses the automatic choice).  Every
+ * configuration sums partial fluxes in a fixed order, so a given
+ * configuration reproduces its result bit for bit; different
+ * configurations agree to FP32 rounding.                                  */
+tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
+                              int32_t R);
+
+/* The launch shape the next tr_solve / tr_sweep on these problems would
+ * use: out4 = {D, W, S of problem 0, R of problem 0}.                     */
+tr_status tr_get_sweep_plan(tr_context *ctx, int32_t n_inst,
+                            const tr_problem *p, const tr_quadrature *q,
+                            int32_t *out4);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDPNOP_H */

@@ -1,0 +1,263 @@
+"""ctypes binding of libmdpnop (include/mdpnop.h): argument marshalling only.
+
+Fields are torch tensors on the GPU (float32, contiguous, shape (ny, nx) or
+(nx,)); every step of the solve runs in the library's HIP kernels.  The
+library must be built (``python -m paper_2509_01416_amd.build``); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdpnop.so")
+
+TR_OK = 0
+TR_NOT_CONVERGED = 1
+TR_RECAST_DIVERGED = 2
+TR_ERR_INVALID_ARG = -1
+TR_ERR_HIP = -2
+TR_ERR_OOM = -3
+TR_ERR_NONFINITE = -4
+
+EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
+           "tr_sweep", "tr_solve", "no_recast_guess", "no_model_create",
+           "no_model_destroy", "no_model_param_count", "no_model_get_params",
+           "no_model_set_params", "no_forward", "no_train_step",
+           "tr_check_args", "tr_set_sweep_config", "tr_get_sweep_plan")
+
+
+class TrProblem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("sigma_t", ctypes.c_void_p),
+                ("sigma_s", ctypes.c_void_p), ("source", ctypes.c_void_p),
+                ("bc", ctypes.c_int32 * 4)]
+
+
+class TrQuadrature(ctypes.Structure):
+    _fields_ = [("n_dir", ctypes.c_int32), ("mu", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class TrStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("balance_rel", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class MdpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} missing: build it with "
+                           "`python -m paper_2509_01416_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.tr_context_create.argtypes = [P(vp), vp]
+    lib.tr_context_destroy.argtypes = [vp]
+    lib.tr_context_destroy.restype = None
+    lib.tr_last_error.argtypes = [vp]
+    lib.tr_last_error.restype = ctypes.c_char_p
+    lib.tr_sweep.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(vp), P(vp)]
+    lib.tr_solve.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(vp), P(vp),
+                             d, i32, P(TrStats)]
+    lib.no_recast_guess.argtypes = [vp, vp, i32, P(TrProblem), d, d, d, i32, P(vp),
+                                    P(TrStats)]
+    lib.no_model_create.argtypes = [vp, P(vp), i32, i32, i32, i32, vp]
+    lib.no_model_destroy.argtypes = [vp]
+    lib.no_model_destroy.restype = None
+    lib.no_model_param_count.argtypes = [vp]
+    lib.no_model_param_count.restype = i64
+    lib.no_model_get_params.argtypes = [vp, vp, vp]
+    lib.no_model_set_params.argtypes = [vp, vp, vp]
+    lib.no_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.no_train_step.argtypes = [vp, vp, i32, vp, vp, d, P(d), vp]
+    lib.tr_check_args.argtypes = [i32, P(TrProblem), P(TrQuadrature), d, i32,
+                                  ctypes.c_char_p, i32]
+    lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
+    lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if f.restype is ctypes.c_int:       # default: tr_status
+            f.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------- problems
+
+@dataclass
+class Problem:
+    """One instance: device tensors sigma_t, sigma_s, source (float32)."""
+    sigma_t: object
+    sigma_s: object
+    source: object
+    lx: float = 10.0
+    ly: float = 10.0
+    bc: tuple = (0, 0, 0, 0)
+
+    @property
+    def dim(self) -> int:
+        return 1 if self.sigma_t.dim() == 1 else 2
+
+    @property
+    def nx(self) -> int:
+        return int(self.sigma_t.shape[-1])
+
+    @property
+    def ny(self) -> int:
+        return 1 if self.dim == 1 else int(self.sigma_t.shape[0])
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def make_problems(problems: Sequence[Problem]):
+    arr = (TrProblem * len(problems))()
+    for i, p in enumerate(problems):
+        for t in (p.sigma_t, p.sigma_s, p.source):
+            if t is not None and (str(t.dtype) != "torch.float32"
+                                  or t.device.type != "cuda"):
+                raise ValueError("fields must be float32 GPU tensors")
+        arr[i].dim = p.dim
+        arr[i].nx = p.nx
+        arr[i].ny = p.ny
+        arr[i].lx = float(p.lx)
+        arr[i].ly = float(p.ly)
+        arr[i].sigma_t = _ptr(p.sigma_t)
+        arr[i].sigma_s = _ptr(p.sigma_s)
+        arr[i].source = _ptr(p.source)
+        for f in range(4):
+            arr[i].bc[f] = int(p.bc[f]) if f < len(p.bc) else 0
+    return arr
+
+
+class Quad:
+    """Host quadrature arrays kept alive for the duration of calls."""
+
+    def __init__(self, mu, eta, w):
+        self.mu = np.ascontiguousarray(mu, dtype=np.float64)
+        self.eta = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
+        self.w = np.ascontiguousarray(w, dtype=np.float64)
+        self.struct = TrQuadrature(
+            len(self.w), self.mu.ctypes.data,
+            None if self.eta is None else self.eta.ctypes.data, self.w.ctypes.data)
+
+    @classmethod
+    def from_inputs(cls, q):
+        return cls(q.mu, q.eta, q.w)
+
+
+def _ptr_array(ts) -> ctypes.Array:
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+# ---------------------------------------------------------------- context
+
+class Context:
+    """tr_context bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.tr_context_create(ctypes.byref(h),
+                                        ctypes.c_void_p(stream.cuda_stream))
+        if rc != TR_OK:
+            raise MdpError(rc, "tr_context_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.tr_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self.lib.tr_last_error(self.handle).decode()
+
+    def check(self, rc: int, allow=(TR_OK, TR_NOT_CONVERGED, TR_RECAST_DIVERGED)):
+        if rc not in allow:
+            raise MdpError(rc, self.last_error())
+        return rc
+
+    # -------------------------------------------------------------- calls
+    def set_sweep_config(self, D=0, W=0, S=0, R=0):
+        self.check(self.lib.tr_set_sweep_config(self.handle, D, W, S, R), allow=(TR_OK,))
+
+    def sweep_plan(self, problems, quad: Quad):
+        arr = make_problems(problems)
+        out = (ctypes.c_int32 * 4)()
+        self.check(self.lib.tr_get_sweep_plan(self.handle, len(problems), arr,
+                                              ctypes.byref(quad.struct), out),
+                   allow=(TR_OK,))
+        return dict(D=out[0], W=out[1], S=out[2], R=out[3])
+
+
+def tr_sweep(ctx: Context, problems: Sequence[Problem], quad: Quad,
+             emission: Sequence, phi_out: Sequence) -> int:
+    arr = make_problems(problems)
+    rc = ctx.lib.tr_sweep(ctx.handle, len(problems), arr, ctypes.byref(quad.struct),
+                          _ptr_array(emission), _ptr_array(phi_out))
+    return ctx.check(rc, allow=(TR_OK,))
+
+
+def tr_solve(ctx: Context, problems: Sequence[Problem], quad: Quad,
+             phi_init: Optional[Sequence], phi_out: Sequence, tol: float,
+             max_iter: int, raise_on_error: bool = True):
+    """Returns (status, list of per-instance stats dicts)."""
+    n = len(problems)
+    arr = make_problems(problems)
+    stats = (TrStats * n)()
+    init = None if phi_init is None else _ptr_array(phi_init)
+    rc = ctx.lib.tr_solve(ctx.handle, n, arr, ctypes.byref(quad.struct), init,
+                          _ptr_array(phi_out), float(tol), int(max_iter), stats)
+    if raise_on_error:
+        ctx.check(rc)
+    return rc, [dict(status=s.status, iterations=s.iterations,
+                     residual=s.residual, balance_rel=s.balance_rel,
+                     seconds=s.seconds) for s in stats]
+
+
+def tr_check_args(problems_struct, n: int, quad: Quad, tol: float,
+                  max_iter: int):
+    """Host-only argument check on a prepared TrProblem array."""
+    lib = load()
+    buf = ctypes.create_string_buffer(512)
+    rc = lib.tr_check_args(n, problems_struct, ctypes.byref(quad.struct),
+                           float(tol), int(max_iter), buf, 512)
+    return rc, buf.value.decode()

@@ -1,0 +1,676 @@
+// host.cpp -- the C ABI of libmdpnop (see include/mdpnop.h): argument
+// checks, quadrature tables, launch planning, workspaces and the source
+// iteration driver.  All device work goes to the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mdpnop.h"
+#include "common.h"
+#include "host_internal.h"
+
+namespace mdp {
+
+bool launch_sweep2d(int D, int nwork, int W, int KB, size_t lds_bytes,
+                    const InstDesc* insts, const SweepWork* work,
+                    const DirTable* dt, const int* done, const int* iter,
+                    int use_faces, hipStream_t s);
+size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx);
+void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
+                    const int* done, const int* iter, int use_faces, int M,
+                    hipStream_t s);
+void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
+                 hipStream_t s);
+void launch_init(int n_inst, int nblocks, const InstDesc* insts,
+                 const int2* blocks, const DirTable* dt, IterState st,
+                 hipStream_t s);
+void launch_combine(int nblocks, const InstDesc* insts, const int2* blocks,
+                    const int* done, double2* red, int mode, int norm_kind,
+                    hipStream_t s);
+void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
+                     IterState st, double tol, int norm_kind, hipStream_t s);
+void launch_balance(int n_inst, const InstDesc* insts, const DirTable* dt,
+                    const int* iter, double* bal, hipStream_t s);
+
+// ------------------------------------------------------------ helpers ----
+
+void Ctx::fail(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+}
+
+bool Ctx::hip_ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    fail("%s: %s", what, hipGetErrorString(e));
+    return false;
+}
+
+// Grow-only device arena; sub-allocations are 256-byte aligned.
+bool Arena::reserve(Ctx* c, size_t bytes) {
+    if (bytes <= cap) return true;
+    if (base) { (void)hipFree(base); base = nullptr; cap = 0; }
+    size_t want = std::max(bytes, cap * 3 / 2);
+    if (hipMalloc(&base, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&base, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            base = nullptr;
+            c->fail("out of device memory (%zu bytes)", bytes);
+            return false;
+        }
+        want = bytes;
+    }
+    cap = want;
+    return true;
+}
+
+bool PinnedBuf::reserve(Ctx* c, size_t bytes) {
+    if (bytes <= cap) return true;
+    if (ptr) { (void)hipHostFree(ptr); ptr = nullptr; cap = 0; }
+    if (hipHostMalloc(&ptr, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+        c->fail("out of pinned host memory (%zu bytes)", bytes);
+        return false;
+    }
+    cap = bytes;
+    return true;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// --------------------------------------------------------- quadrature ----
+
+int octant_of(double mu, double eta, int dim) {
+    if (dim == 1) return mu > 0 ? 0 : 1;
+    if (mu > 0 && eta > 0) return 0;
+    if (mu < 0 && eta > 0) return 1;
+    if (mu < 0 && eta < 0) return 2;
+    return 3;
+}
+
+static int find_dir(const tr_quadrature* q, double mu, double eta, int dim) {
+    for (int k = 0; k < q->n_dir; ++k) {
+        const double de = dim == 2 ? std::fabs(q->eta[k] - eta) : 0.0;
+        if (std::fabs(q->mu[k] - mu) < 1e-12 && de < 1e-12) return k;
+    }
+    return -1;
+}
+
+bool build_dirtable(Ctx* c, const tr_quadrature* q, int dim, DirTable* t) {
+    if (!q || q->n_dir <= 0 || q->n_dir > kMaxDir || !q->mu || !q->w ||
+        (dim == 2 && !q->eta)) {
+        c->fail("quadrature: need 1..%d directions with mu, w%s", kMaxDir,
+                dim == 2 ? ", eta" : "");
+        return false;
+    }
+    const int M = q->n_dir;
+    double sw = 0.0;
+    std::memset(t, 0, sizeof(DirTable));
+    t->M = M;
+    for (int m = 0; m < M; ++m) {
+        const double mu = q->mu[m], eta = dim == 2 ? q->eta[m] : 0.0, w = q->w[m];
+        if (!std::isfinite(mu) || !std::isfinite(eta) || !std::isfinite(w) ||
+            w < 0.0 || mu == 0.0 || (dim == 2 && eta == 0.0) ||
+            std::fabs(mu) > 1.0 || std::fabs(eta) > 1.0) {
+            c->fail("quadrature: direction %d invalid (mu=%g eta=%g w=%g)", m,
+                    mu, eta, w);
+            return false;
+        }
+        sw += w;
+        const int o = octant_of(mu, eta, dim);
+        t->list[o][t->count[o]++] = m;
+        t->amu[m] = (float)std::fabs(mu);
+        t->aeta[m] = (float)std::fabs(eta);
+        t->mu[m] = (float)mu;
+        t->eta[m] = (float)eta;
+        t->w[m] = (float)w;
+        const int mx = find_dir(q, -mu, eta, dim);
+        const int my = dim == 2 ? find_dir(q, mu, -eta, dim) : m;
+        if (mx < 0 || my < 0 || std::fabs(q->w[mx] - w) > 1e-12 ||
+            std::fabs(q->w[my] - w) > 1e-12) {
+            c->fail("quadrature: not reflection symmetric at direction %d", m);
+            return false;
+        }
+        t->mirx[m] = mx;
+        t->miry[m] = my;
+    }
+    if (std::fabs(sw - 1.0) > 1e-12) {
+        c->fail("quadrature: weights sum to %.15g, expected 1", sw);
+        return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------- arguments ----
+
+bool check_problems(Ctx* c, int n_inst, const tr_problem* p, bool need_xs) {
+    if (n_inst <= 0 || !p) {
+        c->fail("need n_inst > 0 problems");
+        return false;
+    }
+    const int dim = p[0].dim;
+    for (int i = 0; i < n_inst; ++i) {
+        const tr_problem& P = p[i];
+        if (P.dim != 1 && P.dim != 2) {
+            c->fail("problem %d: dim must be 1 or 2", i);
+            return false;
+        }
+        if (P.dim != dim) {
+            c->fail("problem %d: all problems of a call must share dim", i);
+            return false;
+        }
+        const int ny = P.dim == 1 ? 1 : P.ny;
+        if (P.nx <= 0 || ny <= 0 || (int64_t)P.nx * ny > (1LL << 30)) {
+            c->fail("problem %d: bad grid %d x %d", i, P.nx, P.ny);
+            return false;
+        }
+        if (P.dim == 2 && P.ny <= 0) {
+            c->fail("problem %d: ny must be positive", i);
+            return false;
+        }
+        if (!(P.lx > 0.0) || !std::isfinite(P.lx) ||
+            (P.dim == 2 && (!(P.ly > 0.0) || !std::isfinite(P.ly)))) {
+            c->fail("problem %d: extents must be positive and finite", i);
+            return false;
+        }
+        if (!P.sigma_t || (need_xs && (!P.sigma_s || !P.source))) {
+            c->fail("problem %d: missing field pointer", i);
+            return false;
+        }
+        const int nb = P.dim == 1 ? 2 : 4;
+        for (int f = 0; f < nb; ++f)
+            if (P.bc[f] != TR_BC_VACUUM && P.bc[f] != TR_BC_REFLECTIVE) {
+                c->fail("problem %d: bc[%d] = %d is not a tr_bc", i, f, P.bc[f]);
+                return false;
+            }
+    }
+    return true;
+}
+
+}  // namespace mdp
+
+using namespace mdp;
+
+// ===================================================================== ABI
+
+extern "C" tr_status tr_context_create(tr_context** ctx, void* hip_stream) {
+    if (!ctx) return TR_ERR_INVALID_ARG;
+    *ctx = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return TR_ERR_HIP;
+    }
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) return TR_ERR_OOM;
+    c->device = dev;
+    c->stream = (hipStream_t)hip_stream;
+    *ctx = reinterpret_cast<tr_context*>(c);
+    return TR_OK;
+}
+
+extern "C" void tr_context_destroy(tr_context* ctx) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->release();
+    delete c;
+}
+
+extern "C" const char* tr_last_error(const tr_context* ctx) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(ctx);
+    return c ? c->err.c_str() : "null context";
+}
+
+void Ctx::release() {
+    if (arena.base) (void)hipFree(arena.base);
+    arena.base = nullptr;
+    arena.cap = 0;
+    if (pinned.ptr) (void)hipHostFree(pinned.ptr);
+    pinned.ptr = nullptr;
+    pinned.cap = 0;
+    release_fno();
+}
+
+// --------------------------------------------------------------- plan ----
+
+namespace mdp {
+
+// Rows per lane segment: the largest of 64/32/16 that fits nx and wastes
+// the fewest lane-rows on the last block (ties go to the larger R).
+static int pick_R(int nx, int ny) {
+    int best = 1, bestw = 1 << 30;
+    for (int R = 64; R >= 1; R >>= 1) {
+        if (R > nx) continue;
+        const int waste = ((ny + R - 1) / R) * R - ny;
+        if (waste < bestw) { best = R; bestw = waste; }
+    }
+    return best;
+}
+
+Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
+    Plan pl;
+    int nd = 0;
+    for (int o = 0; o < 4; ++o) nd = std::max(nd, dt.count[o]);
+    pl.R.resize(n_inst);
+    int nseg_min = 64;
+    for (int i = 0; i < n_inst; ++i) {
+        pl.R[i] = (c->force_R > 0 && c->force_R <= p[i].nx) ? c->force_R
+                                                            : pick_R(p[i].nx, p[i].ny);
+        nseg_min = std::min(nseg_min, 64 / pl.R[i]);
+    }
+    pl.D = c->force_D > 0 ? c->force_D : 1;
+    // enough workgroups to cover every CU at least once
+    int S;
+    if (c->force_S > 0) {
+        S = c->force_S;
+    } else {
+        const int units = 4 * n_inst;
+        S = std::max(1, (256 + units - 1) / units);
+    }
+    S = std::min(S, std::max(1, (nd + pl.D - 1) / pl.D));
+    int W = c->force_W > 0 ? c->force_W
+                           : (nd + nseg_min * pl.D * S - 1) / (nseg_min * pl.D * S);
+    W = std::max(1, std::min(16, W));
+    // recompute S for the capacity actually chosen
+    pl.W = W;
+    pl.S.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const int cap = W * (64 / pl.R[i]) * pl.D;
+        pl.S[i] = std::max(1, (nd + cap - 1) / cap);
+    }
+    pl.KB = 16;
+    int mx = 0;
+    for (int i = 0; i < n_inst; ++i) mx = std::max(mx, (64 / pl.R[i]) * p[i].nx);
+    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx) > 64 * 1024) pl.KB /= 2;
+    pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx);
+    return pl;
+}
+
+// Builds descriptors and workspaces for n_inst problems.  emission != nullptr
+// selects a bare sweep (Q = caller emission, phi = phi_out).
+bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
+                const float* const* phi_init, float* const* phi_out,
+                const float* const* emission, Setup* su) {
+    const int dim = p[0].dim;
+    if (!build_dirtable(this, q, dim, &su->dt)) return false;
+    const int M = su->dt.M;
+    if (dim == 2) {
+        for (int o = 0; o < 4; ++o)
+            if (su->dt.count[o] != su->dt.count[0]) {
+                fail("quadrature: octants hold different direction counts");
+                return false;
+            }
+        su->plan = make_plan(this, n_inst, p, su->dt);
+        if (su->plan.lds > 64 * 1024) {
+            fail("grid too wide for the sweep's LDS ring (nx=%d)", p[0].nx);
+            return false;
+        }
+    }
+    su->inst.resize(n_inst);
+    su->blocks.clear();
+    su->work.clear();
+    size_t off = 0;
+    std::vector<size_t> offQ(n_inst), offP(n_inst), offF(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const tr_problem& P = p[i];
+        InstDesc& d = su->inst[i];
+        std::memset(&d, 0, sizeof d);
+        d.dim = dim;
+        d.nx = P.nx;
+        d.ny = dim == 1 ? 1 : P.ny;
+        d.nf = std::max(d.nx, d.ny);
+        d.cells = d.nx * d.ny;
+        d.dx = P.lx / P.nx;
+        d.dy = dim == 1 ? 1.0 : P.ly / P.ny;
+        d.inv_dx = (float)(1.0 / d.dx);
+        d.inv_dy = (float)(1.0 / d.dy);
+        for (int f = 0; f < 4; ++f) d.bc[f] = (dim == 1 && f >= 2) ? 0 : P.bc[f];
+        d.st = P.sigma_t;
+        d.ss = P.sigma_s;
+        d.q = P.source;
+        d.phi = phi_out[i];
+        d.phi_init = phi_init ? phi_init[i] : nullptr;
+        if (dim == 2) {
+            d.R = su->plan.R[i];
+            d.S = su->plan.S[i];
+            d.P = 4 * d.S;
+            for (int o = 0; o < 4; ++o)
+                for (int s = 0; s < d.S; ++s) su->work.push_back({i, o, s, 0});
+        } else {
+            d.R = 1;
+            d.S = 1;
+            d.P = M;
+        }
+        d.red0 = (int)su->blocks.size();
+        for (int c0 = 0; c0 < d.cells; c0 += kCombineChunk)
+            su->blocks.push_back(make_int2(i, c0));
+        d.nred = (int)su->blocks.size() - d.red0;
+        if (!emission) {
+            offQ[i] = off;
+            off += align_up(sizeof(float) * d.cells);
+        }
+        offP[i] = off;
+        off += align_up(sizeof(float) * (size_t)d.P * d.cells);
+        offF[i] = off;
+        off += align_up(sizeof(float) * (dim == 1 ? (size_t)4 * M
+                                                   : (size_t)8 * d.nf * M));
+    }
+    // fixed-size tables after the per-instance workspaces
+    const size_t oInst = off;
+    off += align_up(sizeof(InstDesc) * n_inst);
+    const size_t oWork = off;
+    off += align_up(sizeof(SweepWork) * std::max<size_t>(1, su->work.size()));
+    const size_t oBlk = off;
+    off += align_up(sizeof(int2) * su->blocks.size());
+    const size_t oDt = off;
+    off += align_up(sizeof(DirTable));
+    const size_t oRed = off;
+    off += align_up(sizeof(double2) * su->blocks.size());
+    const size_t oDone = off;
+    off += align_up(sizeof(int) * n_inst);
+    const size_t oIter = off;
+    off += align_up(sizeof(int) * n_inst);
+    const size_t oStat = off;
+    off += align_up(sizeof(int) * n_inst);
+    const size_t oRes = off;
+    off += align_up(sizeof(double) * n_inst);
+    const size_t oBal = off;
+    off += align_up(sizeof(double) * 3 * n_inst);
+    const size_t oFlag = off;
+    off += align_up(sizeof(int) * n_inst);
+    const size_t oSa = off;
+    off += align_up(sizeof(float) * n_inst);
+    if (!arena.reserve(this, off)) return false;
+    char* b = (char*)arena.base;
+    for (int i = 0; i < n_inst; ++i) {
+        InstDesc& d = su->inst[i];
+        d.Q = emission ? const_cast<float*>(emission[i]) : (float*)(b + offQ[i]);
+        d.part = (float*)(b + offP[i]);
+        d.face = (float*)(b + offF[i]);
+    }
+    su->d_inst = (InstDesc*)(b + oInst);
+    su->d_work = (SweepWork*)(b + oWork);
+    su->d_blocks = (int2*)(b + oBlk);
+    su->d_dt = (DirTable*)(b + oDt);
+    su->d_red = (double2*)(b + oRed);
+    su->st.done = (int*)(b + oDone);
+    su->st.iter = (int*)(b + oIter);
+    su->st.status = (int*)(b + oStat);
+    su->st.resid = (double*)(b + oRes);
+    su->d_bal = (double*)(b + oBal);
+    su->d_flags = (int*)(b + oFlag);
+    su->d_samax = (float*)(b + oSa);
+    // stage the tables through pinned memory
+    const size_t hsz = oRed - oInst;
+    if (!pinned.reserve(this, hsz + 4096 + (size_t)n_inst * 64)) return false;
+    if (!hip_ok(hipStreamSynchronize(stream), "sync")) return false;
+    char* h = (char*)pinned.ptr;
+    std::memcpy(h + (oInst - oInst), su->inst.data(), sizeof(InstDesc) * n_inst);
+    if (!su->work.empty())
+        std::memcpy(h + (oWork - oInst), su->work.data(),
+                    sizeof(SweepWork) * su->work.size());
+    std::memcpy(h + (oBlk - oInst), su->blocks.data(),
+                sizeof(int2) * su->blocks.size());
+    std::memcpy(h + (oDt - oInst), &su->dt, sizeof(DirTable));
+    if (!hip_ok(hipMemcpyAsync(b + oInst, h, hsz, hipMemcpyHostToDevice, stream),
+                "table upload"))
+        return false;
+    return true;
+}
+
+bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
+                       const int* iter, int use_faces) {
+    if (su.inst[0].dim == 1) {
+        launch_sweep1d(n_inst, su.d_inst, su.d_dt, done, iter, use_faces, su.dt.M,
+                       stream);
+    } else {
+        if (!launch_sweep2d(su.plan.D, (int)su.work.size(), su.plan.W, su.plan.KB,
+                            su.plan.lds, su.d_inst, su.d_work, su.d_dt, done, iter,
+                            use_faces, stream)) {
+            fail("unsupported directions-per-lane D=%d", su.plan.D);
+            return false;
+        }
+    }
+    return hip_ok(hipGetLastError(), "sweep launch");
+}
+
+// Field checks on the device: non-finite values, cross-section ranges, and a
+// singular system (no absorption anywhere and no vacuum face).
+tr_status Ctx::scan_fields(const Setup& su, int n_inst, const tr_problem* p,
+                           bool need_xs, tr_stats* stats) {
+    (void)need_xs;
+    launch_scan(n_inst, su.d_inst, su.d_flags, su.d_samax, stream);
+    if (!hip_ok(hipGetLastError(), "scan launch")) return TR_ERR_HIP;
+    int* hf = (int*)pinned.ptr;
+    float* hs = (float*)((char*)pinned.ptr + align_up(sizeof(int) * n_inst));
+    if (!hip_ok(hipMemcpyAsync(hf, su.d_flags, sizeof(int) * n_inst,
+                               hipMemcpyDeviceToHost, stream), "flag copy") ||
+        !hip_ok(hipMemcpyAsync(hs, su.d_samax, sizeof(float) * n_inst,
+                               hipMemcpyDeviceToHost, stream), "flag copy") ||
+        !hip_ok(hipStreamSynchronize(stream), "sync"))
+        return TR_ERR_HIP;
+    tr_status worst = TR_OK;
+    for (int i = 0; i < n_inst; ++i) {
+        tr_status s = TR_OK;
+        if (hf[i] & 1) {
+            s = TR_ERR_NONFINITE;
+            fail("problem %d: non-finite field value", i);
+        } else if (hf[i] & 2) {
+            s = TR_ERR_INVALID_ARG;
+            fail("problem %d: need sigma_t > 0 and 0 <= sigma_s <= sigma_t", i);
+        } else if (hs[i] <= 0.f) {
+            const int nb = p[i].dim == 1 ? 2 : 4;
+            bool vac = false;
+            for (int f = 0; f < nb; ++f) vac |= p[i].bc[f] == TR_BC_VACUUM;
+            if (!vac) {
+                s = TR_ERR_INVALID_ARG;
+                fail("problem %d: no absorption and no vacuum face (singular)", i);
+            }
+        }
+        if (stats) stats[i].status = s;
+        if (s < worst) worst = s;
+    }
+    return worst;
+}
+
+}  // namespace mdp
+
+extern "C" tr_status tr_sweep(tr_context* ctx, int32_t n_inst, const tr_problem* p,
+                              const tr_quadrature* q,
+                              const float* const* emission,
+                              float* const* phi_out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!check_problems(c, n_inst, p, false)) return TR_ERR_INVALID_ARG;
+    if (!emission || !phi_out) {
+        c->fail("emission and phi_out are required");
+        return TR_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < n_inst; ++i)
+        if (!emission[i] || !phi_out[i]) {
+            c->fail("problem %d: null emission or phi_out", i);
+            return TR_ERR_INVALID_ARG;
+        }
+    Setup su;
+    if (!c->setup(n_inst, p, q, nullptr, phi_out, emission, &su))
+        return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
+    if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return TR_ERR_HIP;
+    launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, nullptr,
+                   su.d_red, 1, 0, c->stream);
+    if (!c->hip_ok(hipGetLastError(), "combine launch")) return TR_ERR_HIP;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "sync")) return TR_ERR_HIP;
+    return TR_OK;
+}
+
+extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem* p,
+                              const tr_quadrature* q, const float* const* phi_init,
+                              float* const* phi_out, double tol, int32_t max_iter,
+                              tr_stats* stats) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!check_problems(c, n_inst, p, true)) return TR_ERR_INVALID_ARG;
+    if (!phi_out || max_iter <= 0 || !std::isfinite(tol) || tol == 0.0) {
+        c->fail("need phi_out, max_iter > 0 and a finite non-zero tol");
+        return TR_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < n_inst; ++i)
+        if (!phi_out[i]) {
+            c->fail("problem %d: null phi_out", i);
+            return TR_ERR_INVALID_ARG;
+        }
+    const int norm_kind = tol < 0 ? 1 : 0;
+    const double atol = std::fabs(tol);
+    Setup su;
+    if (!c->setup(n_inst, p, q, phi_init, phi_out, nullptr, &su))
+        return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
+    if (stats)
+        for (int i = 0; i < n_inst; ++i) stats[i] = tr_stats{0, 0, 0.0, 0.0, 0.0};
+    tr_status s0 = c->scan_fields(su, n_inst, p, true, stats);
+    if (s0 < 0) return s0;
+    launch_init(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_dt,
+                su.st, c->stream);
+    if (!c->hip_ok(hipGetLastError(), "init launch")) return TR_ERR_HIP;
+    int* hdone = (int*)c->pinned.ptr;
+    int done_iters = 0, chunk = 4;
+    bool all = false;
+    while (done_iters < max_iter && !all) {
+        const int k = std::min(chunk, max_iter - done_iters);
+        for (int it = 0; it < k; ++it) {
+            if (!c->launch_sweep(su, n_inst, su.st.done, su.st.iter, 1)) return TR_ERR_HIP;
+            launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
+                           su.d_red, 0, norm_kind, c->stream);
+            launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind,
+                            c->stream);
+        }
+        if (!c->hip_ok(hipGetLastError(), "iteration launch")) return TR_ERR_HIP;
+        done_iters += k;
+        if (!c->hip_ok(hipMemcpyAsync(hdone, su.st.done, sizeof(int) * n_inst,
+                                      hipMemcpyDeviceToHost, c->stream),
+                       "flag copy") ||
+            !c->hip_ok(hipStreamSynchronize(c->stream), "sync"))
+            return TR_ERR_HIP;
+        all = true;
+        for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
+        chunk = std::min(chunk * 2, 64);
+    }
+    launch_balance(n_inst, su.d_inst, su.d_dt, su.st.iter, su.d_bal, c->stream);
+    if (!c->hip_ok(hipGetLastError(), "balance launch")) return TR_ERR_HIP;
+    // read back iteration state
+    if (!c->pinned.reserve(c, 2 * align_up(sizeof(int) * n_inst) +
+                                   align_up(sizeof(double) * n_inst) +
+                                   align_up(sizeof(double) * 3 * n_inst)))
+        return TR_ERR_OOM;
+    char* h = (char*)c->pinned.ptr;
+    int* hit = (int*)h;
+    int* hst = (int*)(h + align_up(sizeof(int) * n_inst));
+    double* hres = (double*)(h + 2 * align_up(sizeof(int) * n_inst));
+    double* hbal = (double*)(h + 2 * align_up(sizeof(int) * n_inst) +
+                             align_up(sizeof(double) * n_inst));
+    if (!c->hip_ok(hipMemcpyAsync(hit, su.st.iter, sizeof(int) * n_inst,
+                                  hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !c->hip_ok(hipMemcpyAsync(hst, su.st.status, sizeof(int) * n_inst,
+                                  hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !c->hip_ok(hipMemcpyAsync(hres, su.st.resid, sizeof(double) * n_inst,
+                                  hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !c->hip_ok(hipMemcpyAsync(hbal, su.d_bal, sizeof(double) * 3 * n_inst,
+                                  hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !c->hip_ok(hipStreamSynchronize(c->stream), "sync"))
+        return TR_ERR_HIP;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    tr_status worst = TR_OK;
+    for (int i = 0; i < n_inst; ++i) {
+        tr_status s = hst[i] == 0 ? TR_OK
+                                  : (hst[i] == -4 ? TR_ERR_NONFINITE : TR_NOT_CONVERGED);
+        if (s == TR_ERR_NONFINITE) c->fail("problem %d: non-finite iterate", i);
+        if (stats) {
+            stats[i].status = s;
+            stats[i].iterations = hit[i];
+            stats[i].residual = hres[i];
+            const double sq = hbal[3 * i], sa = hbal[3 * i + 1], lk = hbal[3 * i + 2];
+            stats[i].balance_rel = sq != 0.0 ? std::fabs(sq - sa - lk) / std::fabs(sq)
+                                             : std::fabs(sa + lk);
+            stats[i].seconds = secs;
+        }
+        if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+        else if (worst >= 0 && s > worst) worst = s;
+    }
+    c->last_sweeps = done_iters;
+    return worst;
+}
+
+extern "C" tr_status tr_check_args(int32_t n_inst, const tr_problem* p,
+                                   const tr_quadrature* q, double tol,
+                                   int32_t max_iter, char* msg, int32_t msg_len) {
+    Ctx c;
+    tr_status s = TR_OK;
+    DirTable* dt = new DirTable();
+    if (!check_problems(&c, n_inst, p, true)) s = TR_ERR_INVALID_ARG;
+    else if (!build_dirtable(&c, q, p[0].dim, dt)) s = TR_ERR_INVALID_ARG;
+    else if (max_iter <= 0 || !std::isfinite(tol) || tol == 0.0) {
+        c.fail("need max_iter > 0 and a finite non-zero tol");
+        s = TR_ERR_INVALID_ARG;
+    }
+    delete dt;
+    if (msg && msg_len > 0) {
+        std::snprintf(msg, (size_t)msg_len, "%s", c.err.c_str());
+    }
+    return s;
+}
+
+// Tuning knobs for the autotuner and tests: force directions per lane (D),
+// waves per workgroup (W), slices (S) and rows per segment (R); 0 = auto.
+extern "C" tr_status tr_set_sweep_config(tr_context* ctx, int32_t D, int32_t W,
+                                         int32_t S, int32_t R) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    const int okD[] = {0, 1, 2, 3, 4, 5, 6, 9, 10};
+    bool good = false;
+    for (int v : okD) good |= D == v;
+    if (!good || W < 0 || W > 16 || S < 0 || R < 0 || R > 64 || (R & (R - 1))) {
+        c->fail("sweep config out of range");
+        return TR_ERR_INVALID_ARG;
+    }
+    c->force_D = D;
+    c->force_W = W;
+    c->force_S = S;
+    c->force_R = R;
+    return TR_OK;
+}
+
+// Sweep launch plan the next call would use (for logs and the tuner).
+extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
+                                       const tr_problem* p, const tr_quadrature* q,
+                                       int32_t* out4) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c || !out4) return TR_ERR_INVALID_ARG;
+    if (!check_problems(c, n_inst, p, false)) return TR_ERR_INVALID_ARG;
+    DirTable* dt = new DirTable();
+    if (!build_dirtable(c, q, p[0].dim, dt)) {
+        delete dt;
+        return TR_ERR_INVALID_ARG;
+    }
+    Plan pl = make_plan(c, n_inst, p, *dt);
+    delete dt;
+    out4[0] = pl.D;
+    out4[1] = pl.W;
+    out4[2] = pl.S.empty() ? 0 : pl.S[0];
+    out4[3] = pl.R.empty() ? 0 : pl.R[0];
+    return TR_OK;
+}

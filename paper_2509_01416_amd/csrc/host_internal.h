@@ -1,0 +1,82 @@
+// host_internal.h -- host-side state of a tr_context (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mdp {
+
+struct Ctx;
+
+struct Arena {
+    void* base = nullptr;
+    size_t cap = 0;
+    bool reserve(Ctx* c, size_t bytes);
+};
+
+struct PinnedBuf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    bool reserve(Ctx* c, size_t bytes);
+};
+
+// Launch plan of the 2-D sweep: D directions per lane, W waves per
+// workgroup, per-instance rows per segment R and slices S, LDS block KB.
+struct Plan {
+    int D = 1, W = 1, KB = 16;
+    size_t lds = 0;
+    std::vector<int> R, S;
+};
+
+struct Setup {
+    DirTable dt;
+    Plan plan;
+    std::vector<InstDesc> inst;
+    std::vector<SweepWork> work;
+    std::vector<int2> blocks;
+    InstDesc* d_inst = nullptr;
+    SweepWork* d_work = nullptr;
+    int2* d_blocks = nullptr;
+    DirTable* d_dt = nullptr;
+    double2* d_red = nullptr;
+    IterState st{};
+    double* d_bal = nullptr;
+    int* d_flags = nullptr;
+    float* d_samax = nullptr;
+};
+
+struct FnoWork;
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Arena arena;          // per-call solver workspace
+    PinnedBuf pinned;     // staging and flag read-back
+    int force_D = 0, force_W = 0, force_S = 0, force_R = 0;
+    int last_sweeps = 0;
+    FnoWork* fno = nullptr;   // network workspaces
+
+    void fail(const char* fmt, ...);
+    bool hip_ok(hipError_t e, const char* what);
+    void release();
+    void release_fno();
+    bool setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
+               const float* const* phi_init, float* const* phi_out,
+               const float* const* emission, Setup* su);
+    bool launch_sweep(const Setup& su, int n_inst, const int* done,
+                      const int* iter, int use_faces);
+    tr_status scan_fields(const Setup& su, int n_inst, const tr_problem* p,
+                          bool need_xs, tr_stats* stats);
+};
+
+size_t align_up(size_t x);
+bool build_dirtable(Ctx* c, const tr_quadrature* q, int dim, DirTable* t);
+bool check_problems(Ctx* c, int n_inst, const tr_problem* p, bool need_xs);
+Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt);
+
+}  // namespace mdp

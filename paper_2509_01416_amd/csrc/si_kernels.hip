@@ -1,0 +1,341 @@
+// si_kernels.hip -- the non-sweep kernels of the source iteration
+// (arXiv 2509.01416: the model-based iteration M of Eq. 3a/4b, realised as
+// S_N source iteration in section 5.1):
+//   * 1-D slab sweep (Eq. 12 with diamond differencing);
+//   * argument scan (finite values, 0 <= sigma_s <= sigma_t, sigma_t > 0);
+//   * initialisation of the iterate, the emission and the boundary faces;
+//   * combine: phi_new = sum of the sweep's partial planes in fixed order,
+//     next emission Q = sigma_s phi_new + q, FP64 change-norm partials;
+//   * finalize: per-instance FP64 change norm, convergence flag;
+//   * FP64 particle balance of the converged iterate.
+#include <math.h>
+
+#include "common.h"
+
+namespace mdp {
+
+// ------------------------------------------------------------ 1-D sweep ---
+// One thread per (instance, direction); each walks its cells in upwind order
+// and writes w_m psi_m to its own partial plane (P = M planes).
+__global__ void sweep1d_kernel(const InstDesc* __restrict__ insts,
+                               const DirTable* __restrict__ dt,
+                               const int* __restrict__ done,
+                               const int* __restrict__ iter, int use_faces) {
+    const int n = blockIdx.x;
+    if (done != nullptr && done[n]) return;
+    const InstDesc& I = insts[n];
+    const int M = dt->M;
+    const int par = (iter != nullptr ? iter[n] : 0) & 1;
+    const float* fprev = I.face + (size_t)par * 2 * M;
+    float* fcur = I.face + (size_t)(par ^ 1) * 2 * M;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        const float mu = dt->mu[m];
+        const bool pos = mu > 0.f;
+        const float a = 2.0f * dt->amu[m] * I.inv_dx;
+        const float wm = dt->w[m];
+        const int fin = pos ? 0 : 1, fout = pos ? 1 : 0;
+        float in = (use_faces && I.bc[fin] == 1) ? fprev[fin * M + dt->mirx[m]] : 0.f;
+        float* part = I.part + (size_t)m * I.cells;
+        const int nx = I.nx;
+        for (int ii = 0; ii < nx; ++ii) {
+            const int i = pos ? ii : nx - 1 - ii;
+            const float psi = fmaf(a, in, I.Q[i]) * __builtin_amdgcn_rcpf(I.st[i] + a);
+            in = psi + psi - in;
+            part[i] = wm * psi;
+        }
+        fcur[fout * M + m] = in;
+    }
+}
+
+// ------------------------------------------------------- argument scan ---
+// flags[n] bit 0: a non-finite value; bit 1: sigma_t <= 0, sigma_s < 0 or
+// sigma_s > sigma_t.  samax[n] = max(sigma_t - sigma_s).
+__global__ void scan_kernel(const InstDesc* __restrict__ insts, int* flags,
+                            float* samax) {
+    const int n = blockIdx.x;
+    const InstDesc& I = insts[n];
+    int bad = 0;
+    float mx = 0.f;
+    for (int c = threadIdx.x; c < I.cells; c += blockDim.x) {
+        const float st = I.st[c], ss = I.ss[c], q = I.q[c];
+        if (!isfinite(st) || !isfinite(ss) || !isfinite(q)) bad |= 1;
+        if (I.phi_init != nullptr && !isfinite(I.phi_init[c])) bad |= 1;
+        if (!(st > 0.f) || ss < 0.f || ss > st) bad |= 2;
+        mx = fmaxf(mx, st - ss);
+    }
+    __shared__ int sbad[1024];
+    __shared__ float smx[1024];
+    sbad[threadIdx.x] = bad;
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0;
+        float m = 0.f;
+        for (int t = 0; t < (int)blockDim.x; ++t) {
+            b |= sbad[t];
+            m = fmaxf(m, smx[t]);
+        }
+        flags[n] = b;
+        samax[n] = m;
+    }
+}
+
+// ------------------------------------------------------------- init ------
+// Grid: one block per reduction block (instance, chunk) of the combine.
+__global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
+                                  const int2* __restrict__ blocks) {
+    const int2 bi = blocks[blockIdx.x];
+    const InstDesc& I = insts[bi.x];
+    const int c1 = min(bi.y + kCombineChunk, I.cells);
+    for (int c = bi.y + threadIdx.x; c < c1; c += blockDim.x) {
+        const float p = I.phi_init != nullptr ? I.phi_init[c] : 0.f;
+        I.phi[c] = p;
+        I.Q[c] = fmaf(I.ss[c], p, I.q[c]);
+    }
+}
+
+// Faces of parity 0: isotropic at the adjacent cell's initial flux (warm
+// start) or zero.  One block per instance.
+__global__ void init_faces_kernel(const InstDesc* __restrict__ insts,
+                                  const DirTable* __restrict__ dt,
+                                  IterState st) {
+    const int n = blockIdx.x;
+    const InstDesc& I = insts[n];
+    const int M = dt->M;
+    if (threadIdx.x == 0) {
+        st.done[n] = 0;
+        st.iter[n] = 0;
+        st.status[n] = 1;
+        st.resid[n] = INFINITY;
+    }
+    if (I.dim == 1) {
+        for (int e = threadIdx.x; e < 2 * M; e += blockDim.x) {
+            const int f = e / M;
+            float v = 0.f;
+            if (I.phi_init != nullptr) v = I.phi_init[f == 0 ? 0 : I.nx - 1];
+            I.face[e] = v;
+        }
+        return;
+    }
+    const int nf = I.nf;
+    const int total = 4 * nf * M;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int f = e / (nf * M);
+        const int kk = (e / M) % nf;
+        float v = 0.f;
+        if (I.phi_init != nullptr) {
+            const int len = f < 2 ? I.ny : I.nx;
+            if (kk < len) {
+                int c;
+                if (f == 0) c = kk * I.nx;
+                else if (f == 1) c = kk * I.nx + I.nx - 1;
+                else if (f == 2) c = kk;
+                else c = (I.ny - 1) * I.nx + kk;
+                v = I.phi_init[c];
+            }
+        }
+        I.face[e] = v;
+    }
+}
+
+// ------------------------------------------------------------ combine ----
+// mode 0: source-iteration update (phi, Q, change-norm partials);
+// mode 1: bare sweep (phi = sum of planes).
+__global__ void __launch_bounds__(kCombineThreads)
+combine_kernel(const InstDesc* __restrict__ insts,
+               const int2* __restrict__ blocks, const int* __restrict__ done,
+               double2* __restrict__ red, int mode, int norm_kind) {
+    const int2 bi = blocks[blockIdx.x];
+    const int n = bi.x;
+    if (done != nullptr && done[n]) return;
+    const InstDesc& I = insts[n];
+    const int cells = I.cells, P = I.P;
+    const int c1 = min(bi.y + kCombineChunk, cells);
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = bi.y + threadIdx.x; c < c1; c += blockDim.x) {
+        const float* pp = I.part + c;
+        float s = 0.f;
+        for (int p = 0; p < P; ++p) s += pp[(size_t)p * cells];
+        if (mode == 1) {
+            I.phi[c] = s;
+            continue;
+        }
+        const float old = I.phi[c];
+        I.phi[c] = s;
+        I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
+        const double d = (double)s - (double)old;
+        if (norm_kind == 0) {
+            s1 += d * d;
+            s2 += (double)s * (double)s;
+        } else {
+            const double as = fabs((double)s);
+            const double rel = as > 0.0 ? fabs(d) / as : (d != 0.0 ? INFINITY : 0.0);
+            s1 = fmax(s1, rel);
+        }
+    }
+    if (mode == 1) return;
+    __shared__ double r1[kCombineThreads], r2[kCombineThreads];
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = kCombineThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            if (norm_kind == 0) {
+                r1[threadIdx.x] += r1[threadIdx.x + h];
+                r2[threadIdx.x] += r2[threadIdx.x + h];
+            } else {
+                r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + h]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = make_double2(r1[0], r2[0]);
+}
+
+// ----------------------------------------------------------- finalize ----
+__global__ void finalize_kernel(const InstDesc* __restrict__ insts,
+                                const double2* __restrict__ red, IterState st,
+                                int n_inst, double tol, int norm_kind) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_inst || st.done[n]) return;
+    const InstDesc& I = insts[n];
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < I.nred; ++b) {
+        const double2 v = red[I.red0 + b];
+        if (norm_kind == 0) { s1 += v.x; s2 += v.y; }
+        else s1 = fmax(s1, v.x);
+    }
+    double r;
+    if (norm_kind == 0)
+        r = s2 > 0.0 ? sqrt(s1 / s2) : (s1 == 0.0 ? 0.0 : INFINITY);
+    else
+        r = s1;
+    st.resid[n] = r;
+    st.iter[n] += 1;
+    if (!isfinite(s1) || !isfinite(s2)) {
+        st.status[n] = -4;
+        st.done[n] = 1;
+    } else if (r < tol) {
+        st.status[n] = 0;
+        st.done[n] = 1;
+    }
+}
+
+// ------------------------------------------------------------ balance ----
+// bal[n] = {sum q V, sum sigma_a phi V, leakage} in FP64 for the last sweep.
+__global__ void balance_kernel(const InstDesc* __restrict__ insts,
+                               const DirTable* __restrict__ dt,
+                               const int* __restrict__ iter, double* bal) {
+    const int n = blockIdx.x;
+    const InstDesc& I = insts[n];
+    const int M = dt->M;
+    const double V = I.dx * I.dy;
+    double sq = 0.0, sa = 0.0, lk = 0.0;
+    for (int c = threadIdx.x; c < I.cells; c += blockDim.x) {
+        sq += (double)I.q[c] * V;
+        sa += ((double)I.st[c] - (double)I.ss[c]) * (double)I.phi[c] * V;
+    }
+    const int it = iter[n];
+    const int pc = it & 1, pp = (it + 1) & 1;   // current / previous parity
+    if (I.dim == 1) {
+        const float* fc = I.face + (size_t)pc * 2 * M;
+        const float* fp = I.face + (size_t)pp * 2 * M;
+        for (int e = threadIdx.x; e < 2 * M; e += blockDim.x) {
+            const int f = e / M, m = e - f * M;
+            const double on = f == 0 ? -(double)dt->mu[m] : (double)dt->mu[m];
+            double psi;
+            if (on > 0.0) psi = fc[f * M + m];
+            else psi = I.bc[f] == 1 ? fp[f * M + dt->mirx[m]] : 0.0;
+            lk += (double)dt->w[m] * on * psi;
+        }
+    } else {
+        const int nf = I.nf;
+        const size_t fs = (size_t)4 * nf * M;
+        const float* fc = I.face + (size_t)pc * fs;
+        const float* fp = I.face + (size_t)pp * fs;
+        const int total = 4 * nf * M;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const int f = e / (nf * M);
+            const int kk = (e / M) % nf;
+            const int m = e % M;
+            const int len = f < 2 ? I.ny : I.nx;
+            if (kk >= len) continue;
+            double on;
+            if (f == 0) on = -(double)dt->mu[m];
+            else if (f == 1) on = (double)dt->mu[m];
+            else if (f == 2) on = -(double)dt->eta[m];
+            else on = (double)dt->eta[m];
+            const double A = f < 2 ? I.dy : I.dx;
+            double psi;
+            if (on > 0.0) {
+                psi = fc[e];
+            } else if (I.bc[f] == 1) {
+                const int mm = f < 2 ? dt->mirx[m] : dt->miry[m];
+                psi = fp[((size_t)f * nf + kk) * M + mm];
+            } else {
+                psi = 0.0;
+            }
+            lk += (double)dt->w[m] * on * psi * A;
+        }
+    }
+    __shared__ double r[3][256];
+    r[0][threadIdx.x] = sq;
+    r[1][threadIdx.x] = sa;
+    r[2][threadIdx.x] = lk;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) r[k][threadIdx.x] += r[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bal[3 * n + 0] = r[0][0];
+        bal[3 * n + 1] = r[1][0];
+        bal[3 * n + 2] = r[2][0];
+    }
+}
+
+// ------------------------------------------------------------ launchers --
+void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
+                    const int* done, const int* iter, int use_faces, int M,
+                    hipStream_t s) {
+    const int th = M <= 64 ? 64 : (M <= 256 ? 256 : 1024);
+    hipLaunchKernelGGL(sweep1d_kernel, dim3(n_inst), dim3(th), 0, s, insts, dt,
+                       done, iter, use_faces);
+}
+
+void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(scan_kernel, dim3(n_inst), dim3(256), 0, s, insts, flags,
+                       samax);
+}
+
+void launch_init(int n_inst, int nblocks, const InstDesc* insts,
+                 const int2* blocks, const DirTable* dt, IterState st,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(init_cells_kernel, dim3(nblocks), dim3(kCombineThreads), 0,
+                       s, insts, blocks);
+    hipLaunchKernelGGL(init_faces_kernel, dim3(n_inst), dim3(256), 0, s, insts,
+                       dt, st);
+}
+
+void launch_combine(int nblocks, const InstDesc* insts, const int2* blocks,
+                    const int* done, double2* red, int mode, int norm_kind,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(nblocks), dim3(kCombineThreads), 0, s,
+                       insts, blocks, done, red, mode, norm_kind);
+}
+
+void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
+                     IterState st, double tol, int norm_kind, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, s,
+                       insts, red, st, n_inst, tol, norm_kind);
+}
+
+void launch_balance(int n_inst, const InstDesc* insts, const DirTable* dt,
+                    const int* iter, double* bal, hipStream_t s) {
+    hipLaunchKernelGGL(balance_kernel, dim3(n_inst), dim3(256), 0, s, insts, dt,
+                       iter, bal);
+}
+
+}  // namespace mdp

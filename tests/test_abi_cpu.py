@@ -1,0 +1,77 @@
+"""The C ABI without a GPU: every declared symbol is exported, and the
+host-side argument checks reject what the header says they reject."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_01416_amd import binding as B
+from paper_2509_01416_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mdpnop.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:tr_status|void|int64_t|const char \*)\s*\**\s*"
+                                 r"([a-z_]+)\s*\(", txt)))
+
+
+def test_all_declared_symbols_exported():
+    lib = B.load()
+    names = _declared()
+    assert "tr_solve" in names and "tr_sweep" in names and "no_recast_guess" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def _prob(nx=8, ny=8, dim=2, lx=1.0, bc=(0, 0, 0, 0)):
+    arr = (B.TrProblem * 1)()
+    arr[0].dim, arr[0].nx, arr[0].ny = dim, nx, ny
+    arr[0].lx, arr[0].ly = lx, 1.0
+    arr[0].sigma_t = arr[0].sigma_s = arr[0].source = 0x1000  # never read
+    for f in range(4):
+        arr[0].bc[f] = bc[f]
+    return arr
+
+
+def test_check_args_accepts_valid():
+    q = B.Quad.from_inputs(I.level_symmetric_2d(8))
+    rc, msg = B.tr_check_args(_prob(), 1, q, 1e-6, 100)
+    assert rc == B.TR_OK, msg
+
+
+@pytest.mark.parametrize("kw,needle", [(dict(nx=0), "grid"), (dict(dim=3), "dim"),
+                                       (dict(lx=-1.0), "extent"),
+                                       (dict(bc=(0, 2, 0, 0)), "tr_bc")])
+def test_check_args_rejects_problem(kw, needle):
+    q = B.Quad.from_inputs(I.level_symmetric_2d(8))
+    rc, msg = B.tr_check_args(_prob(**kw), 1, q, 1e-6, 100)
+    assert rc == B.TR_ERR_INVALID_ARG and needle in msg
+
+
+def test_check_args_rejects_quadrature():
+    lq = I.level_symmetric_2d(8)
+    q = B.Quad(lq.mu, lq.eta, lq.w * 1.01)
+    rc, msg = B.tr_check_args(_prob(), 1, q, 1e-6, 100)
+    assert rc == B.TR_ERR_INVALID_ARG and "sum" in msg
+    mu = lq.mu.copy()
+    mu[0] *= 0.9
+    q = B.Quad(mu, lq.eta, lq.w)
+    rc, msg = B.tr_check_args(_prob(), 1, q, 1e-6, 100)
+    assert rc == B.TR_ERR_INVALID_ARG and "symmetric" in msg
+    rc, msg = B.tr_check_args(_prob(), 1, B.Quad.from_inputs(lq), 0.0, 100)
+    assert rc == B.TR_ERR_INVALID_ARG
+    rc, msg = B.tr_check_args(_prob(), 1, B.Quad.from_inputs(lq), 1e-6, 0)
+    assert rc == B.TR_ERR_INVALID_ARG
+
+
+def test_check_args_1d():
+    gl = I.gauss_legendre(8)
+    q = B.Quad(gl.mu, None, gl.w)
+    rc, msg = B.tr_check_args(_prob(nx=200, ny=1, dim=1), 1, q, -1e-8, 100)
+    assert rc == B.TR_OK, msg

@@ -1,0 +1,206 @@
+"""Parity of the HIP source-iteration path against the FP64 oracle.
+
+Every call goes through the C ABI (libmdpnop.so via the ctypes binding).
+Tolerances:
+  * one sweep in FP32: each cell update is a handful of fused operations
+    (relative rounding <= ~4 eps32 per cell) and a face flux is carried along
+    at most nx + ny cells with gain <= 1 per cell, so the error relative to
+    max|phi| is bounded by ~4 eps32 (nx + ny); the tests use that bound;
+  * converged source iteration: FP32 fixed point within eps32 / (1 - rho)
+    of the FP64 one; the bar is 1e-5 relative L2 (the library's stated
+    accuracy target) against the oracle run to 1e-13.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import log, rel_inf, rel_l2, to_problem
+from paper_2509_01416_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01416_amd import binding as B
+    assert torch.cuda.is_available()
+    ctx = B.Context()
+    yield torch, B, ctx
+    ctx.close()
+
+
+def _sweep_case(env, insts, quad):
+    torch, B, ctx = env
+    probs = [to_problem(i, torch) for i in insts]
+    rng = np.random.Generator(np.random.PCG64(99))
+    Qs = [rng.uniform(0.0, 2.0, (i.ny, i.nx)) for i in insts]
+    em = [torch.tensor(q.astype(np.float32), device="cuda") for q in Qs]
+    out = [torch.zeros_like(e) for e in em]
+    B.tr_sweep(ctx, probs, B.Quad.from_inputs(quad), em, out)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for inst, q, o in zip(insts, Qs, out):
+        ref = oracle.sweep2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu,
+                             quad.eta, quad.w, inst.sigma_t.astype(np.float32),
+                             q.astype(np.float32))
+        e = rel_inf(o.cpu().numpy(), ref)
+        bound = 4 * EPS32 * (inst.nx + inst.ny) + 8 * EPS32
+        log(f"  sweep {inst.nx}x{inst.ny} M={quad.n_dir}: rel_inf={e:.3e} bound={bound:.3e}")
+        assert e <= bound
+        worst = max(worst, e)
+    return worst
+
+
+@pytest.mark.parametrize("shape,n", [((4, 4), 4), ((37, 23), 8), ((64, 64), 8),
+                                     ((100, 70), 16), ((17, 130), 8)])
+def test_sweep_parity(env, shape, n):
+    nx, ny = shape
+    log(f"[tr_sweep] {nx}x{ny} S{n}")
+    inst = I.random_instance(nx, ny, seed=nx * 7 + ny, lx=7.0, ly=5.0)
+    _sweep_case(env, [inst], I.level_symmetric_2d(n))
+
+
+def test_sweep_batched_uneven(env):
+    log("[tr_sweep] batched uneven")
+    insts = [I.random_instance(n, n, seed=100 + n) for n in (32, 48, 64, 96, 128, 40)]
+    _sweep_case(env, insts, I.level_symmetric_2d(8))
+
+
+@pytest.mark.parametrize("D,W,S,R", [(1, 10, 1, 64), (2, 5, 1, 64), (1, 5, 1, 32),
+                                     (1, 1, 10, 64), (3, 2, 2, 16), (4, 1, 3, 32)])
+def test_sweep_configs_agree(env, D, W, S, R):
+    torch, B, ctx = env
+    log(f"[tr_sweep] config D={D} W={W} S={S} R={R}")
+    ctx.set_sweep_config(D, W, S, R)
+    try:
+        insts = [I.random_instance(n, n, seed=200 + n) for n in (64, 96)]
+        _sweep_case(env, insts, I.level_symmetric_2d(8))
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+
+
+def _solve(env, insts, quad, tol, max_iter=20000, phi0=None):
+    torch, B, ctx = env
+    probs = [to_problem(i, torch) for i in insts]
+    out = [torch.zeros_like(p.sigma_t) for p in probs]
+    init = None
+    if phi0 is not None:
+        init = [None if p is None else torch.tensor(p.astype(np.float32), device="cuda")
+                for p in phi0]
+    rc, st = B.tr_solve(ctx, probs, B.Quad.from_inputs(quad), init, out, tol, max_iter)
+    torch.cuda.synchronize()
+    return rc, st, [o.cpu().numpy().astype(np.float64) for o in out]
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 0, 1, 0), (1, 1, 1, 0)])
+def test_solve_parity_small(env, bc):
+    log(f"[tr_solve] small bc={bc}")
+    quad = I.level_symmetric_2d(8)
+    insts = [I.random_instance(nx, ny, seed=3 + nx, lx=5.0, ly=4.0, bc=bc)
+             for nx, ny in ((24, 16), (33, 47))]
+    rc, st, phis = _solve(env, insts, quad, 1e-7)
+    assert rc == 0
+    for inst, s, phi in zip(insts, st, phis):
+        ref = oracle.solve_instance(inst, quad, tol=1e-13)
+        e = rel_l2(phi, ref.phi)
+        log(f"  {inst.nx}x{inst.ny}: iters gpu={s['iterations']} oracle={ref.iterations} "
+            f"rel_l2={e:.3e} balance={s['balance_rel']:.2e}")
+        assert e < 1e-5
+        assert s["balance_rel"] < 1e-4
+
+
+def test_infinite_medium_gpu(env):
+    log("[tr_solve] infinite medium")
+    quad = I.level_symmetric_2d(8)
+    inst = I.random_instance(40, 30, seed=5, bc=(1, 1, 1, 1))
+    kappa = 3.0
+    inst.source = kappa * (inst.sigma_t - inst.sigma_s)
+    rc, st, phis = _solve(env, [inst], quad, 1e-7)
+    assert rc == 0
+    assert np.abs(phis[0] - kappa).max() < 1e-4 * kappa
+
+
+def test_slab_1d_gpu(env):
+    log("[tr_solve] 1-D slab 200 cells S8")
+    wl = I.slab_1d()
+    inst, quad = wl.instances[0], wl.quad
+    rc, st, phis = _solve(env, [inst], quad, -1e-7)
+    ref = oracle.solve_instance(inst, quad, tol=1e-14)
+    e = rel_l2(phis[0], ref.phi)
+    log(f"  iters gpu={st[0]['iterations']} rel_l2={e:.3e}")
+    assert rc == 0 and e < 1e-5
+
+
+def test_sinusoid_128_full(env):
+    log("[tr_solve] 128^2 S8 sinusoidal, tol 1e-6")
+    wl = I.sinusoid_128()
+    inst, quad = wl.instances[0], wl.quad
+    rc, st, phis = _solve(env, [inst], quad, wl.tol)
+    ref = oracle.solve_instance(inst, quad, tol=1e-12)
+    e = rel_l2(phis[0], ref.phi)
+    z = oracle.solve_instance(inst, quad, tol=wl.tol)
+    log(f"  iters gpu={st[0]['iterations']} oracle(1e-6)={z.iterations} rel_l2={e:.3e} "
+        f"balance={st[0]['balance_rel']:.2e}")
+    assert rc == 0
+    assert abs(st[0]["iterations"] - z.iterations) <= 2
+    assert e < 1e-5
+
+
+def test_warm_start_invariance(env):
+    log("[tr_solve] warm start reaches the same answer")
+    quad = I.level_symmetric_2d(8)
+    inst = I.random_instance(48, 40, seed=12, bc=(1, 0, 0, 0))
+    ref = oracle.solve_instance(inst, quad, tol=1e-13)
+    rng = np.random.Generator(np.random.PCG64(3))
+    guess = ref.phi * (1 + 0.02 * rng.standard_normal(ref.phi.shape))
+    rc0, s0, p0 = _solve(env, [inst], quad, 1e-7)
+    rc1, s1, p1 = _solve(env, [inst], quad, 1e-7, phi0=[guess])
+    log(f"  zero iters={s0[0]['iterations']} warm iters={s1[0]['iterations']}")
+    assert rc0 == 0 and rc1 == 0
+    assert rel_l2(p1[0], ref.phi) < 1e-5
+    assert s1[0]["iterations"] < s0[0]["iterations"]
+
+
+def test_determinism_and_batch_equals_single(env):
+    torch, B, ctx = env
+    log("[tr_solve] determinism; batched == single")
+    quad = I.level_symmetric_2d(8)
+    insts = [I.random_instance(n, n, seed=300 + n) for n in (32, 64, 96)]
+    ctx.set_sweep_config(1, 5, 1, 32)
+    try:
+        _, _, a = _solve(env, insts, quad, 1e-6)
+        _, _, b = _solve(env, insts, quad, 1e-6)
+        singles = [_solve(env, [i], quad, 1e-6)[2][0] for i in insts]
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+    for x, y, z in zip(a, b, singles):
+        assert np.array_equal(x, y)
+        assert np.array_equal(x, z)
+
+
+def test_not_converged_and_errors(env):
+    torch, B, ctx = env
+    log("[tr_solve] status codes")
+    quad = I.level_symmetric_2d(4)
+    inst = I.random_instance(16, 16, seed=8)
+    rc, st, _ = _solve(env, [inst], quad, 1e-12, max_iter=3)
+    assert rc == B.TR_NOT_CONVERGED and st[0]["iterations"] == 3
+    bad = I.random_instance(16, 16, seed=9)
+    bad.sigma_s = bad.sigma_t * 1.5
+    with pytest.raises(B.MdpError) as e:
+        _solve(env, [bad], quad, 1e-6)
+    assert e.value.status == B.TR_ERR_INVALID_ARG
+    nan = I.random_instance(16, 16, seed=10)
+    nan.source = nan.source.copy()
+    nan.source[3, 4] = np.nan
+    with pytest.raises(B.MdpError) as e:
+        _solve(env, [nan], quad, 1e-6)
+    assert e.value.status == B.TR_ERR_NONFINITE
+    sing = I.random_instance(16, 16, seed=11, bc=(1, 1, 1, 1))
+    sing.sigma_s = sing.sigma_t.copy()
+    with pytest.raises(B.MdpError) as e:
+        _solve(env, [sing], quad, 1e-6)
+    assert e.value.status == B.TR_ERR_INVALID_ARG
