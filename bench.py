@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the S_N source-iteration hot path on one MI355X.
+
+Workload (default): 16 instances of 256 x 256 cells on a 10 x 10 mfp square,
+level-symmetric S16 (144 directions), two-region sigma_t in {1, 5} split by a
+seeded random line, c = 0.99, Gaussian-random-field sources, vacuum faces,
+tolerance 1e-6 on the relative L2 change.  One step = one pass of the hot
+path over the batch: the equation-recast guess from the operator network
+(when a trained network is available) followed by the source iteration to
+tolerance; without a network the step is the zero-start source iteration.
+
+Prints one JSON line: the metric (cell-angle updates/s over the whole step),
+the warm/zero wall times, the dominant kernel's roofline from HIP events
+recorded live on the library stream, and the FP64 oracle's throughput on a
+bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# x 2 flop (FMA) = 78.6 TFLOP/s (the 157.3 TFLOP/s headline needs packed FP32,
+# which this library does not use)
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# algorithmic work of one diamond-difference cell-angle update:
+# 2 FMA numerator (4), denominator add (1), reciprocal (1), product (1),
+# 2 psi (1), two outgoing faces (2), weighted accumulation FMA (2) = 12 flop
+FLOP_PER_UPDATE = 12
+# algorithmic HBM bytes per cell per source iteration: read sigma_t, sigma_s,
+# q, phi_old; write phi_new (FP32)
+BYTES_PER_CELL_ITER = 20
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=16)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--zero-only", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=20000,
+                    help="cap on source iterations per solve (profiling runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, target_s: float):
+    """Oracle (FP64, plain C) on a bounded sample: every instance of the
+    workload, a fixed number of source iterations, one thread per instance."""
+    import oracle
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(16, ncpu, len(wl.instances)))
+    inst = wl.instances[0]
+    t0 = time.perf_counter()
+    oracle.solve_instance(inst, wl.quad, tol=0.0 + 1e-300, max_iter=1)
+    t1 = time.perf_counter() - t0
+    rounds = (len(wl.instances) + threads - 1) // threads
+    iters = int(max(2, min(2000, target_s / max(t1, 1e-6) / rounds)))
+    t0 = time.perf_counter()
+    res = oracle.solve_many(wl.instances, wl.quad, tol=1e-300, threads=threads,
+                            max_iter=iters)
+    dt = time.perf_counter() - t0
+    ups = sum(r.iterations * i.cells for r, i in zip(res, wl.instances)) * wl.quad.n_dir
+    return {"value": ups / dt, "unit": "cell-angle updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(wl.instances)} instances x {iters} source iterations "
+                      f"(FP64 C oracle, one thread per instance), {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this "
+              "build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2509_01416_amd import binding as B
+    from paper_2509_01416_amd import inputs as I
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    wl = I.hard_two_region(args.instances, args.n)
+    quad = B.Quad.from_inputs(wl.quad)
+    M = wl.quad.n_dir
+    log(f"[bench] workload {wl.name}: {len(wl.instances)} x {args.n}^2, M={M}")
+    dev = "cuda"
+    probs = [B.Problem(sigma_t=torch.tensor(i.sigma_t, dtype=torch.float32, device=dev),
+                       sigma_s=torch.tensor(i.sigma_s, dtype=torch.float32, device=dev),
+                       source=torch.tensor(i.source, dtype=torch.float32, device=dev),
+                       lx=i.lx, ly=i.ly) for i in wl.instances]
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    cells = sum(i.cells for i in wl.instances)
+    ctx = B.Context()
+    plan = ctx.sweep_plan(probs, quad)
+    log(f"[bench] sweep plan {plan}")
+
+    def zero_step():
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)
+        return st
+
+    step = zero_step
+    for w in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {w}: iterations {[s['iterations'] for s in st][:4]}...")
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    updates = 0
+    its = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = step()
+        its.append([s["iterations"] for s in st])
+        updates += sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * M
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = dt * 1e3 / args.steps
+    log(f"[bench] {args.steps} steps in {dt:.3f} s; profile {prof}")
+
+    sweep_ms = prof["sweep_ms"]
+    flops = updates * FLOP_PER_UPDATE
+    achieved = flops / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
+    cell_iters = updates / M
+    hbm = cell_iters * BYTES_PER_CELL_ITER / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None,
+            "traffic": None, "kernel": "sweep2d_kernel",
+            "avg_launch_ms": sweep_ms / max(1, prof["sweep_launches"]),
+            "launches": prof["sweep_launches"],
+            "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None}
+
+    if args.calib_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        a.fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+        log(f"[bench] cpu {cpu}")
+
+    out = {
+        "metric": "cell-angle updates/s; wall time to 1e-6 residual, NO warm start vs zero start",
+        "value": updates / dt,
+        "unit": "cell-angle updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "instances": len(wl.instances),
+                   "grid": f"{args.n}x{args.n}", "directions": M,
+                   "tol": args.tol, "start": "zero",
+                   "sweep_plan": plan},
+        "iterations": its[-1],
+        "zero_start_ms": ms_step,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

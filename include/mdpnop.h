@@ -182,7 +182,7 @@ tr_status tr_check_args(int32_t n_inst, const tr_problem *p,
                         char *msg, int32_t msg_len);
 
 /* Force the 2-D sweep's launch shape on this context (0 = automatic):
- * D directions per lane (1,2,3,4,5,6,9,10), W waves per workgroup (1..16),
+ * D directions per lane (1,2,3,4,6,9), W waves per workgroup (1..16),
  * S direction slices per octant, R rows per lane segment (a power of two
  * <= 64; a problem narrower than R uses the automatic choice).  Every
  * configuration sums partial fluxes in a fixed order, so a given
@@ -191,11 +191,20 @@ tr_status tr_check_args(int32_t n_inst, const tr_problem *p,
 tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
                               int32_t R);
 
+/* Kernel timing for benchmarks: with enable != 0, tr_solve records HIP
+ * events on the context stream around every sweep launch and around every
+ * combine+finalize pair (totals reset by each call of this function).    */
+tr_status tr_profile_enable(tr_context *ctx, int32_t enable);
+/* out4 = {sweep ms, sweep launches, combine+finalize ms, their count}.   */
+tr_status tr_profile_read(tr_context *ctx, double *out4);
+
 /* The launch shape the next tr_solve / tr_sweep on these problems would
- * use: out4 = {D, W, S of problem 0, R of problem 0}.                     */
+ * use: out5 = {D, W, S of problem 0, R of problem 0, KB}.  ctx may be NULL
+ * (host-only: default limits, automatic choices); field pointers are not
+ * read.                                                                    */
 tr_status tr_get_sweep_plan(tr_context *ctx, int32_t n_inst,
                             const tr_problem *p, const tr_quadrature *q,
-                            int32_t *out4);
+                            int32_t *out5);
 
 #ifdef __cplusplus
 }

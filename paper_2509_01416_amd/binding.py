@@ -29,7 +29,8 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "tr_sweep", "tr_solve", "no_recast_guess", "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_forward", "no_train_step",
-           "tr_check_args", "tr_set_sweep_config", "tr_get_sweep_plan")
+           "tr_check_args", "tr_set_sweep_config", "tr_get_sweep_plan",
+           "tr_profile_enable", "tr_profile_read")
 
 
 class TrProblem(ctypes.Structure):
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_char_p, i32]
     lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
+    lib.tr_profile_enable.argtypes = [vp, i32]
+    lib.tr_profile_read.argtypes = [vp, P(d)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:       # default: tr_status
@@ -219,13 +222,17 @@ class Context:
     def set_sweep_config(self, D=0, W=0, S=0, R=0):
         self.check(self.lib.tr_set_sweep_config(self.handle, D, W, S, R), allow=(TR_OK,))
 
+    def profile(self, enable: bool = True):
+        self.check(self.lib.tr_profile_enable(self.handle, int(enable)), allow=(TR_OK,))
+
+    def profile_read(self) -> dict:
+        out = (ctypes.c_double * 4)()
+        self.check(self.lib.tr_profile_read(self.handle, out), allow=(TR_OK,))
+        return dict(sweep_ms=out[0], sweep_launches=int(out[1]),
+                    combine_ms=out[2], combine_launches=int(out[3]))
+
     def sweep_plan(self, problems, quad: Quad):
-        arr = make_problems(problems)
-        out = (ctypes.c_int32 * 4)()
-        self.check(self.lib.tr_get_sweep_plan(self.handle, len(problems), arr,
-                                              ctypes.byref(quad.struct), out),
-                   allow=(TR_OK,))
-        return dict(D=out[0], W=out[1], S=out[2], R=out[3])
+        return sweep_plan(make_problems(problems), len(problems), quad, self.handle)
 
 
 def tr_sweep(ctx: Context, problems: Sequence[Problem], quad: Quad,
@@ -261,3 +268,14 @@ def tr_check_args(problems_struct, n: int, quad: Quad, tol: float,
     rc = lib.tr_check_args(n, problems_struct, ctypes.byref(quad.struct),
                            float(tol), int(max_iter), buf, 512)
     return rc, buf.value.decode()
+
+
+def sweep_plan(problems_struct, n: int, quad: Quad, handle=None) -> dict:
+    """Launch shape of the 2-D sweep for prepared problems (host-only when
+    handle is None)."""
+    lib = load()
+    out = (ctypes.c_int32 * 5)()
+    rc = lib.tr_get_sweep_plan(handle, n, problems_struct, ctypes.byref(quad.struct), out)
+    if rc != TR_OK:
+        raise MdpError(rc, "tr_get_sweep_plan failed")
+    return dict(D=out[0], W=out[1], S=out[2], R=out[3], KB=out[4])

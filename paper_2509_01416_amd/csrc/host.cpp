@@ -18,11 +18,13 @@
 
 namespace mdp {
 
-bool launch_sweep2d(int D, int nwork, int W, int KB, size_t lds_bytes,
-                    const InstDesc* insts, const SweepWork* work,
-                    const DirTable* dt, const int* done, const int* iter,
-                    int use_faces, hipStream_t s);
-size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx);
+bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
+                    size_t lds_bytes, const InstDesc* insts,
+                    const SweepWork* work, const DirTable* dt, const int* done,
+                    const int* iter, int use_faces, hipStream_t s);
+size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx);
+int sweep2d_max_kb(int W, int R);
+int sweep2d_max_w(int D);
 void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
                     const int* done, const int* iter, int use_faces, int M,
                     hipStream_t s);
@@ -216,6 +218,11 @@ extern "C" tr_status tr_context_create(tr_context** ctx, void* hip_stream) {
     Ctx* c = new (std::nothrow) Ctx();
     if (!c) return TR_ERR_OOM;
     c->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
+        c->lds_limit = prop.sharedMemPerBlock;
+    else
+        (void)hipGetLastError();
     c->stream = (hipStream_t)hip_stream;
     *ctx = reinterpret_cast<tr_context*>(c);
     return TR_OK;
@@ -234,7 +241,41 @@ extern "C" const char* tr_last_error(const tr_context* ctx) {
     return c ? c->err.c_str() : "null context";
 }
 
+bool Ctx::prof_begin(int kind) {
+    if (!prof || ev_used >= kProfSlots) return false;
+    hipEvent_t* e = ev[ev_used];
+    if (!e[0]) {
+        if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    ev_kind[ev_used] = kind;
+    (void)hipEventRecord(e[0], stream);
+    return true;
+}
+
+void Ctx::prof_end() { (void)hipEventRecord(ev[ev_used++][1], stream); }
+
+void Ctx::prof_collect() {
+    for (int i = 0; i < ev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[i][0], ev[i][1]) == hipSuccess) {
+            prof_ms[ev_kind[i]] += ms;
+            prof_n[ev_kind[i]] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    ev_used = 0;
+}
+
 void Ctx::release() {
+    for (auto& e : ev) {
+        if (e[0]) (void)hipEventDestroy(e[0]);
+        if (e[1]) (void)hipEventDestroy(e[1]);
+        e[0] = e[1] = nullptr;
+    }
     if (arena.base) (void)hipFree(arena.base);
     arena.base = nullptr;
     arena.cap = 0;
@@ -248,54 +289,114 @@ void Ctx::release() {
 
 namespace mdp {
 
-// Rows per lane segment: the largest of 64/32/16 that fits nx and wastes
-// the fewest lane-rows on the last block (ties go to the larger R).
-static int pick_R(int nx, int ny) {
-    int best = 1, bestw = 1 << 30;
-    for (int R = 64; R >= 1; R >>= 1) {
-        if (R > nx) continue;
-        const int waste = ((ny + R - 1) / R) * R - ny;
-        if (waste < bestw) { best = R; bestw = waste; }
-    }
-    return best;
+// Launch planning for the 2-D sweep.  A segment of R lanes streams through
+// ceil(ny/R) row blocks of nx cells: T = ceil(ny/R)*nx + R - 1 steps, and an
+// octant of nd directions needs v = ceil(nd*R/(64*D)) waves.  The plan picks
+// R per instance to minimise the modelled time
+//     max( sum_i 4 v_i T_i / NW , max_i T_i )
+// (NW = waves the chip keeps busy), trying the widest feasible R for every
+// instance (latency-bound batches) and the R with the fewest lane-steps
+// 4 v T per instance (throughput-bound batches).  W waves per workgroup and
+// S slices per octant then give at least one workgroup per CU.
+namespace {
+constexpr double kBusyWaves = 2048.0;   // ~2 waves per SIMD on 256 CUs
+constexpr int kCUs = 256;
+
+long long seg_steps(int nx, int ny, int R) {
+    return (long long)((ny + R - 1) / R) * nx + R - 1;
 }
+int oct_waves(int nd, int R, int D) {
+    const int per = (64 / R) * D;
+    return (nd + per - 1) / per;
+}
+}  // namespace
 
 Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
     Plan pl;
     int nd = 0;
     for (int o = 0; o < 4; ++o) nd = std::max(nd, dt.count[o]);
-    pl.R.resize(n_inst);
-    int nseg_min = 64;
-    for (int i = 0; i < n_inst; ++i) {
-        pl.R[i] = (c->force_R > 0 && c->force_R <= p[i].nx) ? c->force_R
-                                                            : pick_R(p[i].nx, p[i].ny);
-        nseg_min = std::min(nseg_min, 64 / pl.R[i]);
-    }
     pl.D = c->force_D > 0 ? c->force_D : 1;
-    // enough workgroups to cover every CU at least once
-    int S;
-    if (c->force_S > 0) {
-        S = c->force_S;
-    } else {
-        const int units = 4 * n_inst;
-        S = std::max(1, (256 + units - 1) / units);
+    pl.R.assign(n_inst, 1);
+    auto model = [&](const std::vector<int>& Rs) {
+        double work = 0.0, tmax = 0.0;
+        for (int i = 0; i < n_inst; ++i) {
+            const double T = (double)seg_steps(p[i].nx, p[i].ny, Rs[i]);
+            work += 4.0 * oct_waves(nd, Rs[i], pl.D) * T;
+            tmax = std::max(tmax, T);
+        }
+        return std::max(work / kBusyWaves, tmax);
+    };
+    // R: a power of two <= min(64, nx) that divides ny (the sweep kernel's
+    // ring writer is the last lane of each segment)
+    auto feasible = [&](int i, int R) { return R <= p[i].nx && p[i].ny % R == 0; };
+    std::vector<int> wide(n_inst), lean(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        int rw = 1;
+        while (rw * 2 <= 64 && feasible(i, rw * 2)) rw *= 2;
+        wide[i] = rw;
+        double best = 1e300;
+        int rb = rw;
+        for (int R = rw; R >= 1; R >>= 1) {
+            if (!feasible(i, R)) continue;
+            const double cost = (double)oct_waves(nd, R, pl.D) * seg_steps(p[i].nx, p[i].ny, R);
+            if (cost < best * 0.999) { best = cost; rb = R; }
+        }
+        lean[i] = rb;
     }
-    S = std::min(S, std::max(1, (nd + pl.D - 1) / pl.D));
-    int W = c->force_W > 0 ? c->force_W
-                           : (nd + nseg_min * pl.D * S - 1) / (nseg_min * pl.D * S);
-    W = std::max(1, std::min(16, W));
-    // recompute S for the capacity actually chosen
-    pl.W = W;
+    pl.R = model(wide) <= model(lean) ? wide : lean;
+    if (c->force_R > 0)
+        for (int i = 0; i < n_inst; ++i)
+            if (feasible(i, c->force_R)) pl.R[i] = c->force_R;
+    // W and S: the largest W (fewest partial planes) that still yields at
+    // least one workgroup per CU (or every wave in its own slice)
+    int vmax = 1;
+    long long vsum = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const int v = oct_waves(nd, pl.R[i], pl.D);
+        vmax = std::max(vmax, v);
+        vsum += 4LL * v;
+    }
+    const long long want = std::min<long long>(kCUs, vsum);
+    const int wcap = sweep2d_max_w(pl.D);
+    int W = std::min(wcap, vmax);
+    if (c->force_W > 0) {
+        W = std::min(c->force_W, wcap);
+    } else {
+        for (; W > 1; --W) {
+            long long wgs = 0;
+            for (int i = 0; i < n_inst; ++i) {
+                const int v = oct_waves(nd, pl.R[i], pl.D);
+                wgs += 4LL * ((v + W - 1) / W);
+            }
+            if (wgs >= want) break;
+        }
+    }
     pl.S.resize(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const int cap = W * (64 / pl.R[i]) * pl.D;
-        pl.S[i] = std::max(1, (nd + cap - 1) / cap);
+        pl.S[i] = c->force_S > 0 ? std::max(c->force_S, (nd + cap - 1) / cap)
+                                 : std::max(1, (nd + cap - 1) / cap);
     }
-    pl.KB = 16;
-    int mx = 0;
-    for (int i = 0; i < n_inst; ++i) mx = std::max(mx, (64 / pl.R[i]) * p[i].nx);
-    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx) > 64 * 1024) pl.KB /= 2;
-    pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx);
+    if (c->force_W <= 0) {   // same slice counts with the fewest idle waves
+        int wmin = 1;
+        for (int i = 0; i < n_inst; ++i) {
+            const int v = oct_waves(nd, pl.R[i], pl.D);
+            wmin = std::max(wmin, (v + pl.S[i] - 1) / pl.S[i]);
+        }
+        W = wmin;
+    }
+    pl.W = W;
+    int mx = 0, Rmax = 1, nxmax = 1;
+    for (int i = 0; i < n_inst; ++i) {
+        mx = std::max(mx, (64 / pl.R[i]) * p[i].nx);
+        Rmax = std::max(Rmax, pl.R[i]);
+        nxmax = std::max(nxmax, p[i].nx);
+    }
+    pl.KB = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax));
+    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax) > c->lds_limit)
+        pl.KB /= 2;
+    pl.KB = std::max(pl.KB, 2);
+    pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax);
     return pl;
 }
 
@@ -314,7 +415,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
                 return false;
             }
         su->plan = make_plan(this, n_inst, p, su->dt);
-        if (su->plan.lds > 64 * 1024) {
+        if (su->plan.lds > lds_limit) {
             fail("grid too wide for the sweep's LDS ring (nx=%d)", p[0].nx);
             return false;
         }
@@ -437,9 +538,12 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
         launch_sweep1d(n_inst, su.d_inst, su.d_dt, done, iter, use_faces, su.dt.M,
                        stream);
     } else {
-        if (!launch_sweep2d(su.plan.D, (int)su.work.size(), su.plan.W, su.plan.KB,
-                            su.plan.lds, su.d_inst, su.d_work, su.d_dt, done, iter,
-                            use_faces, stream)) {
+        bool refl = false;
+        for (const InstDesc& d : su.inst)
+            for (int f = 0; f < 4; ++f) refl |= d.bc[f] == TR_BC_REFLECTIVE;
+        if (!launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
+                            su.plan.W, su.plan.KB, su.plan.lds, su.d_inst,
+                            su.d_work, su.d_dt, done, iter, use_faces, stream)) {
             fail("unsupported directions-per-lane D=%d", su.plan.D);
             return false;
         }
@@ -552,11 +656,15 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
     while (done_iters < max_iter && !all) {
         const int k = std::min(chunk, max_iter - done_iters);
         for (int it = 0; it < k; ++it) {
+            const bool p0 = c->prof_begin(0);
             if (!c->launch_sweep(su, n_inst, su.st.done, su.st.iter, 1)) return TR_ERR_HIP;
+            if (p0) c->prof_end();
+            const bool p1 = c->prof_begin(1);
             launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
                            su.d_red, 0, norm_kind, c->stream);
             launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind,
                             c->stream);
+            if (p1) c->prof_end();
         }
         if (!c->hip_ok(hipGetLastError(), "iteration launch")) return TR_ERR_HIP;
         done_iters += k;
@@ -565,6 +673,7 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
                        "flag copy") ||
             !c->hip_ok(hipStreamSynchronize(c->stream), "sync"))
             return TR_ERR_HIP;
+        c->prof_collect();
         all = true;
         for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
         chunk = std::min(chunk * 2, 64);
@@ -640,7 +749,7 @@ extern "C" tr_status tr_set_sweep_config(tr_context* ctx, int32_t D, int32_t W,
                                          int32_t S, int32_t R) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     if (!c) return TR_ERR_INVALID_ARG;
-    const int okD[] = {0, 1, 2, 3, 4, 5, 6, 9, 10};
+    const int okD[] = {0, 1, 2, 3, 4, 6, 9};
     bool good = false;
     for (int v : okD) good |= D == v;
     if (!good || W < 0 || W > 16 || S < 0 || R < 0 || R > 64 || (R & (R - 1))) {
@@ -658,8 +767,9 @@ extern "C" tr_status tr_set_sweep_config(tr_context* ctx, int32_t D, int32_t W,
 extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
                                        const tr_problem* p, const tr_quadrature* q,
                                        int32_t* out4) {
-    Ctx* c = reinterpret_cast<Ctx*>(ctx);
-    if (!c || !out4) return TR_ERR_INVALID_ARG;
+    Ctx tmp;
+    Ctx* c = ctx ? reinterpret_cast<Ctx*>(ctx) : &tmp;
+    if (!out4) return TR_ERR_INVALID_ARG;
     if (!check_problems(c, n_inst, p, false)) return TR_ERR_INVALID_ARG;
     DirTable* dt = new DirTable();
     if (!build_dirtable(c, q, p[0].dim, dt)) {
@@ -672,5 +782,27 @@ extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
     out4[1] = pl.W;
     out4[2] = pl.S.empty() ? 0 : pl.S[0];
     out4[3] = pl.R.empty() ? 0 : pl.R[0];
+    out4[4] = pl.KB;
+    return TR_OK;
+}
+
+// Kernel timing: enable != 0 starts (and resets) event timing of the sweep
+// launches and of the combine+finalize pair inside tr_solve.
+extern "C" tr_status tr_profile_enable(tr_context* ctx, int32_t enable) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    for (int k = 0; k < 4; ++k) { c->prof_ms[k] = 0.0; c->prof_n[k] = 0; }
+    return TR_OK;
+}
+
+extern "C" tr_status tr_profile_read(tr_context* ctx, double* out4) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c || !out4) return TR_ERR_INVALID_ARG;
+    out4[0] = c->prof_ms[0];
+    out4[1] = (double)c->prof_n[0];
+    out4[2] = c->prof_ms[1];
+    out4[3] = (double)c->prof_n[1];
     return TR_OK;
 }

@@ -57,9 +57,22 @@ struct Ctx {
     std::string err;
     Arena arena;          // per-call solver workspace
     PinnedBuf pinned;     // staging and flag read-back
-    int force_D = 0, force_W = 0, force_S = 0, force_R = 0;
+    int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
+    size_t lds_limit = 64 * 1024;   // per-workgroup LDS (device property)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces
+
+    // optional kernel timing with HIP events on the context stream
+    static constexpr int kProfSlots = 128;
+    bool prof = false;
+    hipEvent_t ev[kProfSlots][2] = {};
+    int ev_kind[kProfSlots] = {};
+    int ev_used = 0;
+    double prof_ms[4] = {0, 0, 0, 0};
+    long long prof_n[4] = {0, 0, 0, 0};
+    bool prof_begin(int kind);      // records the start event; false if full
+    void prof_end();
+    void prof_collect();            // after a stream synchronisation
 
     void fail(const char* fmt, ...);
     bool hip_ok(hipError_t e, const char* what);

@@ -20,44 +20,94 @@
 //     drain; the first lane of a block receives the y-face flux of the last
 //     lane of the previous block through a small LDS ring (written nx-R+1
 //     steps earlier, R <= nx);
+//   * the steps are processed in blocks of KB.  The (sigma_t, Q) pairs a
+//     block needs (KB steps x R rows, identical for every wave) are loaded
+//     cooperatively and coalesced one block ahead and staged in LDS, so the
+//     HBM latency hides behind a block of compute;
 //   * the W waves of the workgroup process identical cells at identical
 //     steps, each for its own directions; their partial scalar fluxes are
-//     combined in LDS every KB steps, in fixed wave order, and one partial
+//     combined in LDS after each block, in fixed wave order, and one partial
 //     plane per (octant, slice) is written to HBM.  The planes are summed in
 //     fixed order by the combine kernel, so the result is bitwise
-//     reproducible (no floating-point atomics).
+//     reproducible (no floating-point atomics);
 //   * angular fluxes never leave the chip except on boundary faces, which are
 //     stored for reflective inflow (lagged one iteration) and leakage.
 #include "common.h"
 
 namespace mdp {
 
+constexpr int kMaxPrefetch = 4;   // staged values per thread per block
+constexpr int kMaxRed = 2;        // reduced outputs per thread per block
+
+// Largest workgroup per directions-per-lane D, so that the register budget
+// (512 per SIMD lane / waves per SIMD) holds D directions without spills.
 template <int D>
-__global__ void __launch_bounds__(1024)
+struct SweepBounds {
+    static constexpr int threads = D <= 2 ? 1024 : (D <= 4 ? 512 : 256);
+};
+
+// Global-address-space views: loads and stores through them are global_*
+// instructions (counted on vmcnt only), never flat ones.
+#define MDP_GLOBAL __attribute__((address_space(1)))
+typedef MDP_GLOBAL float gfloat;
+typedef const MDP_GLOBAL float cgfloat;
+
+// Position of a (step, row) pair of the segment stream: u = t - row is split
+// as u = kk*nx + ip; the cursor advances by whole blocks without division.
+struct Cursor {
+    int ip, kk;
+    __device__ __forceinline__ void advance(int by, int nx) {
+        ip += by;
+        while (ip >= nx) { ip -= nx; ++kk; }
+    }
+};
+
+// Cell of row rr at cursor c, or -1 outside the grid / before the start.
+__device__ __forceinline__ int cursor_cell(Cursor c, int rr, int R, int nx,
+                                           int ny, int nblk, bool xpos,
+                                           bool ypos) {
+    if (c.ip < 0 || c.ip >= nx || c.kk >= nblk) return -1;
+    const int jp = c.kk * R + rr;
+    if (jp >= ny) return -1;
+    const int i = xpos ? c.ip : nx - 1 - c.ip;
+    const int j = ypos ? jp : ny - 1 - jp;
+    return j * nx + i;
+}
+
+// REFL: some inflow face of this launch is reflective (face loads inside the
+// step loop); the vacuum instance has no global loads in the loop at all.
+// KB: steps per block (a power of two); the step loop is fully unrolled.
+template <int D, bool REFL, int KB>
+__global__ void __launch_bounds__(SweepBounds<D>::threads)
 sweep2d_kernel(const InstDesc* __restrict__ insts,
                const SweepWork* __restrict__ work,
                const DirTable* __restrict__ dt, const int* __restrict__ done,
-               const int* __restrict__ iter, int KB, int use_faces) {
+               const int* __restrict__ iter, int use_faces) {
     extern __shared__ float smem[];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    constexpr int lkb = KB >= 16 ? 4 : (KB >= 8 ? 3 : (KB >= 4 ? 2 : (KB >= 2 ? 1 : 0)));
+    static_assert((1 << lkb) == KB, "KB must be a power of two <= 16");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
     const int W = blockDim.x >> 6;
+    const int nthreads = blockDim.x;
     const SweepWork wk = work[blockIdx.x];
     const int n = wk.inst;
     if (done != nullptr && done[n]) return;   // uniform over the workgroup
     const InstDesc& I = insts[n];
-    const int R = I.R, nseg = 64 / R, seg = lane / R, r = lane - seg * R;
+    const int R = I.R, lr = __ffs(R) - 1;
+    const int nseg = 64 >> lr, seg = lane >> lr, r = lane & (R - 1);
     const int o = wk.oct;
     const bool xpos = (o == 0 || o == 3), ypos = (o == 0 || o == 1);
     const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
     const int par = (iter != nullptr ? iter[n] : 0) & 1;
     const size_t fstride = (size_t)4 * nf * M;
-    const float* __restrict__ fprev = I.face + (size_t)par * fstride;
-    float* __restrict__ fcur = I.face + (size_t)(par ^ 1) * fstride;
+    cgfloat* __restrict__ fprev = (cgfloat*)(I.face + (size_t)par * fstride);
+    gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(par ^ 1) * fstride);
     const int fxin = xpos ? 0 : 1, fxout = xpos ? 1 : 0;
     const int fyin = ypos ? 2 : 3, fyout = ypos ? 3 : 2;
-    const bool rx = use_faces && I.bc[fxin] == 1;
-    const bool ry = use_faces && I.bc[fyin] == 1;
+    const bool rx = REFL && use_faces && I.bc[fxin] == 1;
+    const bool ry = REFL && use_faces && I.bc[fyin] == 1;
 
     float a[D], b[D], c[D], w[D];
     int mi[D], mxr[D], myr[D];
@@ -81,139 +131,289 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
         c[d] = a[d] + b[d];
     }
 
+    // LDS: pbuf[2][KB][W*64+1] | sbuf[2][2][KB][65] | ring[W][nseg][D][nx]
+    //      | sink[W][D][nx] (target of the ring store of non-writing lanes).
+    // The +1 pads make the block-level staging stores and reduction reads,
+    // whose consecutive threads step through KB rows, conflict-free.
+    const int PSTR = W * 64 + 1;
     float* pbuf = smem;
-    float* ring = smem + 2 * KB * W * 64 + (size_t)((wv * nseg + seg) * D) * nx;
-    const int nblk = (ny + R - 1) / R;
+    float* sbuf = smem + 2 * KB * PSTR;
+    float* rings = sbuf + 4 * KB * 65;
+    float* ring = rings + (size_t)((wv * nseg + seg) * D) * nx;
+    float* sink = rings + (size_t)W * nseg * D * nx + (size_t)wv * D * nx;
+    const int nblk = (ny + R - 1) >> lr;
     const int T = nblk * nx + R - 1;
-    const float* __restrict__ St = I.st;
-    const float* __restrict__ Qb = I.Q;
-    float* __restrict__ part = I.part + (size_t)(o * I.S + wk.slice) * I.cells;
+    cgfloat* __restrict__ St = (cgfloat*)I.st;
+    cgfloat* __restrict__ Qb = (cgfloat*)I.Q;
+    gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
+
+    // Staging slots of this thread: element e = (field, row, step) packed as
+    // f << (lr+lkb) | rr << lkb | t2; each keeps a cursor for its (step, row).
+    const int nstage = 2 * KB * R;
+    const int npf = (nstage + nthreads - 1) / nthreads;   // slots in use
+    float pf[kMaxPrefetch];
+    bool pv[kMaxPrefetch];
+    Cursor sc[kMaxPrefetch];
+#pragma unroll
+    for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+        const int e = tid + jx * nthreads;
+        sc[jx].ip = (e & (KB - 1)) - ((e >> lkb) & (R - 1));
+        sc[jx].kk = 0;
+        sc[jx].advance(0, nx);   // normalise: 0 <= ip < nx once ip >= 0
+    }
+    // all addresses first, then unconditional loads back to back (an empty
+    // slot reads cell 0); the per-slot default is applied at store time
+    auto stage_load = [&]() {
+        int cells[kMaxPrefetch];
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            const int rr = (e >> lkb) & (R - 1);
+            const int cell = cursor_cell(sc[jx], rr, R, nx, ny, nblk, xpos, ypos);
+            pv[jx] = cell >= 0 && e < nstage;
+            cells[jx] = pv[jx] ? cell : 0;
+            sc[jx].advance(KB, nx);
+        }
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            cgfloat* src = (e >> (lkb + lr)) == 0 ? St : Qb;
+            pf[jx] = src[cells[jx]];
+        }
+    };
+    auto stage_store = [&](int h) {
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            if (e < nstage) {
+                const int f = e >> (lkb + lr);
+                const int rr = (e >> lkb) & (R - 1);
+                const int t2 = e & (KB - 1);
+                const float def = f == 0 ? 1.f : 0.f;
+                sbuf[((h * 2 + f) * KB + t2) * 65 + rr] = pv[jx] ? pf[jx] : def;
+            }
+        }
+    };
+    // Reduction slots: output e = rr << lkb | t2 of a block.
+    const int nout = KB * R;
+    const int nredu = (nout + nthreads - 1) / nthreads;
+    Cursor rc_[kMaxRed];
+#pragma unroll
+    for (int jx = 0; jx < kMaxRed; ++jx) {
+        const int e = tid + jx * nthreads;
+        rc_[jx].ip = (e & (KB - 1)) - (e >> lkb);
+        rc_[jx].kk = 0;
+        rc_[jx].advance(0, nx);
+    }
+
+    // The ring of each wave segment starts with the y-inflow boundary (the
+    // "row block -1"), so the first lane of a segment always takes its
+    // incoming y flux from the ring: vacuum zero or the reflected face.
+    for (int e = r; e < D * nx; e += R) {
+        const int d = e / nx, ipc = e - d * nx;
+        float v = 0.f;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            if (dd == d && REFL && ry && mi[dd] >= 0) {
+                const int i = xpos ? ipc : nx - 1 - ipc;
+                v = fprev[((size_t)fyin * nf + i) * M + myr[dd]];
+            }
+        }
+        ring[e] = v;
+    }
+    stage_load();
+    stage_store(0);
+    __syncthreads();
 
     float xin[D], yo[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) { xin[d] = 0.f; yo[d] = 0.f; }
-
+    const bool first = r == 0;
+    // R divides ny (the planner guarantees it), so the top row of every row
+    // block is lane R-1: it alone stores into the ring, the other lanes store
+    // into the sink.  Before its first cell (ip < 0) lane R-1 stores into
+    // column 0, which lane 0 has already read and which lane R-1 rewrites on
+    // reaching it.
+    float* wbase = (r == R - 1) ? ring : sink;
     int ip = -r, k = 0;   // position of this lane: cell ip of row block k
+
+    // One wavefront step.  tt: step within the block; ld/stg: issue the next
+    // block's staging loads / store them to LDS on this step.
+    auto step = [&](int tt, const float* sp, float* pw, bool ld, bool stg, int half) {
+        if (ld) stage_load();
+        const float st = sp[tt * 65];
+        const float q = sp[(KB + tt) * 65];
+        // the first lane of every segment sits at the same (step, row 0)
+        // position, so its ring column is uniform across the wave
+        const int ip0 = __builtin_amdgcn_readfirstlane(ip);
+        float yi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float ys = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                0, __builtin_bit_cast(int, yo[d]), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+            const float rv = ring[d * nx + ip0];
+            yi[d] = first ? rv : ys;
+        }
+        const bool rowstart = ip == 0;
+        if (REFL && rx && rowstart) {
+            const int jp = k * R + r;
+            const int j = ypos ? jp : ny - 1 - jp;
+            const bool ok = k < nblk && jp < ny;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                xin[d] = (ok && mi[d] >= 0) ? fprev[((size_t)fxin * nf + j) * M + mxr[d]] : 0.f;
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d) xin[d] = rowstart ? 0.f : xin[d];
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float rcp = __builtin_amdgcn_rcpf(st + c[d]);
+            const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rcp;
+            xin[d] = fmaf(psi, 2.0f, -xin[d]);
+            yo[d] = fmaf(psi, 2.0f, -yi[d]);
+            acc = fmaf(w[d], psi, acc);
+        }
+        for (int off = R; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        pw[tt * PSTR] = acc;   // lanes of later segments land in unread slots
+        // top row of the block hands its y flux to the ring
+        float* wdst = wbase + max(ip, 0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) wdst[d * nx] = yo[d];
+        if (ip == nx - 1 && k < nblk) {
+            const int jp = k * R + r;
+            const int j = ypos ? jp : ny - 1 - jp;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                if (mi[d] >= 0) fcur[((size_t)fxout * nf + j) * M + mi[d]] = xin[d];
+        }
+        if (stg) stage_store(half ^ 1);
+        __builtin_amdgcn_wave_barrier();
+        ++ip;
+        if (ip == nx) { ip = 0; ++k; }
+    };
+
     for (int t0 = 0, blkno = 0; t0 < T; t0 += KB, ++blkno) {
         const int half = blkno & 1;
         const int tend = min(KB, T - t0);
-        for (int tt = 0; tt < tend; ++tt) {
-            const bool act = ip >= 0 && k < nblk;
-            const int jp = k * R + r;
-            const bool valid = act && jp < ny;
-            const int i = xpos ? ip : nx - 1 - ip;
-            const int j = ypos ? jp : ny - 1 - jp;
-            const int cell = j * nx + i;
-            float st = 1.f, q = 0.f;
-            if (valid) { st = St[cell]; q = Qb[cell]; }
-            float yi[D];
+        const bool more = t0 + KB < T;
+        const float* sp = sbuf + half * 2 * KB * 65 + r;
+        float* pw = pbuf + half * KB * PSTR + wv * 64 + lane;
+        if (tend == KB) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) yi[d] = __shfl_up(yo[d], 1, 64);
-            if (r == 0 && act) {
-                if (k == 0) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        yi[d] = (ry && mi[d] >= 0)
-                                    ? fprev[((size_t)fyin * nf + i) * M + myr[d]]
-                                    : 0.f;
-                } else {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) yi[d] = ring[d * nx + ip];
-                }
-            }
-            if (ip == 0) {
-#pragma unroll
-                for (int d = 0; d < D; ++d)
-                    xin[d] = (valid && rx && mi[d] >= 0)
-                                 ? fprev[((size_t)fxin * nf + j) * M + mxr[d]]
-                                 : 0.f;
-            }
-            float acc = 0.f;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const float rc = __builtin_amdgcn_rcpf(st + c[d]);
-                const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rc;
-                const float p2 = psi + psi;
-                xin[d] = p2 - xin[d];
-                yo[d] = p2 - yi[d];
-                acc = fmaf(w[d], psi, acc);
-            }
-            for (int off = R; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-            if (seg == 0) pbuf[((half * KB + tt) * W + wv) * 64 + r] = acc;
-            if (valid) {
-                if (r == R - 1 && k + 1 < nblk) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) ring[d * nx + ip] = yo[d];
-                }
-                if (ip == nx - 1) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        if (mi[d] >= 0)
-                            fcur[((size_t)fxout * nf + j) * M + mi[d]] = xin[d];
-                }
-                if (jp == ny - 1) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        if (mi[d] >= 0)
-                            fcur[((size_t)fyout * nf + i) * M + mi[d]] = yo[d];
-                }
-            }
-            // keep the ring write of this step ahead of later ring reads
-            __builtin_amdgcn_wave_barrier();
-            ++ip;
-            if (ip == nx) { ip = 0; ++k; }
+            for (int tt = 0; tt < KB; ++tt)
+                step(tt, sp, pw, tt == 0 && more, tt == KB - 1 && more, half);
+        } else {
+            for (int tt = 0; tt < tend; ++tt) step(tt, sp, pw, false, false, half);
         }
         __syncthreads();
         // fixed-order combine of the waves' partial fluxes for this block
-        const int nout = tend * R;
-        for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-            const int rr = e / tend;
-            const int t2 = e - rr * tend;
-            const int u = t0 + t2 - rr;
-            if (u < 0) continue;
-            const int kk = u / nx;
-            if (kk >= nblk) continue;
-            const int ip2 = u - kk * nx;
-            const int jp2 = kk * R + rr;
-            if (jp2 >= ny) continue;
-            const int i2 = xpos ? ip2 : nx - 1 - ip2;
-            const int j2 = ypos ? jp2 : ny - 1 - jp2;
-            const float* pb = pbuf + (size_t)(half * KB + t2) * W * 64 + rr;
-            float s = 0.f;
-            for (int v = 0; v < W; ++v) s += pb[v * 64];
-            part[j2 * nx + i2] = s;
+#pragma unroll
+        for (int jx = 0; jx < kMaxRed; ++jx) {
+            if (jx >= nredu) break;
+            const int e = tid + jx * nthreads;
+            if (e < nout) {
+                const int rr = e >> lkb;
+                const int t2 = e & (KB - 1);
+                const int cell = cursor_cell(rc_[jx], rr, R, nx, ny, nblk, xpos, ypos);
+                if (t2 < tend && cell >= 0) {
+                    const float* pb = pbuf + (size_t)(half * KB + t2) * PSTR + rr;
+                    float s = 0.f;
+                    for (int v = 0; v < W; ++v) s += pb[v * 64];
+                    part[cell] = s;
+                }
+                rc_[jx].advance(KB, nx);
+            }
         }
     }
-}
-
-// Host launcher; returns false for an unsupported D.
-bool launch_sweep2d(int D, int nwork, int W, int KB, size_t lds_bytes,
-                    const InstDesc* insts, const SweepWork* work,
-                    const DirTable* dt, const int* done, const int* iter,
-                    int use_faces, hipStream_t s) {
-    dim3 grid(nwork), block(64 * W);
-    switch (D) {
-#define MDP_CASE(DD)                                                          \
-    case DD:                                                                  \
-        hipLaunchKernelGGL(sweep2d_kernel<DD>, grid, block, lds_bytes, s,     \
-                           insts, work, dt, done, iter, KB, use_faces);       \
-        return true;
-        MDP_CASE(1)
-        MDP_CASE(2)
-        MDP_CASE(3)
-        MDP_CASE(4)
-        MDP_CASE(5)
-        MDP_CASE(6)
-        MDP_CASE(9)
-        MDP_CASE(10)
-#undef MDP_CASE
-        default:
-            return false;
+    // the ring now holds the grid's outgoing y face of every column
+    __builtin_amdgcn_wave_barrier();
+    for (int e = r; e < D * nx; e += R) {
+        const int d = e / nx, ipc = e - d * nx;
+        const int i = xpos ? ipc : nx - 1 - ipc;
+        int m = -1;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd)
+            if (dd == d) m = mi[dd];
+        if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ring[e];
     }
 }
 
-size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx) {
-    return sizeof(float) * ((size_t)2 * KB * W * 64 + (size_t)W * D * max_nseg_nx);
+// Host launcher; returns false for an unsupported (D, KB).
+template <int D, int KB>
+static void launch_dk(bool refl, dim3 grid, dim3 block, size_t lds,
+                      hipStream_t s, const InstDesc* insts,
+                      const SweepWork* work, const DirTable* dt,
+                      const int* done, const int* iter, int use_faces) {
+    if (refl)
+        hipLaunchKernelGGL((sweep2d_kernel<D, true, KB>), grid, block, lds, s,
+                           insts, work, dt, done, iter, use_faces);
+    else
+        hipLaunchKernelGGL((sweep2d_kernel<D, false, KB>), grid, block, lds, s,
+                           insts, work, dt, done, iter, use_faces);
+}
+
+template <int D>
+static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
+                     hipStream_t s, const InstDesc* insts,
+                     const SweepWork* work, const DirTable* dt,
+                     const int* done, const int* iter, int use_faces) {
+    switch (KB) {
+        case 16: launch_dk<D, 16>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
+        case 8: launch_dk<D, 8>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
+        case 4: launch_dk<D, 4>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
+        case 2: launch_dk<D, 2>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
+        default: return false;
+    }
+}
+
+bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
+                    size_t lds_bytes, const InstDesc* insts,
+                    const SweepWork* work, const DirTable* dt, const int* done,
+                    const int* iter, int use_faces, hipStream_t s) {
+    dim3 grid(nwork), block(64 * W);
+    switch (D) {
+        case 1: return launch_d<1>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 2: return launch_d<2>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 3: return launch_d<3>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 4: return launch_d<4>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 6: return launch_d<6>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 9: return launch_d<9>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        default: return false;
+    }
+}
+
+size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx) {
+    return sizeof(float) * ((size_t)2 * KB * (W * 64 + 1) + (size_t)4 * KB * 65 +
+                            (size_t)W * D * max_nseg_nx + (size_t)W * D * max_nx);
+}
+
+// Largest block size whose staging fits kMaxPrefetch values and whose
+// reduction fits kMaxRed outputs per thread.
+int sweep2d_max_kb(int W, int R) {
+    int kb = 16;
+    while (kb > 1 && (2 * kb * R > kMaxPrefetch * 64 * W || kb * R > kMaxRed * 64 * W))
+        kb >>= 1;
+    return kb;
+}
+
+
+
+// Largest W (waves per workgroup) the kernel for D supports.
+int sweep2d_max_w(int D) {
+    switch (D) {
+        case 1: return SweepBounds<1>::threads / 64;
+        case 2: return SweepBounds<2>::threads / 64;
+        case 3: return SweepBounds<3>::threads / 64;
+        case 4: return SweepBounds<4>::threads / 64;
+        case 6: return SweepBounds<6>::threads / 64;
+        case 9: return SweepBounds<9>::threads / 64;
+        default: return 1;
+    }
 }
 
 }  // namespace mdp
