@@ -55,5 +55,6 @@ struct IterState {
 
 constexpr int kCombineThreads = 256;
 constexpr int kCombineChunk = 2048;   // cells per combine block
+constexpr int kXcds = 8;              // accelerator complex dies (L2 domains)
 
 }  // namespace mdp

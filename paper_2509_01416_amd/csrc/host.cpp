@@ -31,9 +31,9 @@ void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
 void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
                  hipStream_t s);
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
-                 const int2* blocks, const DirTable* dt, IterState st,
+                 const int4* blocks, const DirTable* dt, IterState st,
                  hipStream_t s);
-void launch_combine(int nblocks, const InstDesc* insts, const int2* blocks,
+void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     const int* done, double2* red, int mode, int norm_kind,
                     hipStream_t s);
 void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
@@ -457,7 +457,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         }
         d.red0 = (int)su->blocks.size();
         for (int c0 = 0; c0 < d.cells; c0 += kCombineChunk)
-            su->blocks.push_back(make_int2(i, c0));
+            su->blocks.push_back(make_int4(i, c0, (int)su->blocks.size(), 0));
         d.nred = (int)su->blocks.size() - d.red0;
         if (!emission) {
             offQ[i] = off;
@@ -469,17 +469,63 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         off += align_up(sizeof(float) * (dim == 1 ? (size_t)4 * M
                                                    : (size_t)8 * d.nf * M));
     }
+    // XCD-aware order: workgroup b of a launch runs on XCD b % kXcds, so
+    // every instance is given one XCD (balanced by work) and its sweep
+    // workgroups and combine blocks are placed at indices of that XCD; the
+    // instance's fields and partial planes then stay in that XCD's L2.
+    // Queues are padded with no-op entries (instance -1) to keep alignment.
+    {
+        std::vector<int> bucket(n_inst);
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<int> order(n_inst);
+        for (int i = 0; i < n_inst; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return su->inst[x].cells > su->inst[y].cells;
+        });
+        for (int i : order) {
+            int bx = 0;
+            for (int x = 1; x < kXcds; ++x)
+                if (load[x] < load[bx]) bx = x;
+            bucket[i] = bx;
+            load[bx] += (double)su->inst[i].cells * su->inst[i].P;
+        }
+        auto interleave = [&](auto& items, auto bucket_of, auto make_noop) {
+            using T = typename std::decay<decltype(items[0])>::type;
+            std::vector<std::vector<T>> q(kXcds);
+            for (const T& it : items) q[bucket_of(it)].push_back(it);
+            size_t mx = 0;
+            for (auto& v : q) mx = std::max(mx, v.size());
+            std::vector<T> out;
+            out.reserve(mx * kXcds);
+            for (size_t r = 0; r < mx; ++r)
+                for (int x = 0; x < kXcds; ++x)
+                    out.push_back(r < q[x].size() ? q[x][r] : make_noop());
+            // trailing no-ops are not launched
+            while (!out.empty() && (&out.back() != nullptr) && bucket_of(out.back()) < 0)
+                out.pop_back();
+            items.swap(out);
+        };
+        if (!su->work.empty())
+            interleave(su->work,
+                       [&](const SweepWork& w) { return w.inst < 0 ? -1 : bucket[w.inst]; },
+                       []() { return SweepWork{-1, 0, 0, 0}; });
+        interleave(su->blocks,
+                   [&](const int4& b) { return b.x < 0 ? -1 : bucket[b.x]; },
+                   []() { return make_int4(-1, 0, 0, 0); });
+    }
     // fixed-size tables after the per-instance workspaces
+    size_t nslots = 0;
+    for (const InstDesc& d : su->inst) nslots += d.nred;
     const size_t oInst = off;
     off += align_up(sizeof(InstDesc) * n_inst);
     const size_t oWork = off;
     off += align_up(sizeof(SweepWork) * std::max<size_t>(1, su->work.size()));
     const size_t oBlk = off;
-    off += align_up(sizeof(int2) * su->blocks.size());
+    off += align_up(sizeof(int4) * su->blocks.size());
     const size_t oDt = off;
     off += align_up(sizeof(DirTable));
     const size_t oRed = off;
-    off += align_up(sizeof(double2) * su->blocks.size());
+    off += align_up(sizeof(double2) * nslots);
     const size_t oDone = off;
     off += align_up(sizeof(int) * n_inst);
     const size_t oIter = off;
@@ -504,7 +550,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     }
     su->d_inst = (InstDesc*)(b + oInst);
     su->d_work = (SweepWork*)(b + oWork);
-    su->d_blocks = (int2*)(b + oBlk);
+    su->d_blocks = (int4*)(b + oBlk);
     su->d_dt = (DirTable*)(b + oDt);
     su->d_red = (double2*)(b + oRed);
     su->st.done = (int*)(b + oDone);
@@ -524,7 +570,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         std::memcpy(h + (oWork - oInst), su->work.data(),
                     sizeof(SweepWork) * su->work.size());
     std::memcpy(h + (oBlk - oInst), su->blocks.data(),
-                sizeof(int2) * su->blocks.size());
+                sizeof(int4) * su->blocks.size());
     std::memcpy(h + (oDt - oInst), &su->dt, sizeof(DirTable));
     if (!hip_ok(hipMemcpyAsync(b + oInst, h, hsz, hipMemcpyHostToDevice, stream),
                 "table upload"))

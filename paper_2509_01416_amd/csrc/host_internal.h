@@ -37,10 +37,10 @@ struct Setup {
     Plan plan;
     std::vector<InstDesc> inst;
     std::vector<SweepWork> work;
-    std::vector<int2> blocks;
+    std::vector<int4> blocks;   // (instance, first cell, reduction slot, -)
     InstDesc* d_inst = nullptr;
     SweepWork* d_work = nullptr;
-    int2* d_blocks = nullptr;
+    int4* d_blocks = nullptr;
     DirTable* d_dt = nullptr;
     double2* d_red = nullptr;
     IterState st{};

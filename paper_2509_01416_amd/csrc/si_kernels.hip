@@ -81,10 +81,11 @@ __global__ void scan_kernel(const InstDesc* __restrict__ insts, int* flags,
 }
 
 // ------------------------------------------------------------- init ------
-// Grid: one block per reduction block (instance, chunk) of the combine.
+// Grid: one block per reduction block (instance, first cell, slot).
 __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
-                                  const int2* __restrict__ blocks) {
-    const int2 bi = blocks[blockIdx.x];
+                                  const int4* __restrict__ blocks) {
+    const int4 bi = blocks[blockIdx.x];
+    if (bi.x < 0) return;
     const InstDesc& I = insts[bi.x];
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += blockDim.x) {
@@ -140,43 +141,80 @@ __global__ void init_faces_kernel(const InstDesc* __restrict__ insts,
 
 // ------------------------------------------------------------ combine ----
 // mode 0: source-iteration update (phi, Q, change-norm partials);
-// mode 1: bare sweep (phi = sum of planes).
+// mode 1: bare sweep (phi = sum of planes).  The planes of a cell are summed
+// in plane order; with cells % 4 == 0 four cells move per 16-byte access.
+struct CellAcc {
+    double s1 = 0.0, s2 = 0.0;
+};
+
+__device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
+                                             int mode, int norm_kind, CellAcc& a) {
+    if (mode == 1) {
+        I.phi[c] = s;
+        return;
+    }
+    const float old = I.phi[c];
+    I.phi[c] = s;
+    I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
+    const double d = (double)s - (double)old;
+    if (norm_kind == 0) {
+        a.s1 += d * d;
+        a.s2 += (double)s * (double)s;
+    } else {
+        const double as = fabs((double)s);
+        const double rel = as > 0.0 ? fabs(d) / as : (d != 0.0 ? INFINITY : 0.0);
+        a.s1 = fmax(a.s1, rel);
+    }
+}
+
 __global__ void __launch_bounds__(kCombineThreads)
 combine_kernel(const InstDesc* __restrict__ insts,
-               const int2* __restrict__ blocks, const int* __restrict__ done,
+               const int4* __restrict__ blocks, const int* __restrict__ done,
                double2* __restrict__ red, int mode, int norm_kind) {
-    const int2 bi = blocks[blockIdx.x];
+    const int4 bi = blocks[blockIdx.x];
     const int n = bi.x;
+    if (n < 0) return;
     if (done != nullptr && done[n]) return;
     const InstDesc& I = insts[n];
     const int cells = I.cells, P = I.P;
     const int c1 = min(bi.y + kCombineChunk, cells);
-    double s1 = 0.0, s2 = 0.0;
-    for (int c = bi.y + threadIdx.x; c < c1; c += blockDim.x) {
-        const float* pp = I.part + c;
-        float s = 0.f;
-        for (int p = 0; p < P; ++p) s += pp[(size_t)p * cells];
-        if (mode == 1) {
-            I.phi[c] = s;
-            continue;
+    CellAcc acc;
+    if ((cells & 3) == 0) {
+        const float4* pl = reinterpret_cast<const float4*>(I.part);
+        const int q4 = cells >> 2;
+        for (int c = bi.y + 4 * (int)threadIdx.x; c < c1; c += 4 * kCombineThreads) {
+            const float4* pp = pl + (c >> 2);
+            float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+            int p = 0;
+            for (; p + 4 <= P; p += 4) {
+                const float4 v0 = pp[(size_t)p * q4], v1 = pp[(size_t)(p + 1) * q4];
+                const float4 v2 = pp[(size_t)(p + 2) * q4], v3 = pp[(size_t)(p + 3) * q4];
+                s.x += v0.x; s.y += v0.y; s.z += v0.z; s.w += v0.w;
+                s.x += v1.x; s.y += v1.y; s.z += v1.z; s.w += v1.w;
+                s.x += v2.x; s.y += v2.y; s.z += v2.z; s.w += v2.w;
+                s.x += v3.x; s.y += v3.y; s.z += v3.z; s.w += v3.w;
+            }
+            for (; p < P; ++p) {
+                const float4 v = pp[(size_t)p * q4];
+                s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+            }
+            combine_cell(I, c, s.x, mode, norm_kind, acc);
+            combine_cell(I, c + 1, s.y, mode, norm_kind, acc);
+            combine_cell(I, c + 2, s.z, mode, norm_kind, acc);
+            combine_cell(I, c + 3, s.w, mode, norm_kind, acc);
         }
-        const float old = I.phi[c];
-        I.phi[c] = s;
-        I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
-        const double d = (double)s - (double)old;
-        if (norm_kind == 0) {
-            s1 += d * d;
-            s2 += (double)s * (double)s;
-        } else {
-            const double as = fabs((double)s);
-            const double rel = as > 0.0 ? fabs(d) / as : (d != 0.0 ? INFINITY : 0.0);
-            s1 = fmax(s1, rel);
+    } else {
+        for (int c = bi.y + threadIdx.x; c < c1; c += kCombineThreads) {
+            const float* pp = I.part + c;
+            float s = 0.f;
+            for (int p = 0; p < P; ++p) s += pp[(size_t)p * cells];
+            combine_cell(I, c, s, mode, norm_kind, acc);
         }
     }
     if (mode == 1) return;
     __shared__ double r1[kCombineThreads], r2[kCombineThreads];
-    r1[threadIdx.x] = s1;
-    r2[threadIdx.x] = s2;
+    r1[threadIdx.x] = acc.s1;
+    r2[threadIdx.x] = acc.s2;
     __syncthreads();
     for (int h = kCombineThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
@@ -189,7 +227,7 @@ combine_kernel(const InstDesc* __restrict__ insts,
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) red[blockIdx.x] = make_double2(r1[0], r2[0]);
+    if (threadIdx.x == 0) red[bi.z] = make_double2(r1[0], r2[0]);
 }
 
 // ----------------------------------------------------------- finalize ----
@@ -311,7 +349,7 @@ void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
 }
 
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
-                 const int2* blocks, const DirTable* dt, IterState st,
+                 const int4* blocks, const DirTable* dt, IterState st,
                  hipStream_t s) {
     hipLaunchKernelGGL(init_cells_kernel, dim3(nblocks), dim3(kCombineThreads), 0,
                        s, insts, blocks);
@@ -319,7 +357,7 @@ void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                        dt, st);
 }
 
-void launch_combine(int nblocks, const InstDesc* insts, const int2* blocks,
+void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     const int* done, double2* red, int mode, int norm_kind,
                     hipStream_t s) {
     hipLaunchKernelGGL(combine_kernel, dim3(nblocks), dim3(kCombineThreads), 0, s,

@@ -93,6 +93,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     const int nthreads = blockDim.x;
     const SweepWork wk = work[blockIdx.x];
     const int n = wk.inst;
+    if (n < 0) return;                        // XCD alignment padding
     if (done != nullptr && done[n]) return;   // uniform over the workgroup
     const InstDesc& I = insts[n];
     const int R = I.R, lr = __ffs(R) - 1;
