@@ -17,6 +17,7 @@ bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,12 @@ FLOP_PER_UPDATE = 12
 # algorithmic HBM bytes per cell per source iteration: read sigma_t, sigma_s,
 # q, phi_old; write phi_new (FP32)
 BYTES_PER_CELL_ITER = 20
+# HBM bytes per sweep launch on the default workload from rocprofv3
+# FETCH_SIZE / WRITE_SIZE, scaled by a 256 MiB copy (profiles/
+# sweep2d_two_region_16x256_S16.md); valid only for the kernel source with
+# this hash prefix, otherwise reported as null
+SWEEP_TRAFFIC_BYTES = 85.11e6
+SWEEP_TRAFFIC_SRC = "b6062be1dee197c0"
 
 
 def log(msg):
@@ -148,9 +155,15 @@ def main():
     achieved = flops / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
     cell_iters = updates / M
     hbm = cell_iters * BYTES_PER_CELL_ITER / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
+    traffic = None
+    src = os.path.join(ROOT, "paper_2509_01416_amd", "csrc", "sweep2d.hip")
+    default_wl = args.instances == 16 and args.n == 256
+    if default_wl and hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == SWEEP_TRAFFIC_SRC:
+        traffic = SWEEP_TRAFFIC_BYTES
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None,
-            "traffic": None, "kernel": "sweep2d_kernel",
+            "traffic": traffic, "traffic_unit": "bytes per launch",
+            "kernel": "sweep2d_kernel",
             "avg_launch_ms": sweep_ms / max(1, prof["sweep_launches"]),
             "launches": prof["sweep_launches"],
             "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None}
