@@ -123,7 +123,12 @@ tr_status tr_solve(tr_context *ctx, int32_t n_inst, const tr_problem *p,
  * clamped).  On divergence (non-finite change, or an absolute change that
  * grew three times running past the first update's) phi_guess[i] is zeroed
  * and status TR_RECAST_DIVERGED reported, so that a following tr_solve
- * falls back to the zero start.                                            */
+ * falls back to the zero start.  Per-instance stats: status (TR_OK,
+ * TR_NOT_CONVERGED or TR_RECAST_DIVERGED), iterations = network
+ * evaluations, residual = last relative change; balance_rel is NaN (no
+ * transport balance is defined for the network iterate).  Requirements:
+ * 2-D problems on a square grid that is a multiple of the network grid,
+ * sigma_t* > sigma_s* >= 0, tol >= 0, max_iter >= 1.                     */
 tr_status no_recast_guess(tr_context *ctx, const no_model *m, int32_t n_inst,
                           const tr_problem *p, double sigma_t_star,
                           double sigma_s_star, double tol, int32_t max_iter,
@@ -138,8 +143,10 @@ tr_status no_recast_guess(tr_context *ctx, const no_model *m, int32_t n_inst,
  * vector (master copy) in this order:
  *   W0[3][w], b0[w]; per layer R[2][m][m][w][w][2], W[w][w], b[w];
  *   P1[w][128], c1[128], P2[128], c2[1]
- * (2,368,001 values for the supported shape).  The network computes in
- * BF16 on the matrix cores with FP32 accumulation.
+ * (2,368,001 values for the supported shape).  The network computes on
+ * the matrix cores with FP32 accumulation; operands are rounded to BF16
+ * when staged (see no_model_set_fp32).  params_host may be NULL (all
+ * parameters zero).  The model lives on the context's device.
  * ------------------------------------------------------------------- */
 tr_status no_model_create(tr_context *ctx, no_model **m, int32_t width,
                           int32_t modes, int32_t layers, int32_t grid,
@@ -149,8 +156,15 @@ int64_t no_model_param_count(const no_model *m);
 /* Copy the FP32 master parameters to host memory (param_count floats).   */
 tr_status no_model_get_params(tr_context *ctx, const no_model *m,
                               float *params_host);
+/* Replace the FP32 master parameters from host memory; also clears the
+ * Adam moments and step count (a new starting point for training).        */
 tr_status no_model_set_params(tr_context *ctx, no_model *m,
                               const float *params_host);
+/* Operand precision of the matrix-core products: enable = 0 (default)
+ * rounds operands to BF16, enable = 1 keeps them FP32
+ * (v_mfma_f32_16x16x4f32; slower, for checking against FP64 references).
+ * Accumulation is FP32 either way.                                         */
+tr_status no_model_set_fp32(no_model *m, int32_t enable);
 
 /* Network forward for a batch: input[b] and output[b] are device
  * grid*grid FP32 fields (the first input channel; the coordinate channels
@@ -164,7 +178,8 @@ tr_status no_forward(tr_context *ctx, const no_model *m, int32_t batch,
  * refreshed.  input/target: device [batch][grid*grid].  *loss receives the
  * batch MSE before the update.  grad_out (device, param_count floats, may
  * be NULL) receives the gradient; with lr = 0 the parameters are unchanged
- * and the call only evaluates the loss and gradient.                       */
+ * and the call only evaluates the loss and gradient.  Returns
+ * TR_ERR_NONFINITE (parameters already updated) if the loss is not finite. */
 tr_status no_train_step(tr_context *ctx, no_model *m, int32_t batch,
                         const float *input, const float *target, double lr,
                         double *loss, float *grad_out);

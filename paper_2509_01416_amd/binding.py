@@ -28,7 +28,8 @@ TR_ERR_NONFINITE = -4
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "tr_sweep", "tr_solve", "no_recast_guess", "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
-           "no_model_set_params", "no_forward", "no_train_step",
+           "no_model_set_params", "no_model_set_fp32", "no_forward",
+           "no_train_step",
            "tr_check_args", "tr_set_sweep_config", "tr_get_sweep_plan",
            "tr_profile_enable", "tr_profile_read")
 
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.no_model_param_count.restype = i64
     lib.no_model_get_params.argtypes = [vp, vp, vp]
     lib.no_model_set_params.argtypes = [vp, vp, vp]
+    lib.no_model_set_fp32.argtypes = [vp, i32]
     lib.no_forward.argtypes = [vp, vp, i32, vp, vp]
     lib.no_train_step.argtypes = [vp, vp, i32, vp, vp, d, P(d), vp]
     lib.tr_check_args.argtypes = [i32, P(TrProblem), P(TrQuadrature), d, i32,
@@ -279,3 +281,89 @@ def sweep_plan(problems_struct, n: int, quad: Quad, handle=None) -> dict:
     if rc != TR_OK:
         raise MdpError(rc, "tr_get_sweep_plan failed")
     return dict(D=out[0], W=out[1], S=out[2], R=out[3], KB=out[4])
+
+
+# ---------------------------------------------------------------- network
+
+class Model:
+    """no_model handle: the 2-D FNO (width 32, modes 12, 4 layers, 64 x 64)."""
+
+    def __init__(self, ctx: Context, params: Optional[np.ndarray] = None,
+                 width: int = 32, modes: int = 12, layers: int = 4, grid: int = 64):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.grid = grid
+        h = ctypes.c_void_p()
+        buf = None
+        if params is not None:
+            buf = np.ascontiguousarray(params, dtype=np.float32)
+        rc = self.lib.no_model_create(ctx.handle, ctypes.byref(h), width, modes,
+                                      layers, grid,
+                                      None if buf is None else buf.ctypes.data)
+        ctx.check(rc, allow=(TR_OK,))
+        self.handle = h
+        self.n_params = int(self.lib.no_model_param_count(h))
+        if buf is not None and buf.size != self.n_params:
+            self.close()
+            raise ValueError(f"expected {self.n_params} parameters, got {buf.size}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.no_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fp32(self, enable: bool = True):
+        self.ctx.check(self.lib.no_model_set_fp32(self.handle, int(enable)), allow=(TR_OK,))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self.ctx.check(self.lib.no_model_get_params(self.ctx.handle, self.handle,
+                                                    out.ctypes.data), allow=(TR_OK,))
+        return out
+
+    def set_params(self, params: np.ndarray):
+        buf = np.ascontiguousarray(params, dtype=np.float32)
+        if buf.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {buf.size}")
+        self.ctx.check(self.lib.no_model_set_params(self.ctx.handle, self.handle,
+                                                    buf.ctypes.data), allow=(TR_OK,))
+
+    def forward(self, inp, out=None):
+        """inp: float32 GPU tensor (B, grid, grid) -> output tensor (B, grid, grid)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(inp)
+        B = int(inp.shape[0])
+        self.ctx.check(self.lib.no_forward(self.ctx.handle, self.handle, B,
+                                           _ptr(inp), _ptr(out)), allow=(TR_OK,))
+        return out
+
+    def train_step(self, inp, target, lr: float, grad_out=None) -> float:
+        loss = ctypes.c_double()
+        B = int(inp.shape[0])
+        self.ctx.check(self.lib.no_train_step(self.ctx.handle, self.handle, B, _ptr(inp),
+                                              _ptr(target), float(lr), ctypes.byref(loss),
+                                              _ptr(grad_out)), allow=(TR_OK,))
+        return loss.value
+
+
+def no_recast_guess(ctx: Context, model: Model, problems: Sequence[Problem],
+                    sigma_t_star: float, sigma_s_star: float, tol: float,
+                    max_iter: int, phi_guess: Sequence, raise_on_error: bool = True):
+    """Returns (status, list of per-instance stats dicts)."""
+    n = len(problems)
+    arr = make_problems(problems)
+    stats = (TrStats * n)()
+    rc = ctx.lib.no_recast_guess(ctx.handle, model.handle, n, arr, float(sigma_t_star),
+                                 float(sigma_s_star), float(tol), int(max_iter),
+                                 _ptr_array(phi_guess), stats)
+    if raise_on_error:
+        ctx.check(rc)
+    return rc, [dict(status=s.status, iterations=s.iterations, residual=s.residual,
+                     seconds=s.seconds) for s in stats]

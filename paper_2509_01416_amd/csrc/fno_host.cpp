@@ -1,39 +1,675 @@
-// fno_host.cpp -- network entry points (placeholder until the network
-// kernels are linked in).
+// fno_host.cpp -- the network half of the C ABI: the 2-D Fourier neural
+// operator of section 4.2 / Appendix A1 (model state, forward, hand-written
+// backward, MSE + Adam training step) and the equation-recast loop of Eq. 24
+// that turns the trained network into an initial guess for source iteration.
+//
+// Every dense contraction goes through one batched matrix-core GEMM with
+// strided views (launch_gemm).  The truncated 2-D real DFT of a 64 x 64
+// channel is four small products with fixed matrices held on the device:
+//   T  (64 x 24)  = v (64 y x 64 x) . FxT (64 x 24)       rfft along x
+//   X  (48 x 12)  = Fy (48 x 128) . [T_re; T_im]           DFT along y
+//   Z  (128 x 12) = Gy (128 x 48) . Y                      inverse along y
+//   u  (64 x 64)  = Z' (64 y x 24) . Gx (24 x 64)          inverse rfft (x)
+// with the retained modes kx in [0,12), ky in [0,12) U [52,64) and the 1/n^2
+// and Hermitian factor c_kx (1 for kx = 0, else 2) folded into Gx.  The
+// backward pass applies the transposes of the same matrices (read through
+// transposed views), which is the exact adjoint of the forward map.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "../../include/mdpnop.h"
+#include "fno_kernels.h"
 #include "host_internal.h"
+
+namespace mdp {
+
+constexpr int kProj = 128;          // projection width (Appendix A1)
+constexpr int kGridLog2 = 6;        // supported network grid 64 x 64
+constexpr int kGrid = 1 << kGridLog2;
+constexpr int kP = kGrid * kGrid;   // cells per field
+constexpr int kPLog2 = 2 * kGridLog2;
+
+struct FnoWork {
+    Arena act;         // activations of the current batch
+    Arena rc;          // recast-loop fields on the network grid
+    PinnedBuf host;    // norm read-back
+};
+
+}  // namespace mdp
 
 using namespace mdp;
 
-void mdp::Ctx::release_fno() {}
+struct no_model {
+    int device = 0;
+    int width = 0, modes = 0, layers = 0, grid = 0;
+    long long n_params = 0;
+    long long oW0 = 0, ob0 = 0, oP1 = 0, oc1 = 0, oP2 = 0, oc2 = 0;
+    std::vector<long long> oR, oW, ob;
+    float* params = nullptr;   // FP32 master copy
+    float* grad = nullptr;
+    float* am = nullptr;       // Adam first moment
+    float* av = nullptr;       // Adam second moment
+    float* FxT = nullptr;      // [64][24]
+    float* Fy = nullptr;       // [48][128]
+    float* Gy = nullptr;       // [128][48]
+    float* Gx = nullptr;       // [24][64]
+    long long step = 0;
+    int f32 = 0;               // FP32 operands on the matrix cores
+};
 
-extern "C" tr_status no_model_create(tr_context* ctx, no_model** m, int32_t,
-                                     int32_t, int32_t, int32_t, const float*) {
-    if (m) *m = nullptr;
+namespace {
+
+// ------------------------------------------------------------ workspace --
+struct Ws {
+    int B = 0;
+    std::vector<float*> v, z, X;   // layer inputs, pre-activations, kept modes
+    float *h = nullptr, *T = nullptr, *Y = nullptr, *gX = nullptr;
+    float *gv = nullptr, *gv2 = nullptr, *gz = nullptr, *gh = nullptr;
+    float *out = nullptr, *gout = nullptr, *partial = nullptr;
+    double* mse = nullptr;
+};
+
+constexpr int kMaxKsplit = 128;
+constexpr int kMsePartials = 256;
+
+size_t carve(const no_model* m, int B, bool train, char* base, Ws* w) {
+    const long long C = m->width, L = m->layers, mm = m->modes;
+    const long long act = (long long)B * C * kP;
+    const long long modes = (long long)B * C * 2 * 2 * mm * mm;
+    const long long tbuf = (long long)B * C * kGrid * 2 * mm;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    w->B = B;
+    w->v.assign(L, nullptr);
+    w->z.assign(L, nullptr);
+    w->X.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        w->v[l] = (float*)take(4 * act);
+        w->z[l] = (float*)take(4 * act);
+        w->X[l] = (float*)take(4 * modes);
+    }
+    w->h = (float*)take(4 * (size_t)B * kProj * kP);
+    w->T = (float*)take(4 * tbuf);
+    w->Y = (float*)take(4 * modes);
+    if (train) {
+        w->gX = (float*)take(4 * modes);
+        w->gv = (float*)take(4 * act);
+        w->gv2 = (float*)take(4 * act);
+        w->gz = (float*)take(4 * act);
+        w->gh = (float*)take(4 * (size_t)B * kProj * kP);
+        w->out = (float*)take(4 * (size_t)B * kP);
+        w->gout = (float*)take(4 * (size_t)B * kP);
+        w->partial = (float*)take(4 * (size_t)kMaxKsplit * C * kProj);
+        w->mse = (double*)take(8 * kMsePartials);
+    }
+    return off;
+}
+
+bool workspace(Ctx* c, const no_model* m, int B, bool train, Ws* w) {
+    if (!c->fno) {
+        c->fno = new (std::nothrow) FnoWork();
+        if (!c->fno) {
+            c->fail("out of host memory");
+            return false;
+        }
+    }
+    const size_t bytes = carve(m, B, train, nullptr, w);
+    if (!c->fno->act.reserve(c, bytes)) return false;
+    carve(m, B, train, (char*)c->fno->act.base, w);
+    return true;
+}
+
+// ---------------------------------------------------------------- views --
+View mat(const float* p, long long rs, long long cs, long long bs = 0) {
+    View v;
+    v.p = const_cast<float*>(p);
+    v.sr_lo = rs;
+    v.sc_lo = cs;
+    v.sb_lo = bs;
+    return v;
+}
+
+// The (p, y) x kx view of a [y][p][kx] buffer (p = re/im): row r = p*64 + y.
+View tsplit(const float* p, int mm, long long bs) {
+    View v = mat(p, 2 * mm, 1, bs);
+    v.r_ls = kGridLog2;
+    v.sr_hi = mm;
+    v.sr_lo = 2 * mm;
+    return v;
+}
+
+// Reduction over (batch, cell) as the K index of a [b][row][cell] tensor:
+// K index kk = b * P + p.
+View kcols(const float* p, long long rows_per_b) {   // A: (row, kk)
+    View v = mat(p, kP, 1);
+    v.c_ls = kPLog2;
+    v.sc_hi = rows_per_b * kP;
+    v.sc_lo = 1;
+    return v;
+}
+View krows(const float* p, long long rows_per_b) {   // B: (kk, col)
+    View v = mat(p, 1, kP);
+    v.r_ls = kPLog2;
+    v.sr_hi = rows_per_b * kP;
+    v.sr_lo = 1;
+    return v;
+}
+
+struct Runner {
+    Ctx* c;
+    const no_model* m;
+    bool ok = true;
+
+    bool gemm(int M, int N, int K, int G, View A, View B, View C, int acc = 0,
+              const float* bias_row = nullptr, float* partial = nullptr) {
+        GemmArgs a;
+        a.M = M;
+        a.N = N;
+        a.K = K;
+        a.G = G;
+        a.A = A;
+        a.B = B;
+        a.C = C;
+        a.accumulate = acc;
+        a.bias_row = bias_row;
+        a.f32 = m->f32;
+        if (partial && G == 1) {
+            a.ksplit = std::max(1, std::min(kMaxKsplit, K / 2048));
+            a.partial = partial;
+        }
+        if (!launch_gemm(a, c->stream)) {
+            c->fail("gemm batch view cannot be chunked");
+            ok = false;
+        }
+        return ok;
+    }
+
+    // Forward of `B` fields in[b] ([B][P]) -> out ([B][P]); activations kept
+    // in w for a following backward.
+    void forward(const float* in, float* out, Ws& w) {
+        const int C = m->width, L = m->layers, mm = m->modes, B = w.B;
+        const float* P = m->params;
+        const int G = B * C;
+        const long long act = (long long)C * kP;
+        const long long per = 4LL * mm * mm, tb = (long long)kGrid * 2 * mm;
+        launch_lift(in, P + m->oW0, P + m->ob0, w.v[0], B, kGrid, C, c->stream);
+        for (int l = 0; l < L && ok; ++l) {
+            gemm(kGrid, 2 * mm, kGrid, G, mat(w.v[l], kGrid, 1, kP), mat(m->FxT, 2 * mm, 1),
+                 mat(w.T, 2 * mm, 1, tb));
+            gemm(4 * mm, mm, 2 * kGrid, G, mat(m->Fy, 2 * kGrid, 1), tsplit(w.T, mm, tb),
+                 mat(w.X[l], mm, 1, per));
+            launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
+            gemm(2 * kGrid, mm, 4 * mm, G, mat(m->Gy, 4 * mm, 1), mat(w.Y, mm, 1, per),
+                 tsplit(w.T, mm, tb));
+            gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->Gx, kGrid, 1),
+                 mat(w.z[l], kGrid, 1, kP));
+            gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
+                 mat(w.z[l], kP, 1, act), 1, P + m->ob[l]);
+            if (l + 1 < L) launch_gelu(w.z[l], w.v[l + 1], (long long)B * act, c->stream);
+        }
+        const float* vL = w.z[L - 1];
+        gemm(kProj, kP, C, B, mat(P + m->oP1, 1, kProj), mat(vL, kP, 1, act),
+             mat(w.h, kP, 1, (long long)kProj * kP), 0, P + m->oc1);
+        launch_proj_out(w.h, P + m->oP2, P + m->oc2, out, B, kP, kProj, c->stream);
+    }
+
+    // Gradient of sum(gout * out) into m->grad (every entry written).
+    void backward(const float* in, const float* gout, Ws& w) {
+        const int C = m->width, L = m->layers, mm = m->modes, B = w.B;
+        const float* P = m->params;
+        float* g = m->grad;
+        const int G = B * C;
+        const long long act = (long long)C * kP;
+        const long long per = 4LL * mm * mm, tb = (long long)kGrid * 2 * mm;
+        const float* vL = w.z[L - 1];
+        launch_row_reduce(w.h, gout, g + m->oP2, B, kProj, kP, 2, 0, c->stream);
+        launch_row_reduce(gout, nullptr, g + m->oc2, B, 1, kP, 0, 0, c->stream);
+        launch_proj_back(w.h, P + m->oP2, gout, w.gh, B, kP, kProj, c->stream);
+        gemm(C, kProj, B * kP, 1, kcols(vL, C), krows(w.gh, kProj), mat(g + m->oP1, kProj, 1),
+             0, nullptr, w.partial);
+        launch_row_reduce(w.gh, nullptr, g + m->oc1, B, kProj, kP, 0, 0, c->stream);
+        gemm(C, kP, kProj, B, mat(P + m->oP1, kProj, 1), mat(w.gh, kP, 1, (long long)kProj * kP),
+             mat(w.gv, kP, 1, act));
+        float* gv = w.gv;
+        float* gv2 = w.gv2;
+        for (int l = L - 1; l >= 0 && ok; --l) {
+            float* gz = gv;
+            if (l + 1 < L) {
+                launch_gelu_back(w.z[l], gv, w.gz, (long long)B * act, c->stream);
+                gz = w.gz;
+            }
+            gemm(C, C, B * kP, 1, kcols(w.v[l], C), krows(gz, C), mat(g + m->oW[l], C, 1), 0,
+                 nullptr, w.partial);
+            launch_row_reduce(gz, nullptr, g + m->ob[l], B, C, kP, 0, 0, c->stream);
+            gemm(C, kP, C, B, mat(P + m->oW[l], C, 1), mat(gz, kP, 1, act), mat(gv2, kP, 1, act));
+            // spectral path, adjoint of the forward products
+            gemm(kGrid, 2 * mm, kGrid, G, mat(gz, kGrid, 1, kP), mat(m->Gx, 1, kGrid),
+                 mat(w.T, 2 * mm, 1, tb));
+            gemm(4 * mm, mm, 2 * kGrid, G, mat(m->Gy, 1, 4 * mm), tsplit(w.T, mm, tb),
+                 mat(w.Y, mm, 1, per));
+            launch_mix_back_w(w.X[l], w.Y, g + m->oR[l], B, C, mm, c->stream);
+            launch_mix_back_x(w.Y, P + m->oR[l], w.gX, B, C, mm, c->stream);
+            gemm(2 * kGrid, mm, 4 * mm, G, mat(m->Fy, 1, 2 * kGrid), mat(w.gX, mm, 1, per),
+                 tsplit(w.T, mm, tb));
+            gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->FxT, 1, 2 * mm),
+                 mat(gv2, kGrid, 1, kP), 1);
+            std::swap(gv, gv2);
+        }
+        launch_lift_back(in, gv, g + m->oW0, g + m->ob0, B, kGrid, C, c->stream);
+    }
+};
+
+// DFT matrices of the retained modes (FP64 on the host, stored FP32).
+void dft_matrices(int mm, std::vector<float>& FxT, std::vector<float>& Fy,
+                  std::vector<float>& Gy, std::vector<float>& Gx) {
+    const int n = kGrid, w2 = 2 * mm, ny = 2 * mm;
+    const double tp = 2.0 * M_PI / n;
+    FxT.assign((size_t)n * w2, 0.f);
+    for (int x = 0; x < n; ++x)
+        for (int k = 0; k < mm; ++k) {
+            const long long ph = ((long long)k * x) % n;
+            FxT[x * w2 + k] = (float)std::cos(tp * ph);
+            FxT[x * w2 + mm + k] = (float)-std::sin(tp * ph);
+        }
+    Fy.assign((size_t)2 * ny * 2 * n, 0.f);
+    Gy.assign((size_t)2 * n * 2 * ny, 0.f);
+    for (int kyi = 0; kyi < ny; ++kyi) {
+        const int ky = kyi < mm ? kyi : n - 2 * mm + kyi;
+        for (int y = 0; y < n; ++y) {
+            const long long ph = ((long long)ky * y) % n;
+            const float cs = (float)std::cos(tp * ph), sn = (float)std::sin(tp * ph);
+            // X = Fy [T_re; T_im]:  X_re = c T_re + s T_im, X_im = -s T_re + c T_im
+            Fy[(size_t)(0 * ny + kyi) * 2 * n + 0 * n + y] = cs;
+            Fy[(size_t)(0 * ny + kyi) * 2 * n + 1 * n + y] = sn;
+            Fy[(size_t)(1 * ny + kyi) * 2 * n + 0 * n + y] = -sn;
+            Fy[(size_t)(1 * ny + kyi) * 2 * n + 1 * n + y] = cs;
+            // Z = Gy Y:  Z_re = c Y_re - s Y_im, Z_im = s Y_re + c Y_im
+            Gy[(size_t)(0 * n + y) * 2 * ny + 0 * ny + kyi] = cs;
+            Gy[(size_t)(0 * n + y) * 2 * ny + 1 * ny + kyi] = -sn;
+            Gy[(size_t)(1 * n + y) * 2 * ny + 0 * ny + kyi] = sn;
+            Gy[(size_t)(1 * n + y) * 2 * ny + 1 * ny + kyi] = cs;
+        }
+    }
+    Gx.assign((size_t)w2 * n, 0.f);
+    const double inv = 1.0 / ((double)n * n);
+    for (int k = 0; k < mm; ++k) {
+        const double ck = (k == 0 ? 1.0 : 2.0) * inv;
+        for (int x = 0; x < n; ++x) {
+            const long long ph = ((long long)k * x) % n;
+            Gx[(size_t)k * n + x] = (float)(ck * std::cos(tp * ph));
+            Gx[(size_t)(mm + k) * n + x] = (float)(-ck * std::sin(tp * ph));
+        }
+    }
+}
+
+void free_model(no_model* m) {
+    float* bufs[] = {m->params, m->grad, m->am, m->av, m->FxT, m->Fy, m->Gy, m->Gx};
+    for (float* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+bool same_device(Ctx* c, const no_model* m) {
+    if (m->device != c->device) {
+        c->fail("model lives on device %d, context on device %d", m->device, c->device);
+        return false;
+    }
+    return true;
+}
+
+tr_status finish(Ctx* c, const char* what) {
+    if (!c->hip_ok(hipGetLastError(), what)) return TR_ERR_HIP;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "sync")) return TR_ERR_HIP;
+    return TR_OK;
+}
+
+tr_status ws_status(Ctx* c) {
+    return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+void mdp::Ctx::release_fno() {
+    if (!fno) return;
+    if (fno->act.base) (void)hipFree(fno->act.base);
+    if (fno->rc.base) (void)hipFree(fno->rc.base);
+    if (fno->host.ptr) (void)hipHostFree(fno->host.ptr);
+    delete fno;
+    fno = nullptr;
+}
+
+// ===================================================================== ABI
+
+extern "C" tr_status no_model_create(tr_context* ctx, no_model** out, int32_t width,
+                                     int32_t modes, int32_t layers, int32_t grid,
+                                     const float* params_host) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
-    if (c) c->fail("network kernels not built");
-    return TR_ERR_INVALID_ARG;
+    if (!c || !out) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    *out = nullptr;
+    if (width != 32 || modes != 12 || layers != 4 || grid != kGrid) {
+        c->fail("unsupported network shape (width %d, modes %d, layers %d, grid %d); "
+                "supported: 32, 12, 4, 64", width, modes, layers, grid);
+        return TR_ERR_INVALID_ARG;
+    }
+    no_model* m = new (std::nothrow) no_model();
+    if (!m) return TR_ERR_OOM;
+    m->device = c->device;
+    m->width = width;
+    m->modes = modes;
+    m->layers = layers;
+    m->grid = grid;
+    long long o = 0;
+    const long long w = width, mm = modes;
+    m->oW0 = o; o += 3 * w;
+    m->ob0 = o; o += w;
+    for (int l = 0; l < layers; ++l) {
+        m->oR.push_back(o); o += 2 * mm * mm * w * w * 2;
+        m->oW.push_back(o); o += w * w;
+        m->ob.push_back(o); o += w;
+    }
+    m->oP1 = o; o += w * kProj;
+    m->oc1 = o; o += kProj;
+    m->oP2 = o; o += kProj;
+    m->oc2 = o; o += 1;
+    m->n_params = o;
+    std::vector<float> FxT, Fy, Gy, Gx;
+    dft_matrices(modes, FxT, Fy, Gy, Gx);
+    const size_t pb = sizeof(float) * (size_t)o;
+    bool good = c->hip_ok(hipMalloc(&m->params, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->grad, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->am, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->av, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->FxT, 4 * FxT.size()), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->Fy, 4 * Fy.size()), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->Gy, 4 * Gy.size()), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->Gx, 4 * Gx.size()), "hipMalloc");
+    if (good) {
+        hipStream_t s = c->stream;
+        good = (params_host
+                    ? c->hip_ok(hipMemcpyAsync(m->params, params_host, pb, hipMemcpyHostToDevice, s),
+                                "copy")
+                    : c->hip_ok(hipMemsetAsync(m->params, 0, pb, s), "memset")) &&
+               c->hip_ok(hipMemsetAsync(m->grad, 0, pb, s), "memset") &&
+               c->hip_ok(hipMemsetAsync(m->am, 0, pb, s), "memset") &&
+               c->hip_ok(hipMemsetAsync(m->av, 0, pb, s), "memset") &&
+               c->hip_ok(hipMemcpyAsync(m->FxT, FxT.data(), 4 * FxT.size(), hipMemcpyHostToDevice, s), "copy") &&
+               c->hip_ok(hipMemcpyAsync(m->Fy, Fy.data(), 4 * Fy.size(), hipMemcpyHostToDevice, s), "copy") &&
+               c->hip_ok(hipMemcpyAsync(m->Gy, Gy.data(), 4 * Gy.size(), hipMemcpyHostToDevice, s), "copy") &&
+               c->hip_ok(hipMemcpyAsync(m->Gx, Gx.data(), 4 * Gx.size(), hipMemcpyHostToDevice, s), "copy") &&
+               c->hip_ok(hipStreamSynchronize(s), "sync");
+    }
+    if (!good) {
+        (void)hipGetLastError();
+        free_model(m);
+        delete m;
+        return c->err.find("out of memory") != std::string::npos ? TR_ERR_OOM : TR_ERR_HIP;
+    }
+    *out = m;
+    return TR_OK;
 }
-extern "C" void no_model_destroy(no_model*) {}
-extern "C" int64_t no_model_param_count(const no_model*) { return 0; }
-extern "C" tr_status no_model_get_params(tr_context*, const no_model*, float*) {
-    return TR_ERR_INVALID_ARG;
+
+extern "C" void no_model_destroy(no_model* m) {
+    if (!m) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != m->device) (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    free_model(m);
+    if (cur != m->device) (void)hipSetDevice(cur);
+    delete m;
 }
-extern "C" tr_status no_model_set_params(tr_context*, no_model*, const float*) {
-    return TR_ERR_INVALID_ARG;
+
+extern "C" int64_t no_model_param_count(const no_model* m) { return m ? m->n_params : 0; }
+
+extern "C" tr_status no_model_set_fp32(no_model* m, int32_t enable) {
+    if (!m || (enable != 0 && enable != 1)) return TR_ERR_INVALID_ARG;
+    m->f32 = enable;
+    return TR_OK;
 }
-extern "C" tr_status no_forward(tr_context*, const no_model*, int32_t,
-                                const float*, float*) {
-    return TR_ERR_INVALID_ARG;
+
+extern "C" tr_status no_model_get_params(tr_context* ctx, const no_model* m, float* params_host) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || !params_host) {
+        c->fail("null model or buffer");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    if (!c->hip_ok(hipMemcpyAsync(params_host, m->params, 4 * (size_t)m->n_params,
+                                  hipMemcpyDeviceToHost, c->stream), "copy"))
+        return TR_ERR_HIP;
+    return finish(c, "get params");
 }
-extern "C" tr_status no_train_step(tr_context*, no_model*, int32_t, const float*,
-                                   const float*, double, double*, float*) {
-    return TR_ERR_INVALID_ARG;
+
+extern "C" tr_status no_model_set_params(tr_context* ctx, no_model* m, const float* params_host) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || !params_host) {
+        c->fail("null model or buffer");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    const size_t pb = 4 * (size_t)m->n_params;
+    if (!c->hip_ok(hipMemcpyAsync(m->params, params_host, pb, hipMemcpyHostToDevice, c->stream),
+                   "copy") ||
+        !c->hip_ok(hipMemsetAsync(m->am, 0, pb, c->stream), "memset") ||
+        !c->hip_ok(hipMemsetAsync(m->av, 0, pb, c->stream), "memset"))
+        return TR_ERR_HIP;
+    m->step = 0;
+    return finish(c, "set params");
 }
-extern "C" tr_status no_recast_guess(tr_context*, const no_model*, int32_t,
-                                     const tr_problem*, double, double, double,
-                                     int32_t, float* const*, tr_stats*) {
-    return TR_ERR_INVALID_ARG;
+
+extern "C" tr_status no_forward(tr_context* ctx, const no_model* m, int32_t batch,
+                                const float* input, float* output) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || batch <= 0 || !input || !output) {
+        c->fail("no_forward: need a model, batch > 0 and buffers");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    Ws w;
+    if (!workspace(c, m, batch, false, &w)) return ws_status(c);
+    Runner r{c, m};
+    r.forward(input, output, w);
+    if (!r.ok) return TR_ERR_INVALID_ARG;
+    return finish(c, "forward launch");
+}
+
+extern "C" tr_status no_train_step(tr_context* ctx, no_model* m, int32_t batch,
+                                   const float* input, const float* target, double lr,
+                                   double* loss, float* grad_out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || batch <= 0 || !input || !target || !(lr >= 0.0) || !std::isfinite(lr)) {
+        c->fail("no_train_step: need a model, batch > 0, buffers and a finite lr >= 0");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    Ws w;
+    if (!workspace(c, m, batch, true, &w)) return ws_status(c);
+    if (!c->fno->host.reserve(c, sizeof(double) * kMsePartials)) return ws_status(c);
+    Runner r{c, m};
+    r.forward(input, w.out, w);
+    const long long n = (long long)batch * kP;
+    const int nb = launch_mse(w.out, target, w.gout, w.mse, n, c->stream);
+    r.backward(input, w.gout, w);
+    if (!r.ok) return TR_ERR_INVALID_ARG;
+    if (grad_out &&
+        !c->hip_ok(hipMemcpyAsync(grad_out, m->grad, 4 * (size_t)m->n_params,
+                                  hipMemcpyDeviceToDevice, c->stream), "copy"))
+        return TR_ERR_HIP;
+    if (lr > 0.0) {
+        m->step += 1;
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = (float)(1.0 - std::pow(b1, (double)m->step));
+        const float c2 = (float)(1.0 - std::pow(b2, (double)m->step));
+        launch_adam(m->params, m->grad, m->am, m->av, m->n_params, (float)lr, (float)b1,
+                    (float)b2, 1e-8f, c1, c2, c->stream);
+    }
+    double* hp = (double*)c->fno->host.ptr;
+    if (!c->hip_ok(hipMemcpyAsync(hp, w.mse, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                  c->stream), "copy"))
+        return TR_ERR_HIP;
+    const tr_status st = finish(c, "train launch");
+    if (st != TR_OK) return st;
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += hp[i];
+    if (loss) *loss = s / (double)n;
+    if (!std::isfinite(s)) {
+        c->fail("non-finite loss");
+        return TR_ERR_NONFINITE;
+    }
+    return TR_OK;
+}
+
+extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t n_inst,
+                                     const tr_problem* p, double sigma_t_star,
+                                     double sigma_s_star, double tol, int32_t max_iter,
+                                     float* const* phi_guess, tr_stats* stats) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!m || !phi_guess) {
+        c->fail("no_recast_guess: need a model and output pointers");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    if (!check_problems(c, n_inst, p, true)) return TR_ERR_INVALID_ARG;
+    const double sa_star = sigma_t_star - sigma_s_star;
+    if (!(sa_star > 0.0) || !std::isfinite(sa_star) || !(sigma_s_star >= 0.0)) {
+        c->fail("need sigma_t* > sigma_s* >= 0 (finite)");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!(tol >= 0.0) || !std::isfinite(tol) || max_iter < 1) {
+        c->fail("need tol >= 0 and max_iter >= 1");
+        return TR_ERR_INVALID_ARG;
+    }
+    std::vector<int> fac(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const tr_problem& P = p[i];
+        if (P.dim != 2 || P.nx != P.ny || P.nx % kGrid != 0 || !phi_guess[i]) {
+            c->fail("problem %d: need a 2-D square grid that is a multiple of %d and an "
+                    "output pointer", i, kGrid);
+            return TR_ERR_INVALID_ARG;
+        }
+        fac[i] = P.nx / kGrid;
+    }
+    const int B = n_inst;
+    Ws w;
+    if (!workspace(c, m, B, false, &w)) return ws_status(c);
+    FnoWork* fw = c->fno;
+    // recast fields: S, sigma_a, phi, in, out (B x P), scale (B), norms (2B), active (B)
+    const size_t fb = align_up(4 * (size_t)B * kP);
+    const size_t need = 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B) +
+                        align_up(4 * (size_t)B);
+    if (!fw->rc.reserve(c, need) ||
+        !fw->host.reserve(c, 16 * (size_t)B + 4 * (size_t)B))
+        return ws_status(c);
+    char* base = (char*)fw->rc.base;
+    float* S = (float*)base;
+    float* sa = (float*)(base + fb);
+    float* phi = (float*)(base + 2 * fb);
+    float* in = (float*)(base + 3 * fb);
+    float* out = (float*)(base + 4 * fb);
+    float* scale = (float*)(base + 5 * fb);
+    double* norms = (double*)(base + 5 * fb + align_up(4 * (size_t)B));
+    int* active = (int*)(base + 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B));
+    double* hn = (double*)fw->host.ptr;
+    int* hact = (int*)(hn + 2 * B);
+    hipStream_t s = c->stream;
+    for (int i = 0; i < B; ++i) {
+        launch_block_average(p[i].source, p[i].nx, fac[i], S + (size_t)i * kP, kGrid, nullptr, 0, s);
+        launch_block_average(p[i].sigma_t, p[i].nx, fac[i], sa + (size_t)i * kP, kGrid,
+                             p[i].sigma_s, 1, s);
+        hact[i] = 1;
+    }
+    if (!c->hip_ok(hipMemsetAsync(phi, 0, 4 * (size_t)B * kP, s), "memset") ||
+        !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
+        return TR_ERR_HIP;
+    std::vector<int> status(B, TR_NOT_CONVERGED), iters(B, 0), grow(B, 0);
+    std::vector<double> resid(B, 0.0), first(B, 0.0), prev(B, 0.0);
+    int live = B;
+    Runner r{c, m};
+    for (int k = 0; k < max_iter && live > 0; ++k) {
+        launch_recast_input(S, sa, phi, (float)sa_star, in, scale, active, B, kP, s);
+        r.forward(in, out, w);
+        if (!r.ok) return TR_ERR_INVALID_ARG;
+        launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, B, kP, s);
+        if (!c->hip_ok(hipMemcpyAsync(hn, norms, 16 * (size_t)B, hipMemcpyDeviceToHost, s), "copy"))
+            return TR_ERR_HIP;
+        const tr_status st = finish(c, "recast launch");
+        if (st != TR_OK) return st;
+        bool changed = false;
+        for (int b = 0; b < B; ++b) {
+            if (!hact[b]) continue;
+            const double num = std::sqrt(hn[2 * b]), den = std::sqrt(hn[2 * b + 1]);
+            const double d = den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);
+            iters[b] = k + 1;
+            resid[b] = d;
+            int done = -1;
+            if (!std::isfinite(d) || !std::isfinite(num)) {
+                done = TR_RECAST_DIVERGED;
+            } else if (d < tol) {
+                done = TR_OK;
+            } else {
+                grow[b] = (k >= 1 && num > prev[b]) ? grow[b] + 1 : 0;
+                if (k == 0) first[b] = num;
+                if (grow[b] >= 3 && num > first[b]) done = TR_RECAST_DIVERGED;
+            }
+            prev[b] = num;
+            if (done >= 0) {
+                status[b] = done;
+                hact[b] = 0;
+                --live;
+                changed = true;
+                if (done == TR_RECAST_DIVERGED &&
+                    !c->hip_ok(hipMemsetAsync(phi + (size_t)b * kP, 0, 4 * (size_t)kP, s), "memset"))
+                    return TR_ERR_HIP;
+            }
+        }
+        if (changed && live > 0 &&
+            !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
+            return TR_ERR_HIP;
+    }
+    for (int i = 0; i < B; ++i) {
+        if (fac[i] == 1) {
+            if (!c->hip_ok(hipMemcpyAsync(phi_guess[i], phi + (size_t)i * kP, 4 * (size_t)kP,
+                                          hipMemcpyDeviceToDevice, s), "copy"))
+                return TR_ERR_HIP;
+        } else {
+            launch_bilinear_up(phi + (size_t)i * kP, kGrid, fac[i], phi_guess[i], 1.0f, s);
+        }
+    }
+    const tr_status st = finish(c, "recast output");
+    if (st != TR_OK) return st;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = TR_OK;
+    for (int i = 0; i < B; ++i) {
+        worst = std::max(worst, status[i]);
+        if (stats) {
+            stats[i].status = status[i];
+            stats[i].iterations = iters[i];
+            stats[i].residual = resid[i];
+            stats[i].balance_rel = NAN;
+            stats[i].seconds = secs;
+        }
+    }
+    return (tr_status)worst;
 }

@@ -1,0 +1,69 @@
+// fno_kernels.h -- launch interface of the network kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+namespace mdp {
+
+// A strided view of a batched matrix: element (g, r, c) sits at
+//   p + split(g, b_ls, sb_hi, sb_lo) + split(r, ...) + split(c, ...)
+// with split(i, ls, hi, lo) = (i >> ls) * hi + (i & (2^ls - 1)) * lo, or
+// i * lo when ls >= 31 (no split).
+struct View {
+    float* p = nullptr;
+    long long sb_hi = 0, sb_lo = 0;
+    int b_ls = 31;
+    long long sr_hi = 0, sr_lo = 0;
+    int r_ls = 31;
+    long long sc_hi = 0, sc_lo = 0;
+    int c_ls = 31;
+};
+
+struct GemmArgs {
+    int M = 0, N = 0, K = 0, G = 1;
+    View A, B, C;
+    float alpha = 1.f;
+    int accumulate = 0;
+    const float* bias_row = nullptr;   // added per output row m
+    const float* bias_col = nullptr;   // added per output column n
+    int ksplit = 1;
+    float* partial = nullptr;          // [ksplit][G][M][N] when ksplit > 1
+    int f32 = 0;                       // FP32 operands instead of BF16
+};
+
+bool launch_gemm(const GemmArgs& a, hipStream_t s);
+void launch_lift(const float* in, const float* W0, const float* b0, float* out, int B,
+                 int n, int C, hipStream_t s);
+void launch_gelu(const float* z, float* v, long long n, hipStream_t s);
+void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, hipStream_t s);
+void launch_mix(const float* X, const float* R, float* Y, int B, int C, int m, hipStream_t s);
+void launch_mix_back_x(const float* gY, const float* R, float* gX, int B, int C, int m,
+                       hipStream_t s);
+void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C, int m,
+                       hipStream_t s);
+void launch_proj_out(const float* h, const float* P2, const float* c2, float* out, int B,
+                     int P, int K, hipStream_t s);
+void launch_proj_back(const float* h, const float* P2, const float* gout, float* gh, int B,
+                      int P, int K, hipStream_t s);
+void launch_row_reduce(const float* x, const float* w, float* out, int B, int R, int P,
+                       int mode, int accumulate, hipStream_t s);
+void launch_lift_back(const float* in, const float* gv, float* gW0, float* gb0, int B, int n,
+                      int C, hipStream_t s);
+int launch_mse(const float* out, const float* t, float* gout, double* partial, long long n,
+               hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t s);
+void launch_recast_input(const float* S, const float* sa, const float* phi, float sa_star,
+                         float* in, float* scale, const int* active, int B, int P,
+                         hipStream_t s);
+void launch_recast_update(const float* out, const float* scale, float inv_sa_star, float* phi,
+                          double* norms, const int* active, int B, int P, hipStream_t s);
+void launch_block_average(const float* fine, int nf_x, int f, float* coarse, int nc,
+                          const float* sub, int mode, hipStream_t s);
+void launch_bilinear_up(const float* coarse, int nc, int f, float* fine, float scale,
+                        hipStream_t s);
+void launch_scale(float* x, float sc, long long n, hipStream_t s);
+
+}  // namespace mdp

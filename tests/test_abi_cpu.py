@@ -17,7 +17,7 @@ def _declared():
     txt = open(os.path.join(ROOT, "include", "mdpnop.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(?:tr_status|void|int64_t|const char \*)\s*\**\s*"
-                                 r"([a-z_]+)\s*\(", txt)))
+                                 r"([a-z][a-z0-9_]*)\s*\(", txt)))
 
 
 def test_all_declared_symbols_exported():

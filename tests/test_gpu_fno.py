@@ -1,0 +1,297 @@
+"""Parity of the HIP network path (forward, backward, Adam, recast loop)
+against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * FP32 operands (no_model_set_fp32): each product is an FP32 dot product
+    of length <= 128 (rounding <= ~K eps32 relative to the operand norms) and
+    the network stacks about 20 of them, so the relative L2 error is a few
+    1e-6; the bar is 1e-4 for the output and 1e-3 per gradient block;
+  * BF16 operands: every operand carries a relative rounding of 2^-9, so
+    the output deviates by about 1e-2 relative; the bar is 5e-2 relative L2
+    for the output and cosine similarity > 0.99 per gradient block.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import log, rel_l2, to_problem
+from oracle import fno as F
+from oracle import recast as RC
+from paper_2509_01416_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N = 64
+LAY = F.Layout()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01416_amd import binding as B
+    assert torch.cuda.is_available()
+    ctx = B.Context()
+    yield torch, B, ctx
+    ctx.close()
+
+
+def _params(seed):
+    return F.init_params(LAY, seed).astype(np.float32)
+
+
+def _fields(batch, seed):
+    return np.stack([I.grf_2d(N, 10.0, seed=seed + b, mean=0.0, std=1.0, clip_min=None)
+                     for b in range(batch)])
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def _blocks():
+    for name, (o, s) in LAY.offsets().items():
+        if name != "_total":
+            yield name, o, s
+
+
+def test_param_count_and_roundtrip(env):
+    torch, B, ctx = env
+    p = _params(1)
+    m = B.Model(ctx, p)
+    assert m.n_params == 2_368_001 == LAY.n_params
+    back = m.get_params()
+    assert np.array_equal(back, p)
+    q = _params(2)
+    m.set_params(q)
+    assert np.array_equal(m.get_params(), q)
+    m.close()
+
+
+def test_bad_shape_rejected(env):
+    torch, B, ctx = env
+    with pytest.raises(B.MdpError):
+        B.Model(ctx, None, width=64)
+
+
+@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 5e-2)])
+def test_forward_parity(env, fp32, tol):
+    torch, B, ctx = env
+    p = _params(3)
+    x = _fields(3, 700)
+    m = B.Model(ctx, p)
+    m.set_fp32(fp32)
+    out = m.forward(_dev(torch, x)).cpu().numpy()
+    ref, _ = F.forward(p.astype(np.float64), F.make_input(x), LAY)
+    e = rel_l2(out, ref)
+    log(f"  forward fp32={fp32}: rel_l2={e:.3e} (bar {tol})")
+    assert e < tol
+    m.close()
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_gradient_parity(env, fp32):
+    torch, B, ctx = env
+    p = _params(4)
+    x = _fields(2, 800)
+    t = _fields(2, 900) * 0.1
+    m = B.Model(ctx, p)
+    m.set_fp32(fp32)
+    g = torch.zeros(m.n_params, dtype=torch.float32, device="cuda")
+    loss = m.train_step(_dev(torch, x), _dev(torch, t), 0.0, grad_out=g)
+    g = g.cpu().numpy().astype(np.float64)
+    p64 = p.astype(np.float64)
+    out, cache = F.forward(p64, F.make_input(x), LAY)
+    ref_loss, gout = F.mse(out, t)
+    gref, _ = F.backward(p64, cache, gout, LAY)
+    le = abs(loss - ref_loss) / ref_loss
+    log(f"  loss fp32={fp32}: {loss:.6e} vs {ref_loss:.6e} (rel {le:.2e})")
+    assert le < (1e-4 if fp32 else 5e-2)
+    for name, o, s in _blocks():
+        a, b = g[o:o + s], gref[o:o + s]
+        if fp32:
+            e = rel_l2(a, b)
+            log(f"  grad {name}: rel_l2={e:.2e}")
+            assert e < 1e-3, name
+        else:
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            log(f"  grad {name}: cosine={cos:.5f}")
+            assert cos > 0.99, name
+    # lr = 0 leaves the parameters untouched
+    assert np.array_equal(m.get_params(), p)
+    m.close()
+
+
+def test_adam_steps_match_oracle(env):
+    """Two Adam steps in FP32 mode against the oracle's Adam fed with the
+    oracle's gradients.  At t = 1 Adam's step is lr * g / (|g| + eps') for
+    every entry, so entries whose gradient is at rounding level may flip
+    sign; the check bounds their share and the size of every deviation."""
+    torch, B, ctx = env
+    lr = 1e-3
+    p = _params(5)
+    x = _fields(2, 1000)
+    t = _fields(2, 1100) * 0.1
+    m = B.Model(ctx, p)
+    m.set_fp32(True)
+    xd, td = _dev(torch, x), _dev(torch, t)
+    ref = p.astype(np.float64)
+    mm = np.zeros_like(ref)
+    vv = np.zeros_like(ref)
+    for step in (1, 2):
+        m.train_step(xd, td, lr)
+        out, cache = F.forward(ref, F.make_input(x), LAY)
+        _, gout = F.mse(out, t)
+        g, _ = F.backward(ref, cache, gout, LAY)
+        F.adam_step(ref, g, mm, vv, step, lr=lr)
+    got = m.get_params().astype(np.float64)
+    d = np.abs(got - ref)
+    frac = float(np.mean(d > 1e-5))
+    log(f"  adam: max|dp|={d.max():.2e}, share above 1e-5: {frac:.2e}")
+    assert d.max() <= 2 * 2 * lr + 1e-6
+    assert frac < 2e-3
+    moved = np.abs(got - p.astype(np.float64))
+    assert moved.max() > 0.5 * lr
+    m.close()
+
+
+def test_training_reduces_loss(env):
+    torch, B, ctx = env
+    p = _params(6)
+    x = _fields(4, 1200)
+    t = 0.5 * x + 0.2
+    m = B.Model(ctx, p)
+    xd, td = _dev(torch, x), _dev(torch, t)
+    losses = [m.train_step(xd, td, 1e-3) for _ in range(30)]
+    log(f"  training: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+    m.close()
+
+
+def test_forward_batch_independent(env):
+    """A batch entry's output does not depend on its neighbours."""
+    torch, B, ctx = env
+    m = B.Model(ctx, _params(7))
+    x = _fields(5, 1300)
+    full = m.forward(_dev(torch, x)).cpu().numpy()
+    one = m.forward(_dev(torch, x[2:3])).cpu().numpy()
+    assert np.array_equal(full[2:3], one)
+    m.close()
+
+
+# ----------------------------------------------------------------- recast
+
+def _linear_params(gain):
+    """Parameters that make the network the map in -> gain * in for inputs
+    well above -10 (channel 0 carries in + 10 through GELU's linear range)."""
+    d = F.unpack(np.zeros(LAY.n_params), LAY)
+    d["W0"][0, 0] = 1.0
+    d["b0"][0] = 10.0
+    for l in range(1, LAY.layers + 1):
+        d[f"W{l}"][0, 0] = 1.0
+    d["P1"][0, 0] = 1.0
+    d["P2"][0] = gain
+    d["c2"][0] = -10.0 * gain
+    return F.pack(d, LAY).astype(np.float32)
+
+
+def _uniform_problem(torch, B, n, sa, q=1.0):
+    st = np.full((n, n), 1.0)
+    ss = st - sa
+    inst = I.Instance(nx=n, ny=n, lx=10.0, ly=10.0, sigma_t=st, sigma_s=ss,
+                      source=np.full((n, n), q))
+    return to_problem(inst, torch), inst
+
+
+def test_recast_linear_fixed_point(env):
+    """With NO(S) = g S / sigma_a* and sigma_a = 0 the recast iteration is
+    phi <- g (S / sigma_a* + phi), whose fixed point is g S / (sigma_a* (1-g))."""
+    torch, B, ctx = env
+    g = 0.5
+    m = B.Model(ctx, _linear_params(g))
+    m.set_fp32(True)
+    prob, _ = _uniform_problem(torch, B, 128, 0.0, q=0.7)
+    phi = torch.zeros_like(prob.sigma_t)
+    sa_star = I.SIGMA_T_STAR - I.SIGMA_S_STAR
+    rc, st = B.no_recast_guess(ctx, m, [prob], I.SIGMA_T_STAR, I.SIGMA_S_STAR, 1e-6, 60, [phi])
+    exact = g * 0.7 / (sa_star * (1 - g))
+    got = phi.cpu().numpy()
+    log(f"  recast linear: status={rc} iters={st[0]['iterations']} "
+        f"phi={got.mean():.6f} exact={exact:.6f}")
+    assert rc == B.TR_OK and st[0]["status"] == B.TR_OK
+    assert np.allclose(got, exact, rtol=1e-4)
+    m.close()
+
+
+def test_recast_divergence_zeroes_guess(env):
+    torch, B, ctx = env
+    m = B.Model(ctx, _linear_params(2.0))
+    m.set_fp32(True)
+    prob, inst = _uniform_problem(torch, B, 64, 0.0)
+    phi = torch.full_like(prob.sigma_t, 3.0)
+    rc, st = B.no_recast_guess(ctx, m, [prob], I.SIGMA_T_STAR, I.SIGMA_S_STAR, 1e-4, 30, [phi])
+    sa_star = I.SIGMA_T_STAR - I.SIGMA_S_STAR
+    inner = RC.network_inner(lambda s: 2.0 * s, sa_star)
+    _, ost, oit, _ = RC.recast_loop(inst.source, inst.sigma_t - inst.sigma_s, sa_star, inner)
+    log(f"  recast divergent: status={rc} iters={st[0]['iterations']} oracle={ost},{oit}")
+    assert rc == B.TR_RECAST_DIVERGED and ost == RC.DIVERGED
+    assert st[0]["iterations"] == oit
+    assert float(phi.abs().max()) == 0.0
+    m.close()
+
+
+def _bilinear_up(c, f):
+    """Cell-centred bilinear interpolation with clamped edges (test copy)."""
+    n = c.shape[0]
+    pos = (np.arange(n * f) + 0.5) / f - 0.5
+    i0 = np.clip(np.floor(pos).astype(int), 0, n - 1)
+    i1 = np.clip(i0 + 1, 0, n - 1)
+    t = np.clip(pos - np.floor(pos), 0.0, 1.0)
+    t[pos < 0] = 0.0
+    rows = c[i0, :] * (1 - t)[:, None] + c[i1, :] * t[:, None]
+    return rows[:, i0] * (1 - t)[None, :] + rows[:, i1] * t[None, :]
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_recast_parity_with_oracle(env, n):
+    """Five recast updates (tol 0) with a random network in FP32 mode against
+    the oracle loop driving the oracle network; on a finer grid the inputs
+    are block-averaged and the result interpolated back."""
+    torch, B, ctx = env
+    p = _params(8)
+    m = B.Model(ctx, p)
+    m.set_fp32(True)
+    wl = I.fno_eval_set("line", count=2, n=n)
+    probs = [to_problem(i, torch) for i in wl.instances]
+    outs = [torch.zeros_like(pr.sigma_t) for pr in probs]
+    rc, st = B.no_recast_guess(ctx, m, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR, 0.0, 5, outs)
+    assert rc == B.TR_NOT_CONVERGED
+    sa_star = I.SIGMA_T_STAR - I.SIGMA_S_STAR
+    f = n // N
+    p64 = p.astype(np.float64)
+
+    def net(s):
+        out, _ = F.forward(p64, F.make_input(s[None]), LAY)
+        return out[0]
+    inner = RC.network_inner(net, sa_star)
+    for inst, o, s in zip(wl.instances, outs, st):
+        avg = lambda a: np.asarray(a, np.float32).astype(np.float64).reshape(N, f, N, f).mean(axis=(1, 3))
+        S = avg(inst.source)
+        sa = avg(np.asarray(inst.sigma_t, np.float32).astype(np.float64)
+                 - np.asarray(inst.sigma_s, np.float32).astype(np.float64))
+        phi, ost, it, _ = RC.recast_loop(S, sa, sa_star, inner, tol=0.0, max_iter=5)
+        ref = phi if f == 1 else _bilinear_up(phi, f)
+        e = rel_l2(o.cpu().numpy(), ref)
+        log(f"  recast {n}: iters={s['iterations']} rel_l2={e:.2e}")
+        assert s["iterations"] == it == 5
+        assert e < 1e-4
+    m.close()
+
+
+def test_recast_rejects_bad_grid(env):
+    torch, B, ctx = env
+    m = B.Model(ctx, _params(9))
+    prob, _ = _uniform_problem(torch, B, 96, 0.1)
+    phi = torch.zeros_like(prob.sigma_t)
+    with pytest.raises(B.MdpError):
+        B.no_recast_guess(ctx, m, [prob], 1.0, 0.8, 1e-4, 5, [phi])
+    m.close()
