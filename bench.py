@@ -5,13 +5,16 @@ Workload (default): 16 instances of 256 x 256 cells on a 10 x 10 mfp square,
 level-symmetric S16 (144 directions), two-region sigma_t in {1, 5} split by a
 seeded random line, c = 0.99, Gaussian-random-field sources, vacuum faces,
 tolerance 1e-6 on the relative L2 change.  One step = one pass of the hot
-path over the batch: the equation-recast guess from the operator network
-(when a trained network is available) followed by the source iteration to
-tolerance; without a network the step is the zero-start source iteration.
+path over the batch: the equation-recast guess from the trained operator
+network (Eq. 24 on the 64 x 64 network grid, block-averaged inputs, bilinear
+resampling back to 256 x 256), then the source iteration to tolerance started
+from that guess.  The same number of zero-start solves is timed beside it
+(--zero-only times the zero-start solve alone).
 
 Prints one JSON line: the metric (cell-angle updates/s over the whole step),
-the warm/zero wall times, the dominant kernel's roofline from HIP events
-recorded live on the library stream, and the FP64 oracle's throughput on a
+the warm/zero wall times and iteration counts, the dominant kernel's
+roofline from HIP events recorded live on the library stream, the network
+forward's matrix-core throughput, and the FP64 oracle's throughput on a
 bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -67,9 +70,15 @@ def parse():
                     help="target wall time of the oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device copy (counter calibration)")
-    ap.add_argument("--zero-only", action="store_true")
+    ap.add_argument("--zero-only", action="store_true",
+                    help="time the zero-start source iteration alone")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="cap on source iterations per solve (profiling runs)")
+    ap.add_argument("--recast-tol", type=float, default=1e-3,
+                    help="recast-loop tolerance (above the BF16 network's change floor)")
+    ap.add_argument("--recast-max", type=int, default=30)
+    ap.add_argument("--weights", default=None,
+                    help="trained network parameters (default: the packaged file)")
     return ap.parse_args()
 
 
@@ -99,6 +108,20 @@ def cpu_baseline(wl, target_s: float):
                       f"(FP64 C oracle, one thread per instance), {dt:.1f} s wall"}
 
 
+# algorithmic FLOP of one network forward per 64 x 64 sample (dense products
+# as performed: DFT products, per-mode complex mixing, pointwise layers, lift
+# and projection)
+def fno_flop_per_sample(n=64, w=32, m=12, layers=4, proj=128):
+    P = n * n
+    dft = 2 * (n * 2 * m * n + 4 * m * m * 2 * n + 2 * n * m * 4 * m + n * n * 2 * m) * w
+    mix = 2 * m * m * w * w * 8
+    point = 2 * w * P * w
+    return 2 * 3 * w * P + layers * (dft + mix + point) + 2 * proj * P * w + 2 * proj * P
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,6 +131,7 @@ def main():
     import torch
     from paper_2509_01416_amd import binding as B
     from paper_2509_01416_amd import inputs as I
+    from paper_2509_01416_amd import train as T
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     wl = I.hard_two_region(args.instances, args.n)
@@ -120,36 +144,56 @@ def main():
                        source=torch.tensor(i.source, dtype=torch.float32, device=dev),
                        lx=i.lx, ly=i.ly) for i in wl.instances]
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
-    cells = sum(i.cells for i in wl.instances)
     ctx = B.Context()
     plan = ctx.sweep_plan(probs, quad)
     log(f"[bench] sweep plan {plan}")
+    model = None if args.zero_only else B.Model(ctx, T.load_weights(args.weights))
 
     def zero_step():
         rc, st = B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)
-        return st
+        return st, None, 0.0
 
-    step = zero_step
+    def warm_step():
+        t0 = time.perf_counter()
+        rcg, sg = B.no_recast_guess(ctx, model, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR,
+                                    args.recast_tol, args.recast_max, phis)
+        tg = time.perf_counter() - t0
+        rc, st = B.tr_solve(ctx, probs, quad, phis, phis, args.tol, args.max_iter)
+        return st, sg, tg
+
+    def timed(step, k, profile):
+        if profile:
+            ctx.profile(True)
+        updates, its, rits, tg = 0, [], [], 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            st, sg, g = step()
+            its.append([s["iterations"] for s in st])
+            if sg is not None:
+                rits.append([s["iterations"] for s in sg])
+            tg += g
+            updates += sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * M
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read() if profile else None
+        if profile:
+            ctx.profile(False)
+        return dict(updates=updates, dt=dt, its=its, rits=rits, guess_s=tg, prof=prof)
+
+    step = zero_step if args.zero_only else warm_step
     for w in range(args.warmup):
-        st = step()
+        st, sg, _ = step()
         log(f"[bench] warmup {w}: iterations {[s['iterations'] for s in st][:4]}...")
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    updates = 0
-    its = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        st = step()
-        its.append([s["iterations"] for s in st])
-        updates += sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * M
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ms_step = dt * 1e3 / args.steps
-    log(f"[bench] {args.steps} steps in {dt:.3f} s; profile {prof}")
+        if not args.zero_only:
+            zero_step()
+    main_run = timed(step, args.steps, True)
+    log(f"[bench] {args.steps} steps in {main_run['dt']:.3f} s; profile {main_run['prof']}")
+    zero_run = main_run if args.zero_only else timed(zero_step, args.steps, False)
+    log(f"[bench] zero start: {args.steps} steps in {zero_run['dt']:.3f} s")
 
+    updates, dt, prof = main_run["updates"], main_run["dt"], main_run["prof"]
+    ms_step = dt * 1e3 / args.steps
     sweep_ms = prof["sweep_ms"]
     flops = updates * FLOP_PER_UPDATE
     achieved = flops / (sweep_ms * 1e-3) / 1e12 if sweep_ms > 0 else None
@@ -168,6 +212,31 @@ def main():
             "launches": prof["sweep_launches"],
             "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None}
 
+    network = None
+    if model is not None:
+        # network forward on the recast batch (64 x 64 per instance), timed
+        # with HIP events on the library stream
+        nb = len(probs)
+        xin = torch.randn(nb, 64, 64, device=dev)
+        xout = torch.empty_like(xin)
+        for _ in range(3):
+            model.forward(xin, xout)
+        s = ctx.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(s)
+        for _ in range(reps):
+            model.forward(xin, xout)
+        e1.record(s)
+        e1.synchronize()
+        fwd_ms = e0.elapsed_time(e1) / reps
+        fl = fno_flop_per_sample() * nb
+        network = {"forward_ms": fwd_ms, "batch": nb, "flop_per_sample": fno_flop_per_sample(),
+                   "achieved_TFLOPs": fl / (fwd_ms * 1e-3) / 1e12,
+                   "peak_TFLOPs": BF16_MFMA_PEAK_TFLOPS,
+                   "frac": fl / (fwd_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+                   "dtype": "bf16 operands, fp32 accumulate"}
+
     if args.calib_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         a.fill_(1.0)
@@ -181,6 +250,8 @@ def main():
         cpu = cpu_baseline(wl, args.cpu_seconds)
         log(f"[bench] cpu {cpu}")
 
+    zero_ms = zero_run["dt"] * 1e3 / args.steps
+    mean = lambda rows: float(np.mean(rows[-1])) if rows else None
     out = {
         "metric": "cell-angle updates/s; wall time to 1e-6 residual, NO warm start vs zero start",
         "value": updates / dt,
@@ -190,14 +261,28 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "instances": len(wl.instances),
                    "grid": f"{args.n}x{args.n}", "directions": M,
-                   "tol": args.tol, "start": "zero",
+                   "tol": args.tol,
+                   "start": "zero" if args.zero_only else "operator-network recast warm start",
+                   "recast_tol": None if args.zero_only else args.recast_tol,
+                   "recast_max_iter": None if args.zero_only else args.recast_max,
                    "sweep_plan": plan},
-        "iterations": its[-1],
-        "zero_start_ms": ms_step,
+        "warm_vs_zero": {
+            "warm_ms": None if args.zero_only else ms_step,
+            "zero_ms": zero_ms,
+            "time_reduction": None if args.zero_only else 1.0 - ms_step / zero_ms,
+            "recast_ms": None if args.zero_only else main_run["guess_s"] * 1e3 / args.steps,
+            "recast_iterations_mean": mean(main_run["rits"]),
+            "si_iterations_mean_warm": None if args.zero_only else mean(main_run["its"]),
+            "si_iterations_mean_zero": mean(zero_run["its"]),
+            "zero_start_updates_per_s": zero_run["updates"] / zero_run["dt"]},
+        "iterations": main_run["its"][-1],
         "roofline": roof,
+        "network": network,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if model is not None:
+        model.close()
     ctx.close()
 
 
