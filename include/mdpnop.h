@@ -206,6 +206,14 @@ tr_status tr_check_args(int32_t n_inst, const tr_problem *p,
 tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
                               int32_t R);
 
+/* Sweep kernel selection on this context: generic = 0 (default) uses the
+ * specialised 2-D kernel whenever every problem of a call has 64-row lane
+ * segments and only vacuum faces (the generic kernel otherwise);
+ * generic = 1 always uses the generic kernel.  Both perform the same
+ * floating-point operations in the same order, so for one launch shape
+ * their results agree bit for bit.                                        */
+tr_status tr_set_sweep_kernel(tr_context *ctx, int32_t generic);
+
 /* Kernel timing for benchmarks: with enable != 0, tr_solve records HIP
  * events on the context stream around every sweep launch and around every
  * combine+finalize pair (totals reset by each call of this function).    */
@@ -214,12 +222,12 @@ tr_status tr_profile_enable(tr_context *ctx, int32_t enable);
 tr_status tr_profile_read(tr_context *ctx, double *out4);
 
 /* The launch shape the next tr_solve / tr_sweep on these problems would
- * use: out5 = {D, W, S of problem 0, R of problem 0, KB}.  ctx may be NULL
- * (host-only: default limits, automatic choices); field pointers are not
- * read.                                                                    */
+ * use: out6 = {D, W, S of problem 0, R of problem 0, KB, specialised
+ * kernel (1) or generic (0)}.  ctx may be NULL (host-only: default limits,
+ * automatic choices); field pointers are not read.                        */
 tr_status tr_get_sweep_plan(tr_context *ctx, int32_t n_inst,
                             const tr_problem *p, const tr_quadrature *q,
-                            int32_t *out5);
+                            int32_t *out6);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,8 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
            "no_train_step",
-           "tr_check_args", "tr_set_sweep_config", "tr_get_sweep_plan",
+           "tr_check_args", "tr_set_sweep_config", "tr_set_sweep_kernel",
+           "tr_get_sweep_plan",
            "tr_profile_enable", "tr_profile_read")
 
 
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.tr_check_args.argtypes = [i32, P(TrProblem), P(TrQuadrature), d, i32,
                                   ctypes.c_char_p, i32]
     lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
+    lib.tr_set_sweep_kernel.argtypes = [vp, i32]
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
     lib.tr_profile_enable.argtypes = [vp, i32]
     lib.tr_profile_read.argtypes = [vp, P(d)]
@@ -224,6 +226,9 @@ class Context:
     def set_sweep_config(self, D=0, W=0, S=0, R=0):
         self.check(self.lib.tr_set_sweep_config(self.handle, D, W, S, R), allow=(TR_OK,))
 
+    def set_sweep_kernel(self, generic: bool):
+        self.check(self.lib.tr_set_sweep_kernel(self.handle, int(generic)), allow=(TR_OK,))
+
     def profile(self, enable: bool = True):
         self.check(self.lib.tr_profile_enable(self.handle, int(enable)), allow=(TR_OK,))
 
@@ -276,11 +281,11 @@ def sweep_plan(problems_struct, n: int, quad: Quad, handle=None) -> dict:
     """Launch shape of the 2-D sweep for prepared problems (host-only when
     handle is None)."""
     lib = load()
-    out = (ctypes.c_int32 * 5)()
+    out = (ctypes.c_int32 * 6)()
     rc = lib.tr_get_sweep_plan(handle, n, problems_struct, ctypes.byref(quad.struct), out)
     if rc != TR_OK:
         raise MdpError(rc, "tr_get_sweep_plan failed")
-    return dict(D=out[0], W=out[1], S=out[2], R=out[3], KB=out[4])
+    return dict(D=out[0], W=out[1], S=out[2], R=out[3], KB=out[4], specialised=out[5])
 
 
 # ---------------------------------------------------------------- network

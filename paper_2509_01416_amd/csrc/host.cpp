@@ -23,6 +23,10 @@ bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
                     const SweepWork* work, const DirTable* dt, const int* done,
                     const int* iter, int use_faces, hipStream_t s);
 size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx);
+bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
+                         const InstDesc* insts, const SweepWork* work, const DirTable* dt,
+                         const int* done, const int* iter, hipStream_t s);
+size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx);
 int sweep2d_max_kb(int W, int R);
 int sweep2d_max_w(int D);
 void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
@@ -392,9 +396,32 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
         Rmax = std::max(Rmax, pl.R[i]);
         nxmax = std::max(nxmax, p[i].nx);
     }
-    pl.KB = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax));
-    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax) > c->lds_limit)
-        pl.KB /= 2;
+    // the specialised kernel: 64-row segments everywhere, vacuum faces only,
+    // and nx >= 63 + KB (lane 0's ring column is then always written in an
+    // earlier block)
+    bool fast = !c->force_generic;
+    int nxmin = 1 << 30;
+    for (int i = 0; i < n_inst; ++i) {
+        fast = fast && pl.R[i] == 64;
+        for (int f = 0; f < 4; ++f) fast = fast && p[i].bc[f] == TR_BC_VACUUM;
+        nxmin = std::min(nxmin, p[i].nx);
+    }
+    const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax));
+    if (fast) {
+        int kb = kb0;
+        while (kb > 2 && (nxmin < 63 + kb || sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) > c->lds_limit))
+            kb /= 2;
+        if (kb >= 2 && nxmin >= 63 + kb &&
+            sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) <= c->lds_limit) {
+            pl.fast = true;
+            pl.KB = kb;
+            pl.lds = sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax);
+            return pl;
+        }
+    }
+    pl.fast = false;
+    pl.KB = kb0;
+    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax) > c->lds_limit) pl.KB /= 2;
     pl.KB = std::max(pl.KB, 2);
     pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax);
     return pl;
@@ -587,9 +614,15 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
         bool refl = false;
         for (const InstDesc& d : su.inst)
             for (int f = 0; f < 4; ++f) refl |= d.bc[f] == TR_BC_REFLECTIVE;
-        if (!launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
-                            su.plan.W, su.plan.KB, su.plan.lds, su.d_inst,
-                            su.d_work, su.d_dt, done, iter, use_faces, stream)) {
+        const bool ok =
+            su.plan.fast
+                ? launch_sweep2d_fast(su.plan.D, (int)su.work.size(), su.plan.W, su.plan.KB,
+                                      su.plan.lds, su.d_inst, su.d_work, su.d_dt, done, iter,
+                                      stream)
+                : launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
+                                 su.plan.W, su.plan.KB, su.plan.lds, su.d_inst, su.d_work,
+                                 su.d_dt, done, iter, use_faces, stream);
+        if (!ok) {
             fail("unsupported directions-per-lane D=%d", su.plan.D);
             return false;
         }
@@ -809,13 +842,24 @@ extern "C" tr_status tr_set_sweep_config(tr_context* ctx, int32_t D, int32_t W,
     return TR_OK;
 }
 
+extern "C" tr_status tr_set_sweep_kernel(tr_context* ctx, int32_t generic) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    if (generic != 0 && generic != 1) {
+        c->fail("generic must be 0 or 1");
+        return TR_ERR_INVALID_ARG;
+    }
+    c->force_generic = generic != 0;
+    return TR_OK;
+}
+
 // Sweep launch plan the next call would use (for logs and the tuner).
 extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
                                        const tr_problem* p, const tr_quadrature* q,
-                                       int32_t* out4) {
+                                       int32_t* out6) {
     Ctx tmp;
     Ctx* c = ctx ? reinterpret_cast<Ctx*>(ctx) : &tmp;
-    if (!out4) return TR_ERR_INVALID_ARG;
+    if (!out6) return TR_ERR_INVALID_ARG;
     if (!check_problems(c, n_inst, p, false)) return TR_ERR_INVALID_ARG;
     DirTable* dt = new DirTable();
     if (!build_dirtable(c, q, p[0].dim, dt)) {
@@ -824,11 +868,12 @@ extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
     }
     Plan pl = make_plan(c, n_inst, p, *dt);
     delete dt;
-    out4[0] = pl.D;
-    out4[1] = pl.W;
-    out4[2] = pl.S.empty() ? 0 : pl.S[0];
-    out4[3] = pl.R.empty() ? 0 : pl.R[0];
-    out4[4] = pl.KB;
+    out6[0] = pl.D;
+    out6[1] = pl.W;
+    out6[2] = pl.S.empty() ? 0 : pl.S[0];
+    out6[3] = pl.R.empty() ? 0 : pl.R[0];
+    out6[4] = pl.KB;
+    out6[5] = p[0].dim == 2 && pl.fast ? 1 : 0;
     return TR_OK;
 }
 

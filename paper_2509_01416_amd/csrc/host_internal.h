@@ -28,6 +28,7 @@ struct PinnedBuf {
 // workgroup, per-instance rows per segment R and slices S, LDS block KB.
 struct Plan {
     int D = 1, W = 1, KB = 16;
+    bool fast = false;   // specialised kernel (R = 64 everywhere, vacuum faces)
     size_t lds = 0;
     std::vector<int> R, S;
 };
@@ -58,6 +59,7 @@ struct Ctx {
     Arena arena;          // per-call solver workspace
     PinnedBuf pinned;     // staging and flag read-back
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
+    bool force_generic = false;   // never use the specialised sweep kernel
     size_t lds_limit = 64 * 1024;   // per-workgroup LDS (device property)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces

@@ -344,6 +344,290 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Specialisation for the common shape: every instance of the launch has
+// 64-row segments (R = 64: a wave is one segment), 64 | ny, nx >= 63 + KB,
+// and only vacuum inflow faces.  Lane l works on u = t - l = k*nx + ip, so
+// with lane 0 at column ip0 the lane that starts a row on step t is the one
+// with (l - ip0) mod nx == 0, and the y flux lane 0 needs on step t was
+// produced by lane 63 on step t - (nx - 63), at least KB + 1 steps (so in an
+// earlier block) before.  That makes every per-step LDS address an immediate
+// offset from a per-block base and leaves no scalar bookkeeping in the step:
+//   * lane 0 reads its y inflow from a ring of nx + KB entries (the first KB
+//     mirrored at the end, so a block never wraps) and receives it as the
+//     "old" operand of the lane shift (a lane with no source keeps it);
+//   * every lane writes its y outflow to its own [lane][step] slot; after
+//     the block, lane 63's slots are copied into the ring;
+//   * a lane captures the x outflow of its finished row when it restarts
+//     (restart step e = (l - ip0) mod nx precomputed per block), and the 64
+//     rows of a block are stored together after the block in which lane 63
+//     restarted (lane 0 restarts only nx - 63 > KB steps later);
+//   * the loads of step tt + 1 are issued before the arithmetic of step tt.
+// The arithmetic and the reduction order are those of the generic kernel.
+template <int D, int KB>
+__global__ void __launch_bounds__(SweepBounds<D>::threads)
+sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
+                    const SweepWork* __restrict__ work,
+                    const DirTable* __restrict__ dt, const int* __restrict__ done,
+                    const int* __restrict__ iter) {
+    extern __shared__ float smem[];
+    constexpr int lkb = KB >= 16 ? 4 : (KB >= 8 ? 3 : (KB >= 4 ? 2 : (KB >= 2 ? 1 : 0)));
+    static_assert((1 << lkb) == KB, "KB must be a power of two <= 16");
+    constexpr int R = 64, lr = 6, PST = KB + 1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int W = blockDim.x >> 6;
+    const int nthreads = blockDim.x;
+    const SweepWork wk = work[blockIdx.x];
+    const int n = wk.inst;
+    if (n < 0) return;
+    if (done != nullptr && done[n]) return;
+    const InstDesc& I = insts[n];
+    const int o = wk.oct;
+    const bool xpos = (o == 0 || o == 3), ypos = (o == 0 || o == 1);
+    const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
+    const int par = (iter != nullptr ? iter[n] : 0) & 1;
+    const size_t fstride = (size_t)4 * nf * M;
+    gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(par ^ 1) * fstride);
+    const int fxout = xpos ? 1 : 0, fyout = ypos ? 3 : 2;
+
+    float a[D], b[D], c[D], w[D];
+    int mi[D];
+    const int nd = dt->count[o];
+    const int base = wk.slice * (W * D) + wv * D;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int kk = base + d;
+        if (kk < nd) {
+            const int m = dt->list[o][kk];
+            a[d] = 2.0f * dt->amu[m] * I.inv_dx;
+            b[d] = 2.0f * dt->aeta[m] * I.inv_dy;
+            w[d] = dt->w[m];
+            mi[d] = m;
+        } else {
+            a[d] = 0.f; b[d] = 0.f; w[d] = 0.f; mi[d] = -1;
+        }
+        c[d] = a[d] + b[d];
+    }
+
+    // LDS: pbuf[2][W*64][KB+1] | sbuf[2][2][KB][65] | ring[W][D][nx+KB]
+    //      | yob[W*64][D][KB+1]
+    const int RS = nx + KB;
+    float* pbuf = smem;
+    float* sbuf = smem + 2 * W * 64 * PST;
+    float* ringw = sbuf + 4 * KB * 65 + (size_t)(wv * D) * RS;
+    float* yobw = sbuf + 4 * KB * 65 + (size_t)W * D * RS + (size_t)(wv * 64) * D * PST;
+    float* yol = yobw + lane * D * PST;   // this lane's y-outflow slots
+    const int nblk = ny >> lr;
+    const int T = nblk * nx + R - 1;
+    cgfloat* __restrict__ St = (cgfloat*)I.st;
+    cgfloat* __restrict__ Qb = (cgfloat*)I.Q;
+    gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
+
+    const int nstage = 2 * KB * R;
+    const int npf = (nstage + nthreads - 1) / nthreads;
+    float pf[kMaxPrefetch];
+    bool pv[kMaxPrefetch];
+    Cursor sc[kMaxPrefetch];
+#pragma unroll
+    for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+        const int e = tid + jx * nthreads;
+        sc[jx].ip = (e & (KB - 1)) - ((e >> lkb) & (R - 1));
+        sc[jx].kk = 0;
+        sc[jx].advance(0, nx);
+    }
+    auto stage_load = [&]() {
+        int cells[kMaxPrefetch];
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            const int rr = (e >> lkb) & (R - 1);
+            const int cell = cursor_cell(sc[jx], rr, R, nx, ny, nblk, xpos, ypos);
+            pv[jx] = cell >= 0 && e < nstage;
+            cells[jx] = pv[jx] ? cell : 0;
+            sc[jx].advance(KB, nx);
+        }
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            cgfloat* src = (e >> (lkb + lr)) == 0 ? St : Qb;
+            pf[jx] = src[cells[jx]];
+        }
+    };
+    auto stage_store = [&](int h) {
+#pragma unroll
+        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+            if (jx >= npf) break;
+            const int e = tid + jx * nthreads;
+            if (e < nstage) {
+                const int f = e >> (lkb + lr);
+                const int rr = (e >> lkb) & (R - 1);
+                const int t2 = e & (KB - 1);
+                const float def = f == 0 ? 1.f : 0.f;
+                sbuf[((h * 2 + f) * KB + t2) * 65 + rr] = pv[jx] ? pf[jx] : def;
+            }
+        }
+    };
+    const int nout = KB * R;
+    const int nredu = (nout + nthreads - 1) / nthreads;
+    Cursor rc_[kMaxRed];
+#pragma unroll
+    for (int jx = 0; jx < kMaxRed; ++jx) {
+        const int e = tid + jx * nthreads;
+        rc_[jx].ip = (e & (KB - 1)) - (e >> lkb);
+        rc_[jx].kk = 0;
+        rc_[jx].advance(0, nx);
+    }
+
+    // vacuum y inflow: the ring (with its mirror) starts at zero
+    for (int e = lane; e < D * RS; e += 64) ringw[e] = 0.f;
+    stage_load();
+    stage_store(0);
+    __syncthreads();
+
+    float xin[D], yo[D], xs[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) { xin[d] = 0.f; yo[d] = 0.f; xs[d] = 0.f; }
+    const bool top = lane == R - 1;
+    auto flush_x = [&](int kb) {
+        const int jp = kb * R + lane;
+        const int j = ypos ? jp : ny - 1 - jp;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (mi[d] >= 0) fcur[((size_t)fxout * nf + j) * M + mi[d]] = xs[d];
+    };
+    int kflush = 0;
+
+    // one step: e = this lane's restart step in the block; ring/sp/pw/yol
+    // are the per-block bases; (st, q, rv) were loaded on the previous step
+    auto math = [&](int tt, int e, float st, float q, const float* rv, float* pw) {
+        float yi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            yi[d] = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                __builtin_bit_cast(int, rv[d]), __builtin_bit_cast(int, yo[d]),
+                0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+        const bool rs = e == tt;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            xs[d] = rs ? xin[d] : xs[d];
+            xin[d] = rs ? 0.f : xin[d];
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float rcp = __builtin_amdgcn_rcpf(st + c[d]);
+            const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rcp;
+            xin[d] = fmaf(psi, 2.0f, -xin[d]);
+            yo[d] = fmaf(psi, 2.0f, -yi[d]);
+            acc = fmaf(w[d], psi, acc);
+        }
+        pw[tt] = acc;
+#pragma unroll
+        for (int d = 0; d < D; ++d) yol[d * PST + tt] = yo[d];
+    };
+
+    for (int t0 = 0, blkno = 0; t0 < T; t0 += KB, ++blkno) {
+        const int half = blkno & 1;
+        const int tend = min(KB, T - t0);
+        const bool more = t0 + KB < T;
+        const int ip0b = t0 % nx;                 // lane 0's column at tt = 0
+        int e = lane - ip0b;
+        if (e < 0) e += nx;                        // restart step of this lane
+        const float* sp = sbuf + half * 2 * KB * 65 + lane;
+        float* pw = pbuf + ((size_t)(half * W + wv) * 64 + lane) * PST;
+        const float* rg = ringw + ip0b;            // ring column of step tt: rg[d*RS + tt]
+        if (tend == KB) {
+            float st = sp[0], q = sp[KB * 65], rv[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) rv[d] = rg[d * RS];
+#pragma unroll
+            for (int tt = 0; tt < KB; ++tt) {
+                if (tt == 0 && more) stage_load();
+                float stn = 0.f, qn = 0.f, rvn[D];
+                if (tt + 1 < KB) {
+                    stn = sp[(tt + 1) * 65];
+                    qn = sp[(KB + tt + 1) * 65];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) rvn[d] = rg[d * RS + tt + 1];
+                }
+                math(tt, e, st, q, rv, pw);
+                if (tt == KB - 1 && more) stage_store(half ^ 1);
+                st = stn;
+                q = qn;
+#pragma unroll
+                for (int d = 0; d < D; ++d) rv[d] = rvn[d];
+            }
+        } else {
+            for (int tt = 0; tt < tend; ++tt) {
+                float rv[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) rv[d] = rg[d * RS + tt];
+                math(tt, e, sp[tt * 65], sp[(KB + tt) * 65], rv, pw);
+            }
+        }
+        // lane 63's y outflow of this block into the ring (and its mirror)
+        {
+            const int j = lane;
+            const int tj = t0 + j;
+            if (j < tend && tj >= R - 1) {
+                int col = ip0b + j - (R - 1);
+                while (col < 0) col += nx;
+                if (col >= nx) col -= nx;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const float v = yobw[(size_t)(R - 1) * D * PST + d * PST + j];
+                    ringw[d * RS + col] = v;
+                    if (col < KB) ringw[d * RS + nx + col] = v;
+                }
+            }
+        }
+        // lane 63 restarted in this block: the x outflow of the previous row
+        // block is complete (lane 0 restarts nx - 63 > KB steps later)
+        {
+            int e63 = (R - 1) - ip0b;
+            if (e63 < 0) e63 += nx;
+            if (e63 < tend && t0 + e63 >= nx) flush_x(kflush++);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jx = 0; jx < kMaxRed; ++jx) {
+            if (jx >= nredu) break;
+            const int e2 = tid + jx * nthreads;
+            if (e2 < nout) {
+                const int rr = e2 >> lkb;
+                const int t2 = e2 & (KB - 1);
+                const int cell = cursor_cell(rc_[jx], rr, R, nx, ny, nblk, xpos, ypos);
+                if (t2 < tend && cell >= 0) {
+                    const float* pb = pbuf + ((size_t)half * W * 64 + rr) * PST + t2;
+                    float s = 0.f;
+                    for (int v = 0; v < W; ++v) s += pb[(size_t)v * 64 * PST];
+                    part[cell] = s;
+                }
+                rc_[jx].advance(KB, nx);
+            }
+        }
+    }
+    // lane 63 never restarts after its last row: capture, then store the
+    // x outflow of the last row block
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs[d] = top ? xin[d] : xs[d];
+    flush_x(nblk - 1);
+    // the ring holds the grid's outgoing y face of every column
+    for (int e = lane; e < D * nx; e += 64) {
+        const int d = e / nx, ipc = e - d * nx;
+        const int i = xpos ? ipc : nx - 1 - ipc;
+        int m = -1;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd)
+            if (dd == d) m = mi[dd];
+        if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ringw[d * RS + ipc];
+    }
+}
+
 // Host launcher; returns false for an unsupported (D, KB).
 template <int D, int KB>
 static void launch_dk(bool refl, dim3 grid, dim3 block, size_t lds,
@@ -370,6 +654,39 @@ static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
         case 2: launch_dk<D, 2>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
         default: return false;
     }
+}
+
+template <int D>
+static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
+                          const int* done, const int* iter) {
+    switch (KB) {
+        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        default: return false;
+    }
+}
+
+bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
+                         const InstDesc* insts, const SweepWork* work, const DirTable* dt,
+                         const int* done, const int* iter, hipStream_t s) {
+    dim3 grid(nwork), block(64 * W);
+    switch (D) {
+        case 1: return launch_fast_d<1>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 2: return launch_fast_d<2>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 3: return launch_fast_d<3>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 4: return launch_fast_d<4>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 6: return launch_fast_d<6>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 9: return launch_fast_d<9>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        default: return false;
+    }
+}
+
+size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx) {
+    return sizeof(float) * ((size_t)2 * W * 64 * (KB + 1) + (size_t)4 * KB * 65 +
+                            (size_t)W * D * (max_nx + KB) + (size_t)W * 64 * D * (KB + 1));
 }
 
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,

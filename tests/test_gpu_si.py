@@ -181,6 +181,52 @@ def test_determinism_and_batch_equals_single(env):
         assert np.array_equal(x, z)
 
 
+@pytest.mark.parametrize("shapes,n,cfg", [
+    ([(66, 64)], 8, (0, 0, 0, 64)),
+    ([(256, 128), (96, 192)], 16, (0, 0, 0, 64)),
+    ([(100, 64), (65, 128)], 8, (2, 3, 0, 64)),
+    ([(128, 64)], 16, (3, 4, 0, 64)),
+    ([(96, 64)], 4, (1, 1, 0, 64)),
+    ([(80, 128), (79, 192)], 8, (1, 2, 0, 64)),
+])
+def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
+    """The specialised sweep (64-row segments, vacuum faces, nx >= 63 + KB)
+    performs the generic kernel's operations in the same order: sweeps and
+    whole solves agree bit for bit, for several launch shapes, block sizes
+    (KB from 2 to 16) and ragged widths."""
+    torch, B, ctx = env
+    quad = I.level_symmetric_2d(n)
+    insts = [I.random_instance(nx, ny, seed=700 + nx + ny) for nx, ny in shapes]
+    probs = [to_problem(i, torch) for i in insts]
+    q = B.Quad.from_inputs(quad)
+    ctx.set_sweep_config(*cfg)
+    try:
+        plan = ctx.sweep_plan(probs, q)
+        assert plan["specialised"] == 1 and plan["R"] == 64
+        rng = np.random.Generator(np.random.PCG64(5))
+        em = [torch.tensor(rng.uniform(0, 2, (i.ny, i.nx)).astype(np.float32), device="cuda")
+              for i in insts]
+        outs = {}
+        for generic in (False, True):
+            ctx.set_sweep_kernel(generic)
+            o = [torch.zeros_like(e) for e in em]
+            B.tr_sweep(ctx, probs, q, em, o)
+            phis = [torch.zeros_like(e) for e in em]
+            _, st = B.tr_solve(ctx, probs, q, None, phis, 1e-6, 2000)
+            outs[generic] = ([x.cpu().numpy() for x in o], [x.cpu().numpy() for x in phis],
+                             [s["iterations"] for s in st])
+        log(f"  specialised vs generic {shapes} S{n} cfg {cfg}: plan {plan}, "
+            f"iterations {outs[False][2]}")
+        for a, b in zip(outs[False][0], outs[True][0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(outs[False][1], outs[True][1]):
+            assert np.array_equal(a, b)
+        assert outs[False][2] == outs[True][2]
+    finally:
+        ctx.set_sweep_kernel(False)
+        ctx.set_sweep_config(0, 0, 0, 0)
+
+
 def test_not_converged_and_errors(env):
     torch, B, ctx = env
     log("[tr_solve] status codes")
