@@ -425,17 +425,29 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     cgfloat* __restrict__ Qb = (cgfloat*)I.Q;
     gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
 
+    // Cell of (step, row) pairs by position u = k*nx + ip (ip < 0 before
+    // the row's first cell), advanced by KB per block without division
+    // (KB < nx, so ip wraps at most once): i = i0 + isg*ip,
+    // j = jr + jsg*64*k with jr the row's j in block 0.
+    const int isg = xpos ? 1 : -1, i0 = xpos ? 0 : nx - 1;
+    const int jsg = ypos ? 1 : -1, j0 = ypos ? 0 : ny - 1;
+    const int jstep = jsg * R;
+    auto pos_cell = [&](int ip, int k, int jr, bool& ok) {
+        ok = ip >= 0 && k < nblk;
+        return ok ? (jr + jstep * k) * nx + (i0 + isg * ip) : 0;
+    };
     const int nstage = 2 * KB * R;
     const int npf = (nstage + nthreads - 1) / nthreads;
     float pf[kMaxPrefetch];
     bool pv[kMaxPrefetch];
-    Cursor sc[kMaxPrefetch];
+    int sip[kMaxPrefetch], sk[kMaxPrefetch], sjr[kMaxPrefetch];
 #pragma unroll
     for (int jx = 0; jx < kMaxPrefetch; ++jx) {
         const int e = tid + jx * nthreads;
-        sc[jx].ip = (e & (KB - 1)) - ((e >> lkb) & (R - 1));
-        sc[jx].kk = 0;
-        sc[jx].advance(0, nx);
+        const int rr = (e >> lkb) & (R - 1);
+        sip[jx] = (e & (KB - 1)) - rr;
+        sk[jx] = 0;
+        sjr[jx] = j0 + jsg * rr;
     }
     auto stage_load = [&]() {
         int cells[kMaxPrefetch];
@@ -443,11 +455,12 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         for (int jx = 0; jx < kMaxPrefetch; ++jx) {
             if (jx >= npf) break;
             const int e = tid + jx * nthreads;
-            const int rr = (e >> lkb) & (R - 1);
-            const int cell = cursor_cell(sc[jx], rr, R, nx, ny, nblk, xpos, ypos);
-            pv[jx] = cell >= 0 && e < nstage;
+            bool ok;
+            const int cell = pos_cell(sip[jx], sk[jx], sjr[jx], ok);
+            pv[jx] = ok && e < nstage;
             cells[jx] = pv[jx] ? cell : 0;
-            sc[jx].advance(KB, nx);
+            sip[jx] += KB;
+            if (sip[jx] >= nx) { sip[jx] -= nx; ++sk[jx]; }
         }
 #pragma unroll
         for (int jx = 0; jx < kMaxPrefetch; ++jx) {
@@ -473,13 +486,14 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     };
     const int nout = KB * R;
     const int nredu = (nout + nthreads - 1) / nthreads;
-    Cursor rc_[kMaxRed];
+    int rip[kMaxRed], rk[kMaxRed], rjr[kMaxRed];
 #pragma unroll
     for (int jx = 0; jx < kMaxRed; ++jx) {
         const int e = tid + jx * nthreads;
-        rc_[jx].ip = (e & (KB - 1)) - (e >> lkb);
-        rc_[jx].kk = 0;
-        rc_[jx].advance(0, nx);
+        const int rr = (e >> lkb) & (R - 1);
+        rip[jx] = (e & (KB - 1)) - rr;
+        rk[jx] = 0;
+        rjr[jx] = j0 + jsg * rr;
     }
 
     // vacuum y inflow: the ring (with its mirror) starts at zero
@@ -600,14 +614,17 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             if (e2 < nout) {
                 const int rr = e2 >> lkb;
                 const int t2 = e2 & (KB - 1);
-                const int cell = cursor_cell(rc_[jx], rr, R, nx, ny, nblk, xpos, ypos);
-                if (t2 < tend && cell >= 0) {
+                bool ok;
+                const int cell = pos_cell(rip[jx], rk[jx], rjr[jx], ok);
+                if (t2 < tend && ok) {
                     const float* pb = pbuf + ((size_t)half * W * 64 + rr) * PST + t2;
                     float s = 0.f;
+#pragma unroll 4
                     for (int v = 0; v < W; ++v) s += pb[(size_t)v * 64 * PST];
                     part[cell] = s;
                 }
-                rc_[jx].advance(KB, nx);
+                rip[jx] += KB;
+                if (rip[jx] >= nx) { rip[jx] -= nx; ++rk[jx]; }
             }
         }
     }
