@@ -44,12 +44,12 @@ FLOP_PER_UPDATE = 12
 # algorithmic HBM bytes per cell per source iteration: read sigma_t, sigma_s,
 # q, phi_old; write phi_new (FP32)
 BYTES_PER_CELL_ITER = 20
-# HBM bytes per sweep launch on the default workload from rocprofv3
-# FETCH_SIZE / WRITE_SIZE, scaled by a 256 MiB copy (profiles/
-# sweep2d_two_region_16x256_S16.md); valid only for the kernel source with
-# this hash prefix, otherwise reported as null
-SWEEP_TRAFFIC_BYTES = 85.11e6
-SWEEP_TRAFFIC_SRC = "b6062be1dee197c0"
+# HBM bytes per sweep launch on the default workload (all 16 instances
+# active) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what the counters
+# read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
+# valid only for the kernel source with this hash prefix, otherwise null
+SWEEP_TRAFFIC_BYTES = 85.04e6
+SWEEP_TRAFFIC_SRC = "9bfcd9c78cdaed7f"
 
 
 def log(msg):
@@ -207,7 +207,7 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None,
             "traffic": traffic, "traffic_unit": "bytes per launch",
-            "kernel": "sweep2d_kernel",
+            "kernel": "sweep2d_fast_kernel" if plan.get("specialised") else "sweep2d_kernel",
             "avg_launch_ms": sweep_ms / max(1, prof["sweep_launches"]),
             "launches": prof["sweep_launches"],
             "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None}
