@@ -25,6 +25,10 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
     return (unsigned short)(u >> 16);
 }
 
+__device__ __forceinline__ float gelu_dev(float z) {
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
 __device__ __forceinline__ long long vidx(int i, int ls, long long hi, long long lo) {
     return ls >= 31 ? (long long)i * lo
                     : (long long)(i >> ls) * hi + (long long)(i & ((1 << ls) - 1)) * lo;
@@ -43,6 +47,13 @@ __device__ __forceinline__ long long voff(const View& v, int g, int r, int c) {
 // check the kernels against the FP64 oracle without BF16 rounding) uses
 // v_mfma_f32_16x16x4f32.  With ksplit > 1, grid.z = G * ksplit and each
 // slice writes its partial tile to `partial` [ksplit][G][M][N].
+//
+// Staging: each thread stages 8 elements of A and 8 of B per K-stage.  The
+// thread-to-element map walks the operand's unit-stride axis with
+// consecutive threads (coalesced), and one view offset is computed per
+// stage; the other 7 elements follow at a constant stride (a split index
+// never breaks inside a 64-row tile or a 32-wide K stage, since splits are
+// at multiples of 64).
 constexpr int kTile = 64, kTK = 32, kPad = 36;   // LDS row = 32 + 4 pad
 
 template <bool F32>
@@ -57,6 +68,18 @@ gemm_kernel(GemmArgs a) {
     const int kchunk = ((a.K + a.ksplit - 1) / a.ksplit + kTK - 1) / kTK * kTK;
     const int kbeg = kz * kchunk, kend = min(a.K, kbeg + kchunk);
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    // A map: k-fast (unit stride along K): m = (tid >> 5) + 8 j, k = tid & 31;
+    //        m-fast: m = tid & 63, k = (tid >> 6) + 4 j.
+    const bool a_kfast = a.A.sc_lo == 1 && a.A.c_ls >= 5;
+    const int am = a_kfast ? (tid >> 5) : (tid & 63);
+    const int ak = a_kfast ? (tid & 31) : (tid >> 6);
+    const long long astep = a_kfast ? 8 * a.A.sr_lo : 4 * a.A.sc_lo;
+    // B map: n-fast: k = (tid >> 6) + 4 j, n = tid & 63;
+    //        k-fast: k = tid & 31, n = (tid >> 5) + 8 j.
+    const bool b_nfast = a.B.sc_lo == 1 && a.B.c_ls >= 6;
+    const int bk = b_nfast ? (tid >> 6) : (tid & 31);
+    const int bn = b_nfast ? (tid & 63) : (tid >> 5);
+    const long long bstep = b_nfast ? 4 * a.B.sr_lo : 8 * a.B.sc_lo;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -64,21 +87,29 @@ gemm_kernel(GemmArgs a) {
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+        {
+            const int kk = k0 + ak;
+            const float* pa = a.A.p + voff(a.A, g, m0 + am, kk);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int e = tid + 256 * j;
-            const int r = e >> 5, k = e & 31;          // A: row-major tile
-            float va = 0.f;
-            if (m0 + r < a.M && k0 + k < kend) va = a.A.p[voff(a.A, g, m0 + r, k0 + k)];
-            const int kb = e >> 6, n = e & 63;         // B: k-major tile
-            float vb = 0.f;
-            if (n0 + n < a.N && k0 + kb < kend) vb = a.B.p[voff(a.B, g, k0 + kb, n0 + n)];
-            if constexpr (F32) {
-                As[r * kPad + k] = va;
-                Bs[n * kPad + kb] = vb;
-            } else {
-                As[r * kPad + k] = to_bf16(va);
-                Bs[n * kPad + kb] = to_bf16(vb);
+            for (int j = 0; j < 8; ++j) {
+                const int m = a_kfast ? am + 8 * j : am;
+                const int k = a_kfast ? ak : ak + 4 * j;
+                float va = 0.f;
+                if (m0 + m < a.M && k0 + k < kend) va = pa[j * astep];
+                if constexpr (F32) As[m * kPad + k] = va;
+                else As[m * kPad + k] = to_bf16(va);
+            }
+        }
+        {
+            const float* pb = a.B.p + voff(a.B, g, k0 + bk, n0 + bn);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = b_nfast ? bk + 4 * j : bk;
+                const int n = b_nfast ? bn : bn + 8 * j;
+                float vb = 0.f;
+                if (n0 + n < a.N && k0 + k < kend) vb = pb[j * bstep];
+                if constexpr (F32) Bs[n * kPad + k] = vb;
+                else Bs[n * kPad + k] = to_bf16(vb);
             }
         }
         __syncthreads();
@@ -130,12 +161,13 @@ gemm_kernel(GemmArgs a) {
                 if (a.ksplit > 1) {
                     a.partial[(((long long)kz * a.G + g) * a.M + m) * a.N + n] = v;
                 } else {
-                    float* pc = a.C.p + voff(a.C, g, m, n);
+                    const long long oc = voff(a.C, g, m, n);
                     float r = a.alpha * v;
-                    if (a.accumulate) r += *pc;
+                    if (a.accumulate) r += a.C.p[oc];
                     if (a.bias_row) r += a.bias_row[m];
                     if (a.bias_col) r += a.bias_col[n];
-                    *pc = r;
+                    a.C.p[oc] = r;
+                    if (a.gelu_out) a.gelu_out[oc] = gelu_dev(r);
                 }
             }
 }
@@ -156,6 +188,7 @@ __global__ void gemm_reduce_kernel(GemmArgs a) {
         if (a.bias_row) r += a.bias_row[m];
         if (a.bias_col) r += a.bias_col[n];
         *pc = r;
+        if (a.gelu_out) a.gelu_out[pc - a.C.p] = gelu_dev(r);
     }
 }
 
@@ -375,6 +408,89 @@ __global__ void row_reduce_kernel(const float* __restrict__ x, const float* __re
     if (threadIdx.x == 0) out[r] = (accumulate ? out[r] : 0.f) + red[0];
 }
 
+// Two-stage row reductions with a fixed order.  Stage 1: block (r, chunk)
+// sums 1024 consecutive cells of sample chunk/nsub of row r (threads stride
+// the cells, then a tree) into part[r * nchunk + chunk]; stage 2 sums a
+// row's chunks in chunk order.  Term: x (mode 0), x w (1), gelu(x) w (2).
+constexpr int kRedCells = 1024;
+
+__global__ void __launch_bounds__(256)
+row_reduce_part_kernel(const float* __restrict__ x, const float* __restrict__ w,
+                       float* __restrict__ part, int Rr, int P, int mode) {
+    const int r = blockIdx.x, ch = blockIdx.y, nch = gridDim.y;
+    const int nsub = P / kRedCells;
+    const int b = ch / nsub, p0 = (ch - b * nsub) * kRedCells;
+    const float* xb = x + ((long long)b * Rr + r) * P + p0;
+    const float* wb = w ? w + (long long)b * P + p0 : nullptr;
+    float s = 0.f;
+    for (int p = threadIdx.x; p < kRedCells; p += blockDim.x) {
+        float t = xb[p];
+        if (mode == 2) t = gelu_f(t);
+        if (mode >= 1) t *= wb[p];
+        s += t;
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)r * nch + ch] = red[0];
+}
+
+__global__ void row_reduce_fin_kernel(const float* __restrict__ part, float* __restrict__ out,
+                                      int Rr, int nch, int accumulate) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Rr) return;
+    float s = 0.f;
+    for (int c = 0; c < nch; ++c) s += part[(long long)r * nch + c];
+    out[r] = (accumulate ? out[r] : 0.f) + s;
+}
+
+// Lift backward in two stages: block (c, chunk) forms the four sums
+// (input, x, y, 1) x gv0 over 1024 cells; stage 2 sums chunks in order.
+__global__ void __launch_bounds__(256)
+lift_back_part_kernel(const float* __restrict__ in, const float* __restrict__ gv,
+                      float* __restrict__ part, int n, int C) {
+    const int c = blockIdx.x, ch = blockIdx.y, nch = gridDim.y;
+    const int P = n * n, nsub = P / kRedCells;
+    const int b = ch / nsub, p0 = (ch - b * nsub) * kRedCells;
+    const float* g = gv + ((long long)b * C + c) * P;
+    const float* a = in + (long long)b * P;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    for (int p = p0 + threadIdx.x; p < p0 + kRedCells; p += blockDim.x) {
+        const float x = ((p % n) + 0.5f) / n, y = ((p / n) + 0.5f) / n;
+        s0 = fmaf(a[p], g[p], s0);
+        s1 = fmaf(x, g[p], s1);
+        s2 = fmaf(y, g[p], s2);
+        s3 += g[p];
+    }
+    __shared__ float red[4][256];
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = s2;
+    red[3][threadIdx.x] = s3;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[((long long)threadIdx.x * C + c) * nch + ch] = red[threadIdx.x][0];
+}
+
+__global__ void lift_back_fin_kernel(const float* __restrict__ part, float* __restrict__ gW0,
+                                     float* __restrict__ gb0, int C, int nch) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // q * C + c
+    if (e >= 4 * C) return;
+    const int q = e / C, c = e - q * C;
+    float s = 0.f;
+    for (int k = 0; k < nch; ++k) s += part[(long long)e * nch + k];
+    if (q < 3) gW0[q * C + c] = s;
+    else gb0[c] = s;
+}
+
 // Lift backward: gW0[j][c] = sum_{b,p} a_j gv0[b][c][p] (a_0 = input,
 // a_1 = x, a_2 = y); gb0[c] = sum gv0.  One block per channel c.
 __global__ void lift_back_kernel(const float* __restrict__ in, const float* __restrict__ gv,
@@ -565,6 +681,248 @@ __global__ void scale_kernel(float* __restrict__ x, float s, long long n) {
         x[e] *= s;
 }
 
+// ---------------------------------------------------- per-mode mixing v2 --
+// One workgroup per retained mode (kyi, kx): that mode's weights
+// R[i][o] (32 x 32 complex, contiguous in the parameter vector) and the
+// batch's mode values are staged in LDS; the batch is processed in chunks of
+// kMixChunk samples.  Layouts as in mix_kernel.
+constexpr int kMixChunk = 64;
+
+__global__ void __launch_bounds__(256)
+mix_mode_kernel(const float* __restrict__ X, const float* __restrict__ R,
+                float* __restrict__ Y, int B, int C, int m) {
+    extern __shared__ float sm[];
+    float* Rs = sm;                         // [C][C][2]
+    float* Xs = sm + 2 * C * C;             // [chunk][C][2]
+    const int md = blockIdx.x;              // kyi * m + kx
+    const int kyi = md / m, kx = md - kyi * m;
+    const int blk = kyi / m, ky = kyi - blk * m;
+    const int per = 4 * m * m, plane = 2 * m * m;
+    const float* w = R + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
+    for (int e = threadIdx.x; e < 2 * C * C; e += blockDim.x) Rs[e] = w[e];
+    for (int b0 = 0; b0 < B; b0 += kMixChunk) {
+        const int nb = min(kMixChunk, B - b0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += blockDim.x) {
+            const float* xb = X + ((long long)(b0 * C) + e) * per;
+            Xs[2 * e] = xb[md];
+            Xs[2 * e + 1] = xb[plane + md];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += blockDim.x) {
+            const int b = e / C, o = e - b * C;
+            const float* xr = Xs + 2 * b * C;
+            float yr = 0.f, yi = 0.f;
+            for (int i = 0; i < C; ++i) {
+                const float xre = xr[2 * i], xim = xr[2 * i + 1];
+                const float wr = Rs[(i * C + o) * 2], wi = Rs[(i * C + o) * 2 + 1];
+                yr = fmaf(xre, wr, fmaf(-xim, wi, yr));
+                yi = fmaf(xre, wi, fmaf(xim, wr, yi));
+            }
+            float* yb = Y + ((long long)(b0 * C) + e) * per;
+            yb[md] = yr;
+            yb[plane + md] = yi;
+        }
+    }
+}
+
+// gX[b][i] = sum_o gY[b][o] conj(R[i][o])
+__global__ void __launch_bounds__(256)
+mix_mode_back_x_kernel(const float* __restrict__ gY, const float* __restrict__ R,
+                       float* __restrict__ gX, int B, int C, int m) {
+    extern __shared__ float sm[];
+    float* Rs = sm;
+    float* Gs = sm + 2 * C * C;
+    const int md = blockIdx.x;
+    const int kyi = md / m, kx = md - kyi * m;
+    const int blk = kyi / m, ky = kyi - blk * m;
+    const int per = 4 * m * m, plane = 2 * m * m;
+    const float* w = R + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
+    // transposed, Rs[o][i], so that threads with consecutive i read
+    // consecutive LDS words
+    for (int e = threadIdx.x; e < C * C; e += blockDim.x) {
+        const int i = e / C, o = e - i * C;
+        Rs[(o * C + i) * 2] = w[2 * e];
+        Rs[(o * C + i) * 2 + 1] = w[2 * e + 1];
+    }
+    for (int b0 = 0; b0 < B; b0 += kMixChunk) {
+        const int nb = min(kMixChunk, B - b0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += blockDim.x) {
+            const float* gb = gY + ((long long)(b0 * C) + e) * per;
+            Gs[2 * e] = gb[md];
+            Gs[2 * e + 1] = gb[plane + md];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += blockDim.x) {
+            const int b = e / C, i = e - b * C;
+            const float* gr = Gs + 2 * b * C;
+            float xr = 0.f, xi = 0.f;
+            for (int o = 0; o < C; ++o) {
+                const float yr = gr[2 * o], yi = gr[2 * o + 1];
+                const float wr = Rs[(o * C + i) * 2], wi = Rs[(o * C + i) * 2 + 1];
+                xr = fmaf(yr, wr, fmaf(yi, wi, xr));
+                xi = fmaf(yi, wr, fmaf(-yr, wi, xi));
+            }
+            float* xb = gX + ((long long)(b0 * C) + e) * per;
+            xb[md] = xr;
+            xb[plane + md] = xi;
+        }
+    }
+}
+
+// gR[i][o] = sum_b conj(X[b][i]) gY[b][o], batch order fixed
+__global__ void __launch_bounds__(256)
+mix_mode_back_w_kernel(const float* __restrict__ X, const float* __restrict__ gY,
+                       float* __restrict__ gR, int B, int C, int m) {
+    extern __shared__ float sm[];
+    float* Xs = sm;                         // [chunk][C][2]
+    float* Gs = sm + 2 * kMixChunk * C;     // [chunk][C][2]
+    const int md = blockIdx.x;
+    const int kyi = md / m, kx = md - kyi * m;
+    const int blk = kyi / m, ky = kyi - blk * m;
+    const int per = 4 * m * m, plane = 2 * m * m;
+    float accr[4] = {0.f, 0.f, 0.f, 0.f}, acci[4] = {0.f, 0.f, 0.f, 0.f};
+    const int nout = C * C;
+    for (int b0 = 0; b0 < B; b0 += kMixChunk) {
+        const int nb = min(kMixChunk, B - b0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += blockDim.x) {
+            const long long src = ((long long)(b0 * C) + e) * per;
+            Xs[2 * e] = X[src + md];
+            Xs[2 * e + 1] = X[src + plane + md];
+            Gs[2 * e] = gY[src + md];
+            Gs[2 * e + 1] = gY[src + plane + md];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e >= nout) break;
+            const int i = e / C, o = e - i * C;
+            float gr = accr[q], gi = acci[q];
+            for (int b = 0; b < nb; ++b) {
+                const float xr = Xs[2 * (b * C + i)], xi = Xs[2 * (b * C + i) + 1];
+                const float yr = Gs[2 * (b * C + o)], yi = Gs[2 * (b * C + o) + 1];
+                gr = fmaf(xr, yr, fmaf(xi, yi, gr));
+                gi = fmaf(xr, yi, fmaf(-xi, yr, gi));
+            }
+            accr[q] = gr;
+            acci[q] = gi;
+        }
+    }
+    float* w = gR + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + q * blockDim.x;
+        if (e >= nout) break;
+        w[2 * e] = accr[q];
+        w[2 * e + 1] = acci[q];
+    }
+}
+
+// ------------------------------------------------- fused projection head --
+// out[b][p] = c2 + sum_k P2[k] gelu(h[b][k][p]),  h = P1^T v + c1 (K = 128
+// hidden units, C = 32 input channels).  One workgroup per (64-pixel tile,
+// sample): wave w computes hidden units 32w..32w+31 for the 64 pixels with
+// 2 x 4 MFMA tiles, applies c1, GELU and P2, reduces its 32 rows, and the
+// four waves' sums are added in wave order.  h is also stored when h_out is
+// given (training needs it).
+template <bool F32>
+__global__ void __launch_bounds__(256)
+proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
+                  const float* __restrict__ c1, const float* __restrict__ P2,
+                  const float* __restrict__ c2, float* __restrict__ out,
+                  float* __restrict__ h_out, int P) {
+    typedef typename std::conditional<F32, float, unsigned short>::type T;
+    constexpr int C = 32, K = 128, NT = 64;
+    __shared__ __attribute__((aligned(16))) T Ws[K * (C + 4)];    // P1^T [k][c]
+    __shared__ __attribute__((aligned(16))) T Vs[NT * (C + 4)];   // [pixel][c]
+    __shared__ float part[4][NT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int p0 = blockIdx.x * NT, b = blockIdx.y;
+    const float* vb = v + (long long)b * C * P;
+    for (int e = tid; e < K * C; e += 256) {          // P1[c][k] -> Ws[k][c]
+        const int c = e / K, k = e - c * K;
+        if constexpr (F32) Ws[k * (C + 4) + c] = P1[e];
+        else Ws[k * (C + 4) + c] = to_bf16(P1[e]);
+    }
+    for (int e = tid; e < C * NT; e += 256) {         // v[c][p] -> Vs[p][c]
+        const int c = e / NT, pp = e - c * NT;
+        const float x = p0 + pp < P ? vb[(long long)c * P + p0 + pp] : 0.f;
+        if constexpr (F32) Vs[pp * (C + 4) + c] = x;
+        else Vs[pp * (C + 4) + c] = to_bf16(x);
+    }
+    __syncthreads();
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int km = wv * 32;
+    if constexpr (F32) {
+#pragma unroll
+        for (int kk = 0; kk < C; kk += 4) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float af = Ws[(km + 16 * i + (lane & 15)) * (C + 4) + kk + (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float bf = Vs[(16 * j + (lane & 15)) * (C + 4) + kk + (lane >> 4)];
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < C; kk += 16) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x4 af = *reinterpret_cast<const bf16x4*>(
+                    Ws + (km + 16 * i + (lane & 15)) * (C + 4) + kk + 4 * (lane >> 4));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bf16x4 bf = *reinterpret_cast<const bf16x4*>(
+                        Vs + (16 * j + (lane & 15)) * (C + 4) + kk + 4 * (lane >> 4));
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane holds rows km + 16i + 4(lane>>4) + q, column 16j + (lane & 15)
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = km + 16 * i + 4 * (lane >> 4) + q;
+            const float ck = c1[k], pk = P2[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float hv = acc[i][j][q] + ck;
+                const int pp = 16 * j + (lane & 15);
+                if (h_out && p0 + pp < P) h_out[((long long)b * K + k) * P + p0 + pp] = hv;
+                s[j] = fmaf(pk, gelu_dev(hv), s[j]);
+            }
+        }
+    // reduce over the four row groups of the wave (lanes l, l+16, l+32, l+48)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float t = s[j];
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        s[j] = t;
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[wv][16 * j + lane] = s[j];
+    __syncthreads();
+    if (tid < NT && p0 + tid < P) {
+        const float r = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+        out[(long long)b * P + p0 + tid] = r + c2[0];
+    }
+}
+
 // ------------------------------------------------------------- launchers --
 static int blocks_for(long long n) {
     return (int)std::max<long long>(1, std::min<long long>(8192, (n + 255) / 256));
@@ -582,18 +940,31 @@ void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, h
     hipLaunchKernelGGL(gelu_back_kernel, dim3(blocks_for(n)), dim3(256), 0, s, z, gv, gz, n);
 }
 void launch_mix(const float* X, const float* R, float* Y, int B, int C, int m, hipStream_t s) {
-    const long long t = (long long)B * C * 2 * m * m;
-    hipLaunchKernelGGL(mix_kernel, dim3(blocks_for(t)), dim3(256), 0, s, X, R, Y, B, C, m);
+    const size_t lds = sizeof(float) * (2 * C * C + 2 * kMixChunk * C);
+    hipLaunchKernelGGL(mix_mode_kernel, dim3(2 * m * m), dim3(256), lds, s, X, R, Y, B, C, m);
 }
 void launch_mix_back_x(const float* gY, const float* R, float* gX, int B, int C, int m,
                        hipStream_t s) {
-    const long long t = (long long)B * C * 2 * m * m;
-    hipLaunchKernelGGL(mix_back_x_kernel, dim3(blocks_for(t)), dim3(256), 0, s, gY, R, gX, B, C, m);
+    const size_t lds = sizeof(float) * (2 * C * C + 2 * kMixChunk * C);
+    hipLaunchKernelGGL(mix_mode_back_x_kernel, dim3(2 * m * m), dim3(256), lds, s, gY, R, gX,
+                       B, C, m);
 }
 void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C, int m,
                        hipStream_t s) {
-    const long long t = (long long)2 * m * m * C * C;
-    hipLaunchKernelGGL(mix_back_w_kernel, dim3(blocks_for(t)), dim3(256), 0, s, X, gY, gR, B, C, m);
+    const size_t lds = sizeof(float) * (4 * kMixChunk * C);
+    hipLaunchKernelGGL(mix_mode_back_w_kernel, dim3(2 * m * m), dim3(256), lds, s, X, gY, gR,
+                       B, C, m);
+}
+void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
+                       const float* c2, float* out, float* h_out, int B, int P, int f32,
+                       hipStream_t s) {
+    dim3 grid((P + 63) / 64, B);
+    if (f32)
+        hipLaunchKernelGGL(proj_fused_kernel<true>, grid, dim3(256), 0, s, v, P1, c1, P2, c2,
+                           out, h_out, P);
+    else
+        hipLaunchKernelGGL(proj_fused_kernel<false>, grid, dim3(256), 0, s, v, P1, c1, P2, c2,
+                           out, h_out, P);
 }
 void launch_proj_out(const float* h, const float* P2, const float* c2, float* out, int B,
                      int P, int K, hipStream_t s) {
@@ -606,13 +977,30 @@ void launch_proj_back(const float* h, const float* P2, const float* gout, float*
                        s, h, P2, gout, gh, B, P, K);
 }
 void launch_row_reduce(const float* x, const float* w, float* out, int B, int R, int P,
-                       int mode, int accumulate, hipStream_t s) {
-    hipLaunchKernelGGL(row_reduce_kernel, dim3(R), dim3(256), 0, s, x, w, out, B, R, P, mode,
-                       accumulate);
+                       int mode, int accumulate, float* scratch, hipStream_t s) {
+    if (scratch == nullptr || P % kRedCells != 0) {
+        hipLaunchKernelGGL(row_reduce_kernel, dim3(R), dim3(256), 0, s, x, w, out, B, R, P,
+                           mode, accumulate);
+        return;
+    }
+    const int nch = B * (P / kRedCells);
+    hipLaunchKernelGGL(row_reduce_part_kernel, dim3(R, nch), dim3(256), 0, s, x, w, scratch, R,
+                       P, mode);
+    hipLaunchKernelGGL(row_reduce_fin_kernel, dim3((R + 127) / 128), dim3(128), 0, s, scratch,
+                       out, R, nch, accumulate);
 }
 void launch_lift_back(const float* in, const float* gv, float* gW0, float* gb0, int B, int n,
-                      int C, hipStream_t s) {
-    hipLaunchKernelGGL(lift_back_kernel, dim3(C), dim3(256), 0, s, in, gv, gW0, gb0, B, n, C);
+                      int C, float* scratch, hipStream_t s) {
+    if (scratch == nullptr || (n * n) % kRedCells != 0) {
+        hipLaunchKernelGGL(lift_back_kernel, dim3(C), dim3(256), 0, s, in, gv, gW0, gb0, B, n,
+                           C);
+        return;
+    }
+    const int nch = B * (n * n / kRedCells);
+    hipLaunchKernelGGL(lift_back_part_kernel, dim3(C, nch), dim3(256), 0, s, in, gv, scratch, n,
+                       C);
+    hipLaunchKernelGGL(lift_back_fin_kernel, dim3((4 * C + 127) / 128), dim3(128), 0, s,
+                       scratch, gW0, gb0, C, nch);
 }
 int launch_mse(const float* out, const float* t, float* gout, double* partial, long long n,
                hipStream_t s) {

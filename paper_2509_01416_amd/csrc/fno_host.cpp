@@ -71,11 +71,11 @@ struct Ws {
     std::vector<float*> v, z, X;   // layer inputs, pre-activations, kept modes
     float *h = nullptr, *T = nullptr, *Y = nullptr, *gX = nullptr;
     float *gv = nullptr, *gv2 = nullptr, *gz = nullptr, *gh = nullptr;
-    float *out = nullptr, *gout = nullptr, *partial = nullptr;
+    float *out = nullptr, *gout = nullptr, *partial = nullptr, *rpart = nullptr;
     double* mse = nullptr;
 };
 
-constexpr int kMaxKsplit = 128;
+constexpr int kMaxKsplit = 1024;
 constexpr int kMsePartials = 256;
 
 size_t carve(const no_model* m, int B, bool train, char* base, Ws* w) {
@@ -98,10 +98,11 @@ size_t carve(const no_model* m, int B, bool train, char* base, Ws* w) {
         w->z[l] = (float*)take(4 * act);
         w->X[l] = (float*)take(4 * modes);
     }
-    w->h = (float*)take(4 * (size_t)B * kProj * kP);
     w->T = (float*)take(4 * tbuf);
     w->Y = (float*)take(4 * modes);
+    w->h = nullptr;
     if (train) {
+        w->h = (float*)take(4 * (size_t)B * kProj * kP);
         w->gX = (float*)take(4 * modes);
         w->gv = (float*)take(4 * act);
         w->gv2 = (float*)take(4 * act);
@@ -110,6 +111,7 @@ size_t carve(const no_model* m, int B, bool train, char* base, Ws* w) {
         w->out = (float*)take(4 * (size_t)B * kP);
         w->gout = (float*)take(4 * (size_t)B * kP);
         w->partial = (float*)take(4 * (size_t)kMaxKsplit * C * kProj);
+        w->rpart = (float*)take(4 * (size_t)4 * kProj * B * (kP / 1024));
         w->mse = (double*)take(8 * kMsePartials);
     }
     return off;
@@ -171,7 +173,8 @@ struct Runner {
     bool ok = true;
 
     bool gemm(int M, int N, int K, int G, View A, View B, View C, int acc = 0,
-              const float* bias_row = nullptr, float* partial = nullptr) {
+              const float* bias_row = nullptr, float* partial = nullptr,
+              float* gelu_out = nullptr) {
         GemmArgs a;
         a.M = M;
         a.N = N;
@@ -182,9 +185,10 @@ struct Runner {
         a.C = C;
         a.accumulate = acc;
         a.bias_row = bias_row;
+        a.gelu_out = gelu_out;
         a.f32 = m->f32;
         if (partial && G == 1) {
-            a.ksplit = std::max(1, std::min(kMaxKsplit, K / 2048));
+            a.ksplit = std::max(1, std::min(kMaxKsplit, K / 256));
             a.partial = partial;
         }
         if (!launch_gemm(a, c->stream)) {
@@ -196,7 +200,7 @@ struct Runner {
 
     // Forward of `B` fields in[b] ([B][P]) -> out ([B][P]); activations kept
     // in w for a following backward.
-    void forward(const float* in, float* out, Ws& w) {
+    void forward(const float* in, float* out, Ws& w, bool keep_h = false) {
         const int C = m->width, L = m->layers, mm = m->modes, B = w.B;
         const float* P = m->params;
         const int G = B * C;
@@ -213,14 +217,15 @@ struct Runner {
                  tsplit(w.T, mm, tb));
             gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->Gx, kGrid, 1),
                  mat(w.z[l], kGrid, 1, kP));
+            // pointwise path, bias and (but after the last layer) GELU
             gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
-                 mat(w.z[l], kP, 1, act), 1, P + m->ob[l]);
-            if (l + 1 < L) launch_gelu(w.z[l], w.v[l + 1], (long long)B * act, c->stream);
+                 mat(w.z[l], kP, 1, act), 1, P + m->ob[l], nullptr,
+                 l + 1 < L ? w.v[l + 1] : nullptr);
         }
         const float* vL = w.z[L - 1];
-        gemm(kProj, kP, C, B, mat(P + m->oP1, 1, kProj), mat(vL, kP, 1, act),
-             mat(w.h, kP, 1, (long long)kProj * kP), 0, P + m->oc1);
-        launch_proj_out(w.h, P + m->oP2, P + m->oc2, out, B, kP, kProj, c->stream);
+        // projection head; h is kept only when a backward pass follows
+        launch_proj_fused(vL, P + m->oP1, P + m->oc1, P + m->oP2, P + m->oc2, out,
+                          keep_h ? w.h : nullptr, B, kP, m->f32, c->stream);
     }
 
     // Gradient of sum(gout * out) into m->grad (every entry written).
@@ -232,12 +237,12 @@ struct Runner {
         const long long act = (long long)C * kP;
         const long long per = 4LL * mm * mm, tb = (long long)kGrid * 2 * mm;
         const float* vL = w.z[L - 1];
-        launch_row_reduce(w.h, gout, g + m->oP2, B, kProj, kP, 2, 0, c->stream);
-        launch_row_reduce(gout, nullptr, g + m->oc2, B, 1, kP, 0, 0, c->stream);
+        launch_row_reduce(w.h, gout, g + m->oP2, B, kProj, kP, 2, 0, w.rpart, c->stream);
+        launch_row_reduce(gout, nullptr, g + m->oc2, B, 1, kP, 0, 0, w.rpart, c->stream);
         launch_proj_back(w.h, P + m->oP2, gout, w.gh, B, kP, kProj, c->stream);
         gemm(C, kProj, B * kP, 1, kcols(vL, C), krows(w.gh, kProj), mat(g + m->oP1, kProj, 1),
              0, nullptr, w.partial);
-        launch_row_reduce(w.gh, nullptr, g + m->oc1, B, kProj, kP, 0, 0, c->stream);
+        launch_row_reduce(w.gh, nullptr, g + m->oc1, B, kProj, kP, 0, 0, w.rpart, c->stream);
         gemm(C, kP, kProj, B, mat(P + m->oP1, kProj, 1), mat(w.gh, kP, 1, (long long)kProj * kP),
              mat(w.gv, kP, 1, act));
         float* gv = w.gv;
@@ -250,7 +255,7 @@ struct Runner {
             }
             gemm(C, C, B * kP, 1, kcols(w.v[l], C), krows(gz, C), mat(g + m->oW[l], C, 1), 0,
                  nullptr, w.partial);
-            launch_row_reduce(gz, nullptr, g + m->ob[l], B, C, kP, 0, 0, c->stream);
+            launch_row_reduce(gz, nullptr, g + m->ob[l], B, C, kP, 0, 0, w.rpart, c->stream);
             gemm(C, kP, C, B, mat(P + m->oW[l], C, 1), mat(gz, kP, 1, act), mat(gv2, kP, 1, act));
             // spectral path, adjoint of the forward products
             gemm(kGrid, 2 * mm, kGrid, G, mat(gz, kGrid, 1, kP), mat(m->Gx, 1, kGrid),
@@ -265,7 +270,7 @@ struct Runner {
                  mat(gv2, kGrid, 1, kP), 1);
             std::swap(gv, gv2);
         }
-        launch_lift_back(in, gv, g + m->oW0, g + m->ob0, B, kGrid, C, c->stream);
+        launch_lift_back(in, gv, g + m->oW0, g + m->ob0, B, kGrid, C, w.rpart, c->stream);
     }
 };
 
@@ -504,7 +509,7 @@ extern "C" tr_status no_train_step(tr_context* ctx, no_model* m, int32_t batch,
     if (!workspace(c, m, batch, true, &w)) return ws_status(c);
     if (!c->fno->host.reserve(c, sizeof(double) * kMsePartials)) return ws_status(c);
     Runner r{c, m};
-    r.forward(input, w.out, w);
+    r.forward(input, w.out, w, true);
     const long long n = (long long)batch * kP;
     const int nb = launch_mse(w.out, target, w.gout, w.mse, n, c->stream);
     r.backward(input, w.gout, w);

@@ -31,6 +31,7 @@ struct GemmArgs {
     int ksplit = 1;
     float* partial = nullptr;          // [ksplit][G][M][N] when ksplit > 1
     int f32 = 0;                       // FP32 operands instead of BF16
+    float* gelu_out = nullptr;         // also write gelu(C) at C's offsets
 };
 
 bool launch_gemm(const GemmArgs& a, hipStream_t s);
@@ -43,14 +44,20 @@ void launch_mix_back_x(const float* gY, const float* R, float* gX, int B, int C,
                        hipStream_t s);
 void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C, int m,
                        hipStream_t s);
+// Projection head in one kernel (width 32, 128 hidden units only).
+void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
+                       const float* c2, float* out, float* h_out, int B, int P, int f32,
+                       hipStream_t s);
 void launch_proj_out(const float* h, const float* P2, const float* c2, float* out, int B,
                      int P, int K, hipStream_t s);
 void launch_proj_back(const float* h, const float* P2, const float* gout, float* gh, int B,
                       int P, int K, hipStream_t s);
+// scratch (device, >= 4 * max(R, C) * B * P / 1024 floats) selects the
+// two-stage parallel form; nullptr the single-stage one.
 void launch_row_reduce(const float* x, const float* w, float* out, int B, int R, int P,
-                       int mode, int accumulate, hipStream_t s);
+                       int mode, int accumulate, float* scratch, hipStream_t s);
 void launch_lift_back(const float* in, const float* gv, float* gW0, float* gb0, int B, int n,
-                      int C, hipStream_t s);
+                      int C, float* scratch, hipStream_t s);
 int launch_mse(const float* out, const float* t, float* gout, double* partial, long long n,
                hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,

@@ -3,12 +3,14 @@ against the FP64 oracle, through the C ABI.
 
 Tolerances:
   * FP32 operands (no_model_set_fp32): each product is an FP32 dot product
-    of length <= 128 (rounding <= ~K eps32 relative to the operand norms) and
-    the network stacks about 20 of them, so the relative L2 error is a few
-    1e-6; the bar is 1e-4 for the output and 1e-3 per gradient block;
-  * BF16 operands: every operand carries a relative rounding of 2^-9, so
-    the output deviates by about 1e-2 relative; the bar is 5e-2 relative L2
-    for the output and cosine similarity > 0.99 per gradient block.
+    of length <= 128 (relative rounding <= ~K eps32 = 8e-6 worst case, about
+    sqrt(K) eps32 = 7e-7 typical) and the network stacks about 20 of them;
+    the bar is 1e-5 relative L2 for the output and for every gradient block
+    (observed: 1.4e-7 output, <= 5e-7 gradients);
+  * BF16 operands: every operand carries a relative rounding of 2^-9 =
+    2e-3, so outputs and gradients deviate by ~1e-3; the bar is 1e-2
+    relative L2 for the output, 2e-2 relative L2 and cosine > 0.999 per
+    gradient block (observed: 1.0e-3 output, cosine >= 0.99999).
 """
 import numpy as np
 import pytest
@@ -72,7 +74,7 @@ def test_bad_shape_rejected(env):
         B.Model(ctx, None, width=64)
 
 
-@pytest.mark.parametrize("fp32,tol", [(True, 1e-4), (False, 5e-2)])
+@pytest.mark.parametrize("fp32,tol", [(True, 1e-5), (False, 1e-2)])
 def test_forward_parity(env, fp32, tol):
     torch, B, ctx = env
     p = _params(3)
@@ -104,17 +106,17 @@ def test_gradient_parity(env, fp32):
     gref, _ = F.backward(p64, cache, gout, LAY)
     le = abs(loss - ref_loss) / ref_loss
     log(f"  loss fp32={fp32}: {loss:.6e} vs {ref_loss:.6e} (rel {le:.2e})")
-    assert le < (1e-4 if fp32 else 5e-2)
+    assert le < (1e-5 if fp32 else 1e-2)
     for name, o, s in _blocks():
         a, b = g[o:o + s], gref[o:o + s]
+        e = rel_l2(a, b)
         if fp32:
-            e = rel_l2(a, b)
             log(f"  grad {name}: rel_l2={e:.2e}")
-            assert e < 1e-3, name
+            assert e < 1e-5, name
         else:
             cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
-            log(f"  grad {name}: cosine={cos:.5f}")
-            assert cos > 0.99, name
+            log(f"  grad {name}: rel_l2={e:.2e} cosine={cos:.6f}")
+            assert e < 2e-2 and cos > 0.999, name
     # lr = 0 leaves the parameters untouched
     assert np.array_equal(m.get_params(), p)
     m.close()
