@@ -145,8 +145,12 @@ def main():
                        lx=i.lx, ly=i.ly) for i in wl.instances]
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
     ctx = B.Context()
+    planned = ctx.sweep_plan(probs, quad)
+    t_tune = time.perf_counter()
+    tuned = ctx.autotune(probs, quad, reps=3)
+    t_tune = time.perf_counter() - t_tune
     plan = ctx.sweep_plan(probs, quad)
-    log(f"[bench] sweep plan {plan}")
+    log(f"[bench] planner {planned}; autotuned {tuned} in {t_tune:.2f} s")
     model = None if args.zero_only else B.Model(ctx, T.load_weights(args.weights))
 
     def zero_step():
@@ -265,7 +269,8 @@ def main():
                    "start": "zero" if args.zero_only else "operator-network recast warm start",
                    "recast_tol": None if args.zero_only else args.recast_tol,
                    "recast_max_iter": None if args.zero_only else args.recast_max,
-                   "sweep_plan": plan},
+                   "sweep_plan": plan, "planner_choice": planned,
+                   "autotune_s": t_tune},
         "warm_vs_zero": {
             "warm_ms": None if args.zero_only else ms_step,
             "zero_ms": zero_ms,

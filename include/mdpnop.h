@@ -206,6 +206,19 @@ tr_status tr_check_args(int32_t n_inst, const tr_problem *p,
 tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
                               int32_t R);
 
+/* Autotuner: times every feasible launch shape (D in 1..4 directions per
+ * lane, W waves per workgroup, slices and block size then chosen by the
+ * planner) with `reps` HIP-event-timed sweeps of these problems (their
+ * sources as emission; one untimed sweep first), and leaves the fastest
+ * forced on the context exactly as tr_set_sweep_config would (reset with
+ * tr_set_sweep_config(ctx, 0, 0, 0, 0)).  out6 (may be NULL) receives the
+ * chosen plan as tr_get_sweep_plan reports it, best_ms (may be NULL) its
+ * time per sweep.  2-D only: for 1-D problems nothing is tuned.  Allocates
+ * one temporary output array per call.                                    */
+tr_status tr_autotune(tr_context *ctx, int32_t n_inst, const tr_problem *p,
+                      const tr_quadrature *q, int32_t reps, int32_t *out6,
+                      double *best_ms);
+
 /* Sweep kernel selection on this context: generic = 0 (default) uses the
  * specialised 2-D kernel whenever every problem of a call has 64-row lane
  * segments and only vacuum faces (the generic kernel otherwise);

@@ -30,7 +30,7 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
            "no_train_step",
-           "tr_check_args", "tr_set_sweep_config", "tr_set_sweep_kernel",
+           "tr_check_args", "tr_autotune", "tr_set_sweep_config", "tr_set_sweep_kernel",
            "tr_get_sweep_plan",
            "tr_profile_enable", "tr_profile_read")
 
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_char_p, i32]
     lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
     lib.tr_set_sweep_kernel.argtypes = [vp, i32]
+    lib.tr_autotune.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), i32, P(i32), P(d)]
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
     lib.tr_profile_enable.argtypes = [vp, i32]
     lib.tr_profile_read.argtypes = [vp, P(d)]
@@ -237,6 +238,17 @@ class Context:
         self.check(self.lib.tr_profile_read(self.handle, out), allow=(TR_OK,))
         return dict(sweep_ms=out[0], sweep_launches=int(out[1]),
                     combine_ms=out[2], combine_launches=int(out[3]))
+
+    def autotune(self, problems, quad: Quad, reps: int = 3) -> dict:
+        """Time the feasible launch shapes on these problems and keep the
+        fastest on this context; returns its plan and time per sweep."""
+        out = (ctypes.c_int32 * 6)()
+        ms = ctypes.c_double()
+        self.check(self.lib.tr_autotune(self.handle, len(problems), make_problems(problems),
+                                        ctypes.byref(quad.struct), int(reps), out,
+                                        ctypes.byref(ms)), allow=(TR_OK,))
+        return dict(D=out[0], W=out[1], S=out[2], R=out[3], KB=out[4], specialised=out[5],
+                    ms=ms.value)
 
     def sweep_plan(self, problems, quad: Quad):
         return sweep_plan(make_problems(problems), len(problems), quad, self.handle)

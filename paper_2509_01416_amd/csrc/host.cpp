@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -840,6 +841,98 @@ extern "C" tr_status tr_set_sweep_config(tr_context* ctx, int32_t D, int32_t W,
     c->force_S = S;
     c->force_R = R;
     return TR_OK;
+}
+
+// Measured launch-shape choice: every candidate (D, W) plan is timed with
+// HIP events over `reps` sweeps of the caller's problems (emission = source),
+// after one untimed sweep; the fastest stays forced on the context.
+extern "C" tr_status tr_autotune(tr_context* ctx, int32_t n_inst, const tr_problem* p,
+                                 const tr_quadrature* q, int32_t reps, int32_t* out6,
+                                 double* best_ms) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!check_problems(c, n_inst, p, true)) return TR_ERR_INVALID_ARG;
+    if (reps < 1 || reps > 100) {
+        c->fail("reps must be in 1..100");
+        return TR_ERR_INVALID_ARG;
+    }
+    size_t total = 0;
+    std::vector<size_t> off(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        off[i] = total;
+        total += align_up(sizeof(float) * (size_t)p[i].nx * (p[i].dim == 1 ? 1 : p[i].ny));
+    }
+    char* buf = nullptr;
+    if (!c->hip_ok(hipMalloc(&buf, total), "hipMalloc")) return TR_ERR_OOM;
+    std::vector<float*> outs(n_inst);
+    std::vector<const float*> em(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        outs[i] = (float*)(buf + off[i]);
+        em[i] = p[i].source;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tr_status rc = TR_OK;
+    const int sD = c->force_D, sW = c->force_W, sS = c->force_S, sR = c->force_R;
+    int bestD = 0, bestW = 0;
+    double best = 1e300;
+    std::vector<std::array<int, 5>> seen;
+    if (!c->hip_ok(hipEventCreate(&e0), "event") || !c->hip_ok(hipEventCreate(&e1), "event")) {
+        rc = TR_ERR_HIP;
+    } else if (p[0].dim == 2) {
+        const int Ds[] = {1, 2, 3, 4};
+        const int Ws[] = {0, 4, 6, 8, 9, 10, 12, 16};
+        for (int D : Ds) {
+            for (int W : Ws) {
+                if (W > sweep2d_max_w(D)) continue;
+                c->force_D = D;
+                c->force_W = W;
+                c->force_S = 0;
+                c->force_R = sR;
+                Setup su;
+                if (!c->setup(n_inst, p, q, nullptr, outs.data(), em.data(), &su)) {
+                    c->err.clear();
+                    continue;   // shape not feasible (LDS)
+                }
+                const std::array<int, 5> key = {su.plan.D, su.plan.W, su.plan.S[0],
+                                                su.plan.KB, su.plan.fast ? 1 : 0};
+                if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+                seen.push_back(key);
+                if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) { rc = TR_ERR_HIP; break; }
+                (void)hipEventRecord(e0, c->stream);
+                for (int r = 0; r < reps; ++r)
+                    if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) { rc = TR_ERR_HIP; break; }
+                (void)hipEventRecord(e1, c->stream);
+                if (rc != TR_OK || !c->hip_ok(hipEventSynchronize(e1), "sync")) {
+                    rc = TR_ERR_HIP;
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    bestD = su.plan.D;
+                    bestW = su.plan.W;
+                }
+            }
+            if (rc != TR_OK) break;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(buf);
+    if (rc != TR_OK) {
+        c->force_D = sD; c->force_W = sW; c->force_S = sS; c->force_R = sR;
+        return rc;
+    }
+    if (bestD > 0) {
+        c->force_D = bestD;
+        c->force_W = bestW;
+        c->force_S = 0;
+    }
+    if (best_ms) *best_ms = best < 1e299 ? best : 0.0;
+    return out6 ? tr_get_sweep_plan(ctx, n_inst, p, q, out6) : TR_OK;
 }
 
 extern "C" tr_status tr_set_sweep_kernel(tr_context* ctx, int32_t generic) {

@@ -149,6 +149,77 @@ def test_sinusoid_128_full(env):
     assert e < 1e-5
 
 
+def test_batched_uneven_256_full(env):
+    """The 256-instance uneven batch (sides 32..128, 4x4-block sigma_t,
+    c in [0.5, 0.95], S8) in one batched solve: every instance converges with
+    particle balance < 1e-4, and sampled instances (one per side length, the
+    smallest and the largest side included) match the FP64 oracle run under
+    the same stopping rule (relative change 1e-6) within 1e-5 relative L2,
+    in the same number of iterations (+-2).  Against the oracle run to 1e-12
+    the distance is the stopping error r rho / (1 - rho) of source
+    iteration, which for the slowest instances (c near 0.95, rho near 0.95)
+    reaches ~2e-5; it is bounded here by 20 x the tolerance."""
+    import time
+    torch, B, ctx = env
+    wl = I.batched_uneven(256)
+    probs = [to_problem(i, torch) for i in wl.instances]
+    quad = B.Quad.from_inputs(wl.quad)
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    plan = ctx.sweep_plan(probs, quad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = B.tr_solve(ctx, probs, quad, None, phis, wl.tol, 5000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = np.array([s["iterations"] for s in st])
+    ups = sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * wl.quad.n_dir
+    log(f"  256 uneven: plan {plan}, iterations {its.min()}..{its.max()}, {dt*1e3:.1f} ms, "
+        f"{ups / dt:.3e} cell-angle updates/s")
+    assert rc == B.TR_OK
+    assert max(s["balance_rel"] for s in st) < 1e-4
+    picked = {}
+    for k, inst in enumerate(wl.instances):
+        picked.setdefault(inst.nx, k)
+    for n, k in sorted(picked.items()):
+        inst = wl.instances[k]
+        same = oracle.solve_instance(inst, wl.quad, tol=wl.tol)
+        tight = oracle.solve_instance(inst, wl.quad, tol=1e-12)
+        got = phis[k].cpu().numpy()
+        e = rel_l2(got, same.phi)
+        et = rel_l2(got, tight.phi)
+        log(f"  instance {k} ({n}^2): {its[k]} iterations (oracle {same.iterations}), "
+            f"rel_l2 vs oracle at 1e-6 {e:.2e}, vs oracle at 1e-12 {et:.2e}")
+        assert abs(int(its[k]) - same.iterations) <= 2
+        assert e < 1e-5
+        assert et < 20 * wl.tol
+
+
+def test_autotune_picks_a_valid_shape(env):
+    """The autotuner leaves a measured launch shape on the context; solves
+    under it agree with the planner's choice to FP32 rounding."""
+    torch, B, ctx = env
+    quad = I.level_symmetric_2d(8)
+    insts = [I.random_instance(n, n, seed=900 + n) for n in (64, 96, 128)]
+    probs = [to_problem(i, torch) for i in insts]
+    q = B.Quad.from_inputs(quad)
+    auto = ctx.sweep_plan(probs, q)
+    base = [torch.zeros_like(p.sigma_t) for p in probs]
+    B.tr_solve(ctx, probs, q, None, base, 1e-7, 3000)
+    try:
+        best = ctx.autotune(probs, q, reps=2)
+        log(f"  autotune: planner {auto} -> tuned {best}")
+        assert best["ms"] > 0.0 and best["D"] in (1, 2, 3, 4)
+        plan = ctx.sweep_plan(probs, q)
+        assert (plan["D"], plan["W"]) == (best["D"], best["W"])
+        tuned = [torch.zeros_like(p.sigma_t) for p in probs]
+        rc, _ = B.tr_solve(ctx, probs, q, None, tuned, 1e-7, 3000)
+        assert rc == B.TR_OK
+        for a, b in zip(tuned, base):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+
+
 def test_warm_start_invariance(env):
     log("[tr_solve] warm start reaches the same answer")
     quad = I.level_symmetric_2d(8)
