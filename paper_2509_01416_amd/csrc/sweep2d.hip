@@ -364,7 +364,9 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 //     restarted (lane 0 restarts only nx - 63 > KB steps later);
 //   * the loads of step tt + 1 are issued before the arithmetic of step tt.
 // The arithmetic and the reduction order are those of the generic kernel.
-template <int D, int KB>
+// WT > 0: the workgroup has exactly WT waves (the cross-wave sums are then
+// fully unrolled, all loads in flight together); WT = 0: any W.
+template <int D, int KB, int WT>
 __global__ void __launch_bounds__(SweepBounds<D>::threads)
 sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                     const SweepWork* __restrict__ work,
@@ -377,8 +379,8 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    const int W = blockDim.x >> 6;
-    const int nthreads = blockDim.x;
+    const int W = WT > 0 ? WT : (int)(blockDim.x >> 6);
+    const int nthreads = W * 64;
     const SweepWork wk = work[blockIdx.x];
     const int n = wk.inst;
     if (n < 0) return;
@@ -607,6 +609,37 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             if (e63 < tend && t0 + e63 >= nx) flush_x(kflush++);
         }
         __syncthreads();
+        if constexpr (WT > 0) {
+            // all partial loads of this thread's outputs first, then the
+            // fixed-order sums
+            constexpr int NR = (KB * R + WT * 64 - 1) / (WT * 64);
+            float vals[NR][WT];
+#pragma unroll
+            for (int jx = 0; jx < NR; ++jx) {
+                const int e2 = min(tid + jx * WT * 64, nout - 1);
+                const float* pb = pbuf + ((size_t)half * WT * 64 + (e2 >> lkb)) * PST +
+                                  (e2 & (KB - 1));
+#pragma unroll
+                for (int v = 0; v < WT; ++v) vals[jx][v] = pb[(size_t)v * 64 * PST];
+            }
+#pragma unroll
+            for (int jx = 0; jx < NR; ++jx) {
+                const int e2 = tid + jx * WT * 64;
+                if (e2 < nout) {
+                    const int t2 = e2 & (KB - 1);
+                    bool ok;
+                    const int cell = pos_cell(rip[jx], rk[jx], rjr[jx], ok);
+                    if (t2 < tend && ok) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int v = 0; v < WT; ++v) s += vals[jx][v];
+                        part[cell] = s;
+                    }
+                    rip[jx] += KB;
+                    if (rip[jx] >= nx) { rip[jx] -= nx; ++rk[jx]; }
+                }
+            }
+        } else {
 #pragma unroll
         for (int jx = 0; jx < kMaxRed; ++jx) {
             if (jx >= nredu) break;
@@ -626,6 +659,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                 rip[jx] += KB;
                 if (rip[jx] >= nx) { rip[jx] -= nx; ++rk[jx]; }
             }
+        }
         }
     }
     // lane 63 never restarts after its last row: capture, then store the
@@ -673,17 +707,32 @@ static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
     }
 }
 
+template <int D, int WT>
+static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
+                           const int* done, const int* iter) {
+    switch (KB) {
+        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        default: return false;
+    }
+}
+
+// Fixed wave counts of the common level-symmetric sets with one direction
+// per lane: S16 (36 directions per octant, 4 slices of 9) and S8 (10 per
+// octant, one slice of 10).
 template <int D>
 static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                           const int* done, const int* iter) {
-    switch (KB) {
-        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        default: return false;
-    }
+    const int W = (int)block.x / 64;
+    if (D == 1 && W == 9)
+        return launch_fast_dw<D, 9>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+    if (D == 1 && W == 10)
+        return launch_fast_dw<D, 10>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+    return launch_fast_dw<D, 0>(KB, grid, block, lds, s, insts, work, dt, done, iter);
 }
 
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
