@@ -923,6 +923,142 @@ proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
     }
 }
 
+// ------------------------------------------------ fused spectral kernels --
+// One workgroup (4 waves) per (sample, channel) of a 64 x 64 field with the
+// retained-mode window of 12 x (12 + 12) modes.  Operands are staged in LDS
+// (BF16, or FP32 for the checking mode) in the layouts the MFMA fragments
+// read: A as [m][k], B as [n][k] (k contiguous).
+//   spec_fwd:  T (64 x 24) = V (64 x 64) . FxT (64 x 24);  X (48 x 12) = Fy (48 x 128) . [T_re; T_im]
+//   spec_inv:  Z (128 x 12) = Gy (128 x 48) . Y (48 x 12); U (64 x 64) = Z' (64 x 24) . Gx (24 x 64)
+// The products accumulate in FP32 in the same k order as the batched GEMM.
+template <bool F32>
+struct Frag;
+template <>
+struct Frag<false> {
+    typedef unsigned short T;
+    static constexpr int KS = 16;   // k per MFMA
+    __device__ static T cvt(float x) { return to_bf16(x); }
+    __device__ static f32x4 mma(const T* a, const T* b, int lane, f32x4 c) {
+        const bf16x4 af = *reinterpret_cast<const bf16x4*>(a + 4 * (lane >> 4));
+        const bf16x4 bf = *reinterpret_cast<const bf16x4*>(b + 4 * (lane >> 4));
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, c, 0, 0, 0);
+    }
+};
+template <>
+struct Frag<true> {
+    typedef float T;
+    static constexpr int KS = 4;
+    __device__ static T cvt(float x) { return x; }
+    __device__ static f32x4 mma(const T* a, const T* b, int lane, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a[lane >> 4], b[lane >> 4], c, 0, 0, 0);
+    }
+};
+
+// C tile (16 x 16) at (m0, n0) of A [m][lda] . B^T [n][ldb] over k in [0, K).
+template <bool F32>
+__device__ __forceinline__ f32x4 tile_mma(const typename Frag<F32>::T* A, int lda,
+                                          const typename Frag<F32>::T* Bt, int ldb, int m0,
+                                          int n0, int K, int lane) {
+    f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+    const typename Frag<F32>::T* a = A + (m0 + (lane & 15)) * lda;
+    const typename Frag<F32>::T* b = Bt + (n0 + (lane & 15)) * ldb;
+    for (int k = 0; k < K; k += Frag<F32>::KS) c = Frag<F32>::mma(a + k, b + k, lane, c);
+    return c;
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(256)
+spec_fwd_kernel(const float* __restrict__ v, const float* __restrict__ FxT,
+                const float* __restrict__ Fy, float* __restrict__ X) {
+    typedef typename Frag<F32>::T T;
+    constexpr int n = 64, mm = 12, LV = 64 + 8, LT = 128 + 8;
+    __shared__ __attribute__((aligned(16))) T Vs[n * LV];          // [y][x]
+    __shared__ __attribute__((aligned(16))) T Fx[32 * LV];         // [j][x], j < 24 used
+    __shared__ __attribute__((aligned(16))) T Fys[48 * LT];        // [(q,kyi)][(p,y)]
+    __shared__ __attribute__((aligned(16))) T Ts[16 * LT];         // [kx][(p,y)]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long long g = blockIdx.x;
+    const float* vg = v + g * n * n;
+    for (int e = tid; e < n * n; e += 256) Vs[(e >> 6) * LV + (e & 63)] = Frag<F32>::cvt(vg[e]);
+    for (int e = tid; e < 32 * n; e += 256) {                      // FxT[x][j] -> Fx[j][x]
+        const int j = e >> 6, x = e & 63;
+        Fx[j * LV + x] = Frag<F32>::cvt(j < 2 * mm ? FxT[x * 2 * mm + j] : 0.f);
+    }
+    for (int e = tid; e < 48 * 128; e += 256) Fys[(e >> 7) * LT + (e & 127)] = Frag<F32>::cvt(Fy[e]);
+    for (int e = tid; e < 16 * LT; e += 256) Ts[e] = Frag<F32>::cvt(0.f);
+    __syncthreads();
+    // T: wave w owns rows 16w..16w+15, both 16-column tiles
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const f32x4 c = tile_mma<F32>(Vs, LV, Fx, LV, 16 * wv, 16 * t, n, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = 16 * wv + 4 * (lane >> 4) + q, j = 16 * t + (lane & 15);
+            if (j < 2 * mm) Ts[(j % mm) * LT + (j / mm) * n + y] = Frag<F32>::cvt(c[q]);
+        }
+    }
+    __syncthreads();
+    // X: waves 0..2 own rows 16w..16w+15 (48 rows), one 16-column tile
+    if (wv < 3) {
+        const f32x4 c = tile_mma<F32>(Fys, LT, Ts, LT, 16 * wv, 0, 128, lane);
+        float* xg = X + g * 48 * mm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * wv + 4 * (lane >> 4) + q, kx = lane & 15;
+            if (kx < mm) xg[r * mm + kx] = c[q];
+        }
+    }
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(256)
+spec_inv_kernel(const float* __restrict__ Y, const float* __restrict__ Gy,
+                const float* __restrict__ Gx, float* __restrict__ U) {
+    typedef typename Frag<F32>::T T;
+    constexpr int n = 64, mm = 12, LG = 48 + 8, LZ = 32 + 8;
+    __shared__ __attribute__((aligned(16))) T Gys[128 * LG];       // [(p,y)][(q,kyi)]
+    __shared__ __attribute__((aligned(16))) T Ys[16 * LG];         // [kx][(q,kyi)]
+    __shared__ __attribute__((aligned(16))) T Zs[n * LZ];          // [y][(p,kx)], 24 of 32 used
+    __shared__ __attribute__((aligned(16))) T Gxs[n * LZ];         // [x][(p,kx)]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long long g = blockIdx.x;
+    const float* yg = Y + g * 48 * mm;
+    for (int e = tid; e < 128 * 48; e += 256) Gys[(e / 48) * LG + (e % 48)] = Frag<F32>::cvt(Gy[e]);
+    for (int e = tid; e < 16 * 48; e += 256) {                     // Y[r][kx] -> Ys[kx][r]
+        const int kx = e / 48, r = e % 48;
+        Ys[kx * LG + r] = Frag<F32>::cvt(kx < mm ? yg[r * mm + kx] : 0.f);
+    }
+    for (int e = tid; e < n * 32; e += 256) {                      // Gx[(p,kx)][x] -> Gxs[x][(p,kx)]
+        const int x = e >> 5, k = e & 31;
+        Gxs[x * LZ + k] = Frag<F32>::cvt(k < 2 * mm ? Gx[k * n + x] : 0.f);
+    }
+    for (int e = tid; e < n * LZ; e += 256) Zs[e] = Frag<F32>::cvt(0.f);
+    __syncthreads();
+    // Z: wave w owns rows 32w..32w+31 (two 16-row tiles), one column tile
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int m0 = 32 * wv + 16 * t;
+        const f32x4 c = tile_mma<F32>(Gys, LG, Ys, LG, m0, 0, 48, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = m0 + 4 * (lane >> 4) + q, kx = lane & 15;   // r = p*64 + y
+            if (kx < mm) Zs[(r & 63) * LZ + (r >> 6) * mm + kx] = Frag<F32>::cvt(c[q]);
+        }
+    }
+    __syncthreads();
+    // U: wave w owns rows 16w..16w+15, four column tiles
+    float* ug = U + g * n * n;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 c = tile_mma<F32>(Zs, LZ, Gxs, LZ, 16 * wv, 16 * t, 32, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = 16 * wv + 4 * (lane >> 4) + q, x = 16 * t + (lane & 15);
+            ug[y * n + x] = c[q];
+        }
+    }
+}
+
 // ------------------------------------------------------------- launchers --
 static int blocks_for(long long n) {
     return (int)std::max<long long>(1, std::min<long long>(8192, (n + 255) / 256));
@@ -954,6 +1090,20 @@ void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C,
     const size_t lds = sizeof(float) * (4 * kMixChunk * C);
     hipLaunchKernelGGL(mix_mode_back_w_kernel, dim3(2 * m * m), dim3(256), lds, s, X, gY, gR,
                        B, C, m);
+}
+void launch_spec_fwd(const float* v, const float* FxT, const float* Fy, float* X, int G,
+                     int f32, hipStream_t s) {
+    if (f32)
+        hipLaunchKernelGGL(spec_fwd_kernel<true>, dim3(G), dim3(256), 0, s, v, FxT, Fy, X);
+    else
+        hipLaunchKernelGGL(spec_fwd_kernel<false>, dim3(G), dim3(256), 0, s, v, FxT, Fy, X);
+}
+void launch_spec_inv(const float* Y, const float* Gy, const float* Gx, float* U, int G,
+                     int f32, hipStream_t s) {
+    if (f32)
+        hipLaunchKernelGGL(spec_inv_kernel<true>, dim3(G), dim3(256), 0, s, Y, Gy, Gx, U);
+    else
+        hipLaunchKernelGGL(spec_inv_kernel<false>, dim3(G), dim3(256), 0, s, Y, Gy, Gx, U);
 }
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,

@@ -208,15 +208,21 @@ struct Runner {
         const long long per = 4LL * mm * mm, tb = (long long)kGrid * 2 * mm;
         launch_lift(in, P + m->oW0, P + m->ob0, w.v[0], B, kGrid, C, c->stream);
         for (int l = 0; l < L && ok; ++l) {
-            gemm(kGrid, 2 * mm, kGrid, G, mat(w.v[l], kGrid, 1, kP), mat(m->FxT, 2 * mm, 1),
-                 mat(w.T, 2 * mm, 1, tb));
-            gemm(4 * mm, mm, 2 * kGrid, G, mat(m->Fy, 2 * kGrid, 1), tsplit(w.T, mm, tb),
-                 mat(w.X[l], mm, 1, per));
-            launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
-            gemm(2 * kGrid, mm, 4 * mm, G, mat(m->Gy, 4 * mm, 1), mat(w.Y, mm, 1, per),
-                 tsplit(w.T, mm, tb));
-            gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->Gx, kGrid, 1),
-                 mat(w.z[l], kGrid, 1, kP));
+            if (mm == 12) {   // the supported mode window: fused DFT kernels
+                launch_spec_fwd(w.v[l], m->FxT, m->Fy, w.X[l], G, m->f32, c->stream);
+                launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
+                launch_spec_inv(w.Y, m->Gy, m->Gx, w.z[l], G, m->f32, c->stream);
+            } else {
+                gemm(kGrid, 2 * mm, kGrid, G, mat(w.v[l], kGrid, 1, kP),
+                     mat(m->FxT, 2 * mm, 1), mat(w.T, 2 * mm, 1, tb));
+                gemm(4 * mm, mm, 2 * kGrid, G, mat(m->Fy, 2 * kGrid, 1), tsplit(w.T, mm, tb),
+                     mat(w.X[l], mm, 1, per));
+                launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
+                gemm(2 * kGrid, mm, 4 * mm, G, mat(m->Gy, 4 * mm, 1), mat(w.Y, mm, 1, per),
+                     tsplit(w.T, mm, tb));
+                gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->Gx, kGrid, 1),
+                     mat(w.z[l], kGrid, 1, kP));
+            }
             // pointwise path, bias and (but after the last layer) GELU
             gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
                  mat(w.z[l], kP, 1, act), 1, P + m->ob[l], nullptr,

@@ -44,6 +44,12 @@ void launch_mix_back_x(const float* gY, const float* R, float* gX, int B, int C,
                        hipStream_t s);
 void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C, int m,
                        hipStream_t s);
+// Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
+// inverse, each in one kernel (layouts as the batched GEMM path).
+void launch_spec_fwd(const float* v, const float* FxT, const float* Fy, float* X, int G,
+                     int f32, hipStream_t s);
+void launch_spec_inv(const float* Y, const float* Gy, const float* Gx, float* U, int G,
+                     int f32, hipStream_t s);
 // Projection head in one kernel (width 32, 128 hidden units only).
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,
