@@ -49,7 +49,7 @@ BYTES_PER_CELL_ITER = 20
 # read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
 # valid only for the kernel source with this hash prefix, otherwise null
 SWEEP_TRAFFIC_BYTES = 85.04e6
-SWEEP_TRAFFIC_SRC = "9bfcd9c78cdaed7f"
+SWEEP_TRAFFIC_SRC = "6f80db543b65c7e6"
 
 
 def log(msg):
