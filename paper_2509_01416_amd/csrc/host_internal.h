@@ -60,7 +60,7 @@ struct Ctx {
     PinnedBuf pinned;     // staging and flag read-back
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
     bool force_generic = false;   // never use the specialised sweep kernel
-    size_t lds_limit = 64 * 1024;   // per-workgroup LDS (device property)
+    size_t lds_limit = 160 * 1024;  // per-workgroup LDS (gfx950; device property when known)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces
 

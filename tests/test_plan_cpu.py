@@ -1,0 +1,62 @@
+"""Host-only launch planning (tr_get_sweep_plan with no context): which
+kernel a batch gets and the constraints the plan must satisfy.  Field
+pointers are never read."""
+import pytest
+
+from paper_2509_01416_amd import binding as B
+from paper_2509_01416_amd import inputs as I
+
+
+def _probs(shapes, bc=(0, 0, 0, 0)):
+    arr = (B.TrProblem * len(shapes))()
+    for k, (nx, ny) in enumerate(shapes):
+        arr[k].dim, arr[k].nx, arr[k].ny = 2, nx, ny
+        arr[k].lx = arr[k].ly = 10.0
+        arr[k].sigma_t = arr[k].sigma_s = arr[k].source = 0x1000
+        for f in range(4):
+            arr[k].bc[f] = bc[f]
+    return arr
+
+
+def _plan(shapes, n=8, bc=(0, 0, 0, 0)):
+    q = B.Quad.from_inputs(I.level_symmetric_2d(n))
+    return B.sweep_plan(_probs(shapes, bc), len(shapes), q)
+
+
+def test_benchmark_batch_gets_the_specialised_kernel():
+    p = _plan([(256, 256)] * 16, n=16)
+    assert p["specialised"] == 1 and p["R"] == 64 and p["D"] == 1
+    # 36 directions per octant in S slices of W waves
+    assert p["W"] * p["S"] >= 36 and p["W"] * (p["S"] - 1) < 36
+    assert p["KB"] == 16
+
+
+@pytest.mark.parametrize("shapes,why", [
+    ([(64, 64)], "nx < 63 + KB"),
+    ([(256, 256), (48, 48)], "segment heights differ (48 needs R = 16)"),
+    ([(256, 200)], "64 does not divide ny"),
+])
+def test_generic_kernel_when_the_specialised_one_does_not_apply(shapes, why):
+    assert _plan(shapes)["specialised"] == 0, why
+
+
+def test_reflective_faces_use_the_generic_kernel():
+    assert _plan([(128, 128)], bc=(1, 0, 0, 0))["specialised"] == 0
+    assert _plan([(128, 128)])["specialised"] == 1
+
+
+def test_block_size_shrinks_to_fit_narrow_grids():
+    # 16 instances at S16 give W = 9 waves, which alone would allow KB = 16;
+    # the specialised kernel needs nx >= 63 + KB
+    p = _plan([(70, 64)] * 16, n=16)    # KB <= 7 -> 4
+    assert p["specialised"] == 1 and p["KB"] == 4
+    p = _plan([(66, 128)] * 16, n=16)   # KB <= 3 -> 2
+    assert p["specialised"] == 1 and p["KB"] == 2
+    p = _plan([(80, 64)] * 16, n=16)    # KB <= 17 -> 16
+    assert p["specialised"] == 1 and p["KB"] == 16
+
+
+def test_plan_rows_divide_ny():
+    for shapes in ([(96, 96)], [(48, 48)], [(100, 40)], [(33, 66)]):
+        p = _plan(shapes)
+        assert shapes[0][1] % p["R"] == 0 and p["R"] <= shapes[0][0]
