@@ -239,17 +239,15 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 __global__ void lift_kernel(const float* __restrict__ in, const float* __restrict__ W0,
                             const float* __restrict__ b0, float* __restrict__ out,
                             int B, int n, int C) {
+    // grid (ceil(n*n / 256), C, B): 32-bit index arithmetic only
     const int P = n * n;
-    const long long total = (long long)B * C * P;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int p = (int)(e % P);
-        const int c = (int)((e / P) % C);
-        const int b = (int)(e / ((long long)C * P));
-        const float x = ((p % n) + 0.5f) / n, y = ((p / n) + 0.5f) / n;
-        out[e] = fmaf(W0[c], in[(long long)b * P + p],
-                      fmaf(W0[C + c], x, fmaf(W0[2 * C + c], y, b0[c])));
-    }
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y, b = blockIdx.z;
+    if (p >= P) return;
+    const int iy = p / n, ix = p - iy * n;
+    const float x = (ix + 0.5f) / n, y = (iy + 0.5f) / n;
+    out[((size_t)b * C + c) * P + p] =
+        fmaf(W0[c], in[(size_t)b * P + p], fmaf(W0[C + c], x, fmaf(W0[2 * C + c], y, b0[c])));
 }
 
 __global__ void gelu_kernel(const float* __restrict__ z, float* __restrict__ v, long long n) {
@@ -1066,8 +1064,12 @@ static int blocks_for(long long n) {
 
 void launch_lift(const float* in, const float* W0, const float* b0, float* out, int B,
                  int n, int C, hipStream_t s) {
-    const long long t = (long long)B * C * n * n;
-    hipLaunchKernelGGL(lift_kernel, dim3(blocks_for(t)), dim3(256), 0, s, in, W0, b0, out, B, n, C);
+    for (int b0i = 0; b0i < B; b0i += 65535) {   // grid.z limit
+        const int nb = std::min(65535, B - b0i);
+        const size_t P = (size_t)n * n;
+        hipLaunchKernelGGL(lift_kernel, dim3((n * n + 255) / 256, C, nb), dim3(256), 0, s,
+                           in + b0i * P, W0, b0, out + b0i * P * C, nb, n, C);
+    }
 }
 void launch_gelu(const float* z, float* v, long long n, hipStream_t s) {
     hipLaunchKernelGGL(gelu_kernel, dim3(blocks_for(n)), dim3(256), 0, s, z, v, n);

@@ -38,6 +38,7 @@ namespace mdp {
 
 constexpr int kMaxPrefetch = 4;   // staged values per thread per block
 constexpr int kMaxRed = 2;        // reduced outputs per thread per block
+constexpr int kMaxPos = 4;        // staging/reduction positions per helper thread
 
 // Largest workgroup per directions-per-lane D, so that the register budget
 // (512 per SIMD lane / waves per SIMD) holds D directions without spills.
@@ -413,90 +414,105 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         c[d] = a[d] + b[d];
     }
 
-    // LDS: pbuf[2][W*64][KB+1] | sbuf[2][2][KB][65] | ring[W][D][nx+KB]
+    // LDS: pbuf[2][W*64][KB+1] | sbuf[2][KB][65 float2] | ring[W][D][nx+KB]
     //      | yob[W*64][D][KB+1]
+    // sbuf holds (sigma_t, Q) pairs, one 8-byte read per lane and step; its
+    // 65-pair rows keep the staging stores (consecutive threads step
+    // through a row's KB steps) free of bank conflicts.
+    constexpr int SROW = 65;
     const int RS = nx + KB;
     float* pbuf = smem;
-    float* sbuf = smem + 2 * W * 64 * PST;
-    float* ringw = sbuf + 4 * KB * 65 + (size_t)(wv * D) * RS;
-    float* yobw = sbuf + 4 * KB * 65 + (size_t)W * D * RS + (size_t)(wv * 64) * D * PST;
+    float2* sbuf = reinterpret_cast<float2*>(smem + 2 * W * 64 * PST);
+    float* ringw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)(wv * D) * RS;
+    float* yobw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)W * D * RS +
+                  (size_t)(wv * 64) * D * PST;
     float* yol = yobw + lane * D * PST;   // this lane's y-outflow slots
     const int nblk = ny >> lr;
     const int T = nblk * nx + R - 1;
-    cgfloat* __restrict__ St = (cgfloat*)I.st;
-    cgfloat* __restrict__ Qb = (cgfloat*)I.Q;
     gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
 
-    // Cell of (step, row) pairs by position u = k*nx + ip (ip < 0 before
-    // the row's first cell), advanced by KB per block without division
-    // (KB < nx, so ip wraps at most once): i = i0 + isg*ip,
-    // j = jr + jsg*64*k with jr the row's j in block 0.
+    // Staging and reduction positions.  A block covers KB steps x 64 rows;
+    // position p = rr*KB + t2 is row rr at step t2, i.e. the cell at stream
+    // position u = t0 + t2 - rr = k*nx + ip (valid for 0 <= u < nblk*nx).
+    // The (sigma_t, Q) pair of a position is staged one block ahead, and its
+    // W partial fluxes are summed after the block, by the same thread, so
+    // one cursor per position serves both.  The cursor advances by KB per
+    // block with one conditional wrap (KB < nx): the cell's byte offset then
+    // moves by a uniform step, dN without a wrap and dW with one.
+    //
+    // Waves v, v+4, v+8, ... of a workgroup share a SIMD.  With W % 4 != 0
+    // the SIMDs of waves 0 .. W%4-1 hold one wave more than the others and
+    // set the pace of the block; the waves on the other SIMDs (the helpers)
+    // then take all staging and reduction work when it fits kMaxPos
+    // positions per thread, otherwise every wave is a helper.
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    const int wm = W & 3, q4 = W >> 2;
+    const bool split = wm != 0 && q4 > 0 && KB <= kMaxPos * q4 * (4 - wm);
+    const int H = split ? q4 * (4 - wm) : W;
+    const int hr = !split ? wvu : ((wvu & 3) >= wm ? (wvu >> 2) * (4 - wm) + (wvu & 3) - wm : -1);
+    const bool helper = hr >= 0;
     const int isg = xpos ? 1 : -1, i0 = xpos ? 0 : nx - 1;
     const int jsg = ypos ? 1 : -1, j0 = ypos ? 0 : ny - 1;
-    const int jstep = jsg * R;
-    auto pos_cell = [&](int ip, int k, int jr, bool& ok) {
-        ok = ip >= 0 && k < nblk;
-        return ok ? (jr + jstep * k) * nx + (i0 + isg * ip) : 0;
-    };
-    const int nstage = 2 * KB * R;
-    const int npf = (nstage + nthreads - 1) / nthreads;
-    float pf[kMaxPrefetch];
-    bool pv[kMaxPrefetch];
-    int sip[kMaxPrefetch], sk[kMaxPrefetch], sjr[kMaxPrefetch];
+    const int dN = 4 * isg * KB, dW = 4 * (jsg * R * nx + isg * (KB - nx));
+    const unsigned U = (unsigned)(nblk * nx);
+    const char* __restrict__ Stb = reinterpret_cast<const char*>(I.st);
+    const char* __restrict__ Qbb = reinterpret_cast<const char*>(I.Q);
+    int cip[kMaxPos], cof[kMaxPos], clo[kMaxPos], rof[kMaxPos];
+    unsigned sad[kMaxPos], rad[kMaxPos];
+    bool cva[kMaxPos], rva[kMaxPos];
+    float pst[kMaxPos], pq[kMaxPos];
 #pragma unroll
-    for (int jx = 0; jx < kMaxPrefetch; ++jx) {
-        const int e = tid + jx * nthreads;
-        const int rr = (e >> lkb) & (R - 1);
-        sip[jx] = (e & (KB - 1)) - rr;
-        sk[jx] = 0;
-        sjr[jx] = j0 + jsg * rr;
+    for (int jx = 0; jx < kMaxPos; ++jx) {
+        const int p = (helper ? hr * 64 + lane : 1 << 30) + jx * H * 64;
+        const int rr = (p >> lkb) & (R - 1), t2 = p & (KB - 1);
+        cip[jx] = t2 - rr;
+        clo[jx] = rr - t2;
+        cof[jx] = 4 * ((j0 + jsg * rr) * nx + i0 + isg * (t2 - rr));
+        cva[jx] = p < KB * R && t2 - rr >= 0;
+        rva[jx] = false;
+        rof[jx] = 0;
+        sad[jx] = (unsigned)(t2 * SROW + rr) * 8u;
+        rad[jx] = (unsigned)(rr * PST + t2) * 4u;
+        pst[jx] = 1.f;
+        pq[jx] = 0.f;
     }
+    const bool pos_on = helper;
+    auto p_live = [&](int jx) { return pos_on && (hr * 64 + jx * H * 64) < KB * R; };
+    // loads of the pairs at the cursor (block t0c)
     auto stage_load = [&]() {
-        int cells[kMaxPrefetch];
 #pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
-            if (jx >= npf) break;
-            const int e = tid + jx * nthreads;
-            bool ok;
-            const int cell = pos_cell(sip[jx], sk[jx], sjr[jx], ok);
-            pv[jx] = ok && e < nstage;
-            cells[jx] = pv[jx] ? cell : 0;
-            sip[jx] += KB;
-            if (sip[jx] >= nx) { sip[jx] -= nx; ++sk[jx]; }
-        }
-#pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
-            if (jx >= npf) break;
-            const int e = tid + jx * nthreads;
-            cgfloat* src = (e >> (lkb + lr)) == 0 ? St : Qb;
-            pf[jx] = src[cells[jx]];
+        for (int jx = 0; jx < kMaxPos; ++jx) {
+            if (!p_live(jx)) break;
+            if (cva[jx]) {
+                pst[jx] = *(cgfloat*)((const MDP_GLOBAL char*)Stb + (unsigned)cof[jx]);
+                pq[jx] = *(cgfloat*)((const MDP_GLOBAL char*)Qbb + (unsigned)cof[jx]);
+            }
         }
     };
     auto stage_store = [&](int h) {
 #pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
-            if (jx >= npf) break;
-            const int e = tid + jx * nthreads;
-            if (e < nstage) {
-                const int f = e >> (lkb + lr);
-                const int rr = (e >> lkb) & (R - 1);
-                const int t2 = e & (KB - 1);
-                const float def = f == 0 ? 1.f : 0.f;
-                sbuf[((h * 2 + f) * KB + t2) * 65 + rr] = pv[jx] ? pf[jx] : def;
-            }
+        for (int jx = 0; jx < kMaxPos; ++jx) {
+            if (!p_live(jx)) break;
+            float2* dst = reinterpret_cast<float2*>(reinterpret_cast<char*>(sbuf) +
+                                                    sad[jx] + (unsigned)(h * KB * SROW * 8));
+            *dst = make_float2(cva[jx] ? pst[jx] : 1.f, cva[jx] ? pq[jx] : 0.f);
         }
     };
-    const int nout = KB * R;
-    const int nredu = (nout + nthreads - 1) / nthreads;
-    int rip[kMaxRed], rk[kMaxRed], rjr[kMaxRed];
+    // keep the cursor of the block just staged for its reduction, then move
+    // it one block on (to the block starting at t0n)
+    auto advance = [&](int t0n) {
 #pragma unroll
-    for (int jx = 0; jx < kMaxRed; ++jx) {
-        const int e = tid + jx * nthreads;
-        const int rr = (e >> lkb) & (R - 1);
-        rip[jx] = (e & (KB - 1)) - rr;
-        rk[jx] = 0;
-        rjr[jx] = j0 + jsg * rr;
-    }
+        for (int jx = 0; jx < kMaxPos; ++jx) {
+            if (!p_live(jx)) break;
+            rof[jx] = cof[jx];
+            rva[jx] = cva[jx];
+            int ip = cip[jx] + KB;
+            const bool wrap = ip >= nx;
+            cip[jx] = wrap ? ip - nx : ip;
+            cof[jx] += wrap ? dW : dN;
+            cva[jx] = (unsigned)(t0n - clo[jx]) < U;
+        }
+    };
 
     // vacuum y inflow: the ring (with its mirror) starts at zero
     for (int e = lane; e < D * RS; e += 64) ringw[e] = 0.f;
@@ -517,8 +533,8 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     };
     int kflush = 0;
 
-    // one step: e = this lane's restart step in the block; ring/sp/pw/yol
-    // are the per-block bases; (st, q, rv) were loaded on the previous step
+    // one step: e = this lane's restart step in the block; ring/pw/yol are
+    // the per-block bases; (st, q, rv) were loaded on the previous step
     auto math = [&](int tt, int e, float st, float q, const float* rv, float* pw) {
         float yi[D];
 #pragma unroll
@@ -546,53 +562,57 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         for (int d = 0; d < D; ++d) yol[d * PST + tt] = yo[d];
     };
 
+    int ip0b = 0;                                  // lane 0's column at tt = 0
     for (int t0 = 0, blkno = 0; t0 < T; t0 += KB, ++blkno) {
         const int half = blkno & 1;
         const int tend = min(KB, T - t0);
         const bool more = t0 + KB < T;
-        const int ip0b = t0 % nx;                 // lane 0's column at tt = 0
         int e = lane - ip0b;
         if (e < 0) e += nx;                        // restart step of this lane
-        const float* sp = sbuf + half * 2 * KB * 65 + lane;
+        const float2* sp = sbuf + half * KB * SROW + lane;
         float* pw = pbuf + ((size_t)(half * W + wv) * 64 + lane) * PST;
         const float* rg = ringw + ip0b;            // ring column of step tt: rg[d*RS + tt]
         if (tend == KB) {
-            float st = sp[0], q = sp[KB * 65], rv[D];
+            float2 sq = sp[0];
+            float rv[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) rv[d] = rg[d * RS];
 #pragma unroll
             for (int tt = 0; tt < KB; ++tt) {
-                if (tt == 0 && more) stage_load();
-                float stn = 0.f, qn = 0.f, rvn[D];
+                if (tt == 0) {
+                    advance(t0 + KB);
+                    if (more) stage_load();
+                }
+                float2 sqn = make_float2(0.f, 0.f);
+                float rvn[D];
                 if (tt + 1 < KB) {
-                    stn = sp[(tt + 1) * 65];
-                    qn = sp[(KB + tt + 1) * 65];
+                    sqn = sp[(tt + 1) * SROW];
 #pragma unroll
                     for (int d = 0; d < D; ++d) rvn[d] = rg[d * RS + tt + 1];
                 }
-                math(tt, e, st, q, rv, pw);
+                math(tt, e, sq.x, sq.y, rv, pw);
                 if (tt == KB - 1 && more) stage_store(half ^ 1);
-                st = stn;
-                q = qn;
+                sq = sqn;
 #pragma unroll
                 for (int d = 0; d < D; ++d) rv[d] = rvn[d];
             }
         } else {
+            advance(t0 + KB);
             for (int tt = 0; tt < tend; ++tt) {
                 float rv[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) rv[d] = rg[d * RS + tt];
-                math(tt, e, sp[tt * 65], sp[(KB + tt) * 65], rv, pw);
+                const float2 sq = sp[tt * SROW];
+                math(tt, e, sq.x, sq.y, rv, pw);
             }
         }
-        // lane 63's y outflow of this block into the ring (and its mirror)
+        // lane 63's y outflow of this block into the ring (and its mirror);
+        // its column ip0b + j - 63 lies in [-63, nx - 49]
         {
             const int j = lane;
-            const int tj = t0 + j;
-            if (j < tend && tj >= R - 1) {
+            if (j < tend && t0 + j >= R - 1) {
                 int col = ip0b + j - (R - 1);
-                while (col < 0) col += nx;
-                if (col >= nx) col -= nx;
+                if (col < 0) col += nx;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const float v = yobw[(size_t)(R - 1) * D * PST + d * PST + j];
@@ -608,58 +628,47 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             if (e63 < 0) e63 += nx;
             if (e63 < tend && t0 + e63 >= nx) flush_x(kflush++);
         }
+        ip0b += KB;
+        if (ip0b >= nx) ip0b -= nx;
         __syncthreads();
-        if constexpr (WT > 0) {
-            // all partial loads of this thread's outputs first, then the
-            // fixed-order sums
-            constexpr int NR = (KB * R + WT * 64 - 1) / (WT * 64);
-            float vals[NR][WT];
+        // fixed-order sums of the waves' partial fluxes of this block (all
+        // partial loads of a thread first)
+        if (helper) {
+            const unsigned hoff = (unsigned)(half * W * 64 * PST) * 4u;
+            if constexpr (WT > 0) {
+                float vals[kMaxPos][WT];
 #pragma unroll
-            for (int jx = 0; jx < NR; ++jx) {
-                const int e2 = min(tid + jx * WT * 64, nout - 1);
-                const float* pb = pbuf + ((size_t)half * WT * 64 + (e2 >> lkb)) * PST +
-                                  (e2 & (KB - 1));
+                for (int jx = 0; jx < kMaxPos; ++jx) {
+                    if (!p_live(jx)) break;
+                    const float* pb = reinterpret_cast<const float*>(
+                        reinterpret_cast<const char*>(pbuf) + rad[jx] + hoff);
 #pragma unroll
-                for (int v = 0; v < WT; ++v) vals[jx][v] = pb[(size_t)v * 64 * PST];
-            }
+                    for (int v = 0; v < WT; ++v) vals[jx][v] = pb[(size_t)v * 64 * PST];
+                }
 #pragma unroll
-            for (int jx = 0; jx < NR; ++jx) {
-                const int e2 = tid + jx * WT * 64;
-                if (e2 < nout) {
-                    const int t2 = e2 & (KB - 1);
-                    bool ok;
-                    const int cell = pos_cell(rip[jx], rk[jx], rjr[jx], ok);
-                    if (t2 < tend && ok) {
+                for (int jx = 0; jx < kMaxPos; ++jx) {
+                    if (!p_live(jx)) break;
+                    if (rva[jx]) {
                         float s = 0.f;
 #pragma unroll
                         for (int v = 0; v < WT; ++v) s += vals[jx][v];
-                        part[cell] = s;
+                        *(gfloat*)((MDP_GLOBAL char*)part + (unsigned)rof[jx]) = s;
                     }
-                    rip[jx] += KB;
-                    if (rip[jx] >= nx) { rip[jx] -= nx; ++rk[jx]; }
                 }
-            }
-        } else {
+            } else {
 #pragma unroll
-        for (int jx = 0; jx < kMaxRed; ++jx) {
-            if (jx >= nredu) break;
-            const int e2 = tid + jx * nthreads;
-            if (e2 < nout) {
-                const int rr = e2 >> lkb;
-                const int t2 = e2 & (KB - 1);
-                bool ok;
-                const int cell = pos_cell(rip[jx], rk[jx], rjr[jx], ok);
-                if (t2 < tend && ok) {
-                    const float* pb = pbuf + ((size_t)half * W * 64 + rr) * PST + t2;
-                    float s = 0.f;
+                for (int jx = 0; jx < kMaxPos; ++jx) {
+                    if (!p_live(jx)) break;
+                    if (rva[jx]) {
+                        const float* pb = reinterpret_cast<const float*>(
+                            reinterpret_cast<const char*>(pbuf) + rad[jx] + hoff);
+                        float s = 0.f;
 #pragma unroll 4
-                    for (int v = 0; v < W; ++v) s += pb[(size_t)v * 64 * PST];
-                    part[cell] = s;
+                        for (int v = 0; v < W; ++v) s += pb[(size_t)v * 64 * PST];
+                        *(gfloat*)((MDP_GLOBAL char*)part + (unsigned)rof[jx]) = s;
+                    }
                 }
-                rip[jx] += KB;
-                if (rip[jx] >= nx) { rip[jx] -= nx; ++rk[jx]; }
             }
-        }
         }
     }
     // lane 63 never restarts after its last row: capture, then store the
