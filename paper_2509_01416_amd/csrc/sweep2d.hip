@@ -39,6 +39,13 @@ namespace mdp {
 constexpr int kMaxPrefetch = 4;   // staged values per thread per block
 constexpr int kMaxRed = 2;        // reduced outputs per thread per block
 constexpr int kMaxPos = 4;        // staging/reduction positions per helper thread
+#ifndef MDP_STEP_AHEAD
+#define MDP_STEP_AHEAD 4
+#endif
+#ifndef MDP_HELPER_SPLIT
+#define MDP_HELPER_SPLIT 1
+#endif
+constexpr int kStepAhead = MDP_STEP_AHEAD;   // LDS read distance of the step loop (steps)
 
 // Largest workgroup per directions-per-lane D, so that the register budget
 // (512 per SIMD lane / waves per SIMD) holds D directions without spills.
@@ -368,7 +375,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 // WT > 0: the workgroup has exactly WT waves (the cross-wave sums are then
 // fully unrolled, all loads in flight together); WT = 0: any W.
 template <int D, int KB, int WT>
-__global__ void __launch_bounds__(SweepBounds<D>::threads)
+__global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<D>::threads)
 sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                     const SweepWork* __restrict__ work,
                     const DirTable* __restrict__ dt, const int* __restrict__ done,
@@ -440,17 +447,23 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     // block with one conditional wrap (KB < nx): the cell's byte offset then
     // moves by a uniform step, dN without a wrap and dW with one.
     //
-    // Waves v, v+4, v+8, ... of a workgroup share a SIMD.  With W % 4 != 0
-    // the SIMDs of waves 0 .. W%4-1 hold one wave more than the others and
-    // set the pace of the block; the waves on the other SIMDs (the helpers)
-    // then take all staging and reduction work when it fits kMaxPos
-    // positions per thread, otherwise every wave is a helper.
+    // The positions form KB slots of 64 (one per wave and round).  Waves v,
+    // v+4, v+8, ... of a workgroup share a SIMD, so with W % 4 != 0 the
+    // SIMDs of waves 0 .. W%4-1 hold one wave more than the others and set
+    // the pace of the steps.  Slots go out evenly (KB / W each) and the
+    // remaining KB % W first to the waves on the other SIMDs.
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
-    const int wm = W & 3, q4 = W >> 2;
-    const bool split = wm != 0 && q4 > 0 && KB <= kMaxPos * q4 * (4 - wm);
-    const int H = split ? q4 * (4 - wm) : W;
-    const int hr = !split ? wvu : ((wvu & 3) >= wm ? (wvu >> 2) * (4 - wm) + (wvu & 3) - wm : -1);
-    const bool helper = hr >= 0;
+    int prio = wvu;   // rank in the order slots are handed out
+    {
+        const int wm = W & 3, q4 = W >> 2;
+        if (MDP_HELPER_SPLIT && wm != 0 && q4 > 0) {
+            const int c = wvu & 3, g = wvu >> 2, H = q4 * (4 - wm);
+            prio = c >= wm ? g * (4 - wm) + (c - wm) : H + g * wm + c;
+        }
+    }
+    const int nsl = KB / W + (prio < KB % W ? 1 : 0);        // slots of this wave
+    const int sbase = prio * (KB / W) + min(prio, KB % W);   // its first slot
+    const bool helper = nsl > 0;
     const int isg = xpos ? 1 : -1, i0 = xpos ? 0 : nx - 1;
     const int jsg = ypos ? 1 : -1, j0 = ypos ? 0 : ny - 1;
     const int dN = 4 * isg * KB, dW = 4 * (jsg * R * nx + isg * (KB - nx));
@@ -463,12 +476,12 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     float pst[kMaxPos], pq[kMaxPos];
 #pragma unroll
     for (int jx = 0; jx < kMaxPos; ++jx) {
-        const int p = (helper ? hr * 64 + lane : 1 << 30) + jx * H * 64;
+        const int p = (sbase + jx) * 64 + lane;
         const int rr = (p >> lkb) & (R - 1), t2 = p & (KB - 1);
         cip[jx] = t2 - rr;
         clo[jx] = rr - t2;
         cof[jx] = 4 * ((j0 + jsg * rr) * nx + i0 + isg * (t2 - rr));
-        cva[jx] = p < KB * R && t2 - rr >= 0;
+        cva[jx] = jx < nsl && t2 - rr >= 0;
         rva[jx] = false;
         rof[jx] = 0;
         sad[jx] = (unsigned)(t2 * SROW + rr) * 8u;
@@ -476,8 +489,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         pst[jx] = 1.f;
         pq[jx] = 0.f;
     }
-    const bool pos_on = helper;
-    auto p_live = [&](int jx) { return pos_on && (hr * 64 + jx * H * 64) < KB * R; };
+    auto p_live = [&](int jx) { return jx < nsl; };
     // loads of the pairs at the cursor (block t0c)
     auto stage_load = [&]() {
 #pragma unroll
@@ -534,7 +546,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     int kflush = 0;
 
     // one step: e = this lane's restart step in the block; ring/pw/yol are
-    // the per-block bases; (st, q, rv) were loaded on the previous step
+    // the per-block bases; (st, q, rv) were loaded on an earlier step
     auto math = [&](int tt, int e, float st, float q, const float* rv, float* pw) {
         float yi[D];
 #pragma unroll
@@ -573,28 +585,37 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         float* pw = pbuf + ((size_t)(half * W + wv) * 64 + lane) * PST;
         const float* rg = ringw + ip0b;            // ring column of step tt: rg[d*RS + tt]
         if (tend == KB) {
-            float2 sq = sp[0];
-            float rv[D];
+            // the LDS reads of step tt + A are issued before the arithmetic
+            // of step tt (A = kStepAhead), so their latency hides behind A
+            // steps of this wave
+            constexpr int A = kStepAhead < KB ? kStepAhead : KB;
+            float2 sq[A + 1];
+            float rv[A + 1][D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) rv[d] = rg[d * RS];
+            for (int k = 0; k < A; ++k) {
+                sq[k] = sp[k * SROW];
+#pragma unroll
+                for (int d = 0; d < D; ++d) rv[k][d] = rg[d * RS + k];
+            }
 #pragma unroll
             for (int tt = 0; tt < KB; ++tt) {
                 if (tt == 0) {
                     advance(t0 + KB);
                     if (more) stage_load();
                 }
-                float2 sqn = make_float2(0.f, 0.f);
-                float rvn[D];
-                if (tt + 1 < KB) {
-                    sqn = sp[(tt + 1) * SROW];
+                if (tt + A < KB) {
+                    sq[A] = sp[(tt + A) * SROW];
 #pragma unroll
-                    for (int d = 0; d < D; ++d) rvn[d] = rg[d * RS + tt + 1];
+                    for (int d = 0; d < D; ++d) rv[A][d] = rg[d * RS + tt + A];
                 }
-                math(tt, e, sq.x, sq.y, rv, pw);
+                math(tt, e, sq[0].x, sq[0].y, rv[0], pw);
                 if (tt == KB - 1 && more) stage_store(half ^ 1);
-                sq = sqn;
 #pragma unroll
-                for (int d = 0; d < D; ++d) rv[d] = rvn[d];
+                for (int k = 0; k < A; ++k) {
+                    sq[k] = sq[k + 1];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) rv[k][d] = rv[k + 1][d];
+                }
             }
         } else {
             advance(t0 + KB);
