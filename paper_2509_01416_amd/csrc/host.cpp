@@ -26,9 +26,10 @@ bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
 size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx);
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                         const int* done, const int* iter, hipStream_t s);
+                         const int* done, const int* iter, bool tally, hipStream_t s);
 size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx);
 int sweep2d_max_kb(int W, int R);
+int sweep2d_fast_max_kb(int W);
 int sweep2d_max_w(int D);
 void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
                     const int* done, const int* iter, int use_faces, int M,
@@ -398,9 +399,9 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
         nxmax = std::max(nxmax, p[i].nx);
     }
     // the specialised kernel: 64-row segments everywhere, vacuum faces only,
-    // and nx >= 63 + KB (lane 0's ring column is then always written in an
-    // earlier block)
-    bool fast = !c->force_generic;
+    // D <= 4, and nx >= 63 + KB (lane 0's ring column is then always written
+    // in an earlier block)
+    bool fast = !c->force_generic && pl.D <= 4;
     int nxmin = 1 << 30;
     for (int i = 0; i < n_inst; ++i) {
         fast = fast && pl.R[i] == 64;
@@ -409,7 +410,7 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
     }
     const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax));
     if (fast) {
-        int kb = kb0;
+        int kb = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_fast_max_kb(W));
         while (kb > 2 && (nxmin < 63 + kb || sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) > c->lds_limit))
             kb /= 2;
         if (kb >= 2 && nxmin >= 63 + kb &&
@@ -607,7 +608,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
 }
 
 bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
-                       const int* iter, int use_faces) {
+                       const int* iter, int use_faces, bool tally) {
     if (su.inst[0].dim == 1) {
         launch_sweep1d(n_inst, su.d_inst, su.d_dt, done, iter, use_faces, su.dt.M,
                        stream);
@@ -619,7 +620,7 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
             su.plan.fast
                 ? launch_sweep2d_fast(su.plan.D, (int)su.work.size(), su.plan.W, su.plan.KB,
                                       su.plan.lds, su.d_inst, su.d_work, su.d_dt, done, iter,
-                                      stream)
+                                      tally, stream)
                 : launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
                                  su.plan.W, su.plan.KB, su.plan.lds, su.d_inst, su.d_work,
                                  su.d_dt, done, iter, use_faces, stream);
@@ -758,6 +759,13 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
         for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
         chunk = std::min(chunk * 2, 64);
     }
+    // The specialised sweep stores no boundary faces while iterating
+    // (vacuum inflow reads none): one more sweep of the final emission
+    // tallies them for the balance, into the current face parity, without
+    // touching the iterate.
+    if (p[0].dim == 2 && su.plan.fast &&
+        !c->launch_sweep(su, n_inst, nullptr, su.st.iter, 1, true))
+        return TR_ERR_HIP;
     launch_balance(n_inst, su.d_inst, su.d_dt, su.st.iter, su.d_bal, c->stream);
     if (!c->hip_ok(hipGetLastError(), "balance launch")) return TR_ERR_HIP;
     // read back iteration state

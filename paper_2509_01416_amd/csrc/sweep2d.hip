@@ -366,15 +366,21 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 //     "old" operand of the lane shift (a lane with no source keeps it);
 //   * every lane writes its y outflow to its own [lane][step] slot; after
 //     the block, lane 63's slots are copied into the ring;
-//   * a lane captures the x outflow of its finished row when it restarts
-//     (restart step e = (l - ip0) mod nx precomputed per block), and the 64
-//     rows of a block are stored together after the block in which lane 63
-//     restarted (lane 0 restarts only nx - 63 > KB steps later);
-//   * the loads of step tt + 1 are issued before the arithmetic of step tt.
+//   * a lane resets its x inflow to the vacuum value when it restarts
+//     (restart step e = (l - ip0) mod nx precomputed per block);
+//   * the LDS loads of step tt + kStepAhead are issued before the arithmetic
+//     of step tt.
 // The arithmetic and the reduction order are those of the generic kernel.
 // WT > 0: the workgroup has exactly WT waves (the cross-wave sums are then
 // fully unrolled, all loads in flight together); WT = 0: any W.
-template <int D, int KB, int WT>
+// TALLY: also store the outgoing boundary faces (for the particle balance;
+// with vacuum inflow nothing else reads them), into the face set of the
+// current parity: a lane captures the x outflow of its finished row when it
+// restarts, and the 64 rows of a block are stored together after the block
+// in which lane 63 restarted (lane 0 restarts only nx - 63 > KB steps
+// later).  The source iteration runs without it and tallies once, after its
+// last iteration.
+template <int D, int KB, int WT, bool TALLY>
 __global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<D>::threads)
 sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                     const SweepWork* __restrict__ work,
@@ -399,7 +405,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
     const int par = (iter != nullptr ? iter[n] : 0) & 1;
     const size_t fstride = (size_t)4 * nf * M;
-    gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(par ^ 1) * fstride);
+    gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(TALLY ? par : par ^ 1) * fstride);
     const int fxout = xpos ? 1 : 0, fyout = ypos ? 3 : 2;
 
     float a[D], b[D], c[D], w[D];
@@ -557,7 +563,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         const bool rs = e == tt;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            xs[d] = rs ? xin[d] : xs[d];
+            if constexpr (TALLY) xs[d] = rs ? xin[d] : xs[d];
             xin[d] = rs ? 0.f : xin[d];
         }
         float acc = 0.f;
@@ -644,7 +650,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         }
         // lane 63 restarted in this block: the x outflow of the previous row
         // block is complete (lane 0 restarts nx - 63 > KB steps later)
-        {
+        if constexpr (TALLY) {
             int e63 = (R - 1) - ip0b;
             if (e63 < 0) e63 += nx;
             if (e63 < tend && t0 + e63 >= nx) flush_x(kflush++);
@@ -692,20 +698,22 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             }
         }
     }
-    // lane 63 never restarts after its last row: capture, then store the
-    // x outflow of the last row block
+    if constexpr (TALLY) {
+        // lane 63 never restarts after its last row: capture, then store the
+        // x outflow of the last row block
 #pragma unroll
-    for (int d = 0; d < D; ++d) xs[d] = top ? xin[d] : xs[d];
-    flush_x(nblk - 1);
-    // the ring holds the grid's outgoing y face of every column
-    for (int e = lane; e < D * nx; e += 64) {
-        const int d = e / nx, ipc = e - d * nx;
-        const int i = xpos ? ipc : nx - 1 - ipc;
-        int m = -1;
+        for (int d = 0; d < D; ++d) xs[d] = top ? xin[d] : xs[d];
+        flush_x(nblk - 1);
+        // the ring holds the grid's outgoing y face of every column
+        for (int e = lane; e < D * nx; e += 64) {
+            const int d = e / nx, ipc = e - d * nx;
+            const int i = xpos ? ipc : nx - 1 - ipc;
+            int m = -1;
 #pragma unroll
-        for (int dd = 0; dd < D; ++dd)
-            if (dd == d) m = mi[dd];
-        if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ringw[d * RS + ipc];
+            for (int dd = 0; dd < D; ++dd)
+                if (dd == d) m = mi[dd];
+            if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ringw[d * RS + ipc];
+        }
     }
 }
 
@@ -737,45 +745,46 @@ static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
     }
 }
 
-template <int D, int WT>
+template <int D, int WT, bool TALLY>
 static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                            const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                            const int* done, const int* iter) {
     switch (KB) {
-        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2, WT>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
         default: return false;
     }
 }
 
 // Fixed wave counts of the common level-symmetric sets with one direction
 // per lane: S16 (36 directions per octant, 4 slices of 9) and S8 (10 per
-// octant, one slice of 10).
+// octant, one slice of 10).  The tally sweep (once per solve) takes the
+// any-W instance.
 template <int D>
 static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                          const int* done, const int* iter) {
+                          const int* done, const int* iter, bool tally) {
     const int W = (int)block.x / 64;
+    if (tally)
+        return launch_fast_dw<D, 0, true>(KB, grid, block, lds, s, insts, work, dt, done, iter);
     if (D == 1 && W == 9)
-        return launch_fast_dw<D, 9>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+        return launch_fast_dw<D, 9, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
     if (D == 1 && W == 10)
-        return launch_fast_dw<D, 10>(KB, grid, block, lds, s, insts, work, dt, done, iter);
-    return launch_fast_dw<D, 0>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+        return launch_fast_dw<D, 10, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+    return launch_fast_dw<D, 0, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
 }
 
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                         const int* done, const int* iter, hipStream_t s) {
+                         const int* done, const int* iter, bool tally, hipStream_t s) {
     dim3 grid(nwork), block(64 * W);
     switch (D) {
-        case 1: return launch_fast_d<1>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
-        case 2: return launch_fast_d<2>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
-        case 3: return launch_fast_d<3>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
-        case 4: return launch_fast_d<4>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
-        case 6: return launch_fast_d<6>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
-        case 9: return launch_fast_d<9>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter);
+        case 1: return launch_fast_d<1>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
+        case 2: return launch_fast_d<2>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
+        case 3: return launch_fast_d<3>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
+        case 4: return launch_fast_d<4>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
         default: return false;
     }
 }
@@ -816,6 +825,14 @@ int sweep2d_max_kb(int W, int R) {
 }
 
 
+
+// Largest block size of the specialised kernel: a wave holds at most
+// kMaxPos staging / reduction slots of 64 positions.
+int sweep2d_fast_max_kb(int W) {
+    int kb = 16;
+    while (kb > 1 && kb > kMaxPos * W) kb >>= 1;
+    return kb;
+}
 
 // Largest W (waves per workgroup) the kernel for D supports.
 int sweep2d_max_w(int D) {

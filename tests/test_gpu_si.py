@@ -147,6 +147,7 @@ def test_sinusoid_128_full(env):
     assert rc == 0
     assert abs(st[0]["iterations"] - z.iterations) <= 2
     assert e < 1e-5
+    assert st[0]["balance_rel"] < 1e-4
 
 
 def test_batched_uneven_256_full(env):
@@ -264,7 +265,8 @@ def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
     """The specialised sweep (64-row segments, vacuum faces, nx >= 63 + KB)
     performs the generic kernel's operations in the same order: sweeps and
     whole solves agree bit for bit, for several launch shapes, block sizes
-    (KB from 2 to 16) and ragged widths."""
+    (KB from 2 to 16) and ragged widths; the particle balance from its
+    final tally sweep closes as well as the generic one."""
     torch, B, ctx = env
     quad = I.level_symmetric_2d(n)
     insts = [I.random_instance(nx, ny, seed=700 + nx + ny) for nx, ny in shapes]
@@ -285,14 +287,19 @@ def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
             phis = [torch.zeros_like(e) for e in em]
             _, st = B.tr_solve(ctx, probs, q, None, phis, 1e-6, 2000)
             outs[generic] = ([x.cpu().numpy() for x in o], [x.cpu().numpy() for x in phis],
-                             [s["iterations"] for s in st])
+                             [s["iterations"] for s in st], [s["balance_rel"] for s in st])
         log(f"  specialised vs generic {shapes} S{n} cfg {cfg}: plan {plan}, "
-            f"iterations {outs[False][2]}")
+            f"iterations {outs[False][2]}, balance {outs[False][3]} vs {outs[True][3]}")
         for a, b in zip(outs[False][0], outs[True][0]):
             assert np.array_equal(a, b)
         for a, b in zip(outs[False][1], outs[True][1]):
             assert np.array_equal(a, b)
         assert outs[False][2] == outs[True][2]
+        # the specialised solve tallies its boundary faces in one extra sweep
+        # of the final emission, the generic one in every sweep: both
+        # balances close to what the stopping rule leaves
+        for bf, bg in zip(outs[False][3], outs[True][3]):
+            assert bf < 1e-5 and bg < 1e-5
     finally:
         ctx.set_sweep_kernel(False)
         ctx.set_sweep_config(0, 0, 0, 0)
