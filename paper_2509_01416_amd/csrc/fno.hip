@@ -964,26 +964,89 @@ __device__ __forceinline__ f32x4 tile_mma(const typename Frag<F32>::T* A, int ld
     return c;
 }
 
+// LDS images of the DFT matrices, built once per model (stage_spec_kernel):
+// the exact padded layouts the two kernels below keep in LDS, per operand
+// precision, so a workgroup copies them with 16-byte loads.
+constexpr int kSpLV = 64 + 8, kSpLT = 128 + 8, kSpLG = 48 + 8, kSpLZ = 32 + 8;
+constexpr int kImgFx = 0;                          // [32][LV]  FxT^T, rows >= 24 zero
+constexpr int kImgFy = kImgFx + 32 * kSpLV;        // [48][LT]  Fy
+constexpr int kImgGy = kImgFy + 48 * kSpLT;        // [128][LG] Gy
+constexpr int kImgGx = kImgGy + 128 * kSpLG;       // [64][LZ]  Gx^T, columns >= 24 zero
+constexpr int kImgElems = kImgGx + 64 * kSpLZ;     // elements per precision
+
+template <bool F32>
+__global__ void stage_spec_kernel(const float* __restrict__ FxT, const float* __restrict__ Fy,
+                                  const float* __restrict__ Gy, const float* __restrict__ Gx,
+                                  typename Frag<F32>::T* __restrict__ img) {
+    constexpr int n = 64, mm = 12;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kImgElems; e += gridDim.x * blockDim.x) {
+        float v = 0.f;
+        if (e < kImgFy) {
+            const int j = e / kSpLV, x = e % kSpLV;
+            if (j < 2 * mm && x < n) v = FxT[x * 2 * mm + j];
+        } else if (e < kImgGy) {
+            const int r = (e - kImgFy) / kSpLT, k = (e - kImgFy) % kSpLT;
+            if (k < 2 * n) v = Fy[r * 2 * n + k];
+        } else if (e < kImgGx) {
+            const int r = (e - kImgGy) / kSpLG, k = (e - kImgGy) % kSpLG;
+            if (k < 4 * mm) v = Gy[r * 4 * mm + k];
+        } else {
+            const int x = (e - kImgGx) / kSpLZ, k = (e - kImgGx) % kSpLZ;
+            if (k < 2 * mm) v = Gx[k * n + x];
+        }
+        img[e] = Frag<F32>::cvt(v);
+    }
+}
+
+// 16-byte copy of `bytes` (a multiple of 16) from global to LDS by 256 threads
+__device__ __forceinline__ void copy16(void* dst, const void* src, int bytes) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(dst);
+    for (int e = threadIdx.x; e < bytes / 16; e += 256) d[e] = s[e];
+}
+
+// 64 x 64 FP32 field -> LDS [y][LV] in the operand precision (float4 loads)
+template <bool F32>
+__device__ __forceinline__ void stage_field(typename Frag<F32>::T* Vs, const float* vg) {
+    const float4* v4 = reinterpret_cast<const float4*>(vg);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = threadIdx.x + 256 * k;        // float4 index: y = e / 16
+        const float4 v = v4[e];
+        typename Frag<F32>::T* d = Vs + (e >> 4) * kSpLV + 4 * (e & 15);
+        if constexpr (F32) {
+            *reinterpret_cast<float4*>(d) = v;
+        } else {
+            const unsigned lo = (unsigned)to_bf16(v.x) | ((unsigned)to_bf16(v.y) << 16);
+            const unsigned hi = (unsigned)to_bf16(v.z) | ((unsigned)to_bf16(v.w) << 16);
+            *reinterpret_cast<uint2*>(d) = make_uint2(lo, hi);
+        }
+    }
+}
+
+template <bool F32>
+__device__ __forceinline__ void zero_lds(typename Frag<F32>::T* p, int elems) {
+    uint4* d = reinterpret_cast<uint4*>(p);
+    const int n16 = elems * (int)sizeof(typename Frag<F32>::T) / 16;
+    for (int e = threadIdx.x; e < n16; e += 256) d[e] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <bool F32>
 __global__ void __launch_bounds__(256)
-spec_fwd_kernel(const float* __restrict__ v, const float* __restrict__ FxT,
-                const float* __restrict__ Fy, float* __restrict__ X) {
+spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __restrict__ img,
+                float* __restrict__ X) {
     typedef typename Frag<F32>::T T;
-    constexpr int n = 64, mm = 12, LV = 64 + 8, LT = 128 + 8;
+    constexpr int n = 64, mm = 12, LV = kSpLV, LT = kSpLT;
     __shared__ __attribute__((aligned(16))) T Vs[n * LV];          // [y][x]
     __shared__ __attribute__((aligned(16))) T Fx[32 * LV];         // [j][x], j < 24 used
     __shared__ __attribute__((aligned(16))) T Fys[48 * LT];        // [(q,kyi)][(p,y)]
     __shared__ __attribute__((aligned(16))) T Ts[16 * LT];         // [kx][(p,y)]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long g = blockIdx.x;
-    const float* vg = v + g * n * n;
-    for (int e = tid; e < n * n; e += 256) Vs[(e >> 6) * LV + (e & 63)] = Frag<F32>::cvt(vg[e]);
-    for (int e = tid; e < 32 * n; e += 256) {                      // FxT[x][j] -> Fx[j][x]
-        const int j = e >> 6, x = e & 63;
-        Fx[j * LV + x] = Frag<F32>::cvt(j < 2 * mm ? FxT[x * 2 * mm + j] : 0.f);
-    }
-    for (int e = tid; e < 48 * 128; e += 256) Fys[(e >> 7) * LT + (e & 127)] = Frag<F32>::cvt(Fy[e]);
-    for (int e = tid; e < 16 * LT; e += 256) Ts[e] = Frag<F32>::cvt(0.f);
+    stage_field<F32>(Vs, v + g * n * n);
+    copy16(Fx, img + kImgFx, 32 * LV * (int)sizeof(T));
+    copy16(Fys, img + kImgFy, 48 * LT * (int)sizeof(T));
+    zero_lds<F32>(Ts, 16 * LT);
     __syncthreads();
     // T: wave w owns rows 16w..16w+15, both 16-column tiles
 #pragma unroll
@@ -1010,10 +1073,10 @@ spec_fwd_kernel(const float* __restrict__ v, const float* __restrict__ FxT,
 
 template <bool F32>
 __global__ void __launch_bounds__(256)
-spec_inv_kernel(const float* __restrict__ Y, const float* __restrict__ Gy,
-                const float* __restrict__ Gx, float* __restrict__ U) {
+spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __restrict__ img,
+                float* __restrict__ U) {
     typedef typename Frag<F32>::T T;
-    constexpr int n = 64, mm = 12, LG = 48 + 8, LZ = 32 + 8;
+    constexpr int n = 64, mm = 12, LG = kSpLG, LZ = kSpLZ;
     __shared__ __attribute__((aligned(16))) T Gys[128 * LG];       // [(p,y)][(q,kyi)]
     __shared__ __attribute__((aligned(16))) T Ys[16 * LG];         // [kx][(q,kyi)]
     __shared__ __attribute__((aligned(16))) T Zs[n * LZ];          // [y][(p,kx)], 24 of 32 used
@@ -1021,16 +1084,13 @@ spec_inv_kernel(const float* __restrict__ Y, const float* __restrict__ Gy,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long g = blockIdx.x;
     const float* yg = Y + g * 48 * mm;
-    for (int e = tid; e < 128 * 48; e += 256) Gys[(e / 48) * LG + (e % 48)] = Frag<F32>::cvt(Gy[e]);
+    copy16(Gys, img + kImgGy, 128 * LG * (int)sizeof(T));
+    copy16(Gxs, img + kImgGx, n * LZ * (int)sizeof(T));
     for (int e = tid; e < 16 * 48; e += 256) {                     // Y[r][kx] -> Ys[kx][r]
         const int kx = e / 48, r = e % 48;
         Ys[kx * LG + r] = Frag<F32>::cvt(kx < mm ? yg[r * mm + kx] : 0.f);
     }
-    for (int e = tid; e < n * 32; e += 256) {                      // Gx[(p,kx)][x] -> Gxs[x][(p,kx)]
-        const int x = e >> 5, k = e & 31;
-        Gxs[x * LZ + k] = Frag<F32>::cvt(k < 2 * mm ? Gx[k * n + x] : 0.f);
-    }
-    for (int e = tid; e < n * LZ; e += 256) Zs[e] = Frag<F32>::cvt(0.f);
+    zero_lds<F32>(Zs, n * LZ);
     __syncthreads();
     // Z: wave w owns rows 32w..32w+31 (two 16-row tiles), one column tile
 #pragma unroll
@@ -1093,19 +1153,32 @@ void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C,
     hipLaunchKernelGGL(mix_mode_back_w_kernel, dim3(2 * m * m), dim3(256), lds, s, X, gY, gR,
                        B, C, m);
 }
-void launch_spec_fwd(const float* v, const float* FxT, const float* Fy, float* X, int G,
-                     int f32, hipStream_t s) {
-    if (f32)
-        hipLaunchKernelGGL(spec_fwd_kernel<true>, dim3(G), dim3(256), 0, s, v, FxT, Fy, X);
-    else
-        hipLaunchKernelGGL(spec_fwd_kernel<false>, dim3(G), dim3(256), 0, s, v, FxT, Fy, X);
+size_t spec_image_bytes() {
+    return (size_t)kImgElems * (sizeof(float) + sizeof(unsigned short));
 }
-void launch_spec_inv(const float* Y, const float* Gy, const float* Gx, float* U, int G,
-                     int f32, hipStream_t s) {
+// img: [FP32 image][BF16 image]
+void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const float* Gx,
+                       void* img, hipStream_t s) {
+    float* f = reinterpret_cast<float*>(img);
+    unsigned short* h = reinterpret_cast<unsigned short*>(f + kImgElems);
+    hipLaunchKernelGGL(stage_spec_kernel<true>, dim3(64), dim3(256), 0, s, FxT, Fy, Gy, Gx, f);
+    hipLaunchKernelGGL(stage_spec_kernel<false>, dim3(64), dim3(256), 0, s, FxT, Fy, Gy, Gx, h);
+}
+void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s) {
+    const float* f = reinterpret_cast<const float*>(img);
     if (f32)
-        hipLaunchKernelGGL(spec_inv_kernel<true>, dim3(G), dim3(256), 0, s, Y, Gy, Gx, U);
+        hipLaunchKernelGGL(spec_fwd_kernel<true>, dim3(G), dim3(256), 0, s, v, f, X);
     else
-        hipLaunchKernelGGL(spec_inv_kernel<false>, dim3(G), dim3(256), 0, s, Y, Gy, Gx, U);
+        hipLaunchKernelGGL(spec_fwd_kernel<false>, dim3(G), dim3(256), 0, s, v,
+                           reinterpret_cast<const unsigned short*>(f + kImgElems), X);
+}
+void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s) {
+    const float* f = reinterpret_cast<const float*>(img);
+    if (f32)
+        hipLaunchKernelGGL(spec_inv_kernel<true>, dim3(G), dim3(256), 0, s, Y, f, U);
+    else
+        hipLaunchKernelGGL(spec_inv_kernel<false>, dim3(G), dim3(256), 0, s, Y,
+                           reinterpret_cast<const unsigned short*>(f + kImgElems), U);
 }
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,

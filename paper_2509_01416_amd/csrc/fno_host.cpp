@@ -59,6 +59,7 @@ struct no_model {
     float* Fy = nullptr;       // [48][128]
     float* Gy = nullptr;       // [128][48]
     float* Gx = nullptr;       // [24][64]
+    void* spec_img = nullptr;  // LDS images of the DFT matrices (mode window 12)
     long long step = 0;
     int f32 = 0;               // FP32 operands on the matrix cores
 };
@@ -209,9 +210,9 @@ struct Runner {
         launch_lift(in, P + m->oW0, P + m->ob0, w.v[0], B, kGrid, C, c->stream);
         for (int l = 0; l < L && ok; ++l) {
             if (mm == 12) {   // the supported mode window: fused DFT kernels
-                launch_spec_fwd(w.v[l], m->FxT, m->Fy, w.X[l], G, m->f32, c->stream);
+                launch_spec_fwd(w.v[l], m->spec_img, w.X[l], G, m->f32, c->stream);
                 launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
-                launch_spec_inv(w.Y, m->Gy, m->Gx, w.z[l], G, m->f32, c->stream);
+                launch_spec_inv(w.Y, m->spec_img, w.z[l], G, m->f32, c->stream);
             } else {
                 gemm(kGrid, 2 * mm, kGrid, G, mat(w.v[l], kGrid, 1, kP),
                      mat(m->FxT, 2 * mm, 1), mat(w.T, 2 * mm, 1, tb));
@@ -327,6 +328,7 @@ void free_model(no_model* m) {
     float* bufs[] = {m->params, m->grad, m->am, m->av, m->FxT, m->Fy, m->Gy, m->Gx};
     for (float* b : bufs)
         if (b) (void)hipFree(b);
+    if (m->spec_img) (void)hipFree(m->spec_img);
 }
 
 bool same_device(Ctx* c, const no_model* m) {
@@ -403,7 +405,8 @@ extern "C" tr_status no_model_create(tr_context* ctx, no_model** out, int32_t wi
                 c->hip_ok(hipMalloc(&m->FxT, 4 * FxT.size()), "hipMalloc") &&
                 c->hip_ok(hipMalloc(&m->Fy, 4 * Fy.size()), "hipMalloc") &&
                 c->hip_ok(hipMalloc(&m->Gy, 4 * Gy.size()), "hipMalloc") &&
-                c->hip_ok(hipMalloc(&m->Gx, 4 * Gx.size()), "hipMalloc");
+                c->hip_ok(hipMalloc(&m->Gx, 4 * Gx.size()), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->spec_img, spec_image_bytes()), "hipMalloc");
     if (good) {
         hipStream_t s = c->stream;
         good = (params_host
@@ -416,8 +419,12 @@ extern "C" tr_status no_model_create(tr_context* ctx, no_model** out, int32_t wi
                c->hip_ok(hipMemcpyAsync(m->FxT, FxT.data(), 4 * FxT.size(), hipMemcpyHostToDevice, s), "copy") &&
                c->hip_ok(hipMemcpyAsync(m->Fy, Fy.data(), 4 * Fy.size(), hipMemcpyHostToDevice, s), "copy") &&
                c->hip_ok(hipMemcpyAsync(m->Gy, Gy.data(), 4 * Gy.size(), hipMemcpyHostToDevice, s), "copy") &&
-               c->hip_ok(hipMemcpyAsync(m->Gx, Gx.data(), 4 * Gx.size(), hipMemcpyHostToDevice, s), "copy") &&
-               c->hip_ok(hipStreamSynchronize(s), "sync");
+               c->hip_ok(hipMemcpyAsync(m->Gx, Gx.data(), 4 * Gx.size(), hipMemcpyHostToDevice, s), "copy");
+        if (good && modes == 12 && grid == kGrid) {
+            launch_stage_spec(m->FxT, m->Fy, m->Gy, m->Gx, m->spec_img, s);
+            good = c->hip_ok(hipGetLastError(), "stage launch");
+        }
+        good = good && c->hip_ok(hipStreamSynchronize(s), "sync");
     }
     if (!good) {
         (void)hipGetLastError();

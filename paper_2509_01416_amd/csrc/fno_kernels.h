@@ -46,10 +46,11 @@ void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C,
                        hipStream_t s);
 // Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
 // inverse, each in one kernel (layouts as the batched GEMM path).
-void launch_spec_fwd(const float* v, const float* FxT, const float* Fy, float* X, int G,
-                     int f32, hipStream_t s);
-void launch_spec_inv(const float* Y, const float* Gy, const float* Gx, float* U, int G,
-                     int f32, hipStream_t s);
+size_t spec_image_bytes();   // FP32 + BF16 LDS images of the DFT matrices
+void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const float* Gx,
+                       void* img, hipStream_t s);
+void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s);
+void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s);
 // Projection head in one kernel (width 32, 128 hidden units only).
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,
