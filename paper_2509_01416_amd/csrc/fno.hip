@@ -1117,6 +1117,58 @@ spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __rest
     }
 }
 
+// ------------------------------------------------- pointwise layer path --
+// z[b][co][p] += sum_ci W[ci][co] v[b][ci][p] + bias[co] (z holds the
+// spectral path on entry); optionally gelu(z) into vn.  C = 32 channels.
+// One workgroup per (64-pixel tile, sample): wave w computes output rows
+// 16 (w & 1) .. +15 and pixels 32 (w >> 1) .. +31 as two 16 x 16 MFMA tiles,
+// with the batched GEMM's operand rounding and k order (so the results are
+// those of the strided GEMM for this shape).  store_z = 0 leaves z as it is
+// (inference: the next layer reads only gelu(z)).
+template <bool F32>
+__global__ void __launch_bounds__(256)
+pointwise_kernel(const float* __restrict__ W, const float* __restrict__ v,
+                 const float* __restrict__ bias, float* __restrict__ z,
+                 float* __restrict__ vn, int P, int store_z) {
+    typedef typename Frag<F32>::T T;
+    constexpr int C = 32, LK = C + 4;
+    __shared__ __attribute__((aligned(16))) T As[C * LK];    // [co][ci]
+    __shared__ __attribute__((aligned(16))) T Bs[64 * LK];   // [p][ci]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int p0 = blockIdx.x * 64, b = blockIdx.y;
+    const size_t base = (size_t)b * C * P;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = tid + 256 * k;                          // W[ci][co], e = ci * 32 + co
+        As[(e & 31) * LK + (e >> 5)] = Frag<F32>::cvt(W[e]);
+    }
+    {
+        const int ci = tid >> 3, n0 = (tid & 7) * 8;           // 8 pixels of channel ci
+        const float4* src = reinterpret_cast<const float4*>(v + base + (size_t)ci * P + p0 + n0);
+        const float4 x0 = src[0], x1 = src[1];
+        const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[(n0 + j) * LK + ci] = Frag<F32>::cvt(xs[j]);
+    }
+    __syncthreads();
+    const int m0 = 16 * (wv & 1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int n0 = 32 * (wv >> 1) + 16 * t;
+        const f32x4 c = tile_mma<F32>(As, LK, Bs, LK, m0, n0, C, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = m0 + 4 * (lane >> 4) + q, p = p0 + n0 + (lane & 15);
+            const size_t o = base + (size_t)m * P + p;
+            float r = c[q];
+            r += z[o];
+            r += bias[m];
+            if (store_z) z[o] = r;
+            if (vn) vn[o] = gelu_dev(r);
+        }
+    }
+}
+
 // ------------------------------------------------------------- launchers --
 static int blocks_for(long long n) {
     return (int)std::max<long long>(1, std::min<long long>(8192, (n + 255) / 256));
@@ -1163,6 +1215,16 @@ void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const
     unsigned short* h = reinterpret_cast<unsigned short*>(f + kImgElems);
     hipLaunchKernelGGL(stage_spec_kernel<true>, dim3(64), dim3(256), 0, s, FxT, Fy, Gy, Gx, f);
     hipLaunchKernelGGL(stage_spec_kernel<false>, dim3(64), dim3(256), 0, s, FxT, Fy, Gy, Gx, h);
+}
+void launch_pointwise(const float* W, const float* v, const float* bias, float* z, float* vn,
+                      int B, int P, int store_z, int f32, hipStream_t s) {
+    dim3 grid(P / 64, B);
+    if (f32)
+        hipLaunchKernelGGL(pointwise_kernel<true>, grid, dim3(256), 0, s, W, v, bias, z, vn, P,
+                           store_z);
+    else
+        hipLaunchKernelGGL(pointwise_kernel<false>, grid, dim3(256), 0, s, W, v, bias, z, vn, P,
+                           store_z);
 }
 void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s) {
     const float* f = reinterpret_cast<const float*>(img);

@@ -224,10 +224,17 @@ struct Runner {
                 gemm(kGrid, kGrid, 2 * mm, G, mat(w.T, 2 * mm, 1, tb), mat(m->Gx, kGrid, 1),
                      mat(w.z[l], kGrid, 1, kP));
             }
-            // pointwise path, bias and (but after the last layer) GELU
-            gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
-                 mat(w.z[l], kP, 1, act), 1, P + m->ob[l], nullptr,
-                 l + 1 < L ? w.v[l + 1] : nullptr);
+            // pointwise path, bias and (but after the last layer) GELU; the
+            // pre-activations are kept for a backward pass and for the head
+            if (C == 32) {
+                launch_pointwise(P + m->oW[l], w.v[l], P + m->ob[l], w.z[l],
+                                 l + 1 < L ? w.v[l + 1] : nullptr, B, kP,
+                                 keep_h || l + 1 == L ? 1 : 0, m->f32, c->stream);
+            } else {
+                gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
+                     mat(w.z[l], kP, 1, act), 1, P + m->ob[l], nullptr,
+                     l + 1 < L ? w.v[l + 1] : nullptr);
+            }
         }
         const float* vL = w.z[L - 1];
         // projection head; h is kept only when a backward pass follows

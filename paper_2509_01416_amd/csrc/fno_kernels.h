@@ -46,6 +46,9 @@ void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C,
                        hipStream_t s);
 // Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
 // inverse, each in one kernel (layouts as the batched GEMM path).
+// Pointwise path of a Fourier layer for C = 32 channels and P % 64 == 0.
+void launch_pointwise(const float* W, const float* v, const float* bias, float* z, float* vn,
+                      int B, int P, int store_z, int f32, hipStream_t s);
 size_t spec_image_bytes();   // FP32 + BF16 LDS images of the DFT matrices
 void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const float* Gx,
                        void* img, hipStream_t s);
