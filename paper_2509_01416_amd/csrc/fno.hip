@@ -1117,6 +1117,73 @@ spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __rest
     }
 }
 
+// ------------------------------------------------- per-mode mixing (MMA) --
+// For every retained mode, Y[b][:] = X[b][:] R (32 x 32 complex), written as
+// one real product on the matrix cores in FP32:
+//   [Yr | Yi] (16 x 64) = [Xr | Xi] (16 x 64) . [[Rr, Ri], [-Ri, Rr]] (64 x 64)
+// X, Y: [B][32][2][2m][m] (modes contiguous); R: [2m][m][Ci][Co][2].
+// Four consecutive modes per workgroup, one per wave; the batch runs in
+// tiles of 16 rows (zero-padded).  X is read and Y written as float4 over the
+// four modes.
+constexpr int kMixLA = 64 + 4;
+__global__ void __launch_bounds__(256)
+mix_mma_kernel(const float* __restrict__ X, const float* __restrict__ R,
+               float* __restrict__ Y, int B, int plane) {
+    constexpr int C = 32, LA = kMixLA;
+    __shared__ __attribute__((aligned(16))) float As[4 * 16 * LA];   // [mode][b][k]
+    __shared__ __attribute__((aligned(16))) float Bs[4 * 64 * LA];   // [mode][n][k]
+    __shared__ __attribute__((aligned(16))) float Os[16 * 64 * 4];   // [b][n][mode]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int md0 = 4 * blockIdx.x, per = 2 * plane;
+    // B operand of the four modes: 2048 complex weights each
+    for (int e = tid; e < 4 * C * C / 2; e += 256) {
+        const int j = e >> 9, cc = (e & 511) * 2;            // two complex weights
+        const float4 w = *reinterpret_cast<const float4*>(R + (size_t)(md0 + j) * C * C * 2 + 2 * cc);
+        float* Bj = Bs + j * 64 * LA;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ci = (cc + h) >> 5, co = (cc + h) & 31;
+            const float rr = h ? w.z : w.x, ri = h ? w.w : w.y;
+            Bj[co * LA + ci] = rr;
+            Bj[(32 + co) * LA + ci] = ri;
+            Bj[co * LA + 32 + ci] = -ri;
+            Bj[(32 + co) * LA + 32 + ci] = rr;
+        }
+    }
+    for (int b0 = 0; b0 < B; b0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < 16 * C * 2; e += 256) {        // (b, c, part)
+            const int bb = e >> 6, c = (e >> 1) & 31, part = e & 1;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (b0 + bb < B)
+                x = *reinterpret_cast<const float4*>(X + ((size_t)(b0 + bb) * C + c) * per +
+                                                    part * plane + md0);
+            const int k = part * 32 + c;
+            As[(0 * 16 + bb) * LA + k] = x.x;
+            As[(1 * 16 + bb) * LA + k] = x.y;
+            As[(2 * 16 + bb) * LA + k] = x.z;
+            As[(3 * 16 + bb) * LA + k] = x.w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 c = tile_mma<true>(As + wv * 16 * LA, LA, Bs + wv * 64 * LA, LA, 0, 16 * t,
+                                           64, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Os[((4 * (lane >> 4) + q) * 64 + 16 * t + (lane & 15)) * 4 + wv] = c[q];
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * 64; e += 256) {           // (b, n = part * 32 + co)
+            const int bb = e >> 6, n = e & 63;
+            if (b0 + bb < B)
+                *reinterpret_cast<float4*>(Y + ((size_t)(b0 + bb) * C + (n & 31)) * per +
+                                           (n >> 5) * plane + md0) =
+                    *reinterpret_cast<const float4*>(Os + e * 4);
+        }
+    }
+}
+
 // ------------------------------------------------- pointwise layer path --
 // z[b][co][p] += sum_ci W[ci][co] v[b][ci][p] + bias[co] (z holds the
 // spectral path on entry); optionally gelu(z) into vn.  C = 32 channels.
@@ -1190,6 +1257,11 @@ void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, h
     hipLaunchKernelGGL(gelu_back_kernel, dim3(blocks_for(n)), dim3(256), 0, s, z, gv, gz, n);
 }
 void launch_mix(const float* X, const float* R, float* Y, int B, int C, int m, hipStream_t s) {
+    if (C == 32 && (2 * m * m) % 4 == 0) {
+        hipLaunchKernelGGL(mix_mma_kernel, dim3(2 * m * m / 4), dim3(256), 0, s, X, R, Y, B,
+                           2 * m * m);
+        return;
+    }
     const size_t lds = sizeof(float) * (2 * C * C + 2 * kMixChunk * C);
     hipLaunchKernelGGL(mix_mode_kernel, dim3(2 * m * m), dim3(256), lds, s, X, R, Y, B, C, m);
 }
