@@ -22,11 +22,12 @@ namespace mdp {
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
                     size_t lds_bytes, const InstDesc* insts,
                     const SweepWork* work, const DirTable* dt, const int* done,
-                    const int* iter, int use_faces, hipStream_t s);
+                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s);
 size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx);
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                         const int* done, const int* iter, bool tally, hipStream_t s);
+                         const int* done, const int* iter, bool tally, const FinArgs& fin,
+                         hipStream_t s);
 size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx);
 int sweep2d_max_kb(int W, int R);
 int sweep2d_fast_max_kb(int W);
@@ -608,7 +609,9 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
 }
 
 bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
-                       const int* iter, int use_faces, bool tally) {
+                       const int* iter, int use_faces, bool tally, const FinArgs* fin) {
+    FinArgs none{};
+    const FinArgs& fa = fin ? *fin : none;
     if (su.inst[0].dim == 1) {
         launch_sweep1d(n_inst, su.d_inst, su.d_dt, done, iter, use_faces, su.dt.M,
                        stream);
@@ -620,10 +623,10 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
             su.plan.fast
                 ? launch_sweep2d_fast(su.plan.D, (int)su.work.size(), su.plan.W, su.plan.KB,
                                       su.plan.lds, su.d_inst, su.d_work, su.d_dt, done, iter,
-                                      tally, stream)
+                                      tally, fa, stream)
                 : launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
                                  su.plan.W, su.plan.KB, su.plan.lds, su.d_inst, su.d_work,
-                                 su.d_dt, done, iter, use_faces, stream);
+                                 su.d_dt, done, iter, use_faces, fa, stream);
         if (!ok) {
             fail("unsupported directions-per-lane D=%d", su.plan.D);
             return false;
@@ -733,18 +736,26 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
     if (!c->hip_ok(hipGetLastError(), "init launch")) return TR_ERR_HIP;
     int* hdone = (int*)c->pinned.ptr;
     int done_iters = 0, chunk = 4;
+    const bool fused_fin = p[0].dim == 2;
     bool all = false;
     while (done_iters < max_iter && !all) {
         const int k = std::min(chunk, max_iter - done_iters);
         for (int it = 0; it < k; ++it) {
+            // 2-D: the convergence test of iteration it - 1 runs in the
+            // prologue of sweep it (FinArgs); the chunk's last iteration is
+            // tested by the finalize kernel before the flags are read back
+            const FinArgs fin{su.d_red, su.st, atol, norm_kind, fused_fin && it > 0 ? 1 : 0,
+                              done_iters + it};
             const bool p0 = c->prof_begin(0);
-            if (!c->launch_sweep(su, n_inst, su.st.done, su.st.iter, 1)) return TR_ERR_HIP;
+            if (!c->launch_sweep(su, n_inst, su.st.done, su.st.iter, 1, false, &fin))
+                return TR_ERR_HIP;
             if (p0) c->prof_end();
             const bool p1 = c->prof_begin(1);
             launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
                            su.d_red, 0, norm_kind, c->stream);
-            launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind,
-                            c->stream);
+            if (!fused_fin || it + 1 == k)
+                launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind,
+                                c->stream);
             if (p1) c->prof_end();
         }
         if (!c->hip_ok(hipGetLastError(), "iteration launch")) return TR_ERR_HIP;

@@ -84,7 +84,8 @@ struct Ctx {
                const float* const* phi_init, float* const* phi_out,
                const float* const* emission, Setup* su);
     bool launch_sweep(const Setup& su, int n_inst, const int* done,
-                      const int* iter, int use_faces, bool tally = false);
+                      const int* iter, int use_faces, bool tally = false,
+                      const FinArgs* fin = nullptr);
     tr_status scan_fields(const Setup& su, int n_inst, const tr_problem* p,
                           bool need_xs, tr_stats* stats);
 };

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(SweepBounds<D>::threads)
 sweep2d_kernel(const InstDesc* __restrict__ insts,
                const SweepWork* __restrict__ work,
                const DirTable* __restrict__ dt, const int* __restrict__ done,
-               const int* __restrict__ iter, int use_faces) {
+               const int* __restrict__ iter, int use_faces, FinArgs fin) {
     extern __shared__ float smem[];
     constexpr int lkb = KB >= 16 ? 4 : (KB >= 8 ? 3 : (KB >= 4 ? 2 : (KB >= 2 ? 1 : 0)));
     static_assert((1 << lkb) == KB, "KB must be a power of two <= 16");
@@ -102,14 +102,18 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     const SweepWork wk = work[blockIdx.x];
     const int n = wk.inst;
     if (n < 0) return;                        // XCD alignment padding
-    if (done != nullptr && done[n]) return;   // uniform over the workgroup
+    if (fin.pending) {   // uniform over the workgroup
+        if (sweep_prologue(insts[n], n, fin, wk.oct == 0 && wk.slice == 0)) return;
+    } else if (done != nullptr && done[n]) {
+        return;
+    }
     const InstDesc& I = insts[n];
     const int R = I.R, lr = __ffs(R) - 1;
     const int nseg = 64 >> lr, seg = lane >> lr, r = lane & (R - 1);
     const int o = wk.oct;
     const bool xpos = (o == 0 || o == 3), ypos = (o == 0 || o == 1);
     const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
-    const int par = (iter != nullptr ? iter[n] : 0) & 1;
+    const int par = (fin.pending ? fin.it : (iter != nullptr ? iter[n] : 0)) & 1;
     const size_t fstride = (size_t)4 * nf * M;
     cgfloat* __restrict__ fprev = (cgfloat*)(I.face + (size_t)par * fstride);
     gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(par ^ 1) * fstride);
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<D>::threads)
 sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                     const SweepWork* __restrict__ work,
                     const DirTable* __restrict__ dt, const int* __restrict__ done,
-                    const int* __restrict__ iter) {
+                    const int* __restrict__ iter, FinArgs fin) {
     extern __shared__ float smem[];
     constexpr int lkb = KB >= 16 ? 4 : (KB >= 8 ? 3 : (KB >= 4 ? 2 : (KB >= 2 ? 1 : 0)));
     static_assert((1 << lkb) == KB, "KB must be a power of two <= 16");
@@ -398,12 +402,16 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     const SweepWork wk = work[blockIdx.x];
     const int n = wk.inst;
     if (n < 0) return;
-    if (done != nullptr && done[n]) return;
+    if (fin.pending) {
+        if (sweep_prologue(insts[n], n, fin, wk.oct == 0 && wk.slice == 0)) return;
+    } else if (done != nullptr && done[n]) {
+        return;
+    }
     const InstDesc& I = insts[n];
     const int o = wk.oct;
     const bool xpos = (o == 0 || o == 3), ypos = (o == 0 || o == 1);
     const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
-    const int par = (iter != nullptr ? iter[n] : 0) & 1;
+    const int par = (fin.pending ? fin.it : (iter != nullptr ? iter[n] : 0)) & 1;
     const size_t fstride = (size_t)4 * nf * M;
     gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(TALLY ? par : par ^ 1) * fstride);
     const int fxout = xpos ? 1 : 0, fyout = ypos ? 3 : 2;
@@ -722,25 +730,25 @@ template <int D, int KB>
 static void launch_dk(bool refl, dim3 grid, dim3 block, size_t lds,
                       hipStream_t s, const InstDesc* insts,
                       const SweepWork* work, const DirTable* dt,
-                      const int* done, const int* iter, int use_faces) {
+                      const int* done, const int* iter, int use_faces, const FinArgs& fin) {
     if (refl)
         hipLaunchKernelGGL((sweep2d_kernel<D, true, KB>), grid, block, lds, s,
-                           insts, work, dt, done, iter, use_faces);
+                           insts, work, dt, done, iter, use_faces, fin);
     else
         hipLaunchKernelGGL((sweep2d_kernel<D, false, KB>), grid, block, lds, s,
-                           insts, work, dt, done, iter, use_faces);
+                           insts, work, dt, done, iter, use_faces, fin);
 }
 
 template <int D>
 static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
                      hipStream_t s, const InstDesc* insts,
                      const SweepWork* work, const DirTable* dt,
-                     const int* done, const int* iter, int use_faces) {
+                     const int* done, const int* iter, int use_faces, const FinArgs& fin) {
     switch (KB) {
-        case 16: launch_dk<D, 16>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
-        case 8: launch_dk<D, 8>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
-        case 4: launch_dk<D, 4>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
-        case 2: launch_dk<D, 2>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces); return true;
+        case 16: launch_dk<D, 16>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 8: launch_dk<D, 8>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 4: launch_dk<D, 4>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 2: launch_dk<D, 2>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
         default: return false;
     }
 }
@@ -748,12 +756,12 @@ static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
 template <int D, int WT, bool TALLY>
 static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                            const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                           const int* done, const int* iter) {
+                           const int* done, const int* iter, const FinArgs& fin) {
     switch (KB) {
-        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
-        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter); return true;
+        case 16: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 16, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter, fin); return true;
+        case 8: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 8, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter, fin); return true;
+        case 4: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 4, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter, fin); return true;
+        case 2: hipLaunchKernelGGL((sweep2d_fast_kernel<D, 2, WT, TALLY>), grid, block, lds, s, insts, work, dt, done, iter, fin); return true;
         default: return false;
     }
 }
@@ -765,26 +773,27 @@ static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_
 template <int D>
 static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                          const int* done, const int* iter, bool tally) {
+                          const int* done, const int* iter, bool tally, const FinArgs& fin) {
     const int W = (int)block.x / 64;
     if (tally)
-        return launch_fast_dw<D, 0, true>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+        return launch_fast_dw<D, 0, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
     if (D == 1 && W == 9)
-        return launch_fast_dw<D, 9, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+        return launch_fast_dw<D, 9, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
     if (D == 1 && W == 10)
-        return launch_fast_dw<D, 10, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
-    return launch_fast_dw<D, 0, false>(KB, grid, block, lds, s, insts, work, dt, done, iter);
+        return launch_fast_dw<D, 10, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+    return launch_fast_dw<D, 0, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
 }
 
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
-                         const int* done, const int* iter, bool tally, hipStream_t s) {
+                         const int* done, const int* iter, bool tally, const FinArgs& fin,
+                         hipStream_t s) {
     dim3 grid(nwork), block(64 * W);
     switch (D) {
-        case 1: return launch_fast_d<1>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
-        case 2: return launch_fast_d<2>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
-        case 3: return launch_fast_d<3>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
-        case 4: return launch_fast_d<4>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally);
+        case 1: return launch_fast_d<1>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally, fin);
+        case 2: return launch_fast_d<2>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally, fin);
+        case 3: return launch_fast_d<3>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally, fin);
+        case 4: return launch_fast_d<4>(KB, grid, block, lds_bytes, s, insts, work, dt, done, iter, tally, fin);
         default: return false;
     }
 }
@@ -797,15 +806,15 @@ size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx) {
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
                     size_t lds_bytes, const InstDesc* insts,
                     const SweepWork* work, const DirTable* dt, const int* done,
-                    const int* iter, int use_faces, hipStream_t s) {
+                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s) {
     dim3 grid(nwork), block(64 * W);
     switch (D) {
-        case 1: return launch_d<1>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
-        case 2: return launch_d<2>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
-        case 3: return launch_d<3>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
-        case 4: return launch_d<4>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
-        case 6: return launch_d<6>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
-        case 9: return launch_d<9>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces);
+        case 1: return launch_d<1>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
+        case 2: return launch_d<2>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
+        case 3: return launch_d<3>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
+        case 4: return launch_d<4>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
+        case 6: return launch_d<6>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
+        case 9: return launch_d<9>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
         default: return false;
     }
 }
