@@ -169,6 +169,22 @@ def test_training_reduces_loss(env):
     m.close()
 
 
+def test_forward_parity_two_row_tiles(env):
+    """A batch of 20 spans two 16-row tiles of the per-mode mixing (the
+    second one ragged): FP32-operand forward against the FP64 oracle."""
+    torch, B, ctx = env
+    p = _params(11)
+    x = _fields(20, 1500)
+    m = B.Model(ctx, p)
+    m.set_fp32(True)
+    out = m.forward(_dev(torch, x)).cpu().numpy()
+    ref, _ = F.forward(p.astype(np.float64), F.make_input(x), LAY)
+    e = rel_l2(out, ref)
+    log(f"  forward batch 20 fp32: rel_l2={e:.3e}")
+    assert e < 1e-5
+    m.close()
+
+
 def test_forward_batch_independent(env):
     """A batch entry's output does not depend on its neighbours."""
     torch, B, ctx = env
