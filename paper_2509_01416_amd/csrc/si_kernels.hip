@@ -147,15 +147,7 @@ struct CellAcc {
     double s1 = 0.0, s2 = 0.0;
 };
 
-__device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
-                                             int mode, int norm_kind, CellAcc& a) {
-    if (mode == 1) {
-        I.phi[c] = s;
-        return;
-    }
-    const float old = I.phi[c];
-    I.phi[c] = s;
-    I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
+__device__ __forceinline__ void combine_norm(float old, float s, int norm_kind, CellAcc& a) {
     const double d = (double)s - (double)old;
     if (norm_kind == 0) {
         a.s1 += d * d;
@@ -165,6 +157,18 @@ __device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
         const double rel = as > 0.0 ? fabs(d) / as : (d != 0.0 ? INFINITY : 0.0);
         a.s1 = fmax(a.s1, rel);
     }
+}
+
+__device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
+                                             int mode, int norm_kind, CellAcc& a) {
+    if (mode == 1) {
+        I.phi[c] = s;
+        return;
+    }
+    const float old = I.phi[c];
+    I.phi[c] = s;
+    I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
+    combine_norm(old, s, norm_kind, a);
 }
 
 __global__ void __launch_bounds__(kCombineThreads)
@@ -179,29 +183,48 @@ combine_kernel(const InstDesc* __restrict__ insts,
     const int cells = I.cells, P = I.P;
     const int c1 = min(bi.y + kCombineChunk, cells);
     CellAcc acc;
-    if ((cells & 3) == 0) {
+    const bool al16 = ((reinterpret_cast<uintptr_t>(I.phi) | reinterpret_cast<uintptr_t>(I.ss) |
+                        reinterpret_cast<uintptr_t>(I.q) | reinterpret_cast<uintptr_t>(I.Q)) &
+                       15) == 0;
+    if ((cells & 3) == 0 && (al16 || mode == 1) &&
+        (reinterpret_cast<uintptr_t>(I.phi) & 15) == 0) {
+        // four cells per thread: every plane load of a thread in flight at
+        // once (8 at a time), the cell fields read and written as float4
         const float4* pl = reinterpret_cast<const float4*>(I.part);
         const int q4 = cells >> 2;
         for (int c = bi.y + 4 * (int)threadIdx.x; c < c1; c += 4 * kCombineThreads) {
             const float4* pp = pl + (c >> 2);
             float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
             int p = 0;
-            for (; p + 4 <= P; p += 4) {
-                const float4 v0 = pp[(size_t)p * q4], v1 = pp[(size_t)(p + 1) * q4];
-                const float4 v2 = pp[(size_t)(p + 2) * q4], v3 = pp[(size_t)(p + 3) * q4];
-                s.x += v0.x; s.y += v0.y; s.z += v0.z; s.w += v0.w;
-                s.x += v1.x; s.y += v1.y; s.z += v1.z; s.w += v1.w;
-                s.x += v2.x; s.y += v2.y; s.z += v2.z; s.w += v2.w;
-                s.x += v3.x; s.y += v3.y; s.z += v3.z; s.w += v3.w;
+            for (; p + 8 <= P; p += 8) {
+                float4 v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = pp[(size_t)(p + j) * q4];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    s.x += v[j].x; s.y += v[j].y; s.z += v[j].z; s.w += v[j].w;
+                }
             }
             for (; p < P; ++p) {
                 const float4 v = pp[(size_t)p * q4];
                 s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
             }
-            combine_cell(I, c, s.x, mode, norm_kind, acc);
-            combine_cell(I, c + 1, s.y, mode, norm_kind, acc);
-            combine_cell(I, c + 2, s.z, mode, norm_kind, acc);
-            combine_cell(I, c + 3, s.w, mode, norm_kind, acc);
+            float4* phi4 = reinterpret_cast<float4*>(I.phi) + (c >> 2);
+            if (mode == 1) {
+                *phi4 = s;
+                continue;
+            }
+            const float4 old = *phi4;
+            const float4 ss = reinterpret_cast<const float4*>(I.ss)[c >> 2];
+            const float4 qq = reinterpret_cast<const float4*>(I.q)[c >> 2];
+            *phi4 = s;
+            reinterpret_cast<float4*>(I.Q)[c >> 2] =
+                make_float4(fmaf(ss.x, s.x, qq.x), fmaf(ss.y, s.y, qq.y),
+                            fmaf(ss.z, s.z, qq.z), fmaf(ss.w, s.w, qq.w));
+            combine_norm(old.x, s.x, norm_kind, acc);
+            combine_norm(old.y, s.y, norm_kind, acc);
+            combine_norm(old.z, s.z, norm_kind, acc);
+            combine_norm(old.w, s.w, norm_kind, acc);
         }
     } else {
         for (int c = bi.y + threadIdx.x; c < c1; c += kCombineThreads) {
