@@ -250,118 +250,11 @@ __global__ void lift_kernel(const float* __restrict__ in, const float* __restric
         fmaf(W0[c], in[(size_t)b * P + p], fmaf(W0[C + c], x, fmaf(W0[2 * C + c], y, b0[c])));
 }
 
-__global__ void gelu_kernel(const float* __restrict__ z, float* __restrict__ v, long long n) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-         e += (long long)gridDim.x * blockDim.x)
-        v[e] = gelu_f(z[e]);
-}
-
 __global__ void gelu_back_kernel(const float* __restrict__ z, const float* __restrict__ gv,
                                  float* __restrict__ gz, long long n) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
          e += (long long)gridDim.x * blockDim.x)
         gz[e] = gv[e] * gelu_grad_f(z[e]);
-}
-
-// Per-mode complex mixing.  X, Y: [B][C][2 (re,im)][2m (ky)][m (kx)];
-// R: [2 blk][m][m][Ci][Co][2] (the flat parameter layout).
-__global__ void mix_kernel(const float* __restrict__ X, const float* __restrict__ R,
-                           float* __restrict__ Y, int B, int C, int m) {
-    const int modes = 2 * m * m;
-    const long long total = (long long)B * C * modes;
-    const int per = 2 * 2 * m * m;   // floats per (b, c)
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int md = (int)(e % modes);
-        const int o = (int)((e / modes) % C);
-        const int b = (int)(e / ((long long)modes * C));
-        const int kyi = md / m, kx = md - kyi * m;   // kyi in [0, 2m)
-        const int blk = kyi / m, ky = kyi - blk * m;
-        const float* w = R + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
-        float yr = 0.f, yi = 0.f;
-        for (int i = 0; i < C; ++i) {
-            const float* xb = X + ((long long)b * C + i) * per;
-            const float xr = xb[kyi * m + kx], xi = xb[2 * m * m + kyi * m + kx];
-            const float wr = w[(i * C + o) * 2], wi = w[(i * C + o) * 2 + 1];
-            yr = fmaf(xr, wr, fmaf(-xi, wi, yr));
-            yi = fmaf(xr, wi, fmaf(xi, wr, yi));
-        }
-        float* yb = Y + ((long long)b * C + o) * per;
-        yb[kyi * m + kx] = yr;
-        yb[2 * m * m + kyi * m + kx] = yi;
-    }
-}
-
-// gX[b][i] = sum_o gY[b][o] conj(R[i][o])
-__global__ void mix_back_x_kernel(const float* __restrict__ gY, const float* __restrict__ R,
-                                  float* __restrict__ gX, int B, int C, int m) {
-    const int modes = 2 * m * m;
-    const long long total = (long long)B * C * modes;
-    const int per = 2 * 2 * m * m;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int md = (int)(e % modes);
-        const int i = (int)((e / modes) % C);
-        const int b = (int)(e / ((long long)modes * C));
-        const int kyi = md / m, kx = md - kyi * m;
-        const int blk = kyi / m, ky = kyi - blk * m;
-        const float* w = R + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
-        float gr = 0.f, gi = 0.f;
-        for (int o = 0; o < C; ++o) {
-            const float* gb = gY + ((long long)b * C + o) * per;
-            const float yr = gb[kyi * m + kx], yi = gb[2 * m * m + kyi * m + kx];
-            const float wr = w[(i * C + o) * 2], wi = w[(i * C + o) * 2 + 1];
-            gr = fmaf(yr, wr, fmaf(yi, wi, gr));      // (yr + i yi)(wr - i wi)
-            gi = fmaf(yi, wr, fmaf(-yr, wi, gi));
-        }
-        float* xb = gX + ((long long)b * C + i) * per;
-        xb[kyi * m + kx] = gr;
-        xb[2 * m * m + kyi * m + kx] = gi;
-    }
-}
-
-// gR[i][o] = sum_b conj(X[b][i]) gY[b][o]  (batch order fixed)
-__global__ void mix_back_w_kernel(const float* __restrict__ X, const float* __restrict__ gY,
-                                  float* __restrict__ gR, int B, int C, int m) {
-    const int modes = 2 * m * m;
-    const long long total = (long long)modes * C * C;
-    const int per = 2 * 2 * m * m;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int o = (int)(e % C);
-        const int i = (int)((e / C) % C);
-        const int md = (int)(e / ((long long)C * C));
-        const int kyi = md / m, kx = md - kyi * m;
-        const int blk = kyi / m, ky = kyi - blk * m;
-        float gr = 0.f, gi = 0.f;
-        for (int b = 0; b < B; ++b) {
-            const float* xb = X + ((long long)b * C + i) * per;
-            const float* yb = gY + ((long long)b * C + o) * per;
-            const float xr = xb[kyi * m + kx], xi = xb[2 * m * m + kyi * m + kx];
-            const float yr = yb[kyi * m + kx], yi = yb[2 * m * m + kyi * m + kx];
-            gr = fmaf(xr, yr, fmaf(xi, yi, gr));      // (xr - i xi)(yr + i yi)
-            gi = fmaf(xr, yi, fmaf(-xi, yr, gi));
-        }
-        float* w = gR + ((((long long)blk * m + ky) * m + kx) * C) * C * 2;
-        w[(i * C + o) * 2] = gr;
-        w[(i * C + o) * 2 + 1] = gi;
-    }
-}
-
-// out[b][p] = sum_k P2[k] gelu(h[b][k][p]) + c2
-__global__ void proj_out_kernel(const float* __restrict__ h, const float* __restrict__ P2,
-                                const float* __restrict__ c2, float* __restrict__ out,
-                                int B, int P, int K) {
-    const long long total = (long long)B * P;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int p = (int)(e % P);
-        const int b = (int)(e / P);
-        const float* hb = h + (long long)b * K * P + p;
-        float s = 0.f;
-        for (int k = 0; k < K; ++k) s = fmaf(P2[k], gelu_f(hb[(long long)k * P]), s);
-        out[e] = s + c2[0];
-    }
 }
 
 // gh[b][k][p] = gout[b][p] P2[k] gelu'(h)
@@ -673,17 +566,12 @@ __global__ void bilinear_up_kernel(const float* __restrict__ coarse, int nc, int
     }
 }
 
-__global__ void scale_kernel(float* __restrict__ x, float s, long long n) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-         e += (long long)gridDim.x * blockDim.x)
-        x[e] *= s;
-}
-
-// ---------------------------------------------------- per-mode mixing v2 --
+// ------------------------------------------------------- per-mode mixing --
 // One workgroup per retained mode (kyi, kx): that mode's weights
 // R[i][o] (32 x 32 complex, contiguous in the parameter vector) and the
 // batch's mode values are staged in LDS; the batch is processed in chunks of
-// kMixChunk samples.  Layouts as in mix_kernel.
+// kMixChunk samples.  X, Y: [B][C][2 (re,im)][2m (ky)][m (kx)];
+// R: [2 blk][m][m][Ci][Co][2] (the flat parameter layout).
 constexpr int kMixChunk = 64;
 
 __global__ void __launch_bounds__(256)
@@ -1250,9 +1138,6 @@ void launch_lift(const float* in, const float* W0, const float* b0, float* out, 
                            in + b0i * P, W0, b0, out + b0i * P * C, nb, n, C);
     }
 }
-void launch_gelu(const float* z, float* v, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(gelu_kernel, dim3(blocks_for(n)), dim3(256), 0, s, z, v, n);
-}
 void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, hipStream_t s) {
     hipLaunchKernelGGL(gelu_back_kernel, dim3(blocks_for(n)), dim3(256), 0, s, z, gv, gz, n);
 }
@@ -1325,11 +1210,6 @@ void launch_proj_fused(const float* v, const float* P1, const float* c1, const f
         hipLaunchKernelGGL(proj_fused_kernel<false>, grid, dim3(256), 0, s, v, P1, c1, P2, c2,
                            out, h_out, P);
 }
-void launch_proj_out(const float* h, const float* P2, const float* c2, float* out, int B,
-                     int P, int K, hipStream_t s) {
-    hipLaunchKernelGGL(proj_out_kernel, dim3(blocks_for((long long)B * P)), dim3(256), 0, s, h,
-                       P2, c2, out, B, P, K);
-}
 void launch_proj_back(const float* h, const float* P2, const float* gout, float* gh, int B,
                       int P, int K, hipStream_t s) {
     hipLaunchKernelGGL(proj_back_kernel, dim3(blocks_for((long long)B * K * P)), dim3(256), 0,
@@ -1393,9 +1273,6 @@ void launch_bilinear_up(const float* coarse, int nc, int f, float* fine, float s
     const long long P = (long long)nc * f * nc * f;
     hipLaunchKernelGGL(bilinear_up_kernel, dim3(blocks_for(P)), dim3(256), 0, s, coarse, nc, f,
                        fine, scale);
-}
-void launch_scale(float* x, float sc, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, sc, n);
 }
 
 }  // namespace mdp

@@ -37,18 +37,17 @@ struct GemmArgs {
 bool launch_gemm(const GemmArgs& a, hipStream_t s);
 void launch_lift(const float* in, const float* W0, const float* b0, float* out, int B,
                  int n, int C, hipStream_t s);
-void launch_gelu(const float* z, float* v, long long n, hipStream_t s);
 void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, hipStream_t s);
 void launch_mix(const float* X, const float* R, float* Y, int B, int C, int m, hipStream_t s);
 void launch_mix_back_x(const float* gY, const float* R, float* gX, int B, int C, int m,
                        hipStream_t s);
 void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C, int m,
                        hipStream_t s);
-// Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
-// inverse, each in one kernel (layouts as the batched GEMM path).
 // Pointwise path of a Fourier layer for C = 32 channels and P % 64 == 0.
 void launch_pointwise(const float* W, const float* v, const float* bias, float* z, float* vn,
                       int B, int P, int store_z, int f32, hipStream_t s);
+// Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
+// inverse, each in one kernel (layouts as the batched GEMM path).
 size_t spec_image_bytes();   // FP32 + BF16 LDS images of the DFT matrices
 void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const float* Gx,
                        void* img, hipStream_t s);
@@ -58,8 +57,6 @@ void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, 
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,
                        hipStream_t s);
-void launch_proj_out(const float* h, const float* P2, const float* c2, float* out, int B,
-                     int P, int K, hipStream_t s);
 void launch_proj_back(const float* h, const float* P2, const float* gout, float* gh, int B,
                       int P, int K, hipStream_t s);
 // scratch (device, >= 4 * max(R, C) * B * P / 1024 floats) selects the
@@ -81,6 +78,5 @@ void launch_block_average(const float* fine, int nf_x, int f, float* coarse, int
                           const float* sub, int mode, hipStream_t s);
 void launch_bilinear_up(const float* coarse, int nc, int f, float* fine, float scale,
                         hipStream_t s);
-void launch_scale(float* x, float sc, long long n, hipStream_t s);
 
 }  // namespace mdp
