@@ -75,3 +75,16 @@ def test_check_args_1d():
     q = B.Quad(gl.mu, None, gl.w)
     rc, msg = B.tr_check_args(_prob(nx=200, ny=1, dim=1), 1, q, -1e-8, 100)
     assert rc == B.TR_OK, msg
+
+
+def test_check_args_rejects_empty_and_mixed_batches():
+    q = B.Quad.from_inputs(I.level_symmetric_2d(8))
+    rc, msg = B.tr_check_args(_prob(), 0, q, 1e-6, 100)
+    assert rc == B.TR_ERR_INVALID_ARG and "n_inst" in msg
+    arr = (B.TrProblem * 2)()
+    for k, dim in enumerate((2, 1)):
+        arr[k].dim, arr[k].nx, arr[k].ny = dim, 8, 8 if dim == 2 else 1
+        arr[k].lx = arr[k].ly = 1.0
+        arr[k].sigma_t = arr[k].sigma_s = arr[k].source = 0x1000
+    rc, msg = B.tr_check_args(arr, 2, q, 1e-6, 100)
+    assert rc == B.TR_ERR_INVALID_ARG and "share dim" in msg

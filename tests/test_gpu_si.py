@@ -328,3 +328,77 @@ def test_not_converged_and_errors(env):
     with pytest.raises(B.MdpError) as e:
         _solve(env, [sing], quad, 1e-6)
     assert e.value.status == B.TR_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("W", [9, 10])
+def test_full_batch_in_benchmark_launch_shapes(env, W):
+    """The benchmark batch itself (16 instances of 256 x 256, S16, c = 0.99,
+    two-region sigma_t) in the launch shapes the autotuner picks for it
+    (D = 1, W = 9 or 10 waves, S = 4 slices, 64-row segments, KB = 16): one
+    sweep of a seeded emission matches the oracle's sweep in every cell of
+    every instance; a zero-start solve to 1e-6 closes the particle balance of
+    every instance, and sampled instances (first, middle, last) are fixed
+    points of one FP64 oracle sweep to within what the stopping rule
+    leaves."""
+    torch, B, ctx = env
+    log(f"[tr_sweep/tr_solve] benchmark batch 16 x 256^2 S16, W={W}")
+    wl = I.hard_two_region(16, 256)
+    quad = wl.quad
+    probs = [to_problem(i, torch) for i in wl.instances]
+    q = B.Quad.from_inputs(quad)
+    ctx.set_sweep_config(1, W, 4, 64)
+    try:
+        plan = ctx.sweep_plan(probs, q)
+        assert plan == dict(D=1, W=W, S=4, R=64, KB=16, specialised=1)
+        _sweep_case(env, wl.instances, quad)
+        phis = [torch.zeros_like(p.sigma_t) for p in probs]
+        rc, st = B.tr_solve(ctx, probs, q, None, phis, 1e-6, 2000)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+    assert rc == B.TR_OK
+    its = [s["iterations"] for s in st]
+    worst_bal = max(s["balance_rel"] for s in st)
+    log(f"  iterations {min(its)}..{max(its)}, worst balance {worst_bal:.2e}")
+    assert worst_bal < 1e-4
+    for k in (0, 7, 15):
+        inst = wl.instances[k]
+        phi = phis[k].cpu().numpy().astype(np.float64)
+        st64 = np.asarray(inst.sigma_t, np.float32).astype(np.float64)
+        ss64 = np.asarray(inst.sigma_s, np.float32).astype(np.float64)
+        q64 = np.asarray(inst.source, np.float32).astype(np.float64)
+        nxt = oracle.sweep2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
+                             st64, ss64 * phi + q64)
+        r = rel_l2(nxt, phi)
+        log(f"  instance {k}: {its[k]} iterations, one FP64 oracle sweep changes it by {r:.2e}")
+        assert r < 5e-6
+
+
+def test_widest_grid_of_the_specialised_kernel(env):
+    """A 32768 x 64 grid (S4, one instance): the specialised kernel's LDS
+    ring holds nx + KB values per wave (139 KB of the 160 KB per workgroup
+    at this width, one wave per workgroup); the sweep matches the oracle."""
+    torch, B, ctx = env
+    log("[tr_sweep] 32768 x 64 S4")
+    inst = I.random_instance(32768, 64, seed=4242, lx=400.0, ly=5.0)
+    quad = I.level_symmetric_2d(4)
+    plan = ctx.sweep_plan([to_problem(inst, torch)], B.Quad.from_inputs(quad))
+    assert plan["specialised"] == 1
+    _sweep_case(env, [inst], quad)
+
+
+def test_too_wide_grid_is_rejected_before_launch(env):
+    """A grid whose LDS ring cannot fit in any launch shape is an argument
+    error with a message, and the context stays usable."""
+    torch, B, ctx = env
+    log("[tr_sweep] 40000 x 64 must be rejected")
+    inst = I.random_instance(40000, 64, seed=5, lx=400.0, ly=5.0)
+    quad = I.level_symmetric_2d(4)
+    p = to_problem(inst, torch)
+    em = torch.ones_like(p.sigma_t)
+    out = torch.zeros_like(em)
+    with pytest.raises(B.MdpError) as e:
+        B.tr_sweep(ctx, [p], B.Quad.from_inputs(quad), [em], [out])
+    assert e.value.status == B.TR_ERR_INVALID_ARG and "too wide" in str(e.value)
+    small = I.random_instance(24, 16, seed=6)
+    _sweep_case(env, [small], quad)
