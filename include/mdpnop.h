@@ -87,7 +87,10 @@ const char *tr_last_error(const tr_context *ctx);
  * phi_out[i] = sum_m w_m psi_m at cell centres.  sigma_s and source of the
  * problems are not read.  Reflective faces receive zero incoming flux (there
  * is no previous sweep); vacuum faces zero as always.
- * Returns TR_OK or an error.                                                */
+ * Returns TR_OK or an error.  A 2-D grid too wide for the sweep's on-chip
+ * face ring (about 38,000 cells in x at 160 KB of LDS per workgroup) is
+ * rejected with TR_ERR_INVALID_ARG before anything is launched; the same
+ * holds for tr_solve.                                                       */
 tr_status tr_sweep(tr_context *ctx, int32_t n_inst, const tr_problem *p,
                    const tr_quadrature *q, const float *const *emission,
                    float *const *phi_out);
