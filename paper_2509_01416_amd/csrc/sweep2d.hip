@@ -40,7 +40,7 @@ constexpr int kMaxPrefetch = 4;   // staged values per thread per block
 constexpr int kMaxRed = 2;        // reduced outputs per thread per block
 constexpr int kMaxPos = 4;        // staging/reduction positions per helper thread
 #ifndef MDP_STEP_AHEAD
-#define MDP_STEP_AHEAD 4
+#define MDP_STEP_AHEAD 6
 #endif
 #ifndef MDP_HELPER_SPLIT
 #define MDP_HELPER_SPLIT 1
@@ -435,15 +435,16 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         c[d] = a[d] + b[d];
     }
 
-    // LDS: pbuf[2][W*64][KB+1] | sbuf[2][KB][65 float2] | ring[W][D][nx+KB]
+    // LDS: pbuf[2][W*64][KB+1] | sbuf[2][KB/2][65 float4] | ring[W][D][nx+KB]
     //      | yob[W*64][D][KB+1]
-    // sbuf holds (sigma_t, Q) pairs, one 8-byte read per lane and step; its
-    // 65-pair rows keep the staging stores (consecutive threads step
-    // through a row's KB steps) free of bank conflicts.
+    // sbuf holds the (sigma_t, Q) pairs of steps 2k and 2k+1 of a row side
+    // by side, one 16-byte read per lane and two steps; its 65-entry rows
+    // keep the staging stores (consecutive threads step through a row's KB
+    // steps) free of bank conflicts.
     constexpr int SROW = 65;
     const int RS = nx + KB;
     float* pbuf = smem;
-    float2* sbuf = reinterpret_cast<float2*>(smem + 2 * W * 64 * PST);
+    float4* sbuf = reinterpret_cast<float4*>(smem + 2 * W * 64 * PST);
     float* ringw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)(wv * D) * RS;
     float* yobw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)W * D * RS +
                   (size_t)(wv * 64) * D * PST;
@@ -498,7 +499,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         cva[jx] = jx < nsl && t2 - rr >= 0;
         rva[jx] = false;
         rof[jx] = 0;
-        sad[jx] = (unsigned)(t2 * SROW + rr) * 8u;
+        sad[jx] = (unsigned)((t2 >> 1) * SROW + rr) * 16u + (unsigned)(t2 & 1) * 8u;
         rad[jx] = (unsigned)(rr * PST + t2) * 4u;
         pst[jx] = 1.f;
         pq[jx] = 0.f;
@@ -559,9 +560,10 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     };
     int kflush = 0;
 
-    // one step: e = this lane's restart step in the block; ring/pw/yol are
-    // the per-block bases; (st, q, rv) were loaded on an earlier step
-    auto math = [&](int tt, int e, float st, float q, const float* rv, float* pw) {
+    // one step: e = this lane's restart step in the block; (st, q, rv) were
+    // loaded on an earlier step; returns this lane's weighted flux sum (the
+    // y outflows are left in yo)
+    auto math = [&](int tt, int e, float st, float q, const float* rv) {
         float yi[D];
 #pragma unroll
         for (int d = 0; d < D; ++d)
@@ -583,9 +585,7 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             yo[d] = fmaf(psi, 2.0f, -yi[d]);
             acc = fmaf(w[d], psi, acc);
         }
-        pw[tt] = acc;
-#pragma unroll
-        for (int d = 0; d < D; ++d) yol[d * PST + tt] = yo[d];
+        return acc;
     };
 
     int ip0b = 0;                                  // lane 0's column at tt = 0
@@ -595,40 +595,71 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         const bool more = t0 + KB < T;
         int e = lane - ip0b;
         if (e < 0) e += nx;                        // restart step of this lane
-        const float2* sp = sbuf + half * KB * SROW + lane;
+        const float4* sp = sbuf + half * (KB / 2) * SROW + lane;   // step pair k: sp[k*SROW]
         float* pw = pbuf + ((size_t)(half * W + wv) * 64 + lane) * PST;
         const float* rg = ringw + ip0b;            // ring column of step tt: rg[d*RS + tt]
         if (tend == KB) {
-            // the LDS reads of step tt + A are issued before the arithmetic
-            // of step tt (A = kStepAhead), so their latency hides behind A
-            // steps of this wave
+            // LDS traffic goes in pairs of steps: one 16-byte read of both
+            // steps' (sigma_t, Q), one two-word read of their ring values,
+            // and after the odd step one two-word write each of the flux
+            // sums and the y outflows.  The reads of steps tt + A, tt + A + 1
+            // are issued before the arithmetic of step tt (A = kStepAhead),
+            // so their latency hides behind A steps of this wave.
             constexpr int A = kStepAhead < KB ? kStepAhead : KB;
-            float2 sq[A + 1];
-            float rv[A + 1][D];
+            static_assert(KB >= 2 && A % 2 == 0, "steps go in pairs");
+            float4 sq[A / 2 + 1];
+            float rv[A + 2][D];
+            float accp = 0.f, yop[D];
+#pragma unroll
+            for (int k = 0; k < A / 2; ++k) sq[k] = sp[k * SROW];
 #pragma unroll
             for (int k = 0; k < A; ++k) {
-                sq[k] = sp[k * SROW];
 #pragma unroll
                 for (int d = 0; d < D; ++d) rv[k][d] = rg[d * RS + k];
             }
 #pragma unroll
             for (int tt = 0; tt < KB; ++tt) {
+                const bool odd = tt & 1;
                 if (tt == 0) {
                     advance(t0 + KB);
                     if (more) stage_load();
                 }
-                if (tt + A < KB) {
-                    sq[A] = sp[(tt + A) * SROW];
+                if (!odd && tt + A < KB) {
+                    sq[A / 2] = sp[((tt + A) >> 1) * SROW];
 #pragma unroll
-                    for (int d = 0; d < D; ++d) rv[A][d] = rg[d * RS + tt + A];
+                    for (int d = 0; d < D; ++d) {
+                        rv[A][d] = rg[d * RS + tt + A];
+                        rv[A + 1][d] = rg[d * RS + tt + A + 1];
+                    }
                 }
-                math(tt, e, sq[0].x, sq[0].y, rv[0], pw);
-                if (tt == KB - 1 && more) stage_store(half ^ 1);
+                const float acc = math(tt, e, odd ? sq[0].z : sq[0].x,
+                                       odd ? sq[0].w : sq[0].y, rv[0]);
+                if (odd) {
+                    pw[tt - 1] = accp;
+                    pw[tt] = acc;
 #pragma unroll
-                for (int k = 0; k < A; ++k) {
-                    sq[k] = sq[k + 1];
+                    for (int d = 0; d < D; ++d) {
+                        yol[d * PST + tt - 1] = yop[d];
+                        yol[d * PST + tt] = yo[d];
+                    }
+                } else {
+                    accp = acc;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) yop[d] = yo[d];
+                }
+                if (tt == KB - 1 && more) stage_store(half ^ 1);
+                // a scheduling fence after each pair keeps the reads where
+                // they are written above (the scheduler otherwise moves some
+                // of them next to their uses)
+                if (odd) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k <= A; ++k) {
 #pragma unroll
                     for (int d = 0; d < D; ++d) rv[k][d] = rv[k + 1][d];
+                }
+                if (odd) {
+#pragma unroll
+                    for (int k = 0; k < A / 2; ++k) sq[k] = sq[k + 1];
                 }
             }
         } else {
@@ -637,8 +668,11 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                 float rv[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) rv[d] = rg[d * RS + tt];
-                const float2 sq = sp[tt * SROW];
-                math(tt, e, sq.x, sq.y, rv, pw);
+                const float4 sq = sp[(tt >> 1) * SROW];
+                const bool odd = tt & 1;
+                pw[tt] = math(tt, e, odd ? sq.z : sq.x, odd ? sq.w : sq.y, rv);
+#pragma unroll
+                for (int d = 0; d < D; ++d) yol[d * PST + tt] = yo[d];
             }
         }
         // lane 63's y outflow of this block into the ring (and its mirror);
