@@ -491,8 +491,13 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     float pst[kMaxPos], pq[kMaxPos];
 #pragma unroll
     for (int jx = 0; jx < kMaxPos; ++jx) {
-        const int p = (sbase + jx) * 64 + lane;
-        const int rr = (p >> lkb) & (R - 1), t2 = p & (KB - 1);
+        // slot sl holds rows sl, sl + KB, sl + 2 KB, ... (KB >= 8): the two
+        // rows of a half-wave then sit 16 banks apart at the 17-word row
+        // pitch of the partial sums, so the cross-wave sums read without
+        // bank conflicts (adjacent rows would collide once per half-wave)
+        const int sl = sbase + jx, t2 = lane & (KB - 1);
+        const int rr = KB >= 8 ? ((lane >> lkb) * KB + sl) & (R - 1)
+                               : (((sl * 64 + lane) >> lkb) & (R - 1));
         cip[jx] = t2 - rr;
         clo[jx] = rr - t2;
         cof[jx] = 4 * ((j0 + jsg * rr) * nx + i0 + isg * (t2 - rr));
