@@ -899,42 +899,100 @@ extern "C" tr_status tr_autotune(tr_context* ctx, int32_t n_inst, const tr_probl
     if (!c->hip_ok(hipEventCreate(&e0), "event") || !c->hip_ok(hipEventCreate(&e1), "event")) {
         rc = TR_ERR_HIP;
     } else if (p[0].dim == 2) {
+        // time one (D, W) shape: one untimed sweep, then `nrep` timed ones;
+        // returns ms per sweep, -1 if the shape is not feasible, -2 on a
+        // HIP error
+        auto time_shape = [&](int D, int W, int nrep, std::array<int, 5>* key) -> double {
+            c->force_D = D;
+            c->force_W = W;
+            c->force_S = 0;
+            c->force_R = sR;
+            Setup su;
+            if (!c->setup(n_inst, p, q, nullptr, outs.data(), em.data(), &su)) {
+                c->err.clear();
+                return -1.0;   // shape not feasible (LDS)
+            }
+            if (key)
+                *key = {su.plan.D, su.plan.W, su.plan.S[0], su.plan.KB, su.plan.fast ? 1 : 0};
+            if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return -2.0;
+            (void)hipEventRecord(e0, c->stream);
+            for (int r = 0; r < nrep; ++r)
+                if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return -2.0;
+            (void)hipEventRecord(e1, c->stream);
+            if (!c->hip_ok(hipEventSynchronize(e1), "sync")) return -2.0;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            return (double)ms / nrep;
+        };
+        struct Cand { int D, W; double ms; };
+        std::vector<Cand> cands;
         const int Ds[] = {1, 2, 3, 4};
         const int Ws[] = {0, 4, 6, 8, 9, 10, 12, 16};
         for (int D : Ds) {
             for (int W : Ws) {
                 if (W > sweep2d_max_w(D)) continue;
-                c->force_D = D;
-                c->force_W = W;
-                c->force_S = 0;
-                c->force_R = sR;
-                Setup su;
-                if (!c->setup(n_inst, p, q, nullptr, outs.data(), em.data(), &su)) {
-                    c->err.clear();
-                    continue;   // shape not feasible (LDS)
+                std::array<int, 5> key{};
+                // feasibility and the resolved shape first (no launch)
+                {
+                    c->force_D = D;
+                    c->force_W = W;
+                    c->force_S = 0;
+                    c->force_R = sR;
+                    Setup su;
+                    if (!c->setup(n_inst, p, q, nullptr, outs.data(), em.data(), &su)) {
+                        c->err.clear();
+                        continue;
+                    }
+                    key = {su.plan.D, su.plan.W, su.plan.S[0], su.plan.KB, su.plan.fast ? 1 : 0};
                 }
-                const std::array<int, 5> key = {su.plan.D, su.plan.W, su.plan.S[0],
-                                                su.plan.KB, su.plan.fast ? 1 : 0};
                 if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
                 seen.push_back(key);
-                if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) { rc = TR_ERR_HIP; break; }
-                (void)hipEventRecord(e0, c->stream);
-                for (int r = 0; r < reps; ++r)
-                    if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) { rc = TR_ERR_HIP; break; }
-                (void)hipEventRecord(e1, c->stream);
-                if (rc != TR_OK || !c->hip_ok(hipEventSynchronize(e1), "sync")) {
-                    rc = TR_ERR_HIP;
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms / reps < best) {
-                    best = ms / reps;
-                    bestD = su.plan.D;
-                    bestW = su.plan.W;
-                }
+                const double ms = time_shape(D, W, reps, nullptr);
+                if (ms == -2.0) { rc = TR_ERR_HIP; break; }
+                if (ms < 0.0) continue;
+                cands.push_back({key[0], key[1], ms});
+                if (ms < best) best = ms;
             }
             if (rc != TR_OK) break;
+        }
+        // the shapes within 5 % of the fastest are timed again in three
+        // interleaved rounds (the first pass times each shape once, in a
+        // fixed order, so clock changes and noise can bias it)
+        std::vector<Cand> fin;
+        for (const Cand& k : cands)
+            if (k.ms <= 1.05 * best) fin.push_back({k.D, k.W, 0.0});
+        if (fin.size() > 4) {
+            std::sort(fin.begin(), fin.end(), [&](const Cand& x, const Cand& y) {
+                auto msof = [&](const Cand& z) {
+                    for (const Cand& k : cands)
+                        if (k.D == z.D && k.W == z.W) return k.ms;
+                    return 1e300;
+                };
+                return msof(x) < msof(y);
+            });
+            fin.resize(4);
+        }
+        const int rounds = fin.size() > 1 ? 3 : 0;
+        for (int r = 0; r < rounds && rc == TR_OK; ++r)
+            for (size_t k = 0; k < fin.size(); ++k) {
+                Cand& f = fin[(k + (size_t)r) % fin.size()];
+                const double ms = time_shape(f.D, f.W, reps, nullptr);
+                if (ms < 0.0) { rc = TR_ERR_HIP; break; }
+                f.ms += ms;
+            }
+        if (rc == TR_OK) {
+            if (rounds > 0) {
+                best = 1e300;
+                for (const Cand& f : fin)
+                    if (f.ms / rounds < best) {
+                        best = f.ms / rounds;
+                        bestD = f.D;
+                        bestW = f.W;
+                    }
+            } else {
+                for (const Cand& k : cands)
+                    if (k.ms <= best) { bestD = k.D; bestW = k.W; }
+            }
         }
     }
     if (e0) (void)hipEventDestroy(e0);
