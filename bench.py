@@ -48,7 +48,7 @@ BYTES_PER_CELL_ITER = 20
 # active) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what the counters
 # read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
 # valid only for the kernel source with this hash prefix, otherwise null
-SWEEP_TRAFFIC_BYTES = 79.82e6
+SWEEP_TRAFFIC_BYTES = 79.80e6
 SWEEP_TRAFFIC_SRC = "282dad4ea9895311"
 
 
