@@ -239,15 +239,18 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 __global__ void lift_kernel(const float* __restrict__ in, const float* __restrict__ W0,
                             const float* __restrict__ b0, float* __restrict__ out,
                             int B, int n, int C) {
-    // grid (ceil(n*n / 256), C, B): 32-bit index arithmetic only
+    // grid (ceil(n*n / 256), B): one pixel per thread, all C channels (the
+    // input is read once; each channel's stores are coalesced)
     const int P = n * n;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y, b = blockIdx.z;
+    const int b = blockIdx.y;
     if (p >= P) return;
     const int iy = p / n, ix = p - iy * n;
     const float x = (ix + 0.5f) / n, y = (iy + 0.5f) / n;
-    out[((size_t)b * C + c) * P + p] =
-        fmaf(W0[c], in[(size_t)b * P + p], fmaf(W0[C + c], x, fmaf(W0[2 * C + c], y, b0[c])));
+    const float v = in[(size_t)b * P + p];
+    float* ob = out + (size_t)b * C * P + p;
+    for (int c = 0; c < C; ++c)
+        ob[(size_t)c * P] = fmaf(W0[c], v, fmaf(W0[C + c], x, fmaf(W0[2 * C + c], y, b0[c])));
 }
 
 __global__ void gelu_back_kernel(const float* __restrict__ z, const float* __restrict__ gv,
@@ -471,10 +474,33 @@ __global__ void recast_input_kernel(const float* __restrict__ S, const float* __
     const float* pb = phi + (long long)b * P;
     float* ib = in + (long long)b * P;
     double s = 0.0;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        const float v = fmaf(sa_star - ab[p], pb[p], Sb[p]);
-        ib[p] = v;
-        s += fabs((double)v);
+    // 64 x 64 grid with 16-byte aligned rows: each thread keeps its 16 cells
+    // in registers (four float4 loads per field issued together)
+    constexpr int kR = 4;
+    const bool regs = P == kR * 4 * 256 && blockDim.x == 256 &&
+                      ((reinterpret_cast<size_t>(Sb) | reinterpret_cast<size_t>(ab) |
+                        reinterpret_cast<size_t>(pb) | reinterpret_cast<size_t>(ib)) & 15) == 0;
+    float4 v4[kR];
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const int e = (k * 256 + (int)threadIdx.x) * 4;
+            const float4 S4 = *reinterpret_cast<const float4*>(Sb + e);
+            const float4 a4 = *reinterpret_cast<const float4*>(ab + e);
+            const float4 p4 = *reinterpret_cast<const float4*>(pb + e);
+            v4[k] = make_float4(fmaf(sa_star - a4.x, p4.x, S4.x), fmaf(sa_star - a4.y, p4.y, S4.y),
+                                fmaf(sa_star - a4.z, p4.z, S4.z), fmaf(sa_star - a4.w, p4.w, S4.w));
+        }
+#pragma unroll
+        for (int k = 0; k < kR; ++k)
+            s += fabs((double)v4[k].x) + fabs((double)v4[k].y) + fabs((double)v4[k].z) +
+                 fabs((double)v4[k].w);
+    } else {
+        for (int p = threadIdx.x; p < P; p += blockDim.x) {
+            const float v = fmaf(sa_star - ab[p], pb[p], Sb[p]);
+            ib[p] = v;
+            s += fabs((double)v);
+        }
     }
     __shared__ double red[256];
     red[threadIdx.x] = s;
@@ -486,7 +512,16 @@ __global__ void recast_input_kernel(const float* __restrict__ S, const float* __
     const float sc = (float)(red[0] / P);
     if (threadIdx.x == 0) scale[b] = sc;
     const float inv = sc > 0.f ? 1.0f / sc : 0.f;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) ib[p] *= inv;
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const int e = (k * 256 + (int)threadIdx.x) * 4;
+            *reinterpret_cast<float4*>(ib + e) =
+                make_float4(v4[k].x * inv, v4[k].y * inv, v4[k].z * inv, v4[k].w * inv);
+        }
+    } else {
+        for (int p = threadIdx.x; p < P; p += blockDim.x) ib[p] *= inv;
+    }
 }
 
 // phi_new = s * out / sa*; FP64 norms of the change and of phi_new.
@@ -498,13 +533,40 @@ __global__ void recast_update_kernel(const float* __restrict__ out, const float*
     if (!active[b]) return;
     const float sc = scale[b] * inv_sa_star;
     double d2 = 0.0, n2 = 0.0;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        const long long e = (long long)b * P + p;
-        const float nv = out[e] * sc;
-        const double d = (double)nv - (double)phi[e];
-        d2 += d * d;
-        n2 += (double)nv * nv;
-        phi[e] = nv;
+    const float* ob = out + (long long)b * P;
+    float* fb = phi + (long long)b * P;
+    constexpr int kR = 4;
+    if (P == kR * 4 * 256 && blockDim.x == 256 &&
+        ((reinterpret_cast<size_t>(ob) | reinterpret_cast<size_t>(fb)) & 15) == 0) {
+        // 64 x 64 grid: all loads of a thread issued together
+        float4 o4[kR], f4[kR];
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const int e = (k * 256 + (int)threadIdx.x) * 4;
+            o4[k] = *reinterpret_cast<const float4*>(ob + e);
+            f4[k] = *reinterpret_cast<const float4*>(fb + e);
+        }
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const float nv[4] = {o4[k].x * sc, o4[k].y * sc, o4[k].z * sc, o4[k].w * sc};
+            const float ov[4] = {f4[k].x, f4[k].y, f4[k].z, f4[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double d = (double)nv[j] - (double)ov[j];
+                d2 += d * d;
+                n2 += (double)nv[j] * nv[j];
+            }
+            *reinterpret_cast<float4*>(fb + (k * 256 + (int)threadIdx.x) * 4) =
+                make_float4(nv[0], nv[1], nv[2], nv[3]);
+        }
+    } else {
+        for (int p = threadIdx.x; p < P; p += blockDim.x) {
+            const float nv = ob[p] * sc;
+            const double d = (double)nv - (double)fb[p];
+            d2 += d * d;
+            n2 += (double)nv * nv;
+            fb[p] = nv;
+        }
     }
     __shared__ double r1[256], r2[256];
     r1[threadIdx.x] = d2;
@@ -1134,7 +1196,7 @@ void launch_lift(const float* in, const float* W0, const float* b0, float* out, 
     for (int b0i = 0; b0i < B; b0i += 65535) {   // grid.z limit
         const int nb = std::min(65535, B - b0i);
         const size_t P = (size_t)n * n;
-        hipLaunchKernelGGL(lift_kernel, dim3((n * n + 255) / 256, C, nb), dim3(256), 0, s,
+        hipLaunchKernelGGL(lift_kernel, dim3((n * n + 255) / 256, nb), dim3(256), 0, s,
                            in + b0i * P, W0, b0, out + b0i * P * C, nb, n, C);
     }
 }
