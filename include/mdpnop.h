@@ -171,7 +171,8 @@ tr_status no_model_set_fp32(no_model *m, int32_t enable);
 
 /* Network forward for a batch: input[b] and output[b] are device
  * grid*grid FP32 fields (the first input channel; the coordinate channels
- * are generated inside).                                                   */
+ * are generated inside).  1 <= batch <= 65535 (also for no_train_step and
+ * n_inst of no_recast_guess), else TR_ERR_INVALID_ARG.                     */
 tr_status no_forward(tr_context *ctx, const no_model *m, int32_t batch,
                      const float *input, float *output);
 

@@ -30,6 +30,7 @@
 namespace mdp {
 
 constexpr int kProj = 128;          // projection width (Appendix A1)
+constexpr int kMaxBatch = 65535;    // samples per call (the batch is a grid dimension)
 constexpr int kGridLog2 = 6;        // supported network grid 64 x 64
 constexpr int kGrid = 1 << kGridLog2;
 constexpr int kP = kGrid * kGrid;   // cells per field
@@ -501,8 +502,8 @@ extern "C" tr_status no_forward(tr_context* ctx, const no_model* m, int32_t batc
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     if (!c) return TR_ERR_INVALID_ARG;
     c->err.clear();
-    if (!m || batch <= 0 || !input || !output) {
-        c->fail("no_forward: need a model, batch > 0 and buffers");
+    if (!m || batch <= 0 || batch > kMaxBatch || !input || !output) {
+        c->fail("no_forward: need a model, 0 < batch <= %d and buffers", kMaxBatch);
         return TR_ERR_INVALID_ARG;
     }
     if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
@@ -520,8 +521,10 @@ extern "C" tr_status no_train_step(tr_context* ctx, no_model* m, int32_t batch,
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     if (!c) return TR_ERR_INVALID_ARG;
     c->err.clear();
-    if (!m || batch <= 0 || !input || !target || !(lr >= 0.0) || !std::isfinite(lr)) {
-        c->fail("no_train_step: need a model, batch > 0, buffers and a finite lr >= 0");
+    if (!m || batch <= 0 || batch > kMaxBatch || !input || !target || !(lr >= 0.0) ||
+        !std::isfinite(lr)) {
+        c->fail("no_train_step: need a model, 0 < batch <= %d, buffers and a finite lr >= 0",
+                kMaxBatch);
         return TR_ERR_INVALID_ARG;
     }
     if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
@@ -572,6 +575,10 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
     const auto t0 = std::chrono::steady_clock::now();
     if (!m || !phi_guess) {
         c->fail("no_recast_guess: need a model and output pointers");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (n_inst > kMaxBatch) {
+        c->fail("no_recast_guess: at most %d problems per call", kMaxBatch);
         return TR_ERR_INVALID_ARG;
     }
     if (!same_device(c, m)) return TR_ERR_INVALID_ARG;

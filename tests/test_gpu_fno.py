@@ -74,6 +74,19 @@ def test_bad_shape_rejected(env):
         B.Model(ctx, None, width=64)
 
 
+def test_batch_limit_rejected_before_launch(env):
+    """A batch above 65535 (a grid dimension of the network kernels) is an
+    argument error; the buffers are never touched, so small ones serve."""
+    torch, B, ctx = env
+    m = B.Model(ctx, _params(4))
+    x = torch.zeros((1, 64, 64), dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    rc = m.lib.no_forward(ctx.handle, m.handle, 65536, x.data_ptr(), y.data_ptr())
+    assert rc == B.TR_ERR_INVALID_ARG and "65535" in ctx.last_error()
+    m.forward(x, y)   # the context and model stay usable
+    m.close()
+
+
 @pytest.mark.parametrize("fp32,tol", [(True, 1e-5), (False, 1e-2)])
 def test_forward_parity(env, fp32, tol):
     torch, B, ctx = env
