@@ -45,8 +45,9 @@ void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     hipStream_t s);
 void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
                      IterState st, double tol, int norm_kind, hipStream_t s);
-void launch_balance(int n_inst, const InstDesc* insts, const DirTable* dt,
-                    const int* iter, double* bal, hipStream_t s);
+void launch_balance(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+                    const DirTable* dt, const int* iter, double* part, double* bal,
+                    hipStream_t s);
 
 // ------------------------------------------------------------ helpers ----
 
@@ -570,6 +571,8 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     off += align_up(sizeof(int) * n_inst);
     const size_t oSa = off;
     off += align_up(sizeof(float) * n_inst);
+    const size_t oBpart = off;
+    off += align_up(sizeof(double) * 3 * std::max<size_t>(1, nslots));
     if (!arena.reserve(this, off)) return false;
     char* b = (char*)arena.base;
     for (int i = 0; i < n_inst; ++i) {
@@ -590,6 +593,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     su->d_bal = (double*)(b + oBal);
     su->d_flags = (int*)(b + oFlag);
     su->d_samax = (float*)(b + oSa);
+    su->d_bpart = (double*)(b + oBpart);
     // stage the tables through pinned memory
     const size_t hsz = oRed - oInst;
     if (!pinned.reserve(this, hsz + 4096 + (size_t)n_inst * 64)) return false;
@@ -777,7 +781,8 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
     if (p[0].dim == 2 && su.plan.fast &&
         !c->launch_sweep(su, n_inst, nullptr, su.st.iter, 1, true))
         return TR_ERR_HIP;
-    launch_balance(n_inst, su.d_inst, su.d_dt, su.st.iter, su.d_bal, c->stream);
+    launch_balance(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_dt, su.st.iter,
+                   su.d_bpart, su.d_bal, c->stream);
     if (!c->hip_ok(hipGetLastError(), "balance launch")) return TR_ERR_HIP;
     // read back iteration state
     if (!c->pinned.reserve(c, 2 * align_up(sizeof(int) * n_inst) +

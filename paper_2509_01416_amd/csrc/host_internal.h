@@ -48,6 +48,7 @@ struct Setup {
     double* d_bal = nullptr;
     int* d_flags = nullptr;
     float* d_samax = nullptr;
+    double* d_bpart = nullptr;   // balance partials, 3 per reduction block
 };
 
 struct FnoWork;

@@ -284,24 +284,36 @@ __global__ void finalize_kernel(const InstDesc* __restrict__ insts,
 
 // ------------------------------------------------------------ balance ----
 // bal[n] = {sum q V, sum sigma_a phi V, leakage} in FP64 for the last sweep.
-__global__ void balance_kernel(const InstDesc* __restrict__ insts,
-                               const DirTable* __restrict__ dt,
-                               const int* __restrict__ iter, double* bal) {
-    const int n = blockIdx.x;
+// Stage 1, one workgroup per reduction block (kCombineChunk cells of one
+// instance): FP64 sums of q V and sigma_a phi V over the block's cells and
+// the leakage of its share of the instance's boundary-face entries (the
+// entries are split evenly over the instance's blocks).
+__global__ void __launch_bounds__(256)
+balance_part_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                    const DirTable* __restrict__ dt, const int* __restrict__ iter,
+                    double* __restrict__ part) {
+    const int4 bi = blocks[blockIdx.x];
+    const int n = bi.x;
+    if (n < 0) return;
     const InstDesc& I = insts[n];
     const int M = dt->M;
     const double V = I.dx * I.dy;
     double sq = 0.0, sa = 0.0, lk = 0.0;
-    for (int c = threadIdx.x; c < I.cells; c += blockDim.x) {
+    const int c1 = min(bi.y + kCombineChunk, I.cells);
+    for (int c = bi.y + (int)threadIdx.x; c < c1; c += blockDim.x) {
         sq += (double)I.q[c] * V;
         sa += ((double)I.st[c] - (double)I.ss[c]) * (double)I.phi[c] * V;
     }
     const int it = iter[n];
     const int pc = it & 1, pp = (it + 1) & 1;   // current / previous parity
+    const int j = bi.z - I.red0;                // this block's rank in the instance
     if (I.dim == 1) {
+        const int total = 2 * M;
+        const int e0 = (int)((long long)total * j / I.nred);
+        const int e1 = (int)((long long)total * (j + 1) / I.nred);
         const float* fc = I.face + (size_t)pc * 2 * M;
         const float* fp = I.face + (size_t)pp * 2 * M;
-        for (int e = threadIdx.x; e < 2 * M; e += blockDim.x) {
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             const int f = e / M, m = e - f * M;
             const double on = f == 0 ? -(double)dt->mu[m] : (double)dt->mu[m];
             double psi;
@@ -315,7 +327,9 @@ __global__ void balance_kernel(const InstDesc* __restrict__ insts,
         const float* fc = I.face + (size_t)pc * fs;
         const float* fp = I.face + (size_t)pp * fs;
         const int total = 4 * nf * M;
-        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int e0 = (int)((long long)total * j / I.nred);
+        const int e1 = (int)((long long)total * (j + 1) / I.nred);
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             const int f = e / (nf * M);
             const int kk = (e / M) % nf;
             const int m = e % M;
@@ -350,10 +364,29 @@ __global__ void balance_kernel(const InstDesc* __restrict__ insts,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        bal[3 * n + 0] = r[0][0];
-        bal[3 * n + 1] = r[1][0];
-        bal[3 * n + 2] = r[2][0];
+        part[3 * bi.z + 0] = r[0][0];
+        part[3 * bi.z + 1] = r[1][0];
+        part[3 * bi.z + 2] = r[2][0];
     }
+}
+
+// Stage 2, one thread per instance: the block partials summed in block order.
+__global__ void balance_fin_kernel(const InstDesc* __restrict__ insts,
+                                   const double* __restrict__ part, int n_inst,
+                                   double* __restrict__ bal) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_inst) return;
+    const InstDesc& I = insts[n];
+    double sq = 0.0, sa = 0.0, lk = 0.0;
+    for (int b = 0; b < I.nred; ++b) {
+        const double* v = part + 3 * (size_t)(I.red0 + b);
+        sq += v[0];
+        sa += v[1];
+        lk += v[2];
+    }
+    bal[3 * n + 0] = sq;
+    bal[3 * n + 1] = sa;
+    bal[3 * n + 2] = lk;
 }
 
 // ------------------------------------------------------------ launchers --
@@ -393,10 +426,13 @@ void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
                        insts, red, st, n_inst, tol, norm_kind);
 }
 
-void launch_balance(int n_inst, const InstDesc* insts, const DirTable* dt,
-                    const int* iter, double* bal, hipStream_t s) {
-    hipLaunchKernelGGL(balance_kernel, dim3(n_inst), dim3(256), 0, s, insts, dt,
-                       iter, bal);
+void launch_balance(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+                    const DirTable* dt, const int* iter, double* part, double* bal,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(balance_part_kernel, dim3(nblocks), dim3(256), 0, s, insts, blocks, dt,
+                       iter, part);
+    hipLaunchKernelGGL(balance_fin_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, part,
+                       n_inst, bal);
 }
 
 }  // namespace mdp
