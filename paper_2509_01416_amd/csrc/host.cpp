@@ -35,8 +35,8 @@ int sweep2d_max_w(int D);
 void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
                     const int* done, const int* iter, int use_faces, int M,
                     hipStream_t s);
-void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
-                 hipStream_t s);
+void launch_scan(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+                 double* part, int* flags, float* samax, hipStream_t s);
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                  const int4* blocks, const DirTable* dt, IterState st,
                  hipStream_t s);
@@ -644,7 +644,8 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
 tr_status Ctx::scan_fields(const Setup& su, int n_inst, const tr_problem* p,
                            bool need_xs, tr_stats* stats) {
     (void)need_xs;
-    launch_scan(n_inst, su.d_inst, su.d_flags, su.d_samax, stream);
+    launch_scan(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_bpart, su.d_flags,
+                su.d_samax, stream);
     if (!hip_ok(hipGetLastError(), "scan launch")) return TR_ERR_HIP;
     int* hf = (int*)pinned.ptr;
     float* hs = (float*)((char*)pinned.ptr + align_up(sizeof(int) * n_inst));

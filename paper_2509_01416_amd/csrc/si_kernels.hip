@@ -50,34 +50,59 @@ __global__ void sweep1d_kernel(const InstDesc* __restrict__ insts,
 // ------------------------------------------------------- argument scan ---
 // flags[n] bit 0: a non-finite value; bit 1: sigma_t <= 0, sigma_s < 0 or
 // sigma_s > sigma_t.  samax[n] = max(sigma_t - sigma_s).
-__global__ void scan_kernel(const InstDesc* __restrict__ insts, int* flags,
-                            float* samax) {
-    const int n = blockIdx.x;
-    const InstDesc& I = insts[n];
+// Stage 1, one workgroup per reduction block: invalid-value flags (bit 0
+// non-finite, bit 1 sigma_t <= 0 or sigma_s outside [0, sigma_t]) and the
+// largest sigma_a over the block's cells.  OR and max are exact, so the
+// per-instance result does not depend on the order.
+__global__ void __launch_bounds__(256)
+scan_part_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                 double* __restrict__ part) {
+    const int4 bi = blocks[blockIdx.x];
+    if (bi.x < 0) return;
+    const InstDesc& I = insts[bi.x];
+    const int c1 = min(bi.y + kCombineChunk, I.cells);
     int bad = 0;
     float mx = 0.f;
-    for (int c = threadIdx.x; c < I.cells; c += blockDim.x) {
+    for (int c = bi.y + (int)threadIdx.x; c < c1; c += blockDim.x) {
         const float st = I.st[c], ss = I.ss[c], q = I.q[c];
         if (!isfinite(st) || !isfinite(ss) || !isfinite(q)) bad |= 1;
         if (I.phi_init != nullptr && !isfinite(I.phi_init[c])) bad |= 1;
         if (!(st > 0.f) || ss < 0.f || ss > st) bad |= 2;
         mx = fmaxf(mx, st - ss);
     }
-    __shared__ int sbad[1024];
-    __shared__ float smx[1024];
+    __shared__ int sbad[256];
+    __shared__ float smx[256];
     sbad[threadIdx.x] = bad;
     smx[threadIdx.x] = mx;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int b = 0;
-        float m = 0.f;
-        for (int t = 0; t < (int)blockDim.x; ++t) {
-            b |= sbad[t];
-            m = fmaxf(m, smx[t]);
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sbad[threadIdx.x] |= sbad[threadIdx.x + h];
+            smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + h]);
         }
-        flags[n] = b;
-        samax[n] = m;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        part[3 * bi.z + 0] = (double)sbad[0];
+        part[3 * bi.z + 1] = (double)smx[0];
+    }
+}
+
+// Stage 2, one thread per instance.
+__global__ void scan_fin_kernel(const InstDesc* __restrict__ insts,
+                                const double* __restrict__ part, int n_inst,
+                                int* __restrict__ flags, float* __restrict__ samax) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_inst) return;
+    const InstDesc& I = insts[n];
+    int bad = 0;
+    float mx = 0.f;
+    for (int b = 0; b < I.nred; ++b) {
+        bad |= (int)part[3 * (size_t)(I.red0 + b)];
+        mx = fmaxf(mx, (float)part[3 * (size_t)(I.red0 + b) + 1]);
+    }
+    flags[n] = bad;
+    samax[n] = mx;
 }
 
 // ------------------------------------------------------------- init ------
@@ -96,21 +121,29 @@ __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
 }
 
 // Faces of parity 0: isotropic at the adjacent cell's initial flux (warm
-// start) or zero.  One block per instance.
-__global__ void init_faces_kernel(const InstDesc* __restrict__ insts,
-                                  const DirTable* __restrict__ dt,
-                                  IterState st) {
-    const int n = blockIdx.x;
+// start) or zero.  One workgroup per reduction block, each taking an even
+// share of its instance's face entries; the instance's first block also
+// resets the iteration state.
+__global__ void __launch_bounds__(256)
+init_faces_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                  const DirTable* __restrict__ dt, IterState st) {
+    const int4 bi = blocks[blockIdx.x];
+    const int n = bi.x;
+    if (n < 0) return;
     const InstDesc& I = insts[n];
     const int M = dt->M;
-    if (threadIdx.x == 0) {
+    const int j = bi.z - I.red0;
+    if (j == 0 && threadIdx.x == 0) {
         st.done[n] = 0;
         st.iter[n] = 0;
         st.status[n] = 1;
         st.resid[n] = INFINITY;
     }
     if (I.dim == 1) {
-        for (int e = threadIdx.x; e < 2 * M; e += blockDim.x) {
+        const int total = 2 * M;
+        const int e0 = (int)((long long)total * j / I.nred);
+        const int e1 = (int)((long long)total * (j + 1) / I.nred);
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             const int f = e / M;
             float v = 0.f;
             if (I.phi_init != nullptr) v = I.phi_init[f == 0 ? 0 : I.nx - 1];
@@ -120,7 +153,9 @@ __global__ void init_faces_kernel(const InstDesc* __restrict__ insts,
     }
     const int nf = I.nf;
     const int total = 4 * nf * M;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int e0 = (int)((long long)total * j / I.nred);
+    const int e1 = (int)((long long)total * (j + 1) / I.nred);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
         const int f = e / (nf * M);
         const int kk = (e / M) % nf;
         float v = 0.f;
@@ -398,10 +433,11 @@ void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
                        done, iter, use_faces);
 }
 
-void launch_scan(int n_inst, const InstDesc* insts, int* flags, float* samax,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(scan_kernel, dim3(n_inst), dim3(256), 0, s, insts, flags,
-                       samax);
+void launch_scan(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+                 double* part, int* flags, float* samax, hipStream_t s) {
+    hipLaunchKernelGGL(scan_part_kernel, dim3(nblocks), dim3(256), 0, s, insts, blocks, part);
+    hipLaunchKernelGGL(scan_fin_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, part,
+                       n_inst, flags, samax);
 }
 
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
@@ -409,7 +445,7 @@ void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                  hipStream_t s) {
     hipLaunchKernelGGL(init_cells_kernel, dim3(nblocks), dim3(kCombineThreads), 0,
                        s, insts, blocks);
-    hipLaunchKernelGGL(init_faces_kernel, dim3(n_inst), dim3(256), 0, s, insts,
+    hipLaunchKernelGGL(init_faces_kernel, dim3(nblocks), dim3(256), 0, s, insts, blocks,
                        dt, st);
 }
 
