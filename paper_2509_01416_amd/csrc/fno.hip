@@ -585,31 +585,44 @@ __global__ void recast_update_kernel(const float* __restrict__ out, const float*
     }
 }
 
-// Block average of a fine field (f x f blocks) onto the network grid.
-__global__ void block_average_kernel(const float* __restrict__ fine, int nf_x, int f,
-                                     float* __restrict__ coarse, int nc, const float* __restrict__ sub,
-                                     int mode) {
+// Block averages of every instance's fields onto the network grid (f x f
+// blocks, FP64 sums in row order): S = mean(q), sa = mean(sigma_t -
+// sigma_s).  Grid (ceil(nc*nc / 256), instances).
+__global__ void recast_average_kernel(const ResampleDesc* __restrict__ d, int nc,
+                                      float* __restrict__ S, float* __restrict__ sa) {
+    const int b = blockIdx.y;
     const int P = nc * nc;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P; e += gridDim.x * blockDim.x) {
-        const int X = e % nc, Y = e / nc;
-        double s = 0.0;
-        for (int j = 0; j < f; ++j)
-            for (int i = 0; i < f; ++i) {
-                const long long c = (long long)(Y * f + j) * nf_x + (X * f + i);
-                s += mode == 0 ? (double)fine[c] : (double)fine[c] - (double)sub[c];
-            }
-        coarse[e] = (float)(s / (f * f));
-    }
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P) return;
+    const ResampleDesc r = d[b];
+    const int X = e % nc, Y = e / nc, f = r.f;
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < f; ++j)
+        for (int i = 0; i < f; ++i) {
+            const long long c = (long long)(Y * f + j) * r.nf + (X * f + i);
+            s1 += (double)r.q[c];
+            s2 += (double)r.st[c] - (double)r.ss[c];
+        }
+    S[(long long)b * P + e] = (float)(s1 / (f * f));
+    sa[(long long)b * P + e] = (float)(s2 / (f * f));
 }
 
-// Bilinear interpolation (cell-centred, edges clamped) of a coarse field to
-// a fine grid that is an integer multiple f of it.
-__global__ void bilinear_up_kernel(const float* __restrict__ coarse, int nc, int f,
-                                   float* __restrict__ fine, float scale) {
-    const int nf = nc * f;
+// Every instance's guess on its own grid: a copy when f = 1, else
+// cell-centred bilinear interpolation with clamped edges.  Grid
+// (ceil(max fine cells / 256), instances).
+__global__ void recast_output_kernel(const ResampleDesc* __restrict__ d, int nc,
+                                     const float* __restrict__ phi) {
+    const int b = blockIdx.y;
+    const ResampleDesc r = d[b];
+    const int f = r.f, nf = r.nf;
     const long long P = (long long)nf * nf;
+    const float* coarse = phi + (long long)b * nc * nc;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < P;
          e += (long long)gridDim.x * blockDim.x) {
+        if (f == 1) {
+            r.guess[e] = coarse[e];
+            continue;
+        }
         const int i = (int)(e % nf), j = (int)(e / nf);
         const float xc = (i + 0.5f) / f - 0.5f, yc = (j + 0.5f) / f - 0.5f;
         int i0 = (int)floorf(xc), j0 = (int)floorf(yc);
@@ -623,8 +636,8 @@ __global__ void bilinear_up_kernel(const float* __restrict__ coarse, int nc, int
         if (j0 > nc - 1) { j0 = nc - 1; }
         const float v00 = coarse[j0 * nc + i0], v10 = coarse[j0 * nc + i1];
         const float v01 = coarse[j1 * nc + i0], v11 = coarse[j1 * nc + i1];
-        const float a = v00 + tx * (v10 - v00), b = v01 + tx * (v11 - v01);
-        fine[e] = scale * (a + ty * (b - a));
+        const float a = v00 + tx * (v10 - v00), bb = v01 + tx * (v11 - v01);
+        r.guess[e] = a + ty * (bb - a);
     }
 }
 
@@ -1325,16 +1338,15 @@ void launch_recast_update(const float* out, const float* scale, float inv_sa_sta
     hipLaunchKernelGGL(recast_update_kernel, dim3(B), dim3(256), 0, s, out, scale, inv_sa_star,
                        phi, norms, active, P);
 }
-void launch_block_average(const float* fine, int nf_x, int f, float* coarse, int nc,
-                          const float* sub, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(block_average_kernel, dim3(blocks_for((long long)nc * nc)), dim3(256), 0,
-                       s, fine, nf_x, f, coarse, nc, sub, mode);
+void launch_recast_average(const ResampleDesc* d, int B, int nc, float* S, float* sa,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(recast_average_kernel, dim3((nc * nc + 255) / 256, B), dim3(256), 0, s,
+                       d, nc, S, sa);
 }
-void launch_bilinear_up(const float* coarse, int nc, int f, float* fine, float scale,
-                        hipStream_t s) {
-    const long long P = (long long)nc * f * nc * f;
-    hipLaunchKernelGGL(bilinear_up_kernel, dim3(blocks_for(P)), dim3(256), 0, s, coarse, nc, f,
-                       fine, scale);
+void launch_recast_output(const ResampleDesc* d, int B, int nc, long long max_cells,
+                          const float* phi, hipStream_t s) {
+    const long long g0 = (max_cells + 255) / 256, g = g0 < 4096 ? g0 : 4096;
+    hipLaunchKernelGGL(recast_output_kernel, dim3((unsigned)g, B), dim3(256), 0, s, d, nc, phi);
 }
 
 }  // namespace mdp

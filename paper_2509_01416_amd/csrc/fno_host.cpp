@@ -606,12 +606,14 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
     Ws w;
     if (!workspace(c, m, B, false, &w)) return ws_status(c);
     FnoWork* fw = c->fno;
-    // recast fields: S, sigma_a, phi, in, out (B x P), scale (B), norms (2B), active (B)
+    // recast fields: S, sigma_a, phi, in, out (B x P), scale (B), norms (2B),
+    // active (B), resampling descriptors (B)
     const size_t fb = align_up(4 * (size_t)B * kP);
+    const size_t dsz = align_up(sizeof(ResampleDesc) * (size_t)B);
     const size_t need = 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B) +
-                        align_up(4 * (size_t)B);
-    if (!fw->rc.reserve(c, need) ||
-        !fw->host.reserve(c, 16 * (size_t)B + 4 * (size_t)B))
+                        align_up(4 * (size_t)B) + dsz;
+    const size_t hoff = align_up(16 * (size_t)B + 4 * (size_t)B);
+    if (!fw->rc.reserve(c, need) || !fw->host.reserve(c, hoff + dsz))
         return ws_status(c);
     char* base = (char*)fw->rc.base;
     float* S = (float*)base;
@@ -622,15 +624,23 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
     float* scale = (float*)(base + 5 * fb);
     double* norms = (double*)(base + 5 * fb + align_up(4 * (size_t)B));
     int* active = (int*)(base + 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B));
+    ResampleDesc* ddesc = (ResampleDesc*)(base + 5 * fb + align_up(4 * (size_t)B) +
+                                          align_up(16 * (size_t)B) + align_up(4 * (size_t)B));
     double* hn = (double*)fw->host.ptr;
     int* hact = (int*)(hn + 2 * B);
+    ResampleDesc* hdesc = (ResampleDesc*)((char*)fw->host.ptr + hoff);
     hipStream_t s = c->stream;
+    long long max_cells = 0;
     for (int i = 0; i < B; ++i) {
-        launch_block_average(p[i].source, p[i].nx, fac[i], S + (size_t)i * kP, kGrid, nullptr, 0, s);
-        launch_block_average(p[i].sigma_t, p[i].nx, fac[i], sa + (size_t)i * kP, kGrid,
-                             p[i].sigma_s, 1, s);
+        hdesc[i] = ResampleDesc{p[i].sigma_t, p[i].sigma_s, p[i].source, phi_guess[i],
+                                p[i].nx, fac[i]};
+        max_cells = std::max(max_cells, (long long)p[i].nx * p[i].nx);
         hact[i] = 1;
     }
+    if (!c->hip_ok(hipMemcpyAsync(ddesc, hdesc, sizeof(ResampleDesc) * (size_t)B,
+                                  hipMemcpyHostToDevice, s), "copy"))
+        return TR_ERR_HIP;
+    launch_recast_average(ddesc, B, kGrid, S, sa, s);
     if (!c->hip_ok(hipMemsetAsync(phi, 0, 4 * (size_t)B * kP, s), "memset") ||
         !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
         return TR_ERR_HIP;
@@ -679,15 +689,7 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
             !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
             return TR_ERR_HIP;
     }
-    for (int i = 0; i < B; ++i) {
-        if (fac[i] == 1) {
-            if (!c->hip_ok(hipMemcpyAsync(phi_guess[i], phi + (size_t)i * kP, 4 * (size_t)kP,
-                                          hipMemcpyDeviceToDevice, s), "copy"))
-                return TR_ERR_HIP;
-        } else {
-            launch_bilinear_up(phi + (size_t)i * kP, kGrid, fac[i], phi_guess[i], 1.0f, s);
-        }
-    }
+    launch_recast_output(ddesc, B, kGrid, max_cells, phi, s);
     const tr_status st = finish(c, "recast output");
     if (st != TR_OK) return st;
     const double secs =

@@ -74,9 +74,16 @@ void launch_recast_input(const float* S, const float* sa, const float* phi, floa
                          hipStream_t s);
 void launch_recast_update(const float* out, const float* scale, float inv_sa_star, float* phi,
                           double* norms, const int* active, int B, int P, hipStream_t s);
-void launch_block_average(const float* fine, int nf_x, int f, float* coarse, int nc,
-                          const float* sub, int mode, hipStream_t s);
-void launch_bilinear_up(const float* coarse, int nc, int f, float* fine, float scale,
-                        hipStream_t s);
+// Per-instance resampling between a problem's grid (nf x nf, f = nf / nc)
+// and the network grid (nc x nc).
+struct ResampleDesc {
+    const float *st, *ss, *q;   // the problem's fields
+    float* guess;               // the problem's output field
+    int nf, f;
+};
+void launch_recast_average(const ResampleDesc* d, int B, int nc, float* S, float* sa,
+                           hipStream_t s);
+void launch_recast_output(const ResampleDesc* d, int B, int nc, long long max_cells,
+                          const float* phi, hipStream_t s);
 
 }  // namespace mdp
