@@ -402,3 +402,65 @@ def test_too_wide_grid_is_rejected_before_launch(env):
     assert e.value.status == B.TR_ERR_INVALID_ARG and "too wide" in str(e.value)
     small = I.random_instance(24, 16, seed=6)
     _sweep_case(env, [small], quad)
+
+
+def _paper_1d_batch():
+    """The paper's 1-D fixed-source setting (section 5.1): S32 Gauss-Legendre,
+    dL = 0.1 cm on a 10 cm slab (100 cells), vacuum faces; a source drawn
+    from a GRF (mean 0.07, variance 3e-4, correlation length 1.2 cm) at the
+    training cross sections (1.0, 0.5), a heterogeneous slab, a slab with a
+    reflective left face, and a ragged 257-cell slab."""
+    quad = I.gauss_legendre(32)
+    n = 100
+    rng = np.random.Generator(np.random.PCG64(31))
+    src = I.grf_1d(n, 10.0, seed=41, mean=0.07, std=3e-4 ** 0.5, scale=1.2)
+    insts = [I.Instance(nx=n, ny=1, lx=10.0, ly=1.0, sigma_t=np.ones((1, n)),
+                        sigma_s=np.full((1, n), 0.5), source=src.reshape(1, n), dim=1)]
+    st = rng.uniform(0.5, 2.0, (1, n))
+    insts.append(I.Instance(nx=n, ny=1, lx=10.0, ly=1.0, sigma_t=st,
+                            sigma_s=st * rng.uniform(0.3, 0.95, (1, n)),
+                            source=rng.uniform(0.0, 1.0, (1, n)), dim=1))
+    insts.append(I.Instance(nx=n, ny=1, lx=10.0, ly=1.0, sigma_t=np.full((1, n), 1.2),
+                            sigma_s=np.full((1, n), 0.9 * 1.2), source=np.ones((1, n)),
+                            bc=(1, 0, 0, 0), dim=1))
+    m = 257
+    st = rng.uniform(0.8, 1.5, (1, m))
+    insts.append(I.Instance(nx=m, ny=1, lx=25.7, ly=1.0, sigma_t=st, sigma_s=0.8 * st,
+                            source=rng.uniform(0.0, 1.0, (1, m)), dim=1))
+    return insts, quad
+
+
+def test_paper_1d_setting_sweep(env):
+    """One batched 1-D sweep of a seeded emission against the oracle's sweep,
+    element by element (bound as for the 2-D sweep with ny = 1)."""
+    torch, B, ctx = env
+    insts, quad = _paper_1d_batch()
+    probs = [to_problem(i, torch) for i in insts]
+    rng = np.random.Generator(np.random.PCG64(77))
+    Qs = [rng.uniform(0.0, 2.0, i.nx) for i in insts]
+    em = [torch.tensor(q.astype(np.float32), device="cuda") for q in Qs]
+    out = [torch.zeros_like(e) for e in em]
+    B.tr_sweep(ctx, probs, B.Quad.from_inputs(quad), em, out)
+    torch.cuda.synchronize()
+    for inst, q, o in zip(insts, Qs, out):
+        ref = oracle.sweep1d(inst.nx, inst.lx, quad.mu, quad.w,
+                             inst.sigma_t.astype(np.float32), q.astype(np.float32))
+        e = rel_inf(o.cpu().numpy(), ref)
+        bound = 4 * EPS32 * (inst.nx + 1) + 8 * EPS32
+        log(f"  1-D sweep {inst.nx} cells S32: rel_inf={e:.3e} bound={bound:.3e}")
+        assert e <= bound
+
+
+def test_paper_1d_setting_solve(env):
+    """Batched 1-D source iteration (max-relative change 1e-9) against the
+    oracle's fixed point (1e-14): 1e-5 relative L2, balance 1e-4."""
+    insts, quad = _paper_1d_batch()
+    rc, st, phis = _solve(env, insts, quad, -1e-9)
+    assert rc == 0
+    for inst, s, phi in zip(insts, st, phis):
+        ref = oracle.solve_instance(inst, quad, tol=1e-14)
+        e = rel_l2(phi, ref.phi)
+        log(f"  1-D {inst.nx} cells bc={inst.bc[:2]}: iters gpu={s['iterations']} "
+            f"oracle={ref.iterations} rel_l2={e:.3e} balance={s['balance_rel']:.2e}")
+        assert e < 1e-5
+        assert s["balance_rel"] < 1e-4
