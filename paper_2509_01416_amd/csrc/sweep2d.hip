@@ -143,6 +143,15 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
         }
         c[d] = a[d] + b[d];
     }
+    // one direction per wave and one segment per wave (D = 1, R = 64): the
+    // direction weight is applied in the cross-wave sums instead of the
+    // step, as the specialised kernel does (same operations, same order)
+    const bool fold = D == 1 && nseg == 1;
+    const float wm = fold ? 1.0f : w[0];
+    auto wave_w = [&](int v) {
+        const int kk = wk.slice * W + v;
+        return kk < nd ? dt->w[dt->list[o][kk]] : 0.f;
+    };
 
     // LDS: pbuf[2][KB][W*64+1] | sbuf[2][2][KB][65] | ring[W][nseg][D][nx]
     //      | sink[W][D][nx] (target of the ring store of non-writing lanes).
@@ -289,7 +298,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
             const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rcp;
             xin[d] = fmaf(psi, 2.0f, -xin[d]);
             yo[d] = fmaf(psi, 2.0f, -yi[d]);
-            acc = fmaf(w[d], psi, acc);
+            acc = fmaf(D == 1 ? wm : w[d], psi, acc);
         }
         for (int off = R; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
         pw[tt * PSTR] = acc;   // lanes of later segments land in unread slots
@@ -336,7 +345,11 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
                 if (t2 < tend && cell >= 0) {
                     const float* pb = pbuf + (size_t)(half * KB + t2) * PSTR + rr;
                     float s = 0.f;
-                    for (int v = 0; v < W; ++v) s += pb[v * 64];
+                    if (fold) {
+                        for (int v = 0; v < W; ++v) s = fmaf(wave_w(v), pb[v * 64], s);
+                    } else {
+                        for (int v = 0; v < W; ++v) s += pb[v * 64];
+                    }
                     part[cell] = s;
                 }
                 rc_[jx].advance(KB, nx);
@@ -435,6 +448,17 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
         c[d] = a[d] + b[d];
     }
 
+    // D = 1: each wave's partial flux is its direction's psi and the
+    // direction weights are applied in the cross-wave sums (one VALU
+    // operation less per step); wave v of the slice holds direction
+    // slice * W + v
+    auto wave_w = [&](int v) {
+        const int kk = wk.slice * W + v;
+        return kk < nd ? dt->w[dt->list[o][kk]] : 0.f;
+    };
+    float wsl[WT > 0 ? WT : 1];
+#pragma unroll
+    for (int v = 0; v < (WT > 0 ? WT : 1); ++v) wsl[v] = wave_w(v);
     // LDS: pbuf[2][W*64][KB+1] | sbuf[2][KB/2][65 float4] | ring[W][D][nx+KB]
     //      | yob[W*64][D][KB+1]
     // sbuf holds the (sigma_t, Q) pairs of steps 2k and 2k+1 of a row side
@@ -588,7 +612,8 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rcp;
             xin[d] = fmaf(psi, 2.0f, -xin[d]);
             yo[d] = fmaf(psi, 2.0f, -yi[d]);
-            acc = fmaf(w[d], psi, acc);
+            if constexpr (D == 1) acc = psi;   // weight applied in the sums
+            else acc = fmaf(w[d], psi, acc);
         }
         return acc;
     };
@@ -725,7 +750,10 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                     if (rva[jx]) {
                         float s = 0.f;
 #pragma unroll
-                        for (int v = 0; v < WT; ++v) s += vals[jx][v];
+                        for (int v = 0; v < WT; ++v) {
+                            if constexpr (D == 1) s = fmaf(wsl[v], vals[jx][v], s);
+                            else s += vals[jx][v];
+                        }
                         *(gfloat*)((MDP_GLOBAL char*)part + (unsigned)rof[jx]) = s;
                     }
                 }
@@ -738,7 +766,10 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
                             reinterpret_cast<const char*>(pbuf) + rad[jx] + hoff);
                         float s = 0.f;
 #pragma unroll 4
-                        for (int v = 0; v < W; ++v) s += pb[(size_t)v * 64 * PST];
+                        for (int v = 0; v < W; ++v) {
+                            if constexpr (D == 1) s = fmaf(wave_w(v), pb[(size_t)v * 64 * PST], s);
+                            else s += pb[(size_t)v * 64 * PST];
+                        }
                         *(gfloat*)((MDP_GLOBAL char*)part + (unsigned)rof[jx]) = s;
                     }
                 }
