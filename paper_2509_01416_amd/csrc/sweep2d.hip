@@ -838,15 +838,19 @@ static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_
 
 // Fixed wave counts of the common level-symmetric sets with one direction
 // per lane: S16 (36 directions per octant, 4 slices of 9) and S8 (10 per
-// octant, one slice of 10).  The tally sweep (once per solve) takes the
-// any-W instance.
+// octant, one slice of 10), for the iteration sweeps and the tally sweep.
 template <int D>
 static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                           const int* done, const int* iter, bool tally, const FinArgs& fin) {
     const int W = (int)block.x / 64;
-    if (tally)
+    if (tally) {
+        if (D == 1 && W == 9)
+            return launch_fast_dw<D, 9, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+        if (D == 1 && W == 10)
+            return launch_fast_dw<D, 10, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
         return launch_fast_dw<D, 0, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+    }
     if (D == 1 && W == 9)
         return launch_fast_dw<D, 9, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
     if (D == 1 && W == 10)
