@@ -148,10 +148,11 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     // step, as the specialised kernel does (same operations, same order)
     const bool fold = D == 1 && nseg == 1;
     const float wm = fold ? 1.0f : w[0];
-    auto wave_w = [&](int v) {
-        const int kk = wk.slice * W + v;
-        return kk < nd ? dt->w[dt->list[o][kk]] : 0.f;
-    };
+    __shared__ float wsh[16];   // weight of each wave's direction (W <= 16)
+    if (tid < 16) {
+        const int kk = wk.slice * W + tid;
+        wsh[tid] = tid < W && kk < nd ? dt->w[dt->list[o][kk]] : 0.f;
+    }
 
     // LDS: pbuf[2][KB][W*64+1] | sbuf[2][2][KB][65] | ring[W][nseg][D][nx]
     //      | sink[W][D][nx] (target of the ring store of non-writing lanes).
@@ -346,7 +347,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
                     const float* pb = pbuf + (size_t)(half * KB + t2) * PSTR + rr;
                     float s = 0.f;
                     if (fold) {
-                        for (int v = 0; v < W; ++v) s = fmaf(wave_w(v), pb[v * 64], s);
+                        for (int v = 0; v < W; ++v) s = fmaf(wsh[v], pb[v * 64], s);
                     } else {
                         for (int v = 0; v < W; ++v) s += pb[v * 64];
                     }
@@ -894,8 +895,9 @@ bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
 }
 
 size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx) {
+    // + 16: the kernel's static table of wave weights
     return sizeof(float) * ((size_t)2 * KB * (W * 64 + 1) + (size_t)4 * KB * 65 +
-                            (size_t)W * D * max_nseg_nx + (size_t)W * D * max_nx);
+                            (size_t)W * D * max_nseg_nx + (size_t)W * D * max_nx + 16);
 }
 
 // Largest block size whose staging fits kMaxPrefetch values and whose
