@@ -48,8 +48,8 @@ BYTES_PER_CELL_ITER = 20
 # active) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what the counters
 # read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
 # valid only for the kernel source with this hash prefix, otherwise null
-SWEEP_TRAFFIC_BYTES = 79.87e6
-SWEEP_TRAFFIC_SRC = "138a627a4f61c82e"
+SWEEP_TRAFFIC_BYTES = 79.76e6
+SWEEP_TRAFFIC_SRC = "85bbd97bb6afe0b9"
 
 
 def log(msg):
