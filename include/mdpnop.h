@@ -213,8 +213,10 @@ tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
 /* Autotuner: times every feasible launch shape (D in 1..4 directions per
  * lane, W waves per workgroup, slices and block size then chosen by the
  * planner) with `reps` HIP-event-timed sweeps of these problems (their
- * sources as emission; one untimed sweep first), and leaves the fastest
- * forced on the context exactly as tr_set_sweep_config would (reset with
+ * sources as emission; one untimed sweep first), times the shapes within
+ * 5 % of the fastest again in three interleaved rounds, and leaves the one
+ * with the lowest total forced on the context exactly as
+ * tr_set_sweep_config would (reset with
  * tr_set_sweep_config(ctx, 0, 0, 0, 0)).  out6 (may be NULL) receives the
  * chosen plan as tr_get_sweep_plan reports it, best_ms (may be NULL) its
  * time per sweep.  2-D only: for 1-D problems nothing is tuned.  Allocates
