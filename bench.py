@@ -245,6 +245,22 @@ def main():
                    "peak_TFLOPs": BF16_MFMA_PEAK_TFLOPS,
                    "frac": fl / (fwd_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
                    "dtype": "bf16 operands, fp32 accumulate"}
+        # one training step at the training batch (forward, MSE, backward,
+        # Adam, loss read-back), wall time; lr = 0 leaves the parameters as
+        # they are
+        tb = 32
+        tin = torch.randn(tb, 64, 64, device=dev)
+        tgt = torch.randn(tb, 64, 64, device=dev)
+        for _ in range(2):
+            model.train_step(tin, tgt, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        treps = 10
+        for _ in range(treps):
+            model.train_step(tin, tgt, 0.0)
+        torch.cuda.synchronize()
+        network["train_step_ms"] = (time.perf_counter() - t0) * 1e3 / treps
+        network["train_batch"] = tb
 
     if args.calib_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
