@@ -124,3 +124,35 @@ def test_hard_case_fixed_point_property(env):
         # the last GPU change was < 1e-6 (scaled by c < 1 through one more
         # sweep) plus the FP32 rounding of the GPU sweep itself
         assert r < 5e-6
+
+
+def test_pipeline_bitwise_reproducible(env):
+    """No floating-point atomics anywhere on the path: the recast guess and
+    the warm-started solve on 256 x 256 S16 instances (the specialised sweep
+    in the benchmark's launch shape) repeat bit for bit, with the same
+    iteration counts."""
+    torch, B, ctx, model = env
+    wl = I.hard_two_region(4, 256)
+    probs = [to_problem(i, torch) for i in wl.instances]
+    quad = B.Quad.from_inputs(wl.quad)
+    ctx.set_sweep_config(1, 9, 4, 64)
+    try:
+        assert ctx.sweep_plan(probs, quad)["specialised"] == 1
+        runs = []
+        for _ in range(2):
+            phis = [torch.zeros_like(p.sigma_t) for p in probs]
+            _, sg = B.no_recast_guess(ctx, model, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR,
+                                      RECAST_TOL, 30, phis)
+            guess = [g.cpu().numpy().copy() for g in phis]
+            _, st = B.tr_solve(ctx, probs, quad, phis, phis, 1e-6, 20000)
+            runs.append((guess, [p.cpu().numpy() for p in phis],
+                         [s["iterations"] for s in sg], [s["iterations"] for s in st]))
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+    (g0, p0, r0, i0), (g1, p1, r1, i1) = runs
+    log(f"  reproducibility: recast iterations {r0}, SI iterations {i0}")
+    assert r0 == r1 and i0 == i1
+    for a, b in zip(g0, g1):
+        assert np.array_equal(a, b)
+    for a, b in zip(p0, p1):
+        assert np.array_equal(a, b)
