@@ -173,23 +173,37 @@ gemm_kernel(GemmArgs a) {
 }
 
 // Sum of split-K partials in slice order, then the epilogue.
-__global__ void gemm_reduce_kernel(GemmArgs a) {
+// Fixed-order split-K reduction: a workgroup takes 64 consecutive outputs
+// (coalesced partial loads) and kRedWaves waves; wave w sums the slices
+// kz = w, w + kRedWaves, ... in order, and the wave sums are added in wave
+// order before the epilogue.
+constexpr int kRedWaves = 16;
+__global__ void __launch_bounds__(64 * kRedWaves) gemm_reduce_kernel(GemmArgs a) {
     const long long total = (long long)a.G * a.M * a.N;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int n = (int)(e % a.N);
-        const int m = (int)((e / a.N) % a.M);
-        const int g = (int)(e / ((long long)a.M * a.N));
-        float s = 0.f;
-        for (int kz = 0; kz < a.ksplit; ++kz) s += a.partial[(long long)kz * total + e];
-        float* pc = a.C.p + voff(a.C, g, m, n);
-        float r = a.alpha * s;
-        if (a.accumulate) r += *pc;
-        if (a.bias_row) r += a.bias_row[m];
-        if (a.bias_col) r += a.bias_col[n];
-        *pc = r;
-        if (a.gelu_out) a.gelu_out[pc - a.C.p] = gelu_dev(r);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long e = (long long)blockIdx.x * 64 + lane;
+    __shared__ float ps[kRedWaves][64];
+    float s = 0.f;
+    if (e < total) {
+#pragma unroll 4
+        for (int kz = w; kz < a.ksplit; kz += kRedWaves) s += a.partial[(long long)kz * total + e];
     }
+    ps[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || e >= total) return;
+    float t = 0.f;
+#pragma unroll
+    for (int v = 0; v < kRedWaves; ++v) t += ps[v][lane];
+    const int n = (int)(e % a.N);
+    const int m = (int)((e / a.N) % a.M);
+    const int g = (int)(e / ((long long)a.M * a.N));
+    float* pc = a.C.p + voff(a.C, g, m, n);
+    float r = a.alpha * t;
+    if (a.accumulate) r += *pc;
+    if (a.bias_row) r += a.bias_row[m];
+    if (a.bias_col) r += a.bias_col[n];
+    *pc = r;
+    if (a.gelu_out) a.gelu_out[pc - a.C.p] = gelu_dev(r);
 }
 
 static long long hidx(int i, int ls, long long hi, long long lo) {
@@ -218,8 +232,8 @@ bool launch_gemm(const GemmArgs& a0, hipStream_t s) {
             hipLaunchKernelGGL(gemm_kernel<false>, grid, dim3(256), 0, s, a);
         if (a.ksplit > 1) {
             const long long total = (long long)a.G * a.M * a.N;
-            const int blocks = (int)std::min<long long>(4096, (total + 255) / 256);
-            hipLaunchKernelGGL(gemm_reduce_kernel, dim3(blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((total + 63) / 64)),
+                               dim3(64 * kRedWaves), 0, s, a);
         }
     }
     return true;
