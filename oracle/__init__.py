@@ -11,7 +11,9 @@ Contents
   * ``recast``: the equation-recast loop of Eq. 24 with a caller-given inner
     solution operator (the exact transport operator at p* for the closed-form
     check, or a network);
-  * ``fno``: FP64 forward/backward of the Fourier neural operator and Adam.
+  * ``fno``: FP64 forward/backward of the Fourier neural operator and Adam;
+  * ``eigen``: the one-group k-eigenvalue power iteration (section 5.2
+    Eq. 26, Appendix A2 Eq. A1-A4) around the source iteration.
 """
 from __future__ import annotations
 

@@ -1,0 +1,116 @@
+"""FP64 oracle of the one-group k-eigenvalue power iteration.
+
+TEST INFRASTRUCTURE ONLY (imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg).
+
+Section 5.2, Eq. 26: the fixed source of Eq. 12 is replaced by the fission
+emission nu*sigma_f*phi/k (per unit weight in this library's normalisation,
+where the weights sum to 1).  Appendix A2 (Eq. A1-A4) solves it with two
+nested loops:
+  * inner M: the fixed-source problem with the current fission source,
+    iterated to convergence (here the FP64 source iteration of ``si1d`` /
+    ``si2d``, warm-started from the current eigenfunction);
+  * outer P: new eigenvalue from the fission-production ratio and
+    normalisation of the eigenfunction, then a new fission source.
+
+Update P (the normalisation condition of Appendix A2):
+    F(phi)   = sum_cells nu_sigma_f * phi * V
+    k_new    = k * F(phi_half) / F(phi)
+    phi_new  = phi_half / F(phi_half)          (so that F(phi_new) = 1)
+Stopping rule (section 5.2 applies one tolerance to k and to phi):
+    |k_new - k| / k_new < tol_k  and
+    max|phi_new - phi| / max|phi_new| < tol_phi.
+"""
+from __future__ import annotations
+
+from typing import Callable
+
+import numpy as np
+
+from . import si1d, si2d
+
+
+class EigenResult:
+    def __init__(self, k, phi, outer, inner, dk, dphi, converged, k_hist):
+        self.k = k
+        self.phi = phi
+        self.outer = outer
+        self.inner = inner
+        self.dk = dk
+        self.dphi = dphi
+        self.converged = converged
+        self.k_history = k_hist
+
+
+def fission_production(nu_sigma_f, phi, vol):
+    """F(phi) = sum nu_sigma_f * phi * V over the cells (FP64)."""
+    return float(np.sum(np.asarray(nu_sigma_f, float) * np.asarray(phi, float)) * vol)
+
+
+def power_iteration(inner: Callable[[np.ndarray, np.ndarray], tuple],
+                    nu_sigma_f, vol, phi0=None, k0=1.0, tol_k=1e-10,
+                    tol_phi=1e-10, max_outer=10000) -> EigenResult:
+    """Outer loop P around a caller-given inner solve (Appendix A2).
+
+    inner(S, phi_warm) -> (phi_half, inner_iterations) solves the fixed-source
+    problem with isotropic source S from the warm start phi_warm.
+    phi0 = None starts from a flat flux."""
+    nsf = np.asarray(nu_sigma_f, float)
+    phi = np.ones_like(nsf) if phi0 is None else np.array(phi0, float)
+    F = fission_production(nsf, phi, vol)
+    if not F > 0:
+        raise ValueError("the initial flux produces no fissions")
+    phi = phi / F
+    k = float(k0)
+    inner_total = 0
+    hist = []
+    dk = dphi = np.inf
+    for n in range(1, max_outer + 1):
+        S = nsf * phi / k                          # Eq. 26 fission emission
+        phi_half, it = inner(S, phi)               # Eq. A2
+        inner_total += it
+        F_half = fission_production(nsf, phi_half, vol)
+        F_old = fission_production(nsf, phi, vol)
+        k_new = k * F_half / F_old                 # Eq. A3: eigenvalue
+        phi_new = phi_half / F_half                # Eq. A3: normalisation
+        dk = abs(k_new - k) / abs(k_new)
+        dphi = np.max(np.abs(phi_new - phi)) / np.max(np.abs(phi_new))
+        k, phi = k_new, phi_new
+        hist.append(k)
+        if dk < tol_k and dphi < tol_phi:
+            return EigenResult(k, phi, n, inner_total, dk, dphi, True, hist)
+    return EigenResult(k, phi, max_outer, inner_total, dk, dphi, False, hist)
+
+
+def si_inner(inst, quad, tol):
+    """Inner M for an ``inputs.Instance``: FP64 source iteration to ``tol``
+    (max-norm in 1-D, relative L2 in 2-D), warm-started."""
+    if inst.dim == 1:
+        def inner(S, phi):
+            r = si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
+                     inst.sigma_s, S, bc=inst.bc[:2], phi0=phi, tol=tol,
+                     norm="max")
+            return r.phi, r.iterations
+    else:
+        def inner(S, phi):
+            r = si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta,
+                     quad.w, inst.sigma_t, inst.sigma_s, S, bc=inst.bc,
+                     phi0=phi, tol=tol, norm="l2")
+            return r.phi, r.iterations
+    return inner
+
+
+def cell_volume(inst) -> float:
+    if inst.dim == 1:
+        return inst.lx / inst.nx
+    return (inst.lx / inst.nx) * (inst.ly / inst.ny)
+
+
+def solve_eigen(inst, quad, nu_sigma_f, tol_inner=1e-12, tol_k=1e-10,
+                tol_phi=1e-10, phi0=None, k0=1.0, max_outer=10000) -> EigenResult:
+    """Model-based k-eigenvalue solve of one instance (its ``source`` field
+    is not used; the fission emission replaces it)."""
+    nsf = np.asarray(nu_sigma_f, float).reshape(np.shape(inst.sigma_t))
+    return power_iteration(si_inner(inst, quad, tol_inner), nsf,
+                           cell_volume(inst), phi0=phi0, k0=k0, tol_k=tol_k,
+                           tol_phi=tol_phi, max_outer=max_outer)

@@ -1,0 +1,145 @@
+"""Pins of the FP64 k-eigenvalue oracle (section 5.2 Eq. 26; Appendix A2).
+
+Each pin stands apart from the oracle's power iteration:
+  * the infinite medium (reflective on every face, uniform data), where the
+    eigenvalue is nu*sigma_f / sigma_a and the flux is flat;
+  * a brute-force eigen-solve on tiny grids: the fixed-source response G of
+    the global diamond-difference system (sparse direct solves, one per
+    cell, tests/dd_direct.py) gives k as the dominant eigenvalue of
+    G diag(nu*sigma_f), with no iteration at all;
+  * the eigenvalue printed for eigen Case 1 (Table 7), under the reading
+    nu = 3 and vacuum slab faces;
+  * linearity: scaling nu*sigma_f by a scales k by a; the limit does not
+    depend on the starting flux or eigenvalue.
+"""
+import numpy as np
+import pytest
+
+from dd_direct import solve_1d, solve_2d
+from oracle import eigen as E
+from paper_2509_01416_amd import inputs as I
+
+
+def _inst_1d(n, lx, st, ss, bc=(0, 0)):
+    return I.Instance(nx=n, ny=1, lx=lx, ly=1.0, sigma_t=np.asarray(st, float).reshape(1, n),
+                      sigma_s=np.asarray(ss, float).reshape(1, n),
+                      source=np.zeros((1, n)), bc=tuple(bc) + (0, 0), dim=1)
+
+
+def _dense_k(inst, quad, nsf):
+    """Dominant eigenvalue and eigenvector of G diag(nu_sigma_f), with G
+    assembled column by column from direct fixed-source solves."""
+    n = inst.cells
+    G = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        if inst.dim == 1:
+            G[:, c] = solve_1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
+                               inst.sigma_s, e, bc=inst.bc[:2])
+        else:
+            G[:, c] = solve_2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta,
+                               quad.w, inst.sigma_t, inst.sigma_s, e.reshape(inst.ny, inst.nx),
+                               inst.bc).reshape(-1)
+    A = G @ np.diag(np.asarray(nsf, float).reshape(-1))
+    vals, vecs = np.linalg.eig(A)
+    j = int(np.argmax(vals.real))
+    v = np.real(vecs[:, j])
+    v = v / E.fission_production(nsf.reshape(-1), v, E.cell_volume(inst))
+    return float(vals[j].real), v
+
+
+def test_infinite_medium_1d():
+    n = 20
+    inst = _inst_1d(n, 4.0, np.full(n, 1.0), np.full(n, 0.5), bc=(1, 1))
+    nsf = np.full((1, n), 0.9)
+    r = E.solve_eigen(inst, I.gauss_legendre(8), nsf)
+    assert r.converged
+    assert abs(r.k - 0.9 / 0.5) < 1e-9
+    assert np.ptp(r.phi) < 1e-9 * np.max(r.phi)
+    assert abs(E.fission_production(nsf, r.phi, E.cell_volume(inst)) - 1.0) < 1e-12
+
+
+def test_infinite_medium_2d():
+    inst = I.Instance(nx=6, ny=5, lx=3.0, ly=2.5, sigma_t=np.full((5, 6), 2.0),
+                      sigma_s=np.full((5, 6), 1.2), source=np.zeros((5, 6)), bc=(1, 1, 1, 1))
+    nsf = np.full((5, 6), 0.5)
+    r = E.solve_eigen(inst, I.level_symmetric_2d(4), nsf)
+    assert r.converged
+    assert abs(r.k - 0.5 / 0.8) < 1e-9
+    assert np.ptp(r.phi) < 1e-9 * np.max(r.phi)
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0)])
+def test_dense_eigensolve_1d(bc):
+    rng = np.random.Generator(np.random.PCG64(3))
+    n = 14
+    st = rng.uniform(0.6, 1.8, n)
+    ss = st * rng.uniform(0.2, 0.7, n)
+    nsf = (st - ss) * rng.uniform(0.8, 2.5, n)
+    nsf[3:6] = 0.0                                   # a non-fissile zone
+    inst = _inst_1d(n, 5.0, st, ss, bc=bc)
+    quad = I.gauss_legendre(8)
+    k_ref, v_ref = _dense_k(inst, quad, nsf.reshape(1, n))
+    r = E.solve_eigen(inst, quad, nsf.reshape(1, n), tol_k=1e-13, tol_phi=1e-12)
+    assert r.converged
+    assert abs(r.k - k_ref) < 1e-10 * k_ref, (r.k, k_ref)
+    assert np.max(np.abs(r.phi.reshape(-1) - v_ref)) < 1e-8 * np.max(np.abs(v_ref))
+
+
+def test_dense_eigensolve_2d():
+    rng = np.random.Generator(np.random.PCG64(5))
+    nx, ny = 5, 4
+    st = rng.uniform(0.5, 1.5, (ny, nx))
+    ss = st * rng.uniform(0.3, 0.8, (ny, nx))
+    nsf = (st - ss) * rng.uniform(1.0, 2.0, (ny, nx))
+    inst = I.Instance(nx=nx, ny=ny, lx=2.0, ly=1.5, sigma_t=st, sigma_s=ss,
+                      source=np.zeros((ny, nx)), bc=(1, 0, 0, 1))
+    quad = I.level_symmetric_2d(4)
+    k_ref, v_ref = _dense_k(inst, quad, nsf)
+    r = E.solve_eigen(inst, quad, nsf, tol_k=1e-13, tol_phi=1e-12)
+    assert r.converged
+    assert abs(r.k - k_ref) < 1e-10 * k_ref, (r.k, k_ref)
+    assert np.max(np.abs(r.phi.reshape(-1) - v_ref)) < 1e-8 * np.max(np.abs(v_ref))
+
+
+def test_eigen_case1_printed_k():
+    """Eigen Case 1 (section 5.2; Table 7 model-based k = 1.71402):
+    sigma_t = 1, sigma_s = 0.5, sigma_f = 0.3 on the 10 cm slab of section
+    5.1 (100 cells, S32).  The paper gives no nu and no boundary condition;
+    nu = 3 and vacuum faces are the reading.  The converged DD value under
+    it is 1.71467 (S8 to S64 and 100 to 1000 cells agree to 1e-4), 0.04 %
+    above the printed number, which came from solvers stopped at 1e-4;
+    the pin allows 5e-4 relative."""
+    n = 100
+    inst = _inst_1d(n, 10.0, np.ones(n), np.full(n, 0.5))
+    nsf = np.full((1, n), 3.0 * 0.3)
+    r = E.solve_eigen(inst, I.gauss_legendre(32), nsf, tol_inner=1e-11,
+                      tol_k=1e-10, tol_phi=1e-9)
+    assert r.converged
+    assert abs(r.k - 1.71402) / 1.71402 < 5e-4, r.k
+    assert abs(r.k - 1.714665) < 2e-5, r.k
+    # symmetric slab: symmetric eigenfunction, peaked at the centre
+    phi = r.phi.reshape(-1)
+    assert np.max(np.abs(phi - phi[::-1])) < 1e-8 * phi.max()
+    assert np.argmax(phi) in (49, 50)
+
+
+def test_linearity_and_start_independence():
+    rng = np.random.Generator(np.random.PCG64(9))
+    n = 30
+    st = rng.uniform(0.8, 1.2, n)
+    ss = 0.6 * st
+    nsf = 0.5 * st
+    inst = _inst_1d(n, 6.0, st, ss)
+    quad = I.gauss_legendre(8)
+    a = E.solve_eigen(inst, quad, nsf.reshape(1, n), tol_k=1e-12, tol_phi=1e-11)
+    b = E.solve_eigen(inst, quad, 2.5 * nsf.reshape(1, n), tol_k=1e-12, tol_phi=1e-11)
+    c = E.solve_eigen(inst, quad, nsf.reshape(1, n), tol_k=1e-12, tol_phi=1e-11,
+                      phi0=rng.uniform(0.1, 1.0, (1, n)), k0=3.0)
+    assert abs(b.k - 2.5 * a.k) < 1e-9 * b.k
+    assert abs(c.k - a.k) < 1e-9 * a.k
+    assert np.max(np.abs(c.phi - a.phi)) < 1e-8 * np.max(a.phi)
+    # F(phi) = 1 after every update
+    for r in (a, c):
+        assert abs(E.fission_production(nsf, r.phi.reshape(-1), 6.0 / n) - 1.0) < 1e-12
