@@ -114,6 +114,45 @@ tr_status tr_solve(tr_context *ctx, int32_t n_inst, const tr_problem *p,
                    float *const *phi_out, double tol, int32_t max_iter,
                    tr_stats *stats);
 
+/* Per-instance results of tr_eigen.  outer: outer updates performed;
+ * inner: source-iteration sweeps summed over all inner solves; k: final
+ * eigenvalue; dk, dphi: the last update's |k_new - k|/k_new and
+ * max|phi_new - phi|/max|phi_new|; balance_rel: particle balance of the last
+ * inner solve (fission emission against absorption plus leakage, FP64).   */
+typedef struct {
+    int32_t status, outer, inner;
+    double k, dk, dphi, balance_rel, seconds;
+} tr_eigen_stats;
+
+/*
+ * One-group k-eigenvalue (section 5.2, Eq. 26; Appendix A2, Eq. A1-A4):
+ * the fixed source of each problem is replaced by the fission emission
+ * nu_sigma_f*phi/k (per unit weight), and power iteration solves
+ *   inner M:  source iteration of the fixed-source problem with source
+ *             S = nu_sigma_f*phi/k, warm-started from phi, to tol_inner
+ *             (same norm convention as tr_solve's tol) or max_inner sweeps;
+ *   outer P:  F(phi) = sum nu_sigma_f*phi*V (FP64),
+ *             k <- k*F(phi_half)/F(phi),  phi <- phi_half/F(phi_half),
+ * until |dk|/k < tol_k and max|dphi|/max|phi| < tol_phi, or max_outer
+ * updates.  nu_sigma_f[i]: DEVICE field (cells, >= 0, finite); the
+ * problems' source pointers are not read (may be NULL).  phi_init[i]
+ * (device, may equal phi_out[i]; NULL array or entry = flat start) must give
+ * F > 0; k_init (HOST, n_inst values > 0; NULL = 1.0) is the starting
+ * eigenvalue.  On return phi_out[i] is the eigenfunction normalised to
+ * F(phi) = 1 and stats[i] (may be NULL) holds k and the counters.  All
+ * instances run as one batch; each stops on its own test.  Status per
+ * instance: TR_OK, TR_NOT_CONVERGED (max_outer reached) or
+ * TR_ERR_NONFINITE; invalid data (negative or non-finite nu_sigma_f, a start
+ * without fissions, the tr_solve field checks) gives TR_ERR_INVALID_ARG
+ * before any iteration.  The context keeps a workspace of two fields per
+ * instance between calls.                                                  */
+tr_status tr_eigen(tr_context *ctx, int32_t n_inst, const tr_problem *p,
+                   const float *const *nu_sigma_f, const tr_quadrature *q,
+                   const float *const *phi_init, float *const *phi_out,
+                   const double *k_init, double tol_k, double tol_phi,
+                   double tol_inner, int32_t max_outer, int32_t max_inner,
+                   tr_eigen_stats *stats);
+
 /*
  * Equation-recast guess (Eq. 24; Eq. 8 in general form): with the network
  * m trained at (sigma_t_star, sigma_s_star), iterate

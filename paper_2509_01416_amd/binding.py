@@ -26,7 +26,7 @@ TR_ERR_OOM = -3
 TR_ERR_NONFINITE = -4
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
-           "tr_sweep", "tr_solve", "no_recast_guess", "no_model_create",
+           "tr_sweep", "tr_solve", "tr_eigen", "no_recast_guess", "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
            "no_train_step",
@@ -52,6 +52,13 @@ class TrStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("balance_rel", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
+
+
+class TrEigenStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("inner", ctypes.c_int32), ("k", ctypes.c_double),
+                ("dk", ctypes.c_double), ("dphi", ctypes.c_double),
+                ("balance_rel", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class MdpError(RuntimeError):
@@ -84,6 +91,8 @@ def load(path: str = LIB_PATH):
                              d, i32, P(TrStats)]
     lib.no_recast_guess.argtypes = [vp, vp, i32, P(TrProblem), d, d, d, i32, P(vp),
                                     P(TrStats)]
+    lib.tr_eigen.argtypes = [vp, i32, P(TrProblem), P(vp), P(TrQuadrature), P(vp), P(vp),
+                             P(d), d, d, d, i32, i32, P(TrEigenStats)]
     lib.no_model_create.argtypes = [vp, P(vp), i32, i32, i32, i32, vp]
     lib.no_model_destroy.argtypes = [vp]
     lib.no_model_destroy.restype = None
@@ -277,6 +286,39 @@ def tr_solve(ctx: Context, problems: Sequence[Problem], quad: Quad,
     return rc, [dict(status=s.status, iterations=s.iterations,
                      residual=s.residual, balance_rel=s.balance_rel,
                      seconds=s.seconds) for s in stats]
+
+
+def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
+             quad: Quad, phi_init: Optional[Sequence], phi_out: Sequence,
+             k_init: Optional[Sequence[float]] = None, tol_k: float = 1e-6,
+             tol_phi: float = 1e-5, tol_inner: float = 1e-6, max_outer: int = 1000,
+             max_inner: int = 10000, raise_on_error: bool = True):
+    """k-eigenvalue power iteration; the problems' source fields are not
+    read.  Returns (status, list of per-instance stats dicts)."""
+    n = len(problems)
+    arr = make_problems(problems)
+    stats = (TrEigenStats * n)()
+    if len(nu_sigma_f) != n or len(phi_out) != n or (phi_init is not None
+                                                     and len(phi_init) != n):
+        raise ValueError("one nu_sigma_f, phi_out (and phi_init) per problem")
+    for i, p in enumerate(problems):
+        for t in [nu_sigma_f[i], phi_out[i]] + ([] if phi_init is None or phi_init[i] is None
+                                                else [phi_init[i]]):
+            if (str(t.dtype) != "torch.float32" or t.device.type != "cuda"
+                    or t.numel() != p.nx * p.ny):
+                raise ValueError(f"problem {i}: nu_sigma_f, phi_init and phi_out must be "
+                                 f"float32 GPU tensors of {p.nx * p.ny} cells")
+    init = None if phi_init is None else _ptr_array(phi_init)
+    kin = None if k_init is None else (ctypes.c_double * n)(*[float(k) for k in k_init])
+    rc = ctx.lib.tr_eigen(ctx.handle, n, arr, _ptr_array(nu_sigma_f),
+                          ctypes.byref(quad.struct), init, _ptr_array(phi_out), kin,
+                          float(tol_k), float(tol_phi), float(tol_inner), int(max_outer),
+                          int(max_inner), stats)
+    if raise_on_error:
+        ctx.check(rc)
+    return rc, [dict(status=s.status, outer=s.outer, inner=s.inner, k=s.k, dk=s.dk,
+                     dphi=s.dphi, balance_rel=s.balance_rel, seconds=s.seconds)
+                for s in stats]
 
 
 def tr_check_args(problems_struct, n: int, quad: Quad, tol: float,

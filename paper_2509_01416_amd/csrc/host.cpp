@@ -39,7 +39,7 @@ void launch_scan(int n_inst, int nblocks, const InstDesc* insts, const int4* blo
                  double* part, int* flags, float* samax, hipStream_t s);
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                  const int4* blocks, const DirTable* dt, IterState st,
-                 hipStream_t s);
+                 const int* skip, hipStream_t s);
 void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     const int* done, double2* red, int mode, int norm_kind,
                     hipStream_t s);
@@ -284,9 +284,11 @@ void Ctx::release() {
         if (e[1]) (void)hipEventDestroy(e[1]);
         e[0] = e[1] = nullptr;
     }
-    if (arena.base) (void)hipFree(arena.base);
-    arena.base = nullptr;
-    arena.cap = 0;
+    for (Arena* a : {&arena, &eig}) {
+        if (a->base) (void)hipFree(a->base);
+        a->base = nullptr;
+        a->cap = 0;
+    }
     if (pinned.ptr) (void)hipHostFree(pinned.ptr);
     pinned.ptr = nullptr;
     pinned.cap = 0;
@@ -639,6 +641,61 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
     return hip_ok(hipGetLastError(), "sweep launch");
 }
 
+// Source iteration from the state launch_init left: sweeps in chunks of
+// 4, 8, ... 64 between read-backs of the per-instance done flags, until every
+// instance is done or max_iter sweeps have run.
+bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, int max_iter,
+                     int* sweeps) {
+    int* hdone = (int*)pinned.ptr;
+    int done_iters = 0, chunk = 4;
+    const bool fused_fin = su.inst[0].dim == 2;
+    bool all = false;
+    while (done_iters < max_iter && !all) {
+        const int k = std::min(chunk, max_iter - done_iters);
+        for (int it = 0; it < k; ++it) {
+            // 2-D: the convergence test of iteration it - 1 runs in the
+            // prologue of sweep it (FinArgs); the chunk's last iteration is
+            // tested by the finalize kernel before the flags are read back
+            const FinArgs fin{su.d_red, su.st, atol, norm_kind, fused_fin && it > 0 ? 1 : 0,
+                              done_iters + it};
+            const bool p0 = prof_begin(0);
+            if (!launch_sweep(su, n_inst, su.st.done, su.st.iter, 1, false, &fin)) return false;
+            if (p0) prof_end();
+            const bool p1 = prof_begin(1);
+            launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
+                           su.d_red, 0, norm_kind, stream);
+            if (!fused_fin || it + 1 == k)
+                launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind, stream);
+            if (p1) prof_end();
+        }
+        if (!hip_ok(hipGetLastError(), "iteration launch")) return false;
+        done_iters += k;
+        if (!hip_ok(hipMemcpyAsync(hdone, su.st.done, sizeof(int) * n_inst,
+                                   hipMemcpyDeviceToHost, stream), "flag copy") ||
+            !hip_ok(hipStreamSynchronize(stream), "sync"))
+            return false;
+        prof_collect();
+        all = true;
+        for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
+        chunk = std::min(chunk * 2, 64);
+    }
+    if (sweeps) *sweeps = done_iters;
+    return true;
+}
+
+// Particle balance of the last sweep into su.d_bal.  The specialised sweep
+// stores no boundary faces while iterating (vacuum inflow reads none): one
+// more sweep of the final emission tallies them, into the current face
+// parity, without touching the iterate.
+bool Ctx::si_balance(const Setup& su, int n_inst) {
+    if (su.inst[0].dim == 2 && su.plan.fast &&
+        !launch_sweep(su, n_inst, nullptr, su.st.iter, 1, true))
+        return false;
+    launch_balance(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_dt, su.st.iter,
+                   su.d_bpart, su.d_bal, stream);
+    return hip_ok(hipGetLastError(), "balance launch");
+}
+
 // Field checks on the device: non-finite values, cross-section ranges, and a
 // singular system (no absorption anywhere and no vacuum face).
 tr_status Ctx::scan_fields(const Setup& su, int n_inst, const tr_problem* p,
@@ -737,54 +794,12 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
     tr_status s0 = c->scan_fields(su, n_inst, p, true, stats);
     if (s0 < 0) return s0;
     launch_init(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_dt,
-                su.st, c->stream);
+                su.st, nullptr, c->stream);
     if (!c->hip_ok(hipGetLastError(), "init launch")) return TR_ERR_HIP;
-    int* hdone = (int*)c->pinned.ptr;
-    int done_iters = 0, chunk = 4;
-    const bool fused_fin = p[0].dim == 2;
-    bool all = false;
-    while (done_iters < max_iter && !all) {
-        const int k = std::min(chunk, max_iter - done_iters);
-        for (int it = 0; it < k; ++it) {
-            // 2-D: the convergence test of iteration it - 1 runs in the
-            // prologue of sweep it (FinArgs); the chunk's last iteration is
-            // tested by the finalize kernel before the flags are read back
-            const FinArgs fin{su.d_red, su.st, atol, norm_kind, fused_fin && it > 0 ? 1 : 0,
-                              done_iters + it};
-            const bool p0 = c->prof_begin(0);
-            if (!c->launch_sweep(su, n_inst, su.st.done, su.st.iter, 1, false, &fin))
-                return TR_ERR_HIP;
-            if (p0) c->prof_end();
-            const bool p1 = c->prof_begin(1);
-            launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
-                           su.d_red, 0, norm_kind, c->stream);
-            if (!fused_fin || it + 1 == k)
-                launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind,
-                                c->stream);
-            if (p1) c->prof_end();
-        }
-        if (!c->hip_ok(hipGetLastError(), "iteration launch")) return TR_ERR_HIP;
-        done_iters += k;
-        if (!c->hip_ok(hipMemcpyAsync(hdone, su.st.done, sizeof(int) * n_inst,
-                                      hipMemcpyDeviceToHost, c->stream),
-                       "flag copy") ||
-            !c->hip_ok(hipStreamSynchronize(c->stream), "sync"))
-            return TR_ERR_HIP;
-        c->prof_collect();
-        all = true;
-        for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
-        chunk = std::min(chunk * 2, 64);
-    }
-    // The specialised sweep stores no boundary faces while iterating
-    // (vacuum inflow reads none): one more sweep of the final emission
-    // tallies them for the balance, into the current face parity, without
-    // touching the iterate.
-    if (p[0].dim == 2 && su.plan.fast &&
-        !c->launch_sweep(su, n_inst, nullptr, su.st.iter, 1, true))
+    int done_iters = 0;
+    if (!c->si_iterate(su, n_inst, atol, norm_kind, max_iter, &done_iters) ||
+        !c->si_balance(su, n_inst))
         return TR_ERR_HIP;
-    launch_balance(n_inst, (int)su.blocks.size(), su.d_inst, su.d_blocks, su.d_dt, su.st.iter,
-                   su.d_bpart, su.d_bal, c->stream);
-    if (!c->hip_ok(hipGetLastError(), "balance launch")) return TR_ERR_HIP;
     // read back iteration state
     if (!c->pinned.reserve(c, 2 * align_up(sizeof(int) * n_inst) +
                                    align_up(sizeof(double) * n_inst) +

@@ -58,6 +58,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     std::string err;
     Arena arena;          // per-call solver workspace
+    Arena eig;            // k-eigenvalue workspace (fission source, last iterate, state)
     PinnedBuf pinned;     // staging and flag read-back
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
     bool force_generic = false;   // never use the specialised sweep kernel
@@ -89,6 +90,9 @@ struct Ctx {
                       const FinArgs* fin = nullptr);
     tr_status scan_fields(const Setup& su, int n_inst, const tr_problem* p,
                           bool need_xs, tr_stats* stats);
+    bool si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, int max_iter,
+                    int* sweeps);
+    bool si_balance(const Setup& su, int n_inst);
 };
 
 size_t align_up(size_t x);

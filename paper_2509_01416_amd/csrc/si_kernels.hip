@@ -108,9 +108,10 @@ __global__ void scan_fin_kernel(const InstDesc* __restrict__ insts,
 // ------------------------------------------------------------- init ------
 // Grid: one block per reduction block (instance, first cell, slot).
 __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
-                                  const int4* __restrict__ blocks) {
+                                  const int4* __restrict__ blocks,
+                                  const int* __restrict__ skip) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0) return;
+    if (bi.x < 0 || (skip != nullptr && skip[bi.x])) return;
     const InstDesc& I = insts[bi.x];
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += blockDim.x) {
@@ -123,16 +124,22 @@ __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
 // Faces of parity 0: isotropic at the adjacent cell's initial flux (warm
 // start) or zero.  One workgroup per reduction block, each taking an even
 // share of its instance's face entries; the instance's first block also
-// resets the iteration state.
+// resets the iteration state.  An instance with skip[n] set keeps its
+// fields, faces and sweep count and is only marked done, so the sweeps pass
+// it by.
 __global__ void __launch_bounds__(256)
 init_faces_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
-                  const DirTable* __restrict__ dt, IterState st) {
+                  const DirTable* __restrict__ dt, IterState st, const int* __restrict__ skip) {
     const int4 bi = blocks[blockIdx.x];
     const int n = bi.x;
     if (n < 0) return;
     const InstDesc& I = insts[n];
     const int M = dt->M;
     const int j = bi.z - I.red0;
+    if (skip != nullptr && skip[n]) {
+        if (j == 0 && threadIdx.x == 0) st.done[n] = 1;
+        return;
+    }
     if (j == 0 && threadIdx.x == 0) {
         st.done[n] = 0;
         st.iter[n] = 0;
@@ -442,11 +449,11 @@ void launch_scan(int n_inst, int nblocks, const InstDesc* insts, const int4* blo
 
 void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                  const int4* blocks, const DirTable* dt, IterState st,
-                 hipStream_t s) {
+                 const int* skip, hipStream_t s) {
     hipLaunchKernelGGL(init_cells_kernel, dim3(nblocks), dim3(kCombineThreads), 0,
-                       s, insts, blocks);
+                       s, insts, blocks, skip);
     hipLaunchKernelGGL(init_faces_kernel, dim3(nblocks), dim3(256), 0, s, insts, blocks,
-                       dt, st);
+                       dt, st, skip);
 }
 
 void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
