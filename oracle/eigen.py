@@ -9,7 +9,9 @@ where the weights sum to 1).  Appendix A2 (Eq. A1-A4) solves it with two
 nested loops:
   * inner M: the fixed-source problem with the current fission source,
     iterated to convergence (here the FP64 source iteration of ``si1d`` /
-    ``si2d``, warm-started from the current eigenfunction);
+    ``si2d``, warm-started from the current eigenfunction), or, in the
+    neural-operator variants (Eq. A5, A7-A8), one network application (SP)
+    or one network application and one sweep (CP);
   * outer P: new eigenvalue from the fission-production ratio and
     normalisation of the eigenfunction, then a new fission source.
 
@@ -52,9 +54,9 @@ def power_iteration(inner: Callable[[np.ndarray, np.ndarray], tuple],
                     tol_phi=1e-10, max_outer=10000) -> EigenResult:
     """Outer loop P around a caller-given inner solve (Appendix A2).
 
-    inner(S, phi_warm) -> (phi_half, inner_iterations) solves the fixed-source
-    problem with isotropic source S from the warm start phi_warm.
-    phi0 = None starts from a flat flux."""
+    inner(S, phi_warm, k) -> (phi_half, inner_iterations) solves the
+    fixed-source problem with isotropic source S = nu_sigma_f phi_warm / k
+    from the warm start phi_warm.  phi0 = None starts from a flat flux."""
     nsf = np.asarray(nu_sigma_f, float)
     phi = np.ones_like(nsf) if phi0 is None else np.array(phi0, float)
     F = fission_production(nsf, phi, vol)
@@ -67,7 +69,7 @@ def power_iteration(inner: Callable[[np.ndarray, np.ndarray], tuple],
     dk = dphi = np.inf
     for n in range(1, max_outer + 1):
         S = nsf * phi / k                          # Eq. 26 fission emission
-        phi_half, it = inner(S, phi)               # Eq. A2
+        phi_half, it = inner(S, phi, k)            # Eq. A2
         inner_total += it
         F_half = fission_production(nsf, phi_half, vol)
         F_old = fission_production(nsf, phi, vol)
@@ -86,13 +88,13 @@ def si_inner(inst, quad, tol):
     """Inner M for an ``inputs.Instance``: FP64 source iteration to ``tol``
     (max-norm in 1-D, relative L2 in 2-D), warm-started."""
     if inst.dim == 1:
-        def inner(S, phi):
+        def inner(S, phi, k):
             r = si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
                      inst.sigma_s, S, bc=inst.bc[:2], phi0=phi, tol=tol,
                      norm="max")
             return r.phi, r.iterations
     else:
-        def inner(S, phi):
+        def inner(S, phi, k):
             r = si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta,
                      quad.w, inst.sigma_t, inst.sigma_s, S, bc=inst.bc,
                      phi0=phi, tol=tol, norm="l2")
@@ -114,3 +116,57 @@ def solve_eigen(inst, quad, nu_sigma_f, tol_inner=1e-12, tol_k=1e-10,
     return power_iteration(si_inner(inst, quad, tol_inner), nsf,
                            cell_volume(inst), phi0=phi0, k0=k0, tol_k=tol_k,
                            tol_phi=tol_phi, max_outer=max_outer)
+
+
+# ------------------------------------------------ neural-operator variants --
+# Appendix A2 (i)-(ii).  linv_star(S) -> phi is the inverse transport operator
+# at the training parameters p* (the network, wrapped by
+# recast.network_inner, or an exact solve for the checks); the parameter
+# deviation enters as the recast source (sigma_a* - sigma_a) phi of Eq. 24.
+
+def sp_inner(linv_star, sigma_a, sigma_a_star):
+    """Simple preconditioning, Eq. A5: the inner solve is one application of
+    linv_star to the fission source plus the recast term of the current
+    iterate."""
+    sa = np.asarray(sigma_a, float)
+
+    def inner(S, phi, k):
+        return linv_star(S + (sigma_a_star - sa) * phi), 1
+    return inner
+
+
+def cp_inner(linv_star, sigma_a, sigma_a_star, sweep, sigma_s, nu_sigma_f):
+    """Constrained preconditioning, Eq. A7-A8: the prediction u of Eq. A7,
+    then one transport sweep (one application of the source-iteration
+    operator) of the emission sigma_s u + nu_sigma_f u / k, the fission
+    term taken from u with the current eigenvalue."""
+    sa = np.asarray(sigma_a, float)
+    ss = np.asarray(sigma_s, float)
+    nsf = np.asarray(nu_sigma_f, float)
+
+    def inner(S, phi, k):
+        u = linv_star(S + (sigma_a_star - sa) * phi)
+        return sweep(ss * u + nsf * u / k), 1
+    return inner
+
+
+def solve_eigen_no(inst, quad, nu_sigma_f, linv_star, sigma_a_star, variant,
+                   tol_k=1e-10, tol_phi=1e-10, phi0=None, k0=1.0,
+                   max_outer=10000) -> EigenResult:
+    """The neural-operator outer loop of one 2-D instance (variant "sp" or
+    "cp"); its result is the starting pair of the model-based refinement
+    (Eq. A6)."""
+    from . import sweep2d
+    nsf = np.asarray(nu_sigma_f, float).reshape(inst.ny, inst.nx)
+    sa = np.asarray(inst.sigma_t, float) - np.asarray(inst.sigma_s, float)
+    if variant == "sp":
+        inner = sp_inner(linv_star, sa, sigma_a_star)
+    elif variant == "cp":
+        def sweep(Q):
+            return sweep2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta,
+                           quad.w, inst.sigma_t, Q, bc=inst.bc)
+        inner = cp_inner(linv_star, sa, sigma_a_star, sweep, inst.sigma_s, nsf)
+    else:
+        raise ValueError(variant)
+    return power_iteration(inner, nsf, cell_volume(inst), phi0=phi0, k0=k0,
+                           tol_k=tol_k, tol_phi=tol_phi, max_outer=max_outer)

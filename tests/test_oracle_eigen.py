@@ -10,7 +10,11 @@ Each pin stands apart from the oracle's power iteration:
   * the eigenvalue printed for eigen Case 1 (Table 7), under the reading
     nu = 3 and vacuum slab faces;
   * linearity: scaling nu*sigma_f by a scales k by a; the limit does not
-    depend on the starting flux or eigenvalue.
+    depend on the starting flux or eigenvalue;
+  * the neural-operator variants SP and CP (Eq. A5, A7-A8): driven by the
+    exact p* operator they reach the model-based eigenpair when only
+    sigma_s differs from p* (then the recast is exact), and with a
+    pointwise linear network SP's eigenvalue has a closed form.
 """
 import numpy as np
 import pytest
@@ -143,3 +147,56 @@ def test_linearity_and_start_independence():
     # F(phi) = 1 after every update
     for r in (a, c):
         assert abs(E.fission_production(nsf, r.phi.reshape(-1), 6.0 / n) - 1.0) < 1e-12
+
+
+# ------------------------------------------- neural-operator variants (A2) --
+
+def _exact_linv_star(inst, quad, st_star, ss_star):
+    """The exact inverse transport operator at uniform p* on the instance's
+    grid (direct solve of the DD system)."""
+    st = np.full((inst.ny, inst.nx), st_star)
+    ss = np.full((inst.ny, inst.nx), ss_star)
+
+    def linv(S):
+        return solve_2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
+                        st, ss, S, inst.bc)
+    return linv
+
+
+@pytest.mark.parametrize("variant", ["sp", "cp"])
+def test_no_variants_exact_when_only_scattering_changes(variant):
+    """With sigma_t = sigma_t* the recast source (sigma_a* - sigma_a) phi is
+    the exact change of the scattering term, so SP and CP driven by the
+    exact operator at p* must converge to the model-based eigenpair."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    nx, ny = 8, 7
+    st_star, ss_star = 1.0, 0.8
+    st = np.full((ny, nx), st_star)
+    ss = rng.uniform(0.5, 0.9, (ny, nx))
+    nsf = rng.uniform(0.2, 0.5, (ny, nx))
+    inst = I.Instance(nx=nx, ny=ny, lx=4.0, ly=3.5, sigma_t=st, sigma_s=ss,
+                      source=np.zeros((ny, nx)))
+    quad = I.level_symmetric_2d(4)
+    ref = E.solve_eigen(inst, quad, nsf, tol_k=1e-12, tol_phi=1e-11)
+    r = E.solve_eigen_no(inst, quad, nsf, _exact_linv_star(inst, quad, st_star, ss_star),
+                         st_star - ss_star, variant, tol_k=1e-12, tol_phi=1e-11)
+    assert r.converged
+    assert abs(r.k - ref.k) < 1e-9 * ref.k, (r.k, ref.k)
+    assert np.max(np.abs(r.phi - ref.phi)) < 1e-8 * np.max(ref.phi)
+
+
+def test_sp_linear_network_closed_form():
+    """A pointwise network NO(S) = g S / sigma_a* on a uniform medium keeps
+    every flux shape, and SP's fixed point solves
+    g (nu_sigma_f / k + sigma_a* - sigma_a) / sigma_a* = 1."""
+    from oracle import recast as RC
+    n = 6
+    g, sa_star, sa, nsf0 = 0.6, 0.2, 0.35, 0.3
+    inst = I.Instance(nx=n, ny=n, lx=3.0, ly=3.0, sigma_t=np.full((n, n), 1.0),
+                      sigma_s=np.full((n, n), 1.0 - sa), source=np.zeros((n, n)))
+    linv = RC.network_inner(lambda x: g * x, sa_star)
+    r = E.solve_eigen_no(inst, I.level_symmetric_2d(4), np.full((n, n), nsf0), linv, sa_star,
+                         "sp", tol_k=1e-13, tol_phi=1e-12)
+    assert r.converged
+    exact = nsf0 / (sa_star / g - sa_star + sa)
+    assert abs(r.k - exact) < 1e-11 * exact, (r.k, exact)
