@@ -176,6 +176,31 @@ tr_status no_recast_guess(tr_context *ctx, const no_model *m, int32_t n_inst,
                           double sigma_s_star, double tol, int32_t max_iter,
                           float *const *phi_guess, tr_stats *stats);
 
+/* Neural-operator variants of the eigenvalue loop (Appendix A2).          */
+typedef enum { NO_EIGEN_SP = 0, NO_EIGEN_CP = 1 } no_eigen_variant;
+
+/*
+ * Neural-operator outer loop of the one-group k-eigenvalue problem
+ * (section 5.2; Appendix A2 (i) simple preconditioning, Eq. A5, and (ii)
+ * constrained preconditioning, Eq. A7-A8).  Per outer update:
+ *   u = NO[ S + (sigma_a* - sigma_a) phi ],  S = nu_sigma_f*phi/k,
+ * with NO as in no_recast_guess (one network application); NO_EIGEN_CP
+ * then applies one transport sweep of sigma_s*u + nu_sigma_f*u/k; then the
+ * outer update of tr_eigen (k, normalisation F(phi) = 1, the same stopping
+ * test on tol_k and tol_phi).  The result is the starting pair for the
+ * model-based refinement of Eq. A6: call tr_eigen with phi_init = phi_out
+ * and k_init = stats[i].k.  Problems: 2-D on the network's 64 x 64 grid,
+ * vacuum faces; the source fields are not read.  Arguments as in tr_eigen;
+ * q is used by NO_EIGEN_CP's sweep (and checked for both).  stats[i].inner
+ * counts transport sweeps (0 for SP); balance_rel is NaN.  Batch limit as
+ * in no_recast_guess.                                                      */
+tr_status no_eigen(tr_context *ctx, const no_model *m, int32_t n_inst,
+                   const tr_problem *p, const float *const *nu_sigma_f,
+                   const tr_quadrature *q, double sigma_t_star, double sigma_s_star,
+                   int32_t variant, const float *const *phi_init,
+                   float *const *phi_out, const double *k_init, double tol_k,
+                   double tol_phi, int32_t max_outer, tr_eigen_stats *stats);
+
 /* ---------------------------------------------------------------------
  * Fourier neural operator (section 4.2, Appendix A1; 2-D form): lift of
  * (field, x, y) to `width` channels, `layers` Fourier layers (retained

@@ -24,9 +24,12 @@ TR_ERR_INVALID_ARG = -1
 TR_ERR_HIP = -2
 TR_ERR_OOM = -3
 TR_ERR_NONFINITE = -4
+NO_EIGEN_SP = 0
+NO_EIGEN_CP = 1
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
-           "tr_sweep", "tr_solve", "tr_eigen", "no_recast_guess", "no_model_create",
+           "tr_sweep", "tr_solve", "tr_eigen", "no_recast_guess", "no_eigen",
+           "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
            "no_train_step",
@@ -91,6 +94,8 @@ def load(path: str = LIB_PATH):
                              d, i32, P(TrStats)]
     lib.no_recast_guess.argtypes = [vp, vp, i32, P(TrProblem), d, d, d, i32, P(vp),
                                     P(TrStats)]
+    lib.no_eigen.argtypes = [vp, vp, i32, P(TrProblem), P(vp), P(TrQuadrature), d, d, i32,
+                             P(vp), P(vp), P(d), d, d, i32, P(TrEigenStats)]
     lib.tr_eigen.argtypes = [vp, i32, P(TrProblem), P(vp), P(TrQuadrature), P(vp), P(vp),
                              P(d), d, d, d, i32, i32, P(TrEigenStats)]
     lib.no_model_create.argtypes = [vp, P(vp), i32, i32, i32, i32, vp]
@@ -288,16 +293,8 @@ def tr_solve(ctx: Context, problems: Sequence[Problem], quad: Quad,
                      seconds=s.seconds) for s in stats]
 
 
-def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
-             quad: Quad, phi_init: Optional[Sequence], phi_out: Sequence,
-             k_init: Optional[Sequence[float]] = None, tol_k: float = 1e-6,
-             tol_phi: float = 1e-5, tol_inner: float = 1e-6, max_outer: int = 1000,
-             max_inner: int = 10000, raise_on_error: bool = True):
-    """k-eigenvalue power iteration; the problems' source fields are not
-    read.  Returns (status, list of per-instance stats dicts)."""
+def _check_eigen_fields(problems, nu_sigma_f, phi_init, phi_out):
     n = len(problems)
-    arr = make_problems(problems)
-    stats = (TrEigenStats * n)()
     if len(nu_sigma_f) != n or len(phi_out) != n or (phi_init is not None
                                                      and len(phi_init) != n):
         raise ValueError("one nu_sigma_f, phi_out (and phi_init) per problem")
@@ -308,6 +305,19 @@ def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
                     or t.numel() != p.nx * p.ny):
                 raise ValueError(f"problem {i}: nu_sigma_f, phi_init and phi_out must be "
                                  f"float32 GPU tensors of {p.nx * p.ny} cells")
+
+
+def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
+             quad: Quad, phi_init: Optional[Sequence], phi_out: Sequence,
+             k_init: Optional[Sequence[float]] = None, tol_k: float = 1e-6,
+             tol_phi: float = 1e-5, tol_inner: float = 1e-6, max_outer: int = 1000,
+             max_inner: int = 10000, raise_on_error: bool = True):
+    """k-eigenvalue power iteration; the problems' source fields are not
+    read.  Returns (status, list of per-instance stats dicts)."""
+    n = len(problems)
+    arr = make_problems(problems)
+    stats = (TrEigenStats * n)()
+    _check_eigen_fields(problems, nu_sigma_f, phi_init, phi_out)
     init = None if phi_init is None else _ptr_array(phi_init)
     kin = None if k_init is None else (ctypes.c_double * n)(*[float(k) for k in k_init])
     rc = ctx.lib.tr_eigen(ctx.handle, n, arr, _ptr_array(nu_sigma_f),
@@ -316,9 +326,53 @@ def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
                           int(max_inner), stats)
     if raise_on_error:
         ctx.check(rc)
-    return rc, [dict(status=s.status, outer=s.outer, inner=s.inner, k=s.k, dk=s.dk,
-                     dphi=s.dphi, balance_rel=s.balance_rel, seconds=s.seconds)
-                for s in stats]
+    return rc, _eigen_stats(stats)
+
+
+def _eigen_stats(stats):
+    return [dict(status=s.status, outer=s.outer, inner=s.inner, k=s.k, dk=s.dk,
+                 dphi=s.dphi, balance_rel=s.balance_rel, seconds=s.seconds) for s in stats]
+
+
+def no_eigen(ctx: Context, model: "Model", problems: Sequence[Problem], nu_sigma_f: Sequence,
+             quad: Quad, sigma_t_star: float, sigma_s_star: float, variant: int,
+             phi_init: Optional[Sequence], phi_out: Sequence,
+             k_init: Optional[Sequence[float]] = None, tol_k: float = 1e-4,
+             tol_phi: float = 1e-4, max_outer: int = 500, raise_on_error: bool = True):
+    """Neural-operator outer loop of the eigenvalue problem (NO_EIGEN_SP or
+    NO_EIGEN_CP).  Returns (status, list of per-instance stats dicts)."""
+    n = len(problems)
+    arr = make_problems(problems)
+    _check_eigen_fields(problems, nu_sigma_f, phi_init, phi_out)
+    stats = (TrEigenStats * n)()
+    init = None if phi_init is None else _ptr_array(phi_init)
+    kin = None if k_init is None else (ctypes.c_double * n)(*[float(k) for k in k_init])
+    rc = ctx.lib.no_eigen(ctx.handle, model.handle, n, arr, _ptr_array(nu_sigma_f),
+                          ctypes.byref(quad.struct), float(sigma_t_star), float(sigma_s_star),
+                          int(variant), init, _ptr_array(phi_out), kin, float(tol_k),
+                          float(tol_phi), int(max_outer), stats)
+    if raise_on_error:
+        ctx.check(rc)
+    return rc, _eigen_stats(stats)
+
+
+def eigen_preconditioned(ctx: Context, model: "Model", problems: Sequence[Problem],
+                         nu_sigma_f: Sequence, quad: Quad, sigma_t_star: float,
+                         sigma_s_star: float, variant: int, phi_out: Sequence,
+                         tol_k: float = 1e-4, tol_phi: float = 1e-4, tol_inner: float = 1e-4,
+                         max_outer: int = 500, max_inner: int = 10000,
+                         no_tol_k: float = 1e-3, no_tol_phi: float = 1e-3,
+                         no_max_outer: int = 100):
+    """SP or CP (Appendix A2): the network loop (its own tolerances: it only
+    preconditions, and a BF16 network settles near 1e-3), then the
+    model-based eigenvalue solve started from its pair (Eq. A6).  phi_out
+    receives the refined eigenfunction.  Returns (status of the refinement,
+    network-loop stats, refined stats)."""
+    _, st1 = no_eigen(ctx, model, problems, nu_sigma_f, quad, sigma_t_star, sigma_s_star,
+                      variant, None, phi_out, None, no_tol_k, no_tol_phi, no_max_outer)
+    rc2, st2 = tr_eigen(ctx, problems, nu_sigma_f, quad, phi_out, phi_out,
+                        [s["k"] for s in st1], tol_k, tol_phi, tol_inner, max_outer, max_inner)
+    return rc2, st1, st2
 
 
 def tr_check_args(problems_struct, n: int, quad: Quad, tol: float,

@@ -233,6 +233,24 @@ eig_apply_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
     }
 }
 
+// Emission of one source-iteration sweep from the current iterate u with
+// the fission term taken from u: Q = sigma_s u + nu_sigma_f u / k.
+__global__ void __launch_bounds__(kThreads)
+eig_emission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                    const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
+                    const int* __restrict__ edone) {
+    const int4 bi = blocks[blockIdx.x];
+    if (bi.x < 0 || edone[bi.x]) return;
+    const InstDesc& I = insts[bi.x];
+    const EigDesc& E = ed[bi.x];
+    const double k = es[bi.x].k;
+    const int c1 = min(bi.y + kCombineChunk, I.cells);
+    for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
+        const double u = I.phi[c];
+        I.Q[c] = (float)((double)I.ss[c] * u + (double)E.nsf[c] * u / k);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads)
 eig_final_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                  const EigState* __restrict__ es) {
@@ -271,6 +289,13 @@ void launch_eig_update(int n_inst, int nblocks, const InstDesc* insts, const int
     hipLaunchKernelGGL(eig_conv_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst,
                        tol_k, tol_phi, 1, last);
     hipLaunchKernelGGL(eig_apply_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
+                       ed, es, edone);
+}
+
+void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
+                         const EigDesc* ed, const EigState* es, const int* edone,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(eig_emission_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
                        ed, es, edone);
 }
 

@@ -39,6 +39,11 @@ void launch_eig_start(int n_inst, int nblocks, const InstDesc* insts, const int4
 void launch_eig_update(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
                        const EigDesc* ed, EigState* es, int* edone, double* part,
                        IterState st, double tol_k, double tol_phi, int last, hipStream_t s);
+// Emission sigma_s u + nu_sigma_f u / k of the running instances into the
+// instances' emission buffers (one sweep of the constrained variant).
+void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
+                         const EigDesc* ed, const EigState* es, const int* edone,
+                         hipStream_t s);
 // After the last outer: the inner solution of every valid instance scaled by
 // its normalisation (F(phi) = 1).
 void launch_eig_final(int nblocks, const InstDesc* insts, const int4* blocks,

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/mdpnop.h"
+#include "eigen_kernels.h"
 #include "fno_kernels.h"
 #include "host_internal.h"
 
@@ -706,4 +707,235 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
         }
     }
     return (tr_status)worst;
+}
+
+// ----------------------------------------------------------- no_eigen ----
+// The neural-operator outer loop of the k-eigenvalue problem (Appendix A2,
+// simple preconditioning Eq. A5 and constrained preconditioning Eq. A7-A8)
+// on the network's own grid.  Per outer update and instance:
+//   u = NO[ S + (sigma_a* - sigma_a) phi ],  S = nu_sigma_f phi / k   (Eq. A5 / A7)
+//   CP only: u <- Sweep(sigma_s u + nu_sigma_f u / k)                    (Eq. A8)
+// then the outer update P of eigen.hip (k, normalisation, convergence).
+namespace mdp {
+void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks, const int* done,
+                    double2* red, int mode, int norm_kind, hipStream_t s);
+}
+
+extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst,
+                              const tr_problem* p, const float* const* nu_sigma_f,
+                              const tr_quadrature* q, double sigma_t_star, double sigma_s_star,
+                              int32_t variant, const float* const* phi_init,
+                              float* const* phi_out, const double* k_init, double tol_k,
+                              double tol_phi, int32_t max_outer, tr_eigen_stats* stats) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!m || !p || !nu_sigma_f || !phi_out || n_inst <= 0) {
+        c->fail("no_eigen: need a model, n_inst > 0 problems, nu_sigma_f and phi_out");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (n_inst > kMaxBatch) {
+        c->fail("no_eigen: at most %d problems per call", kMaxBatch);
+        return TR_ERR_INVALID_ARG;
+    }
+    if (variant != NO_EIGEN_SP && variant != NO_EIGEN_CP) {
+        c->fail("no_eigen: variant must be NO_EIGEN_SP or NO_EIGEN_CP");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!(tol_k > 0.0) || !(tol_phi > 0.0) || !std::isfinite(tol_k) ||
+        !std::isfinite(tol_phi) || max_outer <= 0) {
+        c->fail("no_eigen: need finite tol_k, tol_phi > 0 and max_outer > 0");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    const double sa_star = sigma_t_star - sigma_s_star;
+    if (!(sa_star > 0.0) || !std::isfinite(sa_star) || !(sigma_s_star >= 0.0)) {
+        c->fail("need sigma_t* > sigma_s* >= 0 (finite)");
+        return TR_ERR_INVALID_ARG;
+    }
+    const int B = n_inst;
+    std::vector<tr_problem> pp(p, p + B);
+    for (int i = 0; i < B; ++i) {
+        const tr_problem& P = p[i];
+        if (P.dim != 2 || P.nx != kGrid || P.ny != kGrid || !nu_sigma_f[i] || !phi_out[i]) {
+            c->fail("problem %d: no_eigen needs a 2-D %d x %d grid (the network's), "
+                    "nu_sigma_f and phi_out", i, kGrid, kGrid);
+            return TR_ERR_INVALID_ARG;
+        }
+        for (int f = 0; f < 4; ++f)
+            if (P.bc[f] != TR_BC_VACUUM) {
+                c->fail("problem %d: no_eigen needs vacuum faces", i);
+                return TR_ERR_INVALID_ARG;
+            }
+        if (k_init && (!(k_init[i] > 0.0) || !std::isfinite(k_init[i]))) {
+            c->fail("problem %d: k_init must be positive and finite", i);
+            return TR_ERR_INVALID_ARG;
+        }
+        pp[i].source = P.sigma_t;   // placeholder for the check
+    }
+    if (!check_problems(c, B, pp.data(), true)) return TR_ERR_INVALID_ARG;
+    Ws w;
+    if (!workspace(c, m, B, false, &w)) return ws_status(c);
+    FnoWork* fw = c->fno;
+    // fields (B x P each): nu_sigma_f, sigma_a, phi, in, out, S, Q, prev;
+    // then scale (B), norms (2B), active (B), resampling descriptors (B),
+    // eigen descriptors (B), eigen state (B), done flags (B)
+    const size_t fb = align_up(4 * (size_t)B * kP);
+    size_t off = 8 * fb;
+    const size_t oScale = off;
+    off += align_up(4 * (size_t)B);
+    const size_t oNorm = off;
+    off += align_up(16 * (size_t)B);
+    const size_t oAct = off;
+    off += align_up(4 * (size_t)B);
+    const size_t oRd = off;
+    off += align_up(sizeof(ResampleDesc) * (size_t)B);
+    const size_t oEd = off;
+    off += align_up(sizeof(EigDesc) * (size_t)B);
+    const size_t oEs = off;
+    off += align_up(sizeof(EigState) * (size_t)B);
+    const size_t oDone = off;
+    off += align_up(4 * (size_t)B);
+    const size_t hRd = 0, hAct = align_up(sizeof(ResampleDesc) * (size_t)B),
+                 hDone = hAct + align_up(4 * (size_t)B), hEnd = hDone + align_up(4 * (size_t)B);
+    if (!fw->rc.reserve(c, off) || !fw->host.reserve(c, hEnd)) return ws_status(c);
+    char* base = (char*)fw->rc.base;
+    float* nsfb = (float*)base;
+    float* sa = (float*)(base + fb);
+    float* phi = (float*)(base + 2 * fb);
+    float* in = (float*)(base + 3 * fb);
+    float* out = (float*)(base + 4 * fb);
+    float* Sf = (float*)(base + 5 * fb);
+    float* Q = (float*)(base + 6 * fb);
+    float* prev = (float*)(base + 7 * fb);
+    float* scale = (float*)(base + oScale);
+    double* norms = (double*)(base + oNorm);
+    int* active = (int*)(base + oAct);
+    ResampleDesc* ddesc = (ResampleDesc*)(base + oRd);
+    EigDesc* d_ed = (EigDesc*)(base + oEd);
+    EigState* d_es = (EigState*)(base + oEs);
+    int* d_done = (int*)(base + oDone);
+    char* hb = (char*)fw->host.ptr;
+    ResampleDesc* hdesc = (ResampleDesc*)(hb + hRd);
+    int* hact = (int*)(hb + hAct);
+    int* hdone = (int*)(hb + hDone);
+    hipStream_t s = c->stream;
+    if (!c->hip_ok(hipStreamSynchronize(s), "sync")) return TR_ERR_HIP;
+    // nu_sigma_f and sigma_a gathered into the batch layout (f = 1: copies)
+    for (int i = 0; i < B; ++i)
+        hdesc[i] = ResampleDesc{p[i].sigma_t, p[i].sigma_s, nu_sigma_f[i], phi_out[i], kGrid, 1};
+    if (!c->hip_ok(hipMemcpyAsync(ddesc, hdesc, sizeof(ResampleDesc) * (size_t)B,
+                                  hipMemcpyHostToDevice, s), "copy"))
+        return TR_ERR_HIP;
+    launch_recast_average(ddesc, B, kGrid, nsfb, sa, s);
+    // the sweep's view of the batch: iterate phi, emission Q, source S
+    std::vector<float*> phis(B), Qs(B);
+    for (int i = 0; i < B; ++i) {
+        phis[i] = phi + (size_t)i * kP;
+        Qs[i] = Q + (size_t)i * kP;
+        pp[i].source = Sf + (size_t)i * kP;
+    }
+    Setup su;
+    if (!c->setup(B, pp.data(), q, nullptr, phis.data(), Qs.data(), &su))
+        return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
+    const size_t htab = oDone + align_up(4 * (size_t)B) - oEd;
+    if (!c->hip_ok(hipStreamSynchronize(s), "sync")) return TR_ERR_HIP;
+    if (!c->pinned.reserve(c, htab)) return TR_ERR_OOM;
+    char* h = (char*)c->pinned.ptr;
+    std::memset(h, 0, htab);
+    EigDesc* hd = (EigDesc*)h;
+    EigState* hs = (EigState*)(h + (oEs - oEd));
+    for (int i = 0; i < B; ++i) {
+        hd[i].nsf = nsfb + (size_t)i * kP;
+        hd[i].phi0 = phi_init ? phi_init[i] : nullptr;
+        hd[i].S = Sf + (size_t)i * kP;
+        hd[i].prev = prev + (size_t)i * kP;
+        hd[i].vol = su.inst[i].dx * su.inst[i].dy;
+        hs[i].k = k_init ? k_init[i] : 1.0;
+        hs[i].status = 1;
+    }
+    if (!c->hip_ok(hipMemcpyAsync(d_ed, h, htab, hipMemcpyHostToDevice, s), "copy") ||
+        !c->hip_ok(hipMemsetAsync(su.st.iter, 0, sizeof(int) * B, s), "memset") ||
+        !c->hip_ok(hipMemsetAsync(su.st.status, 0, sizeof(int) * B, s), "memset"))
+        return TR_ERR_HIP;
+    const int nblocks = (int)su.blocks.size();
+    launch_eig_start(B, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart, s);
+    if (!c->hip_ok(hipMemcpyAsync(h, d_es, sizeof(EigState) * B, hipMemcpyDeviceToHost, s),
+                   "copy"))
+        return TR_ERR_HIP;
+    tr_status st0 = finish(c, "eigen start");
+    if (st0 != TR_OK) return st0;
+    for (int i = 0; i < B; ++i) {
+        if (((EigState*)h)[i].status < 0) {
+            c->fail("problem %d: nu_sigma_f must be finite and >= 0 and the starting "
+                    "flux finite with F(phi) > 0", i);
+            return TR_ERR_INVALID_ARG;
+        }
+        hact[i] = 1;
+    }
+    if (!c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
+        return TR_ERR_HIP;
+    Runner r{c, m};
+    for (int outer = 1; outer <= max_outer; ++outer) {
+        launch_recast_input(Sf, sa, phi, (float)sa_star, in, scale, active, B, kP, s);
+        r.forward(in, out, w);
+        if (!r.ok) return TR_ERR_INVALID_ARG;
+        launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, B, kP, s);
+        if (variant == NO_EIGEN_CP) {
+            launch_eig_emission(nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, s);
+            if (!c->launch_sweep(su, B, d_done, nullptr, 0)) return TR_ERR_HIP;
+            launch_combine(nblocks, su.d_inst, su.d_blocks, d_done, su.d_red, 1, 0, s);
+        }
+        launch_eig_update(B, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart,
+                          su.st, tol_k, tol_phi, outer == max_outer ? 1 : 0, s);
+        if (!c->hip_ok(hipMemcpyAsync(hdone, d_done, 4 * (size_t)B, hipMemcpyDeviceToHost, s),
+                       "copy"))
+            return TR_ERR_HIP;
+        const tr_status st = finish(c, "no_eigen outer");
+        if (st != TR_OK) return st;
+        bool all = true, changed = false;
+        for (int i = 0; i < B; ++i) {
+            all &= hdone[i] != 0;
+            if (hdone[i] && hact[i]) {
+                hact[i] = 0;
+                changed = true;
+            }
+        }
+        if (all) break;
+        if (changed && !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B,
+                                                 hipMemcpyHostToDevice, s), "copy"))
+            return TR_ERR_HIP;
+    }
+    launch_eig_final(nblocks, su.d_inst, su.d_blocks, d_es, s);
+    launch_recast_output(ddesc, B, kGrid, kP, phi, s);
+    EigState* rs = (EigState*)h;
+    if (!c->hip_ok(hipMemcpyAsync(rs, d_es, sizeof(EigState) * B, hipMemcpyDeviceToHost, s),
+                   "copy"))
+        return TR_ERR_HIP;
+    const tr_status st = finish(c, "no_eigen output");
+    if (st != TR_OK) return st;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    tr_status worst = TR_OK;
+    for (int i = 0; i < B; ++i) {
+        const EigState& E = rs[i];
+        const tr_status si = E.status == 0 ? TR_OK
+                             : E.status == -4 ? TR_ERR_NONFINITE : TR_NOT_CONVERGED;
+        if (si == TR_ERR_NONFINITE) c->fail("problem %d: non-finite iterate", i);
+        if (stats) {
+            tr_eigen_stats& o = stats[i];
+            o.status = si;
+            o.outer = E.outer;
+            o.inner = variant == NO_EIGEN_CP ? E.outer : 0;
+            o.k = E.k;
+            o.dk = E.dk;
+            o.dphi = E.dphi;
+            o.balance_rel = NAN;
+            o.seconds = secs;
+        }
+        if (si < 0 && (worst >= 0 || si < worst)) worst = si;
+        else if (worst >= 0 && si > worst) worst = si;
+    }
+    return worst;
 }

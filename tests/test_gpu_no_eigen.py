@@ -1,0 +1,158 @@
+"""Parity of the neural-operator eigenvalue loop (no_eigen: simple and
+constrained preconditioning, Appendix A2 Eq. A5-A8) against the oracle.
+
+Tolerances:
+  * a fixed number of outer updates with the network in FP32 mode against
+    the oracle loop driving the FP64 network: the per-update error is the
+    FP32 forward's (about 1e-6 relative, as in the recast parity test) and
+    the outer update is a contraction around the fixed point, so after four
+    updates the bar is 1e-5 on k and 1e-4 relative L2 on the flux, as for
+    five recast updates;
+  * the closed-form case (pointwise linear network): k within 1e-5;
+  * after the model-based refinement (Eq. A6) the result is tr_eigen's, so
+    the bars of the tr_eigen tests apply (k within 1e-5 of the FP64 oracle).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import log, rel_l2, to_problem
+from oracle import eigen as E
+from oracle import fno as F
+from oracle import recast as RC
+from paper_2509_01416_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N = 64
+LAY = F.Layout()
+SA_STAR = I.SIGMA_T_STAR - I.SIGMA_S_STAR
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2509_01416_amd import binding as B
+    from paper_2509_01416_amd import train as T
+    assert torch.cuda.is_available()
+    ctx = B.Context()
+    w = T.load_weights()
+    yield torch, B, ctx, w
+    ctx.close()
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def _case(kind, seed=0):
+    """64 x 64 on 10 x 10 mfp, vacuum: 'flat' is the eigen Case 1 analogue
+    at the training parameters (sigma_t = 1, sigma_s = sigma_s*, uniform
+    nu_sigma_f); 'sine' has sinusoidal sigma_t, sigma_s and nu_sigma_f."""
+    x = (np.arange(N) + 0.5) * 10.0 / N
+    X, Y = np.meshgrid(x, x)
+    if kind == "flat":
+        st = np.full((N, N), I.SIGMA_T_STAR)
+        ss = np.full((N, N), I.SIGMA_S_STAR)
+        nsf = np.full((N, N), 0.3)
+    else:
+        st = 1.0 + 0.3 * np.sin(2 * np.pi * X / 10.0) * np.cos(2 * np.pi * Y / 10.0)
+        ss = st * (0.75 + 0.1 * np.sin(2 * np.pi * (X + Y) / 10.0))
+        nsf = 0.25 + 0.1 * np.cos(2 * np.pi * X / 5.0)
+    inst = I.Instance(nx=N, ny=N, lx=10.0, ly=10.0, sigma_t=st, sigma_s=ss,
+                      source=np.zeros((N, N)))
+    return inst, nsf
+
+
+def _dev(torch, a):
+    return torch.tensor(np.asarray(a, np.float32), device="cuda")
+
+
+def _net64(params):
+    p64 = np.asarray(params, np.float32).astype(np.float64)
+
+    def net(s):
+        out, _ = F.forward(p64, F.make_input(s[None]), LAY)
+        return out[0]
+    return net
+
+
+@pytest.mark.parametrize("variant", ["sp", "cp"])
+def test_no_eigen_parity_trained_network(env, variant):
+    torch, B, ctx, w = env
+    m = B.Model(ctx, w)
+    m.set_fp32(True)
+    inst, nsf = _case("sine")
+    quad = I.level_symmetric_2d(8)
+    v = B.NO_EIGEN_SP if variant == "sp" else B.NO_EIGEN_CP
+    phi = [torch.zeros((N, N), device="cuda")]
+    log(f"no_eigen {variant}: 4 updates, trained network in FP32 mode, 64x64 S8")
+    rc, st = B.no_eigen(ctx, m, [to_problem(inst, torch)], [_dev(torch, nsf)],
+                        B.Quad.from_inputs(quad), I.SIGMA_T_STAR, I.SIGMA_S_STAR, v,
+                        None, phi, None, 1e-30, 1e-30, 4)
+    torch.cuda.synchronize()
+    inst64 = I.Instance(nx=N, ny=N, lx=10.0, ly=10.0, sigma_t=_f32(inst.sigma_t),
+                        sigma_s=_f32(inst.sigma_s), source=np.zeros((N, N)))
+    ref = E.solve_eigen_no(inst64, quad, _f32(nsf), RC.network_inner(_net64(w), SA_STAR),
+                           SA_STAR, variant, tol_k=0.0, tol_phi=0.0, max_outer=4)
+    got = phi[0].cpu().numpy().astype(np.float64)
+    e = rel_l2(got, ref.phi)
+    log(f"  k gpu={st[0]['k']:.7f} oracle={ref.k:.7f} rel_l2={e:.2e} outer={st[0]['outer']}")
+    assert rc == B.TR_NOT_CONVERGED and st[0]["outer"] == 4
+    assert abs(st[0]["k"] - ref.k) < 1e-5 * abs(ref.k)
+    assert e < 1e-4
+    assert st[0]["inner"] == (4 if variant == "cp" else 0)
+    m.close()
+
+
+def test_no_eigen_sp_linear_network_closed_form(env):
+    from test_gpu_fno import _linear_params
+    torch, B, ctx, _ = env
+    g, sa, nsf0 = 0.6, 0.35, 0.3
+    m = B.Model(ctx, _linear_params(g))
+    m.set_fp32(True)
+    inst = I.Instance(nx=N, ny=N, lx=10.0, ly=10.0, sigma_t=np.full((N, N), 1.0),
+                      sigma_s=np.full((N, N), 1.0 - sa), source=np.zeros((N, N)))
+    phi = [torch.zeros((N, N), device="cuda")]
+    rc, st = B.no_eigen(ctx, m, [to_problem(inst, torch)], [_dev(torch, np.full((N, N), nsf0))],
+                        B.Quad.from_inputs(I.level_symmetric_2d(4)), I.SIGMA_T_STAR,
+                        I.SIGMA_S_STAR, B.NO_EIGEN_SP, None, phi, None, 1e-7, 1e-6, 200)
+    exact = nsf0 / (SA_STAR / g - SA_STAR + sa)
+    log(f"  linear SP: k={st[0]['k']:.7f} exact={exact:.7f} outer={st[0]['outer']}")
+    assert rc == B.TR_OK
+    assert abs(st[0]["k"] - exact) < 1e-5 * exact
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["flat", "sine"])
+def test_preconditioned_eigen_refines_to_model_based(env, kind):
+    """SP and CP with the trained network (BF16 inference), each refined by
+    the model-based solver (Eq. A6); the refined k and flux match the FP64
+    model-based oracle.  The network loop stops at 1e-3 or 100 updates."""
+    torch, B, ctx, w = env
+    m = B.Model(ctx, w)
+    inst, nsf = _case(kind)
+    quad = I.level_symmetric_2d(8)
+    ref = E.solve_eigen(inst, quad, nsf, tol_inner=1e-12, tol_k=1e-10, tol_phi=1e-10)
+    probs = [to_problem(inst, torch)]
+    q = B.Quad.from_inputs(quad)
+    cold_phi = [torch.zeros((N, N), device="cuda")]
+    _, cold = B.tr_eigen(ctx, probs, [_dev(torch, nsf)], q, None, cold_phi, None,
+                         1e-6, 1e-5, 1e-6, 300, 5000)
+    for variant in (B.NO_EIGEN_SP, B.NO_EIGEN_CP):
+        phi = [torch.zeros((N, N), device="cuda")]
+        rc, st_no, st = B.eigen_preconditioned(ctx, m, probs, [_dev(torch, nsf)], q,
+                                               I.SIGMA_T_STAR, I.SIGMA_S_STAR, variant, phi,
+                                               tol_k=1e-6, tol_phi=1e-5, tol_inner=1e-6,
+                                               max_outer=300, no_tol_k=1e-3, no_tol_phi=1e-3,
+                                               no_max_outer=100)
+        got = phi[0].cpu().numpy().astype(np.float64)
+        e = float(np.abs(got - ref.phi).max() / np.abs(ref.phi).max())
+        log(f"  {kind} variant={variant}: NO k={st_no[0]['k']:.6f} outer={st_no[0]['outer']}; "
+            f"refined k={st[0]['k']:.7f} outer={st[0]['outer']} inner={st[0]['inner']} "
+            f"(cold: outer={cold[0]['outer']} inner={cold[0]['inner']}); "
+            f"oracle k={ref.k:.7f}; phi err={e:.1e}")
+        assert st_no[0]["status"] in (B.TR_OK, B.TR_NOT_CONVERGED)
+        assert rc == B.TR_OK and st[0]["status"] == B.TR_OK
+        assert abs(st[0]["k"] - ref.k) < 1e-5 * ref.k
+        assert e < 2e-4
+    m.close()
