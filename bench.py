@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--recast-tol", type=float, default=1e-3,
                     help="recast-loop tolerance (above the BF16 network's change floor)")
     ap.add_argument("--recast-max", type=int, default=30)
+    ap.add_argument("--no-eigen", action="store_true",
+                    help="skip the k-eigenvalue measurements")
     ap.add_argument("--weights", default=None,
                     help="trained network parameters (default: the packaged file)")
     return ap.parse_args()
@@ -120,6 +122,77 @@ def fno_flop_per_sample(n=64, w=32, m=12, layers=4, proj=128):
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def eigen_leg(ctx, model, B, I, torch, args):
+    """k-eigenvalue measurements (section 5.2, Appendix A2), tolerance 1e-4
+    on k, the flux and the inner solves (the paper's uniform criterion):
+    the model-based power iteration on 16 x 256^2 S16 (the x-y eigen Case 1
+    analogue), and on the network's 64 x 64 grid the model-based solve beside
+    SP and CP (network loop, then model-based refinement), as wall times
+    normalised to the model-based one."""
+    dev = "cuda"
+    f = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+
+    def batch(wl):
+        probs = [B.Problem(sigma_t=f(i.sigma_t), sigma_s=f(i.sigma_s), source=None,
+                           lx=i.lx, ly=i.ly) for i in wl.instances]
+        return probs, [f(a) for a in wl.extra["nu_sigma_f"]], B.Quad.from_inputs(wl.quad)
+
+    def wall(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, r
+
+    tol = 1e-4
+    wl = I.eigen_case1_2d(16, 256)
+    probs, nsf, quad = batch(wl)
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    run = lambda: B.tr_eigen(ctx, probs, nsf, quad, None, phis, None, tol, tol, tol, 500, 20000)
+    run()
+    ms, (rc, st) = wall(run, 2)
+    M = wl.quad.n_dir
+    sweeps = sum(s["inner"] * i.cells for s, i in zip(st, wl.instances)) * M
+    big = {"workload": wl.name, "ms": ms, "status": rc,
+           "k_mean": float(np.mean([s["k"] for s in st])),
+           "outer_mean": float(np.mean([s["outer"] for s in st])),
+           "inner_sweeps_mean": float(np.mean([s["inner"] for s in st])),
+           "cell_angle_updates_per_s": sweeps / (ms * 1e-3),
+           "balance_rel_max": float(max(s["balance_rel"] for s in st))}
+    log(f"[bench] eigen {wl.name}: {ms:.1f} ms k={big['k_mean']:.5f} "
+        f"outer={big['outer_mean']:.1f} inner={big['inner_sweeps_mean']:.0f}")
+
+    wl = I.eigen_sine_64(16)
+    probs, nsf, quad = batch(wl)
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    mb = lambda: B.tr_eigen(ctx, probs, nsf, quad, None, phis, None, tol, tol, tol, 500, 20000)
+    sp = lambda: B.eigen_preconditioned(ctx, model, probs, nsf, quad, I.SIGMA_T_STAR,
+                                        I.SIGMA_S_STAR, B.NO_EIGEN_SP, phis, tol, tol, tol)
+    cp = lambda: B.eigen_preconditioned(ctx, model, probs, nsf, quad, I.SIGMA_T_STAR,
+                                        I.SIGMA_S_STAR, B.NO_EIGEN_CP, phis, tol, tol, tol)
+    small = {"workload": wl.name}
+    for name, fn in (("model_based", mb), ("sp", sp), ("cp", cp)):
+        fn()
+        ms, r = wall(fn, 3)
+        if name == "model_based":
+            rc, st = r
+            small[name] = {"ms": ms, "status": rc, "k_mean": float(np.mean([s["k"] for s in st])),
+                           "inner_sweeps_mean": float(np.mean([s["inner"] for s in st]))}
+        else:
+            rc, st_no, st = r
+            small[name] = {"ms": ms, "status": rc,
+                           "k_mean": float(np.mean([s["k"] for s in st])),
+                           "network_k_mean": float(np.mean([s["k"] for s in st_no])),
+                           "network_outer_mean": float(np.mean([s["outer"] for s in st_no])),
+                           "refine_inner_sweeps_mean": float(np.mean([s["inner"] for s in st]))}
+        log(f"[bench] eigen {wl.name} {name}: {ms:.1f} ms")
+    base = small["model_based"]["ms"]
+    for name in ("sp", "cp"):
+        small[name]["normalised_time_pct"] = 100.0 * small[name]["ms"] / base
+    return {"tol": tol, "model_based_256": big, "preconditioned_64": small}
 
 
 def main():
@@ -262,6 +335,10 @@ def main():
         network["train_step_ms"] = (time.perf_counter() - t0) * 1e3 / treps
         network["train_batch"] = tb
 
+    eigen = None
+    if model is not None and not args.no_eigen:
+        eigen = eigen_leg(ctx, model, B, I, torch, args)
+
     if args.calib_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         a.fill_(1.0)
@@ -306,6 +383,7 @@ def main():
         "iterations": main_run["its"][-1],
         "roofline": roof,
         "network": network,
+        "eigen": eigen,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

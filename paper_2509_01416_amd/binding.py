@@ -362,7 +362,7 @@ def eigen_preconditioned(ctx: Context, model: "Model", problems: Sequence[Proble
                          tol_k: float = 1e-4, tol_phi: float = 1e-4, tol_inner: float = 1e-4,
                          max_outer: int = 500, max_inner: int = 10000,
                          no_tol_k: float = 1e-3, no_tol_phi: float = 1e-3,
-                         no_max_outer: int = 100):
+                         no_max_outer: int = 30):
     """SP or CP (Appendix A2): the network loop (its own tolerances: it only
     preconditions, and a BF16 network settles near 1e-3), then the
     model-based eigenvalue solve started from its pair (Eq. A6).  phi_out

@@ -370,3 +370,43 @@ def random_instance(nx: int, ny: int, seed: int, lx: float = 10.0,
     q = rng.uniform(0.0, 2.0, size=(ny, nx))
     return Instance(nx=nx, ny=ny, lx=lx, ly=ly, sigma_t=st, sigma_s=c * st,
                     source=q, bc=tuple(bc))
+
+
+def eigen_case1_2d(count: int = 16, n: int = 256, quad_order: int = 16) -> Workload:
+    """k-eigenvalue workload, the x-y analogue of eigen Case 1 (section 5.2):
+    sigma_t = 1, sigma_s = 0.5, nu_sigma_f = 0.9 (sigma_f = 0.3 with the
+    reading nu = 3) on a 10 x 10 mfp square, vacuum faces, n^2 cells,
+    level-symmetric S_N.  Instance i carries a seeded +-2 % GRF perturbation
+    of nu_sigma_f (seed 7000+i) so the batch holds distinct problems.
+    extra["nu_sigma_f"] lists the fission fields; the sources are zero."""
+    insts, nsf = [], []
+    for i in range(count):
+        insts.append(Instance(nx=n, ny=n, lx=10.0, ly=10.0, sigma_t=np.full((n, n), 1.0),
+                              sigma_s=np.full((n, n), 0.5), source=np.zeros((n, n))))
+        g = grf_2d(n, 10.0, seed=7000 + i)
+        nsf.append(0.9 * (1.0 + 0.02 * (g - g.mean()) / max(g.std(), 1e-12)))
+    return Workload(f"eigen_case1_{count}x{n}_S{quad_order}", insts,
+                    level_symmetric_2d(quad_order), tol=1e-4,
+                    description="2-D eigen Case 1 analogue", extra={"nu_sigma_f": nsf})
+
+
+def eigen_sine_64(count: int = 16) -> Workload:
+    """k-eigenvalue workload on the network's 64 x 64 grid (10 x 10 mfp,
+    vacuum, S8): sinusoidal sigma_t, sigma_s and nu_sigma_f in the manner of
+    eigen Case 2 (section 5.2), whose exact forms the paper does not print;
+    instance i shifts the phases by a seeded offset (seed 7500+i)."""
+    n = 64
+    x = (np.arange(n) + 0.5) * 10.0 / n
+    X, Y = np.meshgrid(x, x)
+    insts, nsf = [], []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(7500 + i))
+        a, b = rng.uniform(0.0, 10.0, 2)
+        st = 1.0 + 0.3 * np.sin(2 * np.pi * (X + a) / 10.0) * np.cos(2 * np.pi * (Y + b) / 10.0)
+        ss = st * (0.75 + 0.1 * np.sin(2 * np.pi * (X + Y + a) / 10.0))
+        insts.append(Instance(nx=n, ny=n, lx=10.0, ly=10.0, sigma_t=st, sigma_s=ss,
+                              source=np.zeros((n, n))))
+        nsf.append(0.25 + 0.1 * np.cos(2 * np.pi * (X + b) / 5.0))
+    return Workload(f"eigen_sine_{count}x64_S8", insts, level_symmetric_2d(8), tol=1e-4,
+                    description="2-D sinusoidal eigen problems on the network grid",
+                    extra={"nu_sigma_f": nsf})
