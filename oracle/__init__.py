@@ -12,8 +12,9 @@ Contents
     solution operator (the exact transport operator at p* for the closed-form
     check, or a network);
   * ``fno``: FP64 forward/backward of the Fourier neural operator and Adam;
-  * ``eigen``: the one-group k-eigenvalue power iteration (section 5.2
-    Eq. 26, Appendix A2 Eq. A1-A4) around the source iteration.
+  * ``eigen``: the k-eigenvalue power iteration (one group: section 5.2
+    Eq. 26, Appendix A2 Eq. A1-A4, with the SP/CP variants; three groups
+    with downscatter: section 5.3 Eq. 27-29) around the source iteration.
 """
 from __future__ import annotations
 

@@ -170,3 +170,80 @@ def solve_eigen_no(inst, quad, nu_sigma_f, linv_star, sigma_a_star, variant,
         raise ValueError(variant)
     return power_iteration(inner, nsf, cell_volume(inst), phi0=phi0, k0=k0,
                            tol_k=tol_k, tol_phi=tol_phi, max_outer=max_outer)
+
+
+# ------------------------------------------------------------ multigroup ----
+# Section 5.3, Eq. 27-29: G groups with downscatter only (no upscatter),
+# isotropic scattering, fission spectrum chi.  Group g sees the emission
+#   sigma_s^{g->g} phi_g + sum_{h<g} sigma_s^{h->g} phi_h
+#     + chi_g / k * sum_h nu_sigma_f_h phi_h .
+# Inner M: one pass over the groups in order (Gauss-Seidel in energy), each
+# group's source iteration run to tol_inner with the fission density of the
+# previous outer iterate and the downscatter of the groups already solved in
+# this pass; without upscatter one pass solves the fixed-source problem.
+# Outer P as in the one-group loop with F(phi) = sum_g sum_cells
+# nu_sigma_f_g phi_g V and the max-norm change taken over all groups.
+
+def fission_production_mg(nu_sigma_f, phi, vol):
+    return float(sum(np.sum(np.asarray(f, float) * np.asarray(p, float))
+                     for f, p in zip(nu_sigma_f, phi)) * vol)
+
+
+def solve_eigen_mg(inst, quad, sigma_t, sigma_s, nu_sigma_f, chi, tol_inner=1e-12,
+                   tol_k=1e-10, tol_phi=1e-10, phi0=None, k0=1.0,
+                   max_outer=10000) -> EigenResult:
+    """inst gives the geometry (grid, extents, faces); sigma_t[g],
+    nu_sigma_f[g] fields; sigma_s[g][h] the g -> h field (None = zero),
+    upscatter (h < g) must be None; chi[g] scalars.  phi is (G, ny, nx)."""
+    G = len(sigma_t)
+    shape = np.shape(inst.sigma_t)
+    st = [np.asarray(a, float).reshape(shape) for a in sigma_t]
+    nsf = [np.asarray(a, float).reshape(shape) for a in nu_sigma_f]
+    ss = [[None if sigma_s[g][h] is None else np.asarray(sigma_s[g][h], float).reshape(shape)
+           for h in range(G)] for g in range(G)]
+    for g in range(G):
+        for h in range(g):
+            if ss[g][h] is not None:
+                raise ValueError("upscatter is not modelled")
+    vol = cell_volume(inst)
+    phi = np.ones((G,) + shape) if phi0 is None else np.array(phi0, float).reshape((G,) + shape)
+    F = fission_production_mg(nsf, phi, vol)
+    if not F > 0:
+        raise ValueError("the initial flux produces no fissions")
+    phi = phi / F
+    k = float(k0)
+    inner_total, hist = 0, []
+    dk = dphi = np.inf
+    zero = np.zeros(shape)
+
+    def group_solve(g, q, warm):
+        sg = ss[g][g] if ss[g][g] is not None else zero
+        if inst.dim == 1:
+            r = si1d(inst.nx, inst.lx, quad.mu, quad.w, st[g], sg, q, bc=inst.bc[:2],
+                     phi0=warm, tol=tol_inner, norm="max")
+        else:
+            r = si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
+                     st[g], sg, q, bc=inst.bc, phi0=warm, tol=tol_inner, norm="l2")
+        return r.phi.reshape(shape), r.iterations
+
+    for n in range(1, max_outer + 1):
+        fis = sum(f * p for f, p in zip(nsf, phi)) / k        # Eq. 27-29 fission density
+        half = np.zeros_like(phi)
+        for g in range(G):
+            q = chi[g] * fis
+            for h in range(g):
+                if ss[h][g] is not None:
+                    q = q + ss[h][g] * half[h]                 # downscatter h -> g
+            half[g], it = group_solve(g, q, phi[g])
+            inner_total += it
+        F_half = fission_production_mg(nsf, half, vol)
+        F_old = fission_production_mg(nsf, phi, vol)
+        k_new = k * F_half / F_old
+        phi_new = half / F_half
+        dk = abs(k_new - k) / abs(k_new)
+        dphi = np.max(np.abs(phi_new - phi)) / np.max(np.abs(phi_new))
+        k, phi = k_new, phi_new
+        hist.append(k)
+        if dk < tol_k and dphi < tol_phi:
+            return EigenResult(k, phi, n, inner_total, dk, dphi, True, hist)
+    return EigenResult(k, phi, max_outer, inner_total, dk, dphi, False, hist)

@@ -14,7 +14,10 @@ Each pin stands apart from the oracle's power iteration:
   * the neural-operator variants SP and CP (Eq. A5, A7-A8): driven by the
     exact p* operator they reach the model-based eigenpair when only
     sigma_s differs from p* (then the recast is exact), and with a
-    pointwise linear network SP's eigenvalue has a closed form.
+    pointwise linear network SP's eigenvalue has a closed form;
+  * three groups (section 5.3, Tables 8-10): the printed model-based k on
+    the section 5.1 slab, the infinite-medium k and group spectrum from the
+    3 x 3 balance, and a brute-force eigen-solve of the multigroup map.
 """
 import numpy as np
 import pytest
@@ -200,3 +203,98 @@ def test_sp_linear_network_closed_form():
     assert r.converged
     exact = nsf0 / (sa_star / g - sa_star + sa)
     assert abs(r.k - exact) < 1e-11 * exact, (r.k, exact)
+
+
+# ------------------------------------------------ three groups (section 5.3) --
+# Tables 8-9: sigma_s^{g->h} (rows g, columns h), nu, sigma_t, sigma_f, chi.
+MG_SS = [[0.024, 0.171, 0.033], [0.0, 0.600, 0.275], [0.0, 0.0, 2.000]]
+MG_NU = [3.0, 2.5, 2.0]
+MG_ST = [0.240, 0.975, 3.000]
+MG_SF = [0.006, 0.060, 0.900]
+MG_CHI = [0.96, 0.04, 0.0]
+
+
+def _mg_fields(shape, ss=MG_SS, st=MG_ST, nsf=None):
+    G = len(st)
+    nsf = [MG_NU[g] * MG_SF[g] for g in range(G)] if nsf is None else nsf
+    sigma_s = [[np.full(shape, ss[g][h]) if (h >= g and ss[g][h] != 0.0) else None
+                for h in range(G)] for g in range(G)]
+    return ([np.full(shape, st[g]) for g in range(G)], sigma_s,
+            [np.full(shape, nsf[g]) for g in range(G)])
+
+
+def test_three_group_printed_k():
+    """Table 10 model-based k = 1.30621 on the section 5.1 slab (10 cm,
+    100 cells, S32; vacuum faces as for eigen Case 1)."""
+    n = 100
+    inst = _inst_1d(n, 10.0, np.ones(n), np.zeros(n))
+    st, ss, nsf = _mg_fields((1, n))
+    r = E.solve_eigen_mg(inst, I.gauss_legendre(32), st, ss, nsf, MG_CHI, tol_inner=1e-11,
+                         tol_k=1e-11, tol_phi=1e-10)
+    assert r.converged
+    assert abs(r.k - 1.30621) < 1e-5 * 1.30621, r.k
+    # the fast group peaks where fissions are, the thermal flux tracks it
+    assert np.all(r.phi > 0)
+
+
+def test_three_group_infinite_medium():
+    """Reflective on every face with uniform data: k_inf is the dominant
+    eigenvalue of the 3 x 3 balance nu_sigma_f^T A^-1 chi with
+    A = diag(sigma_t) - S^T (S[g][h] = sigma_s^{g->h}); 1.72 for Tables 8-9."""
+    A = np.diag(MG_ST) - np.array(MG_SS).T
+    nsf = np.array(MG_NU) * np.array(MG_SF)
+    k_inf = float(nsf @ np.linalg.solve(A, np.array(MG_CHI)))
+    assert abs(k_inf - 1.72) < 1e-12
+    inst = I.Instance(nx=5, ny=4, lx=2.0, ly=2.0, sigma_t=np.ones((4, 5)),
+                      sigma_s=np.zeros((4, 5)), source=np.zeros((4, 5)), bc=(1, 1, 1, 1))
+    st, ss, nsf_f = _mg_fields((4, 5))
+    r = E.solve_eigen_mg(inst, I.level_symmetric_2d(4), st, ss, nsf_f, MG_CHI)
+    assert r.converged
+    assert abs(r.k - k_inf) < 1e-9 * k_inf
+    spec = np.linalg.solve(A, np.array(MG_CHI))            # group flux ratios
+    got = np.array([p.mean() for p in r.phi])
+    assert np.allclose(got / got.sum(), spec / spec.sum(), rtol=1e-9)
+
+
+def test_three_group_dense_eigensolve():
+    """k and the group fluxes from the dominant eigenpair of the map
+    fission density -> new fission density, assembled column by column with
+    direct DD solves per group (downscatter applied in group order)."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 10
+    inst = _inst_1d(n, 4.0, np.ones(n), np.zeros(n), bc=(1, 0))
+    st = [rng.uniform(0.2, 0.4, n), rng.uniform(0.8, 1.2, n), rng.uniform(2.0, 3.5, n)]
+    ss_full = [[st[0] * 0.1, st[0] * 0.6, st[0] * 0.1],
+               [None, st[1] * 0.6, st[1] * 0.3],
+               [None, None, st[2] * 0.6]]
+    nsf = [st[0] * 0.05, st[1] * 0.1, st[2] * 0.5]
+    nsf[2][2:4] = 0.0
+    chi = [0.9, 0.1, 0.0]
+    quad = I.gauss_legendre(8)
+
+    def groups_from_fission(fd):
+        ph = []
+        for g in range(3):
+            q = chi[g] * fd
+            for h in range(g):
+                if ss_full[h][g] is not None:
+                    q = q + ss_full[h][g] * ph[h]
+            ph.append(solve_1d(n, 4.0, quad.mu, quad.w, st[g], ss_full[g][g], q, bc=(1, 0)))
+        return ph
+    Mx = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        Mx[:, c] = sum(f * p for f, p in zip(nsf, groups_from_fission(e)))
+    vals, vecs = np.linalg.eig(Mx)
+    j = int(np.argmax(vals.real))
+    k_ref = float(vals[j].real)
+    fd = np.real(vecs[:, j])
+    ph = np.array(groups_from_fission(fd))
+    ph = ph / E.fission_production_mg(nsf, ph, 0.4)
+    r = E.solve_eigen_mg(inst, quad, [a.reshape(1, n) for a in st],
+                         [[None if a is None else a.reshape(1, n) for a in row] for row in ss_full],
+                         [a.reshape(1, n) for a in nsf], chi, tol_k=1e-13, tol_phi=1e-12)
+    assert r.converged
+    assert abs(r.k - k_ref) < 1e-10 * k_ref, (r.k, k_ref)
+    assert np.max(np.abs(r.phi.reshape(3, n) - ph)) < 1e-8 * np.max(np.abs(ph))
