@@ -176,6 +176,43 @@ tr_status no_recast_guess(tr_context *ctx, const no_model *m, int32_t n_inst,
                           double sigma_s_star, double tol, int32_t max_iter,
                           float *const *phi_guess, tr_stats *stats);
 
+/* Multigroup data of one problem (section 5.3, Eq. 27-29; Tables 8-9).
+ * DEVICE fields (cells, as tr_problem's): sigma_t[g], nu_sigma_f[g] for
+ * g < n_groups; sigma_s[g*n_groups + h] is the g -> h scattering field,
+ * NULL meaning zero; the within-group field g -> g is required; upscatter
+ * (h < g) must be NULL.  chi: HOST array of n_groups fission-spectrum
+ * fractions (>= 0, not all zero).  n_groups <= 8.                         */
+typedef struct {
+    int32_t n_groups;
+    const float *const *sigma_t;
+    const float *const *sigma_s;
+    const float *const *nu_sigma_f;
+    const double *chi;
+} tr_multigroup;
+
+/*
+ * Multigroup k-eigenvalue with downscatter (section 5.3, Eq. 27-29; the
+ * power iteration of Appendix A2).  Per outer iteration the groups are
+ * solved in order (Gauss-Seidel in energy; exact for the fixed fission
+ * source without upscatter), group g by source iteration to tol_inner on
+ *   chi_g * sum_h nu_sigma_f_h phi_h / k  (previous outer iterate)
+ *   + sum_{h<g} sigma_s^{h->g} phi_h      (this pass's solutions),
+ * warm-started from the current iterate; then k <- k F(phi_half)/F(phi) and
+ * phi <- phi_half / F(phi_half) with F(phi) = sum_g sum nu_sigma_f_g phi_g V,
+ * stopping as tr_eigen with the change norm over all groups.
+ * geom[i]: grid, extents and faces of problem i (its field pointers are
+ * not read); mg[i]: its data (the same n_groups for every problem).
+ * phi_init / phi_out: n_inst*n_groups DEVICE fields, entry i*n_groups + g
+ * (phi_init NULL = flat start).  k_init, tolerances, stats as in tr_eigen;
+ * stats[i].inner sums the sweeps of all groups; balance_rel sums the group
+ * balances (sources against removal and leakage).                         */
+tr_status tr_eigen_mg(tr_context *ctx, int32_t n_inst, const tr_problem *geom,
+                      const tr_multigroup *mg, const tr_quadrature *q,
+                      const float *const *phi_init, float *const *phi_out,
+                      const double *k_init, double tol_k, double tol_phi,
+                      double tol_inner, int32_t max_outer, int32_t max_inner,
+                      tr_eigen_stats *stats);
+
 /* Neural-operator variants of the eigenvalue loop (Appendix A2).          */
 typedef enum { NO_EIGEN_SP = 0, NO_EIGEN_CP = 1 } no_eigen_variant;
 

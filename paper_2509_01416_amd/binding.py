@@ -28,7 +28,7 @@ NO_EIGEN_SP = 0
 NO_EIGEN_CP = 1
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
-           "tr_sweep", "tr_solve", "tr_eigen", "no_recast_guess", "no_eigen",
+           "tr_sweep", "tr_solve", "tr_eigen", "tr_eigen_mg", "no_recast_guess", "no_eigen",
            "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
@@ -64,6 +64,12 @@ class TrEigenStats(ctypes.Structure):
                 ("balance_rel", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+class TrMultigroup(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("sigma_t", ctypes.c_void_p),
+                ("sigma_s", ctypes.c_void_p), ("nu_sigma_f", ctypes.c_void_p),
+                ("chi", ctypes.c_void_p)]
+
+
 class MdpError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"status {status}: {msg}")
@@ -96,6 +102,8 @@ def load(path: str = LIB_PATH):
                                     P(TrStats)]
     lib.no_eigen.argtypes = [vp, vp, i32, P(TrProblem), P(vp), P(TrQuadrature), d, d, i32,
                              P(vp), P(vp), P(d), d, d, i32, P(TrEigenStats)]
+    lib.tr_eigen_mg.argtypes = [vp, i32, P(TrProblem), P(TrMultigroup), P(TrQuadrature),
+                                P(vp), P(vp), P(d), d, d, d, i32, i32, P(TrEigenStats)]
     lib.tr_eigen.argtypes = [vp, i32, P(TrProblem), P(vp), P(TrQuadrature), P(vp), P(vp),
                              P(d), d, d, d, i32, i32, P(TrEigenStats)]
     lib.no_model_create.argtypes = [vp, P(vp), i32, i32, i32, i32, vp]
@@ -324,6 +332,62 @@ def tr_eigen(ctx: Context, problems: Sequence[Problem], nu_sigma_f: Sequence,
                           ctypes.byref(quad.struct), init, _ptr_array(phi_out), kin,
                           float(tol_k), float(tol_phi), float(tol_inner), int(max_outer),
                           int(max_inner), stats)
+    if raise_on_error:
+        ctx.check(rc)
+    return rc, _eigen_stats(stats)
+
+
+def tr_eigen_mg(ctx: Context, problems: Sequence[Problem], groups: Sequence[dict],
+                quad: Quad, phi_init: Optional[Sequence[Sequence]], phi_out: Sequence[Sequence],
+                k_init: Optional[Sequence[float]] = None, tol_k: float = 1e-6,
+                tol_phi: float = 1e-5, tol_inner: float = 1e-6, max_outer: int = 1000,
+                max_inner: int = 10000, raise_on_error: bool = True):
+    """Multigroup k-eigenvalue.  problems[i] gives the geometry (its sigma_t
+    only fixes the grid); groups[i] = dict(sigma_t=[G], sigma_s=[[G x G],
+    None = zero], nu_sigma_f=[G], chi=[G floats]); phi_out[i][g] (and
+    phi_init[i][g]) are device fields.  Returns (status, stats dicts)."""
+    n = len(problems)
+    if len(groups) != n or len(phi_out) != n:
+        raise ValueError("one group table and one phi_out list per problem")
+    arr = make_problems(problems)
+    keep = []
+    mg = (TrMultigroup * n)()
+    G = len(groups[0]["sigma_t"])
+    for i, (p, gd) in enumerate(zip(problems, groups)):
+        cells = p.nx * p.ny
+        fields = list(gd["sigma_t"]) + list(gd["nu_sigma_f"]) + list(phi_out[i]) + [
+            t for row in gd["sigma_s"] for t in row if t is not None]
+        if phi_init is not None:
+            fields += [t for t in phi_init[i] if t is not None]
+        for t in fields:
+            if (str(t.dtype) != "torch.float32" or t.device.type != "cuda"
+                    or t.numel() != cells):
+                raise ValueError(f"problem {i}: group fields must be float32 GPU tensors "
+                                 f"of {cells} cells")
+        if len(gd["sigma_t"]) != G or len(phi_out[i]) != G:
+            raise ValueError("every problem needs the same number of groups")
+        st = _ptr_array(gd["sigma_t"])
+        nsf = _ptr_array(gd["nu_sigma_f"])
+        ss = (ctypes.c_void_p * (G * G))()
+        for g in range(G):
+            for h in range(G):
+                t = gd["sigma_s"][g][h]
+                ss[g * G + h] = None if t is None else _ptr(t)
+        chi = (ctypes.c_double * G)(*[float(x) for x in gd["chi"]])
+        keep += [st, nsf, ss, chi]
+        mg[i].n_groups = G
+        mg[i].sigma_t = ctypes.cast(st, ctypes.c_void_p)
+        mg[i].sigma_s = ctypes.cast(ss, ctypes.c_void_p)
+        mg[i].nu_sigma_f = ctypes.cast(nsf, ctypes.c_void_p)
+        mg[i].chi = ctypes.cast(chi, ctypes.c_void_p)
+    out = _ptr_array([t for row in phi_out for t in row])
+    init = None if phi_init is None else _ptr_array([t for row in phi_init for t in row])
+    kin = None if k_init is None else (ctypes.c_double * n)(*[float(k) for k in k_init])
+    stats = (TrEigenStats * n)()
+    rc = ctx.lib.tr_eigen_mg(ctx.handle, n, arr, mg, ctypes.byref(quad.struct), init, out, kin,
+                             float(tol_k), float(tol_phi), float(tol_inner), int(max_outer),
+                             int(max_inner), stats)
+    del keep
     if raise_on_error:
         ctx.check(rc)
     return rc, _eigen_stats(stats)

@@ -11,10 +11,16 @@
 // Converged when |k_new - k| / k_new < tol_k and
 // max|phi_new - phi| / max|phi_new| < tol_phi.
 //
+// Multigroup problems (section 5.3, Eq. 27-29) run G groups of an instance
+// as the pseudo-instances j = i*G + g of the inner solve; F sums over the
+// groups and the change norm takes the maximum over them.  The inner source
+// of group g is chi_g * fission density + downscatter (mg kernels below);
+// with G = 1 it is the fission emission S written by the update.
+//
 // Per-block kernels take one reduction block (kCombineChunk cells of one
-// instance) per 256-thread workgroup and leave their partials in
-// part[3 * slot ...]; per-instance kernels sum them in block order, so every
-// result is independent of scheduling.
+// pseudo-instance) per 256-thread workgroup and leave their partials in
+// part[3 * slot ...]; per-instance kernels sum them in group and block
+// order, so every result is independent of scheduling.
 #include "eigen_kernels.h"
 
 namespace mdp {
@@ -88,16 +94,18 @@ eig_init_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blo
 __global__ void eig_init_fin_kernel(const InstDesc* __restrict__ insts,
                                     const EigDesc* __restrict__ ed, EigState* __restrict__ es,
                                     int* __restrict__ edone, const double* __restrict__ part,
-                                    int n_inst) {
+                                    int n_inst, int G) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_inst) return;
-    const InstDesc& I = insts[n];
     double F = 0.0, bad = 0.0;
-    for (int b = 0; b < I.nred; ++b) {
-        F += part[3 * (I.red0 + b)];
-        bad += part[3 * (I.red0 + b) + 1];
+    for (int g = 0; g < G; ++g) {
+        const InstDesc& I = insts[n * G + g];
+        for (int b = 0; b < I.nred; ++b) {
+            F += part[3 * (I.red0 + b)];
+            bad += part[3 * (I.red0 + b) + 1];
+        }
     }
-    F *= ed[n].vol;
+    F *= ed[n * G].vol;
     if (bad > 0.0 || !isfinite(F) || !(F > 0.0) || !(es[n].k > 0.0)) {
         es[n].status = -1;
         edone[n] = 1;
@@ -110,10 +118,10 @@ __global__ void eig_init_fin_kernel(const InstDesc* __restrict__ insts,
 __global__ void __launch_bounds__(kThreads)
 eig_sum_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                const EigDesc* __restrict__ ed, const int* __restrict__ edone,
-               double* __restrict__ part) {
+               double* __restrict__ part, int G) {
     __shared__ Red3 sh;
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x]) return;
+    if (bi.x < 0 || edone[bi.x / G]) return;
     const InstDesc& I = insts[bi.x];
     const float* nsf = ed[bi.x].nsf;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
@@ -127,15 +135,19 @@ eig_sum_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bloc
 // New eigenvalue and normalisation factor (one thread per instance).
 __global__ void eig_k_kernel(const InstDesc* __restrict__ insts, const EigDesc* __restrict__ ed,
                              EigState* __restrict__ es, int* __restrict__ edone,
-                             const double* __restrict__ part, IterState st, int n_inst) {
+                             const double* __restrict__ part, IterState st, int n_inst, int G) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_inst || edone[n]) return;
-    const InstDesc& I = insts[n];
     EigState& E = es[n];
     double F = 0.0;
-    for (int b = 0; b < I.nred; ++b) F += part[3 * (I.red0 + b)];
-    F *= ed[n].vol;
-    if (st.status[n] == -4 || !isfinite(F) || !(F > 0.0)) {
+    bool bad = false;
+    for (int g = 0; g < G; ++g) {
+        const InstDesc& I = insts[n * G + g];
+        for (int b = 0; b < I.nred; ++b) F += part[3 * (I.red0 + b)];
+        bad |= st.status[n * G + g] == -4;
+    }
+    F *= ed[n * G].vol;
+    if (bad || !isfinite(F) || !(F > 0.0)) {
         E.status = -4;
         edone[n] = 1;
         return;
@@ -153,13 +165,13 @@ __global__ void eig_k_kernel(const InstDesc* __restrict__ insts, const EigDesc* 
 __global__ void __launch_bounds__(kThreads)
 eig_diff_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                 const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
-                const int* __restrict__ edone, double* __restrict__ part, int mode) {
+                const int* __restrict__ edone, double* __restrict__ part, int mode, int G) {
     __shared__ Red3 sh;
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x]) return;
+    if (bi.x < 0 || edone[bi.x / G]) return;
     const InstDesc& I = insts[bi.x];
     const EigDesc& E = ed[bi.x];
-    const double sc = es[bi.x].scale, k = es[bi.x].k;
+    const double sc = es[bi.x / G].scale, k = es[bi.x / G].k;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     double s = 0.0, d = 0.0, m = 0.0;
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
@@ -169,7 +181,7 @@ eig_diff_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blo
         if (mode == 0) {
             I.phi[c] = p;
             E.prev[c] = p;
-            E.S[c] = fission(f, p, k);
+            if (G == 1) E.S[c] = fission(f, p, k);
         } else {
             d = fmax(d, fabs((double)p - (double)E.prev[c]));
             m = fmax(m, fabs((double)p));
@@ -189,23 +201,25 @@ __global__ void eig_conv_kernel(const InstDesc* __restrict__ insts,
                                 const EigDesc* __restrict__ ed, EigState* __restrict__ es,
                                 int* __restrict__ edone, const double* __restrict__ part,
                                 IterState st, int n_inst, double tol_k, double tol_phi,
-                                int mode, int last) {
+                                int mode, int last, int G) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_inst || edone[n]) return;
-    const InstDesc& I = insts[n];
     EigState& E = es[n];
     double F = 0.0, d = 0.0, m = 0.0;
-    for (int b = 0; b < I.nred; ++b) {
-        const double* v = part + 3 * (size_t)(I.red0 + b);
-        F += v[0];
-        d = fmax(d, v[1]);
-        m = fmax(m, v[2]);
+    for (int g = 0; g < G; ++g) {
+        const InstDesc& I = insts[n * G + g];
+        for (int b = 0; b < I.nred; ++b) {
+            const double* v = part + 3 * (size_t)(I.red0 + b);
+            F += v[0];
+            d = fmax(d, v[1]);
+            m = fmax(m, v[2]);
+        }
     }
-    E.F = F * ed[n].vol;
+    E.F = F * ed[n * G].vol;
     if (mode == 0) return;
     E.dphi = m > 0.0 ? d / m : INFINITY;
     E.outer += 1;
-    E.inner += st.iter[n];
+    for (int g = 0; g < G; ++g) E.inner += st.iter[n * G + g];
     if (E.dk < tol_k && E.dphi < tol_phi) {
         E.status = 0;
         edone[n] = 1;
@@ -218,19 +232,72 @@ __global__ void eig_conv_kernel(const InstDesc* __restrict__ insts,
 __global__ void __launch_bounds__(kThreads)
 eig_apply_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                  const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
-                 const int* __restrict__ edone) {
+                 const int* __restrict__ edone, int G) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x]) return;
+    if (bi.x < 0 || edone[bi.x / G]) return;
     const InstDesc& I = insts[bi.x];
     const EigDesc& E = ed[bi.x];
-    const double sc = es[bi.x].scale, k = es[bi.x].k;
+    const double sc = es[bi.x / G].scale, k = es[bi.x / G].k;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
         const float p = scaled(I.phi[c], sc);
         I.phi[c] = p;
         E.prev[c] = p;
-        E.S[c] = fission(E.nsf[c], p, k);
+        if (G == 1) E.S[c] = fission(E.nsf[c], p, k);
     }
+}
+
+// Multigroup: fission density fd = sum_g nu_sigma_f_g phi_g / k of the
+// stored iterate, one pass over the blocks of each instance's group 0 (all
+// groups share the grid and the block layout).
+__global__ void __launch_bounds__(kThreads)
+mg_fission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                  const EigDesc* __restrict__ ed, const MgDesc* __restrict__ md,
+                  const EigState* __restrict__ es, const int* __restrict__ edone, int G) {
+    const int4 bi = blocks[blockIdx.x];
+    if (bi.x < 0 || bi.x % G != 0 || edone[bi.x / G]) return;
+    const int n = bi.x / G;
+    const double k = es[n].k;
+    const int cells = insts[bi.x].cells;
+    const int c1 = min(bi.y + kCombineChunk, cells);
+    for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
+        double f = 0.0;
+        for (int g = 0; g < G; ++g) f += (double)ed[n * G + g].nsf[c] * (double)insts[n * G + g].phi[c];
+        md[n].fd[c] = (float)(f / k);
+    }
+}
+
+// Multigroup: the source of group g, chi_g fd + sum_{h<g} sigma_s^{h->g}
+// phi_h (the groups above g already hold this pass's solution), into the
+// inner solve's source buffer S of pseudo-instance (n, g).
+__global__ void __launch_bounds__(kThreads)
+mg_source_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
+                 const EigDesc* __restrict__ ed, const MgDesc* __restrict__ md,
+                 const int* __restrict__ edone, int G, int g) {
+    const int4 bi = blocks[blockIdx.x];
+    if (bi.x < 0 || bi.x % G != g || edone[bi.x / G]) return;
+    const int n = bi.x / G;
+    const MgDesc& D = md[n];
+    const float chi = D.chi[g];
+    float* S = ed[bi.x].S;
+    const int c1 = min(bi.y + kCombineChunk, insts[bi.x].cells);
+    for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
+        double q = (double)chi * (double)D.fd[c];
+        for (int h = 0; h < g; ++h) {
+            const float* sd = D.ss[h * kMaxGroups + g];
+            if (sd != nullptr) q += (double)sd[c] * (double)insts[n * G + h].phi[c];
+        }
+        S[c] = (float)q;
+    }
+}
+
+// Multigroup: pseudo-instances outside group g, or of finished instances,
+// are skipped by the next inner solve.
+__global__ void mg_mask_kernel(const int* __restrict__ edone, int* __restrict__ skip, int N,
+                               int G, int g) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    skip[j] = (j % G != g || edone[j / G]) ? 1 : 0;
 }
 
 // Emission of one source-iteration sweep from the current iterate u with
@@ -238,7 +305,7 @@ eig_apply_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
 __global__ void __launch_bounds__(kThreads)
 eig_emission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                     const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
-                    const int* __restrict__ edone) {
+                    const int* __restrict__ edone) {   // one group (G = 1)
     const int4 bi = blocks[blockIdx.x];
     if (bi.x < 0 || edone[bi.x]) return;
     const InstDesc& I = insts[bi.x];
@@ -253,43 +320,43 @@ eig_emission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__
 
 __global__ void __launch_bounds__(kThreads)
 eig_final_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
-                 const EigState* __restrict__ es) {
+                 const EigState* __restrict__ es, int G) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || es[bi.x].status < 0) return;
+    if (bi.x < 0 || es[bi.x / G].status < 0) return;
     const InstDesc& I = insts[bi.x];
-    const double sc = es[bi.x].scale;
+    const double sc = es[bi.x / G].scale;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) I.phi[c] = scaled(I.phi[c], sc);
 }
 
 }  // namespace
 
-void launch_eig_start(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_eig_start(int n_inst, int G, int nblocks, const InstDesc* insts, const int4* blocks,
                       const EigDesc* ed, EigState* es, int* edone, double* part,
                       hipStream_t s) {
     const dim3 gi((n_inst + 63) / 64), bi(64);
     hipLaunchKernelGGL(eig_init_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
                        ed, part);
-    hipLaunchKernelGGL(eig_init_fin_kernel, gi, bi, 0, s, insts, ed, es, edone, part, n_inst);
+    hipLaunchKernelGGL(eig_init_fin_kernel, gi, bi, 0, s, insts, ed, es, edone, part, n_inst, G);
     hipLaunchKernelGGL(eig_diff_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       es, edone, part, 0);
+                       es, edone, part, 0, G);
     hipLaunchKernelGGL(eig_conv_kernel, gi, bi, 0, s, insts, ed, es, edone, part, IterState{},
-                       n_inst, 0.0, 0.0, 0, 0);
+                       n_inst, 0.0, 0.0, 0, 0, G);
 }
 
-void launch_eig_update(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_eig_update(int n_inst, int G, int nblocks, const InstDesc* insts, const int4* blocks,
                        const EigDesc* ed, EigState* es, int* edone, double* part,
                        IterState st, double tol_k, double tol_phi, int last, hipStream_t s) {
     const dim3 gi((n_inst + 63) / 64), bi(64);
     hipLaunchKernelGGL(eig_sum_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       edone, part);
-    hipLaunchKernelGGL(eig_k_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst);
+                       edone, part, G);
+    hipLaunchKernelGGL(eig_k_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst, G);
     hipLaunchKernelGGL(eig_diff_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       es, edone, part, 1);
+                       es, edone, part, 1, G);
     hipLaunchKernelGGL(eig_conv_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst,
-                       tol_k, tol_phi, 1, last);
+                       tol_k, tol_phi, 1, last, G);
     hipLaunchKernelGGL(eig_apply_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       ed, es, edone);
+                       ed, es, edone, G);
 }
 
 void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
@@ -299,10 +366,26 @@ void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
                        ed, es, edone);
 }
 
-void launch_eig_final(int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_mg_fission(int G, int nblocks, const InstDesc* insts, const int4* blocks,
+                       const EigDesc* ed, const MgDesc* md, const EigState* es,
+                       const int* edone, hipStream_t s) {
+    hipLaunchKernelGGL(mg_fission_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
+                       ed, md, es, edone, G);
+}
+
+void launch_mg_group(int n_pseudo, int G, int g, int nblocks, const InstDesc* insts,
+                     const int4* blocks, const EigDesc* ed, const MgDesc* md, const int* edone,
+                     int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(mg_source_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
+                       ed, md, edone, G, g);
+    hipLaunchKernelGGL(mg_mask_kernel, dim3((n_pseudo + 255) / 256), dim3(256), 0, s, edone,
+                       skip, n_pseudo, G, g);
+}
+
+void launch_eig_final(int G, int nblocks, const InstDesc* insts, const int4* blocks,
                       const EigState* es, hipStream_t s) {
     hipLaunchKernelGGL(eig_final_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       es);
+                       es, G);
 }
 
 }  // namespace mdp

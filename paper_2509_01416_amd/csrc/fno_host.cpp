@@ -860,7 +860,7 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
         !c->hip_ok(hipMemsetAsync(su.st.status, 0, sizeof(int) * B, s), "memset"))
         return TR_ERR_HIP;
     const int nblocks = (int)su.blocks.size();
-    launch_eig_start(B, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart, s);
+    launch_eig_start(B, 1, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart, s);
     if (!c->hip_ok(hipMemcpyAsync(h, d_es, sizeof(EigState) * B, hipMemcpyDeviceToHost, s),
                    "copy"))
         return TR_ERR_HIP;
@@ -887,7 +887,7 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
             if (!c->launch_sweep(su, B, d_done, nullptr, 0)) return TR_ERR_HIP;
             launch_combine(nblocks, su.d_inst, su.d_blocks, d_done, su.d_red, 1, 0, s);
         }
-        launch_eig_update(B, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart,
+        launch_eig_update(B, 1, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart,
                           su.st, tol_k, tol_phi, outer == max_outer ? 1 : 0, s);
         if (!c->hip_ok(hipMemcpyAsync(hdone, d_done, 4 * (size_t)B, hipMemcpyDeviceToHost, s),
                        "copy"))
@@ -907,7 +907,7 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
                                                  hipMemcpyHostToDevice, s), "copy"))
             return TR_ERR_HIP;
     }
-    launch_eig_final(nblocks, su.d_inst, su.d_blocks, d_es, s);
+    launch_eig_final(1, nblocks, su.d_inst, su.d_blocks, d_es, s);
     launch_recast_output(ddesc, B, kGrid, kP, phi, s);
     EigState* rs = (EigState*)h;
     if (!c->hip_ok(hipMemcpyAsync(rs, d_es, sizeof(EigState) * B, hipMemcpyDeviceToHost, s),
