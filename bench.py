@@ -125,12 +125,13 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def eigen_leg(ctx, model, B, I, torch, args):
-    """k-eigenvalue measurements (section 5.2, Appendix A2), tolerance 1e-4
-    on k, the flux and the inner solves (the paper's uniform criterion):
-    the model-based power iteration on 16 x 256^2 S16 (the x-y eigen Case 1
-    analogue), and on the network's 64 x 64 grid the model-based solve beside
-    SP and CP (network loop, then model-based refinement), as wall times
-    normalised to the model-based one."""
+    """k-eigenvalue measurements (section 5.2-5.3, Appendix A2), tolerance
+    1e-4 on k, the flux and the inner solves (the paper's uniform
+    criterion): the model-based power iteration on 16 x 256^2 S16 (the x-y
+    eigen Case 1 analogue), the three-group problem of Tables 8-9 on
+    16 x 256^2 S16, and on the network's 64 x 64 grid the model-based solve
+    beside SP and CP (network loop, then model-based refinement), as wall
+    times normalised to the model-based one."""
     dev = "cuda"
     f = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
 
@@ -165,6 +166,29 @@ def eigen_leg(ctx, model, B, I, torch, args):
     log(f"[bench] eigen {wl.name}: {ms:.1f} ms k={big['k_mean']:.5f} "
         f"outer={big['outer_mean']:.1f} inner={big['inner_sweeps_mean']:.0f}")
 
+    wl = I.three_group_2d(16, 256)
+    mgp = [B.Problem(sigma_t=f(i.sigma_t), sigma_s=None, source=None, lx=i.lx, ly=i.ly)
+           for i in wl.instances]
+    mgd = [dict(sigma_t=[f(a) for a in gd["sigma_t"]],
+                sigma_s=[[None if a is None else f(a) for a in row] for row in gd["sigma_s"]],
+                nu_sigma_f=[f(a) for a in gd["nu_sigma_f"]], chi=gd["chi"])
+           for gd in wl.extra["groups"]]
+    mgo = [[torch.zeros_like(p.sigma_t) for _ in range(3)] for p in mgp]
+    qmg = B.Quad.from_inputs(wl.quad)
+    run = lambda: B.tr_eigen_mg(ctx, mgp, mgd, qmg, None, mgo, None, tol, tol, tol, 500, 20000)
+    run()
+    ms, (rc, st) = wall(run, 2)
+    sweeps = sum(s["inner"] * i.cells for s, i in zip(st, wl.instances)) * wl.quad.n_dir
+    three = {"workload": wl.name, "ms": ms, "status": rc,
+             "k_mean": float(np.mean([s["k"] for s in st])),
+             "outer_mean": float(np.mean([s["outer"] for s in st])),
+             "inner_sweeps_mean": float(np.mean([s["inner"] for s in st])),
+             "cell_angle_updates_per_s": sweeps / (ms * 1e-3),
+             "balance_rel_max": float(max(s["balance_rel"] for s in st))}
+    log(f"[bench] eigen {wl.name}: {ms:.1f} ms k={three['k_mean']:.5f} "
+        f"outer={three['outer_mean']:.1f} inner={three['inner_sweeps_mean']:.0f}")
+    del mgp, mgd, mgo
+
     wl = I.eigen_sine_64(16)
     probs, nsf, quad = batch(wl)
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
@@ -192,7 +216,8 @@ def eigen_leg(ctx, model, B, I, torch, args):
     base = small["model_based"]["ms"]
     for name in ("sp", "cp"):
         small[name]["normalised_time_pct"] = 100.0 * small[name]["ms"] / base
-    return {"tol": tol, "model_based_256": big, "preconditioned_64": small}
+    return {"tol": tol, "model_based_256": big, "three_group_256": three,
+            "preconditioned_64": small}
 
 
 def main():

@@ -410,3 +410,39 @@ def eigen_sine_64(count: int = 16) -> Workload:
     return Workload(f"eigen_sine_{count}x64_S8", insts, level_symmetric_2d(8), tol=1e-4,
                     description="2-D sinusoidal eigen problems on the network grid",
                     extra={"nu_sigma_f": nsf})
+
+
+# Tables 8-9 (section 5.3): sigma_s^{g->h} (rows g, columns h), nu,
+# sigma_t, sigma_f, chi of the three-group problem.
+THREE_GROUP_SS = ((0.024, 0.171, 0.033), (0.0, 0.600, 0.275), (0.0, 0.0, 2.000))
+THREE_GROUP_NU = (3.0, 2.5, 2.0)
+THREE_GROUP_ST = (0.240, 0.975, 3.000)
+THREE_GROUP_SF = (0.006, 0.060, 0.900)
+THREE_GROUP_CHI = (0.96, 0.04, 0.0)
+
+
+def three_group_2d(count: int = 16, n: int = 256, quad_order: int = 16) -> Workload:
+    """x-y analogue of the three-group problem (section 5.3, Tables 8-9) on
+    a 10 x 10 cm square, vacuum faces, n^2 cells, level-symmetric S_N.
+    Instance i scales every cross section of group g by a seeded +-2 % GRF
+    field (seed 8000 + 3i + g), so the batch holds distinct problems.
+    extra["groups"][i] = dict(sigma_t, sigma_s (3 x 3, None = zero),
+    nu_sigma_f, chi) as numpy fields."""
+    insts, groups = [], []
+    for i in range(count):
+        sc = []
+        for g in range(3):
+            f = grf_2d(n, 10.0, seed=8000 + 3 * i + g)
+            sc.append(1.0 + 0.02 * (f - f.mean()) / max(f.std(), 1e-12))
+        groups.append(dict(
+            sigma_t=[THREE_GROUP_ST[g] * sc[g] for g in range(3)],
+            sigma_s=[[THREE_GROUP_SS[g][h] * sc[g] if (h >= g and THREE_GROUP_SS[g][h] != 0.0)
+                      else None for h in range(3)] for g in range(3)],
+            nu_sigma_f=[THREE_GROUP_NU[g] * THREE_GROUP_SF[g] * sc[g] for g in range(3)],
+            chi=list(THREE_GROUP_CHI)))
+        insts.append(Instance(nx=n, ny=n, lx=10.0, ly=10.0, sigma_t=sc[0], sigma_s=np.zeros((n, n)),
+                              source=np.zeros((n, n))))
+    return Workload(f"three_group_{count}x{n}_S{quad_order}", insts,
+                    level_symmetric_2d(quad_order), tol=1e-4,
+                    description="2-D three-group eigen problems (Tables 8-9)",
+                    extra={"groups": groups})
