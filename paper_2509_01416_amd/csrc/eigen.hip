@@ -12,7 +12,8 @@
 // max|phi_new - phi| / max|phi_new| < tol_phi.
 //
 // Multigroup problems (section 5.3, Eq. 27-29) run G groups of an instance
-// as the pseudo-instances j = i*G + g of the inner solve; F sums over the
+// as the pseudo-instances j = g*n_inst + i of the inner solve (group-major,
+// so that one group's workgroups are contiguous in launch order); F sums over the
 // groups and the change norm takes the maximum over them.  The inner source
 // of group g is chi_g * fission density + downscatter (mg kernels below);
 // with G = 1 it is the fission emission S written by the update.
@@ -99,13 +100,13 @@ __global__ void eig_init_fin_kernel(const InstDesc* __restrict__ insts,
     if (n >= n_inst) return;
     double F = 0.0, bad = 0.0;
     for (int g = 0; g < G; ++g) {
-        const InstDesc& I = insts[n * G + g];
+        const InstDesc& I = insts[g * n_inst + n];
         for (int b = 0; b < I.nred; ++b) {
             F += part[3 * (I.red0 + b)];
             bad += part[3 * (I.red0 + b) + 1];
         }
     }
-    F *= ed[n * G].vol;
+    F *= ed[n].vol;
     if (bad > 0.0 || !isfinite(F) || !(F > 0.0) || !(es[n].k > 0.0)) {
         es[n].status = -1;
         edone[n] = 1;
@@ -118,10 +119,10 @@ __global__ void eig_init_fin_kernel(const InstDesc* __restrict__ insts,
 __global__ void __launch_bounds__(kThreads)
 eig_sum_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                const EigDesc* __restrict__ ed, const int* __restrict__ edone,
-               double* __restrict__ part, int G) {
+               double* __restrict__ part, int NI) {
     __shared__ Red3 sh;
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x / G]) return;
+    if (bi.x < 0 || edone[bi.x % NI]) return;
     const InstDesc& I = insts[bi.x];
     const float* nsf = ed[bi.x].nsf;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
@@ -142,11 +143,11 @@ __global__ void eig_k_kernel(const InstDesc* __restrict__ insts, const EigDesc* 
     double F = 0.0;
     bool bad = false;
     for (int g = 0; g < G; ++g) {
-        const InstDesc& I = insts[n * G + g];
+        const InstDesc& I = insts[g * n_inst + n];
         for (int b = 0; b < I.nred; ++b) F += part[3 * (I.red0 + b)];
-        bad |= st.status[n * G + g] == -4;
+        bad |= st.status[g * n_inst + n] == -4;
     }
-    F *= ed[n * G].vol;
+    F *= ed[n].vol;
     if (bad || !isfinite(F) || !(F > 0.0)) {
         E.status = -4;
         edone[n] = 1;
@@ -165,13 +166,14 @@ __global__ void eig_k_kernel(const InstDesc* __restrict__ insts, const EigDesc* 
 __global__ void __launch_bounds__(kThreads)
 eig_diff_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                 const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
-                const int* __restrict__ edone, double* __restrict__ part, int mode, int G) {
+                const int* __restrict__ edone, double* __restrict__ part, int mode, int NI,
+                int G) {
     __shared__ Red3 sh;
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x / G]) return;
+    if (bi.x < 0 || edone[bi.x % NI]) return;
     const InstDesc& I = insts[bi.x];
     const EigDesc& E = ed[bi.x];
-    const double sc = es[bi.x / G].scale, k = es[bi.x / G].k;
+    const double sc = es[bi.x % NI].scale, k = es[bi.x % NI].k;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     double s = 0.0, d = 0.0, m = 0.0;
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
@@ -207,7 +209,7 @@ __global__ void eig_conv_kernel(const InstDesc* __restrict__ insts,
     EigState& E = es[n];
     double F = 0.0, d = 0.0, m = 0.0;
     for (int g = 0; g < G; ++g) {
-        const InstDesc& I = insts[n * G + g];
+        const InstDesc& I = insts[g * n_inst + n];
         for (int b = 0; b < I.nred; ++b) {
             const double* v = part + 3 * (size_t)(I.red0 + b);
             F += v[0];
@@ -215,11 +217,11 @@ __global__ void eig_conv_kernel(const InstDesc* __restrict__ insts,
             m = fmax(m, v[2]);
         }
     }
-    E.F = F * ed[n * G].vol;
+    E.F = F * ed[n].vol;
     if (mode == 0) return;
     E.dphi = m > 0.0 ? d / m : INFINITY;
     E.outer += 1;
-    for (int g = 0; g < G; ++g) E.inner += st.iter[n * G + g];
+    for (int g = 0; g < G; ++g) E.inner += st.iter[g * n_inst + n];
     if (E.dk < tol_k && E.dphi < tol_phi) {
         E.status = 0;
         edone[n] = 1;
@@ -232,12 +234,12 @@ __global__ void eig_conv_kernel(const InstDesc* __restrict__ insts,
 __global__ void __launch_bounds__(kThreads)
 eig_apply_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                  const EigDesc* __restrict__ ed, const EigState* __restrict__ es,
-                 const int* __restrict__ edone, int G) {
+                 const int* __restrict__ edone, int NI, int G) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || edone[bi.x / G]) return;
+    if (bi.x < 0 || edone[bi.x % NI]) return;
     const InstDesc& I = insts[bi.x];
     const EigDesc& E = ed[bi.x];
-    const double sc = es[bi.x / G].scale, k = es[bi.x / G].k;
+    const double sc = es[bi.x % NI].scale, k = es[bi.x % NI].k;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
         const float p = scaled(I.phi[c], sc);
@@ -253,16 +255,18 @@ eig_apply_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
 __global__ void __launch_bounds__(kThreads)
 mg_fission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                   const EigDesc* __restrict__ ed, const MgDesc* __restrict__ md,
-                  const EigState* __restrict__ es, const int* __restrict__ edone, int G) {
+                  const EigState* __restrict__ es, const int* __restrict__ edone, int NI,
+                  int G) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || bi.x % G != 0 || edone[bi.x / G]) return;
-    const int n = bi.x / G;
+    if (bi.x < 0 || bi.x >= NI || edone[bi.x]) return;   // the blocks of group 0
+    const int n = bi.x;
     const double k = es[n].k;
     const int cells = insts[bi.x].cells;
     const int c1 = min(bi.y + kCombineChunk, cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) {
         double f = 0.0;
-        for (int g = 0; g < G; ++g) f += (double)ed[n * G + g].nsf[c] * (double)insts[n * G + g].phi[c];
+        for (int g = 0; g < G; ++g)
+            f += (double)ed[g * NI + n].nsf[c] * (double)insts[g * NI + n].phi[c];
         md[n].fd[c] = (float)(f / k);
     }
 }
@@ -273,10 +277,10 @@ mg_fission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ b
 __global__ void __launch_bounds__(kThreads)
 mg_source_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
                  const EigDesc* __restrict__ ed, const MgDesc* __restrict__ md,
-                 const int* __restrict__ edone, int G, int g) {
+                 const int* __restrict__ edone, int NI, int g) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || bi.x % G != g || edone[bi.x / G]) return;
-    const int n = bi.x / G;
+    if (bi.x < 0 || bi.x / NI != g || edone[bi.x % NI]) return;
+    const int n = bi.x % NI;
     const MgDesc& D = md[n];
     const float chi = D.chi[g];
     float* S = ed[bi.x].S;
@@ -285,7 +289,7 @@ mg_source_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
         double q = (double)chi * (double)D.fd[c];
         for (int h = 0; h < g; ++h) {
             const float* sd = D.ss[h * kMaxGroups + g];
-            if (sd != nullptr) q += (double)sd[c] * (double)insts[n * G + h].phi[c];
+            if (sd != nullptr) q += (double)sd[c] * (double)insts[h * NI + n].phi[c];
         }
         S[c] = (float)q;
     }
@@ -294,10 +298,10 @@ mg_source_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
 // Multigroup: pseudo-instances outside group g, or of finished instances,
 // are skipped by the next inner solve.
 __global__ void mg_mask_kernel(const int* __restrict__ edone, int* __restrict__ skip, int N,
-                               int G, int g) {
+                               int NI, int g) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    skip[j] = (j % G != g || edone[j / G]) ? 1 : 0;
+    skip[j] = (j / NI != g || edone[j % NI]) ? 1 : 0;
 }
 
 // Emission of one source-iteration sweep from the current iterate u with
@@ -320,11 +324,11 @@ eig_emission_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__
 
 __global__ void __launch_bounds__(kThreads)
 eig_final_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ blocks,
-                 const EigState* __restrict__ es, int G) {
+                 const EigState* __restrict__ es, int NI) {
     const int4 bi = blocks[blockIdx.x];
-    if (bi.x < 0 || es[bi.x / G].status < 0) return;
+    if (bi.x < 0 || es[bi.x % NI].status < 0) return;
     const InstDesc& I = insts[bi.x];
-    const double sc = es[bi.x / G].scale;
+    const double sc = es[bi.x % NI].scale;
     const int c1 = min(bi.y + kCombineChunk, I.cells);
     for (int c = bi.y + threadIdx.x; c < c1; c += kThreads) I.phi[c] = scaled(I.phi[c], sc);
 }
@@ -339,7 +343,7 @@ void launch_eig_start(int n_inst, int G, int nblocks, const InstDesc* insts, con
                        ed, part);
     hipLaunchKernelGGL(eig_init_fin_kernel, gi, bi, 0, s, insts, ed, es, edone, part, n_inst, G);
     hipLaunchKernelGGL(eig_diff_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       es, edone, part, 0, G);
+                       es, edone, part, 0, n_inst, G);
     hipLaunchKernelGGL(eig_conv_kernel, gi, bi, 0, s, insts, ed, es, edone, part, IterState{},
                        n_inst, 0.0, 0.0, 0, 0, G);
 }
@@ -349,14 +353,14 @@ void launch_eig_update(int n_inst, int G, int nblocks, const InstDesc* insts, co
                        IterState st, double tol_k, double tol_phi, int last, hipStream_t s) {
     const dim3 gi((n_inst + 63) / 64), bi(64);
     hipLaunchKernelGGL(eig_sum_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       edone, part, G);
+                       edone, part, n_inst);
     hipLaunchKernelGGL(eig_k_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst, G);
     hipLaunchKernelGGL(eig_diff_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks, ed,
-                       es, edone, part, 1, G);
+                       es, edone, part, 1, n_inst, G);
     hipLaunchKernelGGL(eig_conv_kernel, gi, bi, 0, s, insts, ed, es, edone, part, st, n_inst,
                        tol_k, tol_phi, 1, last, G);
     hipLaunchKernelGGL(eig_apply_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       ed, es, edone, G);
+                       ed, es, edone, n_inst, G);
 }
 
 void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
@@ -366,26 +370,26 @@ void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
                        ed, es, edone);
 }
 
-void launch_mg_fission(int G, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_mg_fission(int n_inst, int G, int nblocks, const InstDesc* insts, const int4* blocks,
                        const EigDesc* ed, const MgDesc* md, const EigState* es,
                        const int* edone, hipStream_t s) {
     hipLaunchKernelGGL(mg_fission_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       ed, md, es, edone, G);
+                       ed, md, es, edone, n_inst, G);
 }
 
 void launch_mg_group(int n_pseudo, int G, int g, int nblocks, const InstDesc* insts,
                      const int4* blocks, const EigDesc* ed, const MgDesc* md, const int* edone,
                      int* skip, hipStream_t s) {
     hipLaunchKernelGGL(mg_source_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       ed, md, edone, G, g);
+                       ed, md, edone, n_pseudo / G, g);
     hipLaunchKernelGGL(mg_mask_kernel, dim3((n_pseudo + 255) / 256), dim3(256), 0, s, edone,
-                       skip, n_pseudo, G, g);
+                       skip, n_pseudo, n_pseudo / G, g);
 }
 
-void launch_eig_final(int G, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_eig_final(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
                       const EigState* es, hipStream_t s) {
     hipLaunchKernelGGL(eig_final_kernel, dim3(nblocks), dim3(kThreads), 0, s, insts, blocks,
-                       es, G);
+                       es, n_inst);
 }
 
 }  // namespace mdp

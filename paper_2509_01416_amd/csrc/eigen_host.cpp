@@ -28,7 +28,9 @@ using namespace mdp;
 namespace {
 
 // One call's problems as the inner solve sees them: N = n_inst * G
-// pseudo-problems j = i*G + g (the source pointers are filled in here).
+// pseudo-problems j = g*n_inst + i, group-major so that one group's sweep
+// workgroups are contiguous in launch order (the source pointers are filled
+// in here).
 struct EigCall {
     int n_inst = 0, G = 1;
     std::vector<tr_problem> pp;                 // N
@@ -56,7 +58,7 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
     }
     if (G > 1)
         for (int i = 0; i < n_inst; ++i) {
-            const tr_problem& P = e.pp[(size_t)i * G];
+            const tr_problem& P = e.pp[i];
             const size_t cells = (size_t)P.nx * (P.dim == 1 ? 1 : P.ny);
             offF[i] = off;
             off += align_up(sizeof(float) * cells);
@@ -88,7 +90,7 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
     const size_t hread = align_up(sizeof(EigState) * n_inst) + align_up(sizeof(double) * 3 * N);
     // the setup's table upload reads the pinned buffer: wait for it first
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "sync")) return TR_ERR_HIP;
-    if (!c->pinned.reserve(c, std::max(htab, hread) + align_up(sizeof(int) * N)))
+    if (!c->pinned.reserve(c, std::max(htab, hread) + 2 * align_up(sizeof(int) * N)))
         return TR_ERR_OOM;
     char* h = (char*)c->pinned.ptr;
     std::memset(h, 0, htab);
@@ -137,8 +139,13 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
     const int norm_kind = tol_inner < 0 ? 1 : 0;
     const double atol = std::fabs(tol_inner);
     int total_sweeps = 0;
+    // a warm inner solve usually needs about as many sweeps as the previous
+    // one of its group: its first chunk takes that many (the most any running
+    // problem needed) before the first read-back of the done flags
+    std::vector<int> last_sw(G, 4), running(n_inst, 1);
+    int* hiters = (int*)((char*)c->pinned.ptr + align_up(sizeof(int) * N));
     for (int outer = 1; outer <= max_outer; ++outer) {
-        if (G > 1) launch_mg_fission(G, nblocks, su.d_inst, su.d_blocks, d_desc, d_mg, d_state,
+        if (G > 1) launch_mg_fission(n_inst, G, nblocks, su.d_inst, su.d_blocks, d_desc, d_mg, d_state,
                                      d_done, c->stream);
         for (int g = 0; g < G; ++g) {
             if (G > 1) launch_mg_group(N, G, g, nblocks, su.d_inst, su.d_blocks, d_desc, d_mg,
@@ -146,8 +153,13 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
             launch_init(N, nblocks, su.d_inst, su.d_blocks, su.d_dt, su.st, d_skip, c->stream);
             if (!c->hip_ok(hipGetLastError(), "init launch")) return TR_ERR_HIP;
             int sw = 0;
-            if (!c->si_iterate(su, N, atol, norm_kind, max_inner, &sw)) return TR_ERR_HIP;
+            if (!c->si_iterate(su, N, atol, norm_kind, max_inner, &sw, last_sw[g], hiters))
+                return TR_ERR_HIP;
             total_sweeps += sw;
+            int need = 1;
+            for (int i = 0; i < n_inst; ++i)
+                if (running[i]) need = std::max(need, hiters[g * n_inst + i]);
+            last_sw[g] = need;
         }
         launch_eig_update(n_inst, G, nblocks, su.d_inst, su.d_blocks, d_desc, d_state, d_done,
                           su.d_bpart, su.st, tol_k, tol_phi, outer == max_outer ? 1 : 0,
@@ -159,12 +171,15 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
             !c->hip_ok(hipStreamSynchronize(c->stream), "sync"))
             return TR_ERR_HIP;
         bool all = true;
-        for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
+        for (int i = 0; i < n_inst; ++i) {
+            running[i] = hdone[i] == 0;
+            all &= hdone[i] != 0;
+        }
         if (all) break;
     }
     // balance of every problem's last inner solve, then its normalisation
     if (!c->si_balance(su, N)) return TR_ERR_HIP;
-    launch_eig_final(G, nblocks, su.d_inst, su.d_blocks, d_state, c->stream);
+    launch_eig_final(n_inst, nblocks, su.d_inst, su.d_blocks, d_state, c->stream);
     if (!c->hip_ok(hipGetLastError(), "eigen final launch")) return TR_ERR_HIP;
     EigState* rs = (EigState*)h;
     double* rb = (double*)(h + align_up(sizeof(EigState) * n_inst));
@@ -194,9 +209,10 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
             // removal and leakage)
             double sq = 0.0, sa = 0.0, lk = 0.0;
             for (int g = 0; g < G; ++g) {
-                sq += rb[3 * (i * G + g)];
-                sa += rb[3 * (i * G + g) + 1];
-                lk += rb[3 * (i * G + g) + 2];
+                const size_t j = (size_t)g * n_inst + i;
+                sq += rb[3 * j];
+                sa += rb[3 * j + 1];
+                lk += rb[3 * j + 2];
             }
             o.balance_rel = sq != 0.0 ? std::fabs(sq - sa - lk) / std::fabs(sq)
                                       : std::fabs(sa + lk);
@@ -286,6 +302,12 @@ extern "C" tr_status tr_eigen_mg(tr_context* ctx, int32_t n_inst, const tr_probl
     EigCall e;
     e.n_inst = n_inst;
     e.G = G;
+    const size_t N = (size_t)n_inst * G;
+    e.pp.resize(N);
+    e.nsf.resize(N);
+    e.phi0.resize(N);
+    e.phi.resize(N);
+    e.chi.resize(N);
     e.down.assign((size_t)n_inst * kMaxGroups * kMaxGroups, nullptr);
     for (int i = 0; i < n_inst; ++i) {
         const tr_multigroup& m = mg[i];
@@ -310,9 +332,10 @@ extern "C" tr_status tr_eigen_mg(tr_context* ctx, int32_t n_inst, const tr_probl
                     c->fail("problem %d: upscatter %d -> %d is not supported", i, g, hh);
                     return TR_ERR_INVALID_ARG;
                 }
-            const size_t j = (size_t)i * G + g;
+            const size_t u = (size_t)i * G + g;           // caller's layout
+            const size_t j = (size_t)g * n_inst + i;      // pseudo-problem
             if (!m.sigma_t[g] || !m.sigma_s[(size_t)g * G + g] || !m.nu_sigma_f[g] ||
-                !phi_out[j]) {
+                !phi_out[u]) {
                 c->fail("problem %d group %d: need sigma_t, the within-group sigma_s, "
                         "nu_sigma_f and phi_out", i, g);
                 return TR_ERR_INVALID_ARG;
@@ -321,11 +344,11 @@ extern "C" tr_status tr_eigen_mg(tr_context* ctx, int32_t n_inst, const tr_probl
             P.sigma_t = m.sigma_t[g];
             P.sigma_s = m.sigma_s[(size_t)g * G + g];
             P.source = P.sigma_t;   // placeholder for the check
-            e.pp.push_back(P);
-            e.nsf.push_back(m.nu_sigma_f[g]);
-            e.phi0.push_back(phi_init ? phi_init[j] : nullptr);
-            e.phi.push_back(phi_out[j]);
-            e.chi.push_back((float)x);
+            e.pp[j] = P;
+            e.nsf[j] = m.nu_sigma_f[g];
+            e.phi0[j] = phi_init ? phi_init[u] : nullptr;
+            e.phi[j] = phi_out[u];
+            e.chi[u] = (float)x;
             for (int hh = g + 1; hh < G; ++hh)
                 e.down[((size_t)i * kMaxGroups + g) * kMaxGroups + hh] =
                     m.sigma_s[(size_t)g * G + hh];

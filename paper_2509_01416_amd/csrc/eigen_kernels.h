@@ -43,7 +43,7 @@ struct EigState {
 };
 
 // Launchers.  n_inst problems of G groups each; the inner solve's
-// instances (insts, blocks) are the pseudo-instances j = i*G + g.
+// instances (insts, blocks) are the pseudo-instances j = g*n_inst + i.
 // Start: phi = phi0 (or 1), then normalise it (F summed over the groups),
 // store it as the previous iterate and, for G = 1, form the first fission
 // source with the starting k.
@@ -62,7 +62,7 @@ void launch_eig_emission(int nblocks, const InstDesc* insts, const int4* blocks,
                          const EigDesc* ed, const EigState* es, const int* edone,
                          hipStream_t s);
 // Multigroup: the fission density of the stored iterate (once per outer).
-void launch_mg_fission(int G, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_mg_fission(int n_inst, int G, int nblocks, const InstDesc* insts, const int4* blocks,
                        const EigDesc* ed, const MgDesc* md, const EigState* es,
                        const int* edone, hipStream_t s);
 // Multigroup: the source of group g and the skip mask of its inner solve.
@@ -71,7 +71,7 @@ void launch_mg_group(int n_pseudo, int G, int g, int nblocks, const InstDesc* in
                      int* skip, hipStream_t s);
 // After the last outer: the inner solution of every valid problem scaled by
 // its normalisation (F(phi) = 1).
-void launch_eig_final(int G, int nblocks, const InstDesc* insts, const int4* blocks,
+void launch_eig_final(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
                       const EigState* es, hipStream_t s);
 
 }  // namespace mdp

@@ -907,7 +907,7 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
                                                  hipMemcpyHostToDevice, s), "copy"))
             return TR_ERR_HIP;
     }
-    launch_eig_final(1, nblocks, su.d_inst, su.d_blocks, d_es, s);
+    launch_eig_final(B, nblocks, su.d_inst, su.d_blocks, d_es, s);
     launch_recast_output(ddesc, B, kGrid, kP, phi, s);
     EigState* rs = (EigState*)h;
     if (!c->hip_ok(hipMemcpyAsync(rs, d_es, sizeof(EigState) * B, hipMemcpyDeviceToHost, s),

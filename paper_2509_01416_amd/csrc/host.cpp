@@ -642,12 +642,16 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
 }
 
 // Source iteration from the state launch_init left: sweeps in chunks of
-// 4, 8, ... 64 between read-backs of the per-instance done flags, until every
-// instance is done or max_iter sweeps have run.
+// first_chunk (default 4), then doubling up to 64, between read-backs of the
+// per-instance done flags, until every instance is done or max_iter sweeps
+// have run.  The convergence test runs after every sweep whatever the chunk
+// size: sweeps past an instance's convergence leave at once, so the chunking
+// changes no result.  iters_host (pinned, optional) receives the
+// per-instance sweep counts with the last read-back.
 bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, int max_iter,
-                     int* sweeps) {
+                     int* sweeps, int first_chunk, int* iters_host) {
     int* hdone = (int*)pinned.ptr;
-    int done_iters = 0, chunk = 4;
+    int done_iters = 0, chunk = std::min(std::max(first_chunk, 1), 64);
     const bool fused_fin = su.inst[0].dim == 2;
     bool all = false;
     while (done_iters < max_iter && !all) {
@@ -672,6 +676,8 @@ bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, in
         done_iters += k;
         if (!hip_ok(hipMemcpyAsync(hdone, su.st.done, sizeof(int) * n_inst,
                                    hipMemcpyDeviceToHost, stream), "flag copy") ||
+            (iters_host && !hip_ok(hipMemcpyAsync(iters_host, su.st.iter, sizeof(int) * n_inst,
+                                                  hipMemcpyDeviceToHost, stream), "copy")) ||
             !hip_ok(hipStreamSynchronize(stream), "sync"))
             return false;
         prof_collect();

@@ -91,7 +91,7 @@ struct Ctx {
     tr_status scan_fields(const Setup& su, int n_inst, const tr_problem* p,
                           bool need_xs, tr_stats* stats);
     bool si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, int max_iter,
-                    int* sweeps);
+                    int* sweeps, int first_chunk = 4, int* iters_host = nullptr);
     bool si_balance(const Setup& su, int n_inst);
 };
 
