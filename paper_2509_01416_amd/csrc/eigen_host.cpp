@@ -83,8 +83,30 @@ tr_status run_eigen(Ctx* c, EigCall& e, const tr_quadrature* q, double tol_k, do
     MgDesc* d_mg = G > 1 ? (MgDesc*)(eb + oMg) : nullptr;
     int* d_skip = G > 1 ? (int*)(eb + oSkip) : d_done;
 
+    // A multigroup inner solve sweeps one group's n_inst problems at a time:
+    // unless the caller forced a launch shape, plan it for those (group 0's
+    // problems, the first n_inst in group-major order) rather than for all
+    // N, whose plan would leave a group pass short of workgroups.
+    const int saved_D = c->force_D, saved_W = c->force_W, saved_S = c->force_S;
+    const bool replan = G > 1 && e.pp[0].dim == 2 && c->force_W <= 0;
+    if (replan) {
+        DirTable dt;
+        if (!build_dirtable(c, q, 2, &dt)) return TR_ERR_INVALID_ARG;
+        const Plan pl = make_plan(c, n_inst, e.pp.data(), dt);
+        int smin = pl.S[0];
+        for (int v : pl.S) smin = std::min(smin, v);
+        c->force_D = pl.D;
+        c->force_W = pl.W;
+        c->force_S = smin;
+    }
     Setup su;
-    if (!c->setup(N, e.pp.data(), q, e.phi.data(), e.phi.data(), nullptr, &su))
+    const bool set_ok = c->setup(N, e.pp.data(), q, e.phi.data(), e.phi.data(), nullptr, &su);
+    if (replan) {
+        c->force_D = saved_D;
+        c->force_W = saved_W;
+        c->force_S = saved_S;
+    }
+    if (!set_ok)
         return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
     const size_t htab = oSkip - oDesc;
     const size_t hread = align_up(sizeof(EigState) * n_inst) + align_up(sizeof(double) * 3 * N);
