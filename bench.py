@@ -140,13 +140,21 @@ def eigen_leg(ctx, model, B, I, torch, args):
                            lx=i.lx, ly=i.ly) for i in wl.instances]
         return probs, [f(a) for a in wl.extra["nu_sigma_f"]], B.Quad.from_inputs(wl.quad)
 
-    def wall(fn, reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+    spread = {}
+
+    def wall(fn, reps, name):
+        # median of reps solves: an isolated call in a process can take
+        # two to three times the steady time (host-side stalls between the
+        # read-backs), and a mean of few calls would report that instead
+        times, r = [], None
         for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             r = fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / reps, r
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        spread[name] = [round(min(times), 2), round(max(times), 2)]
+        return float(np.median(times)), r
 
     tol = 1e-4
     wl = I.eigen_case1_2d(16, 256)
@@ -154,7 +162,7 @@ def eigen_leg(ctx, model, B, I, torch, args):
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
     run = lambda: B.tr_eigen(ctx, probs, nsf, quad, None, phis, None, tol, tol, tol, 500, 20000)
     run()
-    ms, (rc, st) = wall(run, 2)
+    ms, (rc, st) = wall(run, 5, "model_based_256")
     M = wl.quad.n_dir
     sweeps = sum(s["inner"] * i.cells for s, i in zip(st, wl.instances)) * M
     big = {"workload": wl.name, "ms": ms, "status": rc,
@@ -177,7 +185,7 @@ def eigen_leg(ctx, model, B, I, torch, args):
     qmg = B.Quad.from_inputs(wl.quad)
     run = lambda: B.tr_eigen_mg(ctx, mgp, mgd, qmg, None, mgo, None, tol, tol, tol, 500, 20000)
     run()
-    ms, (rc, st) = wall(run, 2)
+    ms, (rc, st) = wall(run, 5, "three_group_256")
     sweeps = sum(s["inner"] * i.cells for s, i in zip(st, wl.instances)) * wl.quad.n_dir
     three = {"workload": wl.name, "ms": ms, "status": rc,
              "k_mean": float(np.mean([s["k"] for s in st])),
@@ -200,7 +208,7 @@ def eigen_leg(ctx, model, B, I, torch, args):
     small = {"workload": wl.name}
     for name, fn in (("model_based", mb), ("sp", sp), ("cp", cp)):
         fn()
-        ms, r = wall(fn, 3)
+        ms, r = wall(fn, 5, name)
         if name == "model_based":
             rc, st = r
             small[name] = {"ms": ms, "status": rc, "k_mean": float(np.mean([s["k"] for s in st])),
@@ -216,7 +224,8 @@ def eigen_leg(ctx, model, B, I, torch, args):
     base = small["model_based"]["ms"]
     for name in ("sp", "cp"):
         small[name]["normalised_time_pct"] = 100.0 * small[name]["ms"] / base
-    return {"tol": tol, "model_based_256": big, "three_group_256": three,
+    return {"tol": tol, "timing": "median of 5 solves after one warm-up",
+            "min_max_ms": spread, "model_based_256": big, "three_group_256": three,
             "preconditioned_64": small}
 
 
