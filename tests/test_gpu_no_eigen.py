@@ -156,3 +156,22 @@ def test_preconditioned_eigen_refines_to_model_based(env, kind):
         assert abs(st[0]["k"] - ref.k) < 1e-5 * ref.k
         assert e < 2e-4
     m.close()
+
+
+def test_no_eigen_rejects_unsupported_problems(env):
+    """no_eigen runs on the network's own 64 x 64 grid with vacuum faces;
+    other grids, reflective faces and unknown variants are rejected before
+    any launch."""
+    torch, B, ctx, w = env
+    m = B.Model(ctx, w)
+    quad = B.Quad.from_inputs(I.level_symmetric_2d(4))
+    for nx, bc, variant in ((32, (0, 0, 0, 0), B.NO_EIGEN_SP), (N, (1, 0, 0, 0), B.NO_EIGEN_CP),
+                            (N, (0, 0, 0, 0), 7)):
+        inst = I.Instance(nx=nx, ny=nx, lx=10.0, ly=10.0, sigma_t=np.ones((nx, nx)),
+                          sigma_s=np.full((nx, nx), 0.8), source=np.zeros((nx, nx)), bc=bc)
+        phi = [torch.zeros((nx, nx), device="cuda")]
+        rc, _ = B.no_eigen(ctx, m, [to_problem(inst, torch)], [_dev(torch, np.full((nx, nx), 0.3))],
+                           quad, I.SIGMA_T_STAR, I.SIGMA_S_STAR, variant, None, phi,
+                           raise_on_error=False)
+        assert rc == B.TR_ERR_INVALID_ARG, (nx, bc, variant)
+    m.close()
