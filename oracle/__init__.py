@@ -83,6 +83,17 @@ def _bc(bc) -> ctypes.Array:
     return (ctypes.c_int * 4)(*[int(b) for b in (list(bc) + [0, 0, 0, 0])[:4]])
 
 
+def _norm_kind(norm: str) -> int:
+    """Stopping rule of si1d/si2d: "l2" relative L2 change < tol, "max"
+    max relative change < tol, "bound" the fixed-point error bound
+    r rho / (1 - rho) < tol with rho = r_l / r_(l-1) (r the relative L2
+    change)."""
+    kinds = {"l2": 0, "max": 1, "bound": 2}
+    if norm not in kinds:
+        raise ValueError(f"unknown stopping rule {norm!r}")
+    return kinds[norm]
+
+
 class SolveResult:
     def __init__(self, phi, status, iterations, residual, leak, dscatter,
                  hist):
@@ -136,7 +147,7 @@ def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
     hist = np.zeros(max_iter)
     rc = lib.or_si2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
                      _dp(ss), _dp(qq), _bc(bc), _dp(p0), float(tol),
-                     int(max_iter), 1 if norm == "max" else 0, _dp(phi),
+                     int(max_iter), _norm_kind(norm), _dp(phi),
                      _dp(stats), _dp(hist))
     if rc < 0:
         raise ValueError(f"or_si2d failed ({rc})")
@@ -179,7 +190,7 @@ def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
     hist = np.zeros(max_iter)
     rc = lib.or_si1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(ss), _dp(qq),
                      _bc(bc), _dp(p0), float(tol), int(max_iter),
-                     1 if norm == "max" else 0, _dp(phi), _dp(stats),
+                     _norm_kind(norm), _dp(phi), _dp(stats),
                      _dp(hist))
     if rc < 0:
         raise ValueError(f"or_si1d failed ({rc})")
@@ -188,8 +199,22 @@ def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
                        hist[:it].copy())
 
 
-def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None):
-    """Solve one inputs.Instance with the oracle (dim from the instance)."""
+def f32_rounded(a) -> np.ndarray:
+    """A field as the FP32 library receives it, widened back to FP64 (the
+    oracle then solves exactly the problem the library is given)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None,
+                   f32_inputs=False):
+    """Solve one inputs.Instance with the oracle (dim from the instance).
+    f32_inputs: round sigma_t, sigma_s and the source to FP32 first."""
+    if f32_inputs:
+        import copy
+        inst = copy.copy(inst)
+        inst.sigma_t = f32_rounded(inst.sigma_t)
+        inst.sigma_s = f32_rounded(inst.sigma_s)
+        inst.source = f32_rounded(inst.source)
     if inst.dim == 1:
         return si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
                     inst.sigma_s, inst.source, bc=inst.bc[:2], phi0=phi0,
@@ -200,14 +225,15 @@ def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None):
 
 
 def solve_many(insts: Sequence, quad, tol, phi0s=None, threads: int = 1,
-               max_iter=100000):
+               max_iter=100000, norm=None, f32_inputs=False):
     """Solve several instances, one per worker thread (the C call releases
     the interpreter lock).  Returns a list of SolveResult."""
     phi0s = phi0s if phi0s is not None else [None] * len(insts)
+    kw = dict(norm=norm, f32_inputs=f32_inputs)
     if threads <= 1:
-        return [solve_instance(i, quad, tol, p, max_iter)
+        return [solve_instance(i, quad, tol, p, max_iter, **kw)
                 for i, p in zip(insts, phi0s)]
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        futs = [ex.submit(solve_instance, i, quad, tol, p, max_iter)
+        futs = [ex.submit(solve_instance, i, quad, tol, p, max_iter, **kw)
                 for i, p in zip(insts, phi0s)]
         return [f.result() for f in futs]

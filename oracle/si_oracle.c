@@ -25,9 +25,15 @@
  *     the mirrored direction's outgoing value from the previous sweep, i.e.
  *     lagged one iteration).
  *
- * Convergence: norm_kind 0 -> ||phi_new - phi_old||_2 / ||phi_new||_2,
- *              norm_kind 1 -> max_i |phi_new_i - phi_old_i| / |phi_new_i|.
- * The paper quotes only a tolerance (1e-4, section 5.1); the norm is this
+ * Convergence: norm_kind 0 -> ||phi_new - phi_old||_2 / ||phi_new||_2 < tol,
+ *              norm_kind 1 -> max_i |phi_new_i - phi_old_i| / |phi_new_i| < tol,
+ *              norm_kind 2 -> error bound of the fixed-point iteration: with
+ *                r_l the norm of kind 0 and rho = r_l / r_(l-1) the observed
+ *                contraction rate, stop once rho < 1 and
+ *                r_l * rho / (1 - rho) < tol (a contraction of rate rho
+ *                leaves the new iterate within r_l rho / (1 - rho) of the
+ *                fixed point, relative to its norm), or r_l = 0.
+ * The paper quotes only a tolerance (1e-4, section 5.1); the norms are this
  * library's reading.
  *
  * Face storage (2-D): face[f][k][m], f = 0 x-, 1 x+, 2 y-, 3 y+; k runs along
@@ -147,6 +153,18 @@ static double change_norm(size_t n, const double *a, const double *b,
     return sqrt(num / den);
 }
 
+/* Stopping test of one iteration: r = change norm of this iteration (kind 0
+ * or 1 as computed by change_norm; kind 2 uses the L2 norm), r_prev = that of
+ * the previous iteration (INFINITY before the second). */
+static int converged(double r, double r_prev, double tol, int kind) {
+    if (kind != 2) return r < tol;
+    if (r == 0.0) return 1;
+    if (!(r_prev < INFINITY) || !(r_prev > 0.0)) return 0;
+    const double rho = r / r_prev;
+    if (!(rho < 1.0)) return 0;
+    return r * rho / (1.0 - rho) < tol;
+}
+
 /*
  * Source iteration to tolerance.  phi0 may be NULL (zero start).  With a
  * warm start, reflective faces start isotropic at the adjacent cell's phi0.
@@ -188,18 +206,19 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     }
     const double V = (lx / nx) * (ly / ny);
     int status = OR_NOT_CONVERGED, it = 0;
-    double r = INFINITY, leak = 0.0, dscat = 0.0;
+    double r = INFINITY, r_prev = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (size_t c = 0; c < n; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
         or_sweep2d(nx, ny, lx, ly, M, mu, eta, w, sigma_t, Q, bc, fa, fb,
                    phin, &leak);
-        r = change_norm(n, phin, phi, norm_kind);
+        r_prev = r;
+        r = change_norm(n, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (size_t c = 0; c < n; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
         memcpy(phi, phin, sizeof(double) * n);
         double *t = fa; fa = fb; fb = t;
         if (hist) hist[it - 1] = r;
-        if (r < tol) { status = OR_OK; break; }
+        if (converged(r, r_prev, tol, norm_kind)) { status = OR_OK; break; }
     }
     if (it > max_iter) it = max_iter;
     if (stats) {
@@ -266,17 +285,18 @@ int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
     }
     const double V = lx / nx;
     int status = OR_NOT_CONVERGED, it;
-    double r = INFINITY, leak = 0.0, dscat = 0.0;
+    double r = INFINITY, r_prev = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (int c = 0; c < nx; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
         or_sweep1d(nx, lx, M, mu, w, sigma_t, Q, bc, fa, fb, phin, &leak);
-        r = change_norm((size_t)nx, phin, phi, norm_kind);
+        r_prev = r;
+        r = change_norm((size_t)nx, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (int c = 0; c < nx; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
         memcpy(phi, phin, sizeof(double) * nx);
         double *t = fa; fa = fb; fb = t;
         if (hist) hist[it - 1] = r;
-        if (r < tol) { status = OR_OK; break; }
+        if (converged(r, r_prev, tol, norm_kind)) { status = OR_OK; break; }
     }
     if (it > max_iter) it = max_iter;
     if (stats) {
