@@ -59,9 +59,9 @@ def _load():
             i, d = ctypes.c_int, ctypes.c_double
             lib.or_sweep2d.argtypes = [i, i, d, d, i, D, D, D, D, D, I, D, D, D, D]
             lib.or_si2d.argtypes = [i, i, d, d, i, D, D, D, D, D, D, I, D, d, i,
-                                    i, D, D, D]
+                                    i, i, D, D, D]
             lib.or_sweep1d.argtypes = [i, d, i, D, D, D, D, I, D, D, D, D]
-            lib.or_si1d.argtypes = [i, d, i, D, D, D, D, D, I, D, d, i, i, D, D, D]
+            lib.or_si1d.argtypes = [i, d, i, D, D, D, D, D, I, D, d, i, i, i, D, D, D]
             for f in (lib.or_sweep2d, lib.or_si2d, lib.or_sweep1d, lib.or_si1d):
                 f.restype = ctypes.c_int
             _lib = lib
@@ -87,7 +87,8 @@ def _norm_kind(norm: str) -> int:
     """Stopping rule of si1d/si2d: "l2" relative L2 change < tol, "max"
     max relative change < tol, "bound" the fixed-point error bound
     r rho / (1 - rho) < tol with rho = r_l / r_(l-1) (r the relative L2
-    change)."""
+    change); with stride K > 1 the bound is tested every K iterations on
+    the change over those K iterations (rho = r_l / r_(l-K))."""
     kinds = {"l2": 0, "max": 1, "bound": 2}
     if norm not in kinds:
         raise ValueError(f"unknown stopping rule {norm!r}")
@@ -133,7 +134,7 @@ def sweep2d(nx, ny, lx, ly, mu, eta, w, sigma_t, emission, bc=(0, 0, 0, 0),
 
 
 def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
-         phi0=None, tol=1e-6, max_iter=100000, norm="l2") -> SolveResult:
+         phi0=None, tol=1e-6, max_iter=100000, norm="l2", stride=1) -> SolveResult:
     """2-D source iteration to tolerance (zero start unless phi0 is given)."""
     lib = _load()
     mu, eta, w = _f64(mu), _f64(eta), _f64(w)
@@ -147,7 +148,7 @@ def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
     hist = np.zeros(max_iter)
     rc = lib.or_si2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
                      _dp(ss), _dp(qq), _bc(bc), _dp(p0), float(tol),
-                     int(max_iter), _norm_kind(norm), _dp(phi),
+                     int(max_iter), _norm_kind(norm), int(stride), _dp(phi),
                      _dp(stats), _dp(hist))
     if rc < 0:
         raise ValueError(f"or_si2d failed ({rc})")
@@ -177,7 +178,7 @@ def sweep1d(nx, lx, mu, w, sigma_t, emission, bc=(0, 0), face_prev=None,
 
 
 def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
-         max_iter=100000, norm="max") -> SolveResult:
+         max_iter=100000, norm="max", stride=1) -> SolveResult:
     lib = _load()
     mu, w = _f64(mu), _f64(w)
     M = mu.shape[0]
@@ -190,7 +191,7 @@ def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
     hist = np.zeros(max_iter)
     rc = lib.or_si1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(ss), _dp(qq),
                      _bc(bc), _dp(p0), float(tol), int(max_iter),
-                     _norm_kind(norm), _dp(phi), _dp(stats),
+                     _norm_kind(norm), int(stride), _dp(phi), _dp(stats),
                      _dp(hist))
     if rc < 0:
         raise ValueError(f"or_si1d failed ({rc})")
@@ -206,7 +207,7 @@ def f32_rounded(a) -> np.ndarray:
 
 
 def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None,
-                   f32_inputs=False):
+                   f32_inputs=False, stride=1):
     """Solve one inputs.Instance with the oracle (dim from the instance).
     f32_inputs: round sigma_t, sigma_s and the source to FP32 first."""
     if f32_inputs:
@@ -218,18 +219,18 @@ def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None,
     if inst.dim == 1:
         return si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
                     inst.sigma_s, inst.source, bc=inst.bc[:2], phi0=phi0,
-                    tol=tol, max_iter=max_iter, norm=norm or "max")
+                    tol=tol, max_iter=max_iter, norm=norm or "max", stride=stride)
     return si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
                 inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
-                phi0=phi0, tol=tol, max_iter=max_iter, norm=norm or "l2")
+                phi0=phi0, tol=tol, max_iter=max_iter, norm=norm or "l2", stride=stride)
 
 
 def solve_many(insts: Sequence, quad, tol, phi0s=None, threads: int = 1,
-               max_iter=100000, norm=None, f32_inputs=False):
+               max_iter=100000, norm=None, f32_inputs=False, stride=1):
     """Solve several instances, one per worker thread (the C call releases
     the interpreter lock).  Returns a list of SolveResult."""
     phi0s = phi0s if phi0s is not None else [None] * len(insts)
-    kw = dict(norm=norm, f32_inputs=f32_inputs)
+    kw = dict(norm=norm, f32_inputs=f32_inputs, stride=stride)
     if threads <= 1:
         return [solve_instance(i, quad, tol, p, max_iter, **kw)
                 for i, p in zip(insts, phi0s)]

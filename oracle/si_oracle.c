@@ -33,6 +33,12 @@
  *                r_l * rho / (1 - rho) < tol (a contraction of rate rho
  *                leaves the new iterate within r_l rho / (1 - rho) of the
  *                fixed point, relative to its norm), or r_l = 0.
+ *              With a stride K > 1 the same test runs only at iterations
+ *                l = K, 2K, ...: r_l is then the relative L2 distance
+ *                between phi_l and phi_(l-K) and rho = r_l / r_(l-K) the
+ *                contraction over K iterations, and the estimate
+ *                r_l rho / (1 - rho) keeps its meaning (the distance of
+ *                phi_l to the fixed point for a geometric error).
  * The paper quotes only a tolerance (1e-4, section 5.1); the norms are this
  * library's reading.
  *
@@ -176,8 +182,8 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
             const double *eta, const double *w, const double *sigma_t,
             const double *sigma_s, const double *q, const int *bc,
             const double *phi0, double tol, int max_iter, int norm_kind,
-            double *phi, double *stats, double *hist) {
-    if (nx <= 0 || ny <= 0 || M <= 0 || max_iter <= 0) return OR_BAD_ARG;
+            int stride, double *phi, double *stats, double *hist) {
+    if (nx <= 0 || ny <= 0 || M <= 0 || max_iter <= 0 || stride <= 0) return OR_BAD_ARG;
     const size_t n = (size_t)nx * ny;
     const int nf = nx > ny ? nx : ny;
     const size_t fsz = (size_t)4 * nf * M;
@@ -185,10 +191,12 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     double *phin = (double *)malloc(sizeof(double) * n);
     double *fa = (double *)calloc(fsz, sizeof(double));
     double *fb = (double *)calloc(fsz, sizeof(double));
-    if (!Q || !phin || !fa || !fb) {
-        free(Q); free(phin); free(fa); free(fb);
+    double *snap = (double *)malloc(sizeof(double) * n);
+    if (!Q || !phin || !fa || !fb || !snap) {
+        free(Q); free(phin); free(fa); free(fb); free(snap);
         return OR_BAD_ARG;
     }
+    if (norm_kind != 2) stride = 1;
     if (phi0) {
         memcpy(phi, phi0, sizeof(double) * n);
         for (int m = 0; m < M; ++m) {
@@ -204,27 +212,31 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     } else {
         memset(phi, 0, sizeof(double) * n);
     }
+    memcpy(snap, phi, sizeof(double) * n);
     const double V = (lx / nx) * (ly / ny);
     int status = OR_NOT_CONVERGED, it = 0;
-    double r = INFINITY, r_prev = INFINITY, leak = 0.0, dscat = 0.0;
+    double r = INFINITY, r_prev = INFINITY, r_step = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (size_t c = 0; c < n; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
         or_sweep2d(nx, ny, lx, ly, M, mu, eta, w, sigma_t, Q, bc, fa, fb,
                    phin, &leak);
-        r_prev = r;
-        r = change_norm(n, phin, phi, norm_kind == 1);
+        r_step = change_norm(n, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (size_t c = 0; c < n; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
         memcpy(phi, phin, sizeof(double) * n);
         double *t = fa; fa = fb; fb = t;
-        if (hist) hist[it - 1] = r;
+        if (hist) hist[it - 1] = r_step;
+        if (it % stride != 0) continue;
+        r_prev = r;
+        r = stride == 1 ? r_step : change_norm(n, phin, snap, 0);
+        memcpy(snap, phin, sizeof(double) * n);
         if (converged(r, r_prev, tol, norm_kind)) { status = OR_OK; break; }
     }
     if (it > max_iter) it = max_iter;
     if (stats) {
         stats[0] = it; stats[1] = r; stats[2] = leak; stats[3] = dscat;
     }
-    free(Q); free(phin); free(fa); free(fb);
+    free(Q); free(phin); free(fa); free(fb); free(snap);
     return status;
 }
 
@@ -264,16 +276,18 @@ int or_sweep1d(int nx, double lx, int M, const double *mu, const double *w,
 int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
             const double *sigma_t, const double *sigma_s, const double *q,
             const int *bc, const double *phi0, double tol, int max_iter,
-            int norm_kind, double *phi, double *stats, double *hist) {
-    if (nx <= 0 || M <= 0 || max_iter <= 0) return OR_BAD_ARG;
+            int norm_kind, int stride, double *phi, double *stats, double *hist) {
+    if (nx <= 0 || M <= 0 || max_iter <= 0 || stride <= 0) return OR_BAD_ARG;
     double *Q = (double *)malloc(sizeof(double) * nx);
     double *phin = (double *)malloc(sizeof(double) * nx);
     double *fa = (double *)calloc((size_t)2 * M, sizeof(double));
     double *fb = (double *)calloc((size_t)2 * M, sizeof(double));
-    if (!Q || !phin || !fa || !fb) {
-        free(Q); free(phin); free(fa); free(fb);
+    double *snap = (double *)malloc(sizeof(double) * nx);
+    if (!Q || !phin || !fa || !fb || !snap) {
+        free(Q); free(phin); free(fa); free(fb); free(snap);
         return OR_BAD_ARG;
     }
+    if (norm_kind != 2) stride = 1;
     if (phi0) {
         memcpy(phi, phi0, sizeof(double) * nx);
         for (int m = 0; m < M; ++m) {
@@ -283,25 +297,29 @@ int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
     } else {
         memset(phi, 0, sizeof(double) * nx);
     }
+    memcpy(snap, phi, sizeof(double) * nx);
     const double V = lx / nx;
     int status = OR_NOT_CONVERGED, it;
-    double r = INFINITY, r_prev = INFINITY, leak = 0.0, dscat = 0.0;
+    double r = INFINITY, r_prev = INFINITY, r_step = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (int c = 0; c < nx; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
         or_sweep1d(nx, lx, M, mu, w, sigma_t, Q, bc, fa, fb, phin, &leak);
-        r_prev = r;
-        r = change_norm((size_t)nx, phin, phi, norm_kind == 1);
+        r_step = change_norm((size_t)nx, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (int c = 0; c < nx; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
         memcpy(phi, phin, sizeof(double) * nx);
         double *t = fa; fa = fb; fb = t;
-        if (hist) hist[it - 1] = r;
+        if (hist) hist[it - 1] = r_step;
+        if (it % stride != 0) continue;
+        r_prev = r;
+        r = stride == 1 ? r_step : change_norm((size_t)nx, phin, snap, 0);
+        memcpy(snap, phin, sizeof(double) * nx);
         if (converged(r, r_prev, tol, norm_kind)) { status = OR_OK; break; }
     }
     if (it > max_iter) it = max_iter;
     if (stats) {
         stats[0] = it; stats[1] = r; stats[2] = leak; stats[3] = dscat;
     }
-    free(Q); free(phin); free(fa); free(fb);
+    free(Q); free(phin); free(fa); free(fb); free(snap);
     return status;
 }

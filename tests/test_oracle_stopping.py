@@ -119,3 +119,31 @@ def test_error_bound_rule_exact_fixed_point_and_first_iteration():
     r = oracle.si2d(4, 4, inst.lx, inst.ly, q.mu, q.eta, q.w, inst.sigma_t,
                     inst.sigma_s, inst.source, tol=1e300, norm="bound")
     assert r.iterations >= 2
+
+
+def test_strided_error_bound_rule():
+    """With a stride K the rule tests every K-th iteration on the change over
+    K iterations: the stop falls on a multiple of K, the reported change is
+    ||phi_l - phi_(l-K)|| / ||phi_l|| of the two iterates, the test at l - K
+    had not passed, and the answer lies within tol of the direct solution."""
+    q, inst, ref = _slow_problem()
+    K = 16
+    for tol in (1e-5, 1e-7):
+        b = oracle.si2d(inst.nx, inst.ny, inst.lx, inst.ly, q.mu, q.eta, q.w,
+                        inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
+                        tol=tol, norm="bound", stride=K)
+        e = np.linalg.norm(b.phi - ref) / np.linalg.norm(ref)
+        assert b.status == oracle.OK and b.iterations % K == 0
+        assert 0.1 * tol < e <= tol, (tol, e)
+        a = oracle.si2d(inst.nx, inst.ny, inst.lx, inst.ly, q.mu, q.eta, q.w,
+                        inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
+                        tol=tol, norm="bound", stride=K, max_iter=b.iterations - K)
+        assert a.status == oracle.NOT_CONVERGED
+        r = np.linalg.norm(b.phi - a.phi) / np.linalg.norm(b.phi)
+        assert abs(b.residual - r) < 1e-12 * r
+        # stride 1 is the plain rule, bit for bit
+        c1 = oracle.si2d(inst.nx, inst.ny, inst.lx, inst.ly, q.mu, q.eta, q.w,
+                         inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
+                         tol=tol, norm="bound", stride=1)
+        c0 = _solve(q, inst, tol, "bound")
+        assert c1.iterations == c0.iterations and np.array_equal(c1.phi, c0.phi)
