@@ -4,7 +4,10 @@
 Workload (default): 16 instances of 256 x 256 cells on a 10 x 10 mfp square,
 level-symmetric S16 (144 directions), two-region sigma_t in {1, 5} split by a
 seeded random line, c = 0.99, Gaussian-random-field sources, vacuum faces,
-tolerance 1e-6 on the relative L2 change.  One step = one pass of the hot
+tolerance 1e-6 under the error-bound stopping rule (the estimated distance
+r rho / (1 - rho) to the fixed point from the change over 16 iterations; the
+plain change rule, --stop change, leaves about 7e-5 at this contraction
+rate).  One step = one pass of the hot
 path over the batch: the equation-recast guess from the trained operator
 network (Eq. 24 on the 64 x 64 network grid, block-averaged inputs, bilinear
 resampling back to 256 x 256), then the source iteration to tolerance started
@@ -12,10 +15,12 @@ from that guess.  The same number of zero-start solves is timed beside it
 (--zero-only times the zero-start solve alone).
 
 Prints one JSON line: the metric (cell-angle updates/s over the whole step),
-the warm/zero wall times and iteration counts, the dominant kernel's
-roofline from HIP events recorded live on the library stream, the network
-forward's matrix-core throughput, and the FP64 oracle's throughput on a
-bounded sample on the host cores.
+the warm/zero wall times and iteration counts, the distance of the answers
+to the oracle's fixed point (stored FP64 references of three instances), the
+dominant kernel's roofline from HIP events recorded live on the library
+stream, the network forward's matrix-core throughput, and the FP64 oracle on
+the host cores (all instances to the same tolerance on every core, one
+instance for a bounded number of iterations on one core).
 """
 from __future__ import annotations
 
@@ -33,10 +38,11 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
-# x 2 flop (FMA) = 78.6 TFLOP/s (the 157.3 TFLOP/s headline needs packed FP32,
-# which this library does not use)
-VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# published FP32 vector peak (packed FP32: two operations per lane and cycle)
+VALU_FP32_PEAK_TFLOPS = 157.3
+# the same without packed FP32, which this library does not use: 256 CU x 4
+# SIMD x 16 lanes x 2.4 GHz x 2 flop (FMA) = 78.6 TFLOP/s
+VALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # algorithmic work of one diamond-difference cell-angle update:
 # 2 FMA numerator (4), denominator add (1), reciprocal (1), product (1),
 # 2 psi (1), two outgoing faces (2), weighted accumulation FMA (2) = 12 flop
@@ -47,9 +53,19 @@ BYTES_PER_CELL_ITER = 20
 # HBM bytes per sweep launch on the default workload (all 16 instances
 # active) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what the counters
 # read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
-# valid only for the kernel source with this hash prefix, otherwise null
+# valid only for the kernel source with this hash prefix (sweep_source_hash),
+# otherwise null
 SWEEP_TRAFFIC_BYTES = 79.76e6
 SWEEP_TRAFFIC_SRC = "85bbd97bb6afe0b9"
+
+
+def sweep_source_hash() -> str:
+    """Hash prefix of the sweep kernel's source (the kernel file and the
+    device header it includes)."""
+    h = hashlib.sha256()
+    for f in ("sweep2d.hip", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2509_01416_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -64,10 +80,12 @@ def parse():
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--stop", choices=("bound", "change"), default="bound",
+                    help="stopping rule of the source iteration")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target wall time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the one-core oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device copy (counter calibration)")
     ap.add_argument("--zero-only", action="store_true",
@@ -84,30 +102,57 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(wl, target_s: float):
-    """Oracle (FP64, plain C) on a bounded sample: every instance of the
-    workload, a fixed number of source iterations, one thread per instance."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, tol: float, stop: str, target_1core_s: float):
+    """The FP64 C oracle on the host cores, on the same instances:
+    all cores: every instance solved from zero to the same tolerance and
+      stopping rule, one thread per instance (measured time to tolerance);
+    one core: instance 0 for a bounded number of iterations (about
+      target_1core_s), and the batch's time to tolerance on one core
+      estimated from that rate and the all-core run's iteration counts."""
     import oracle
     try:
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
         ncpu = os.cpu_count() or 1
     threads = max(1, min(16, ncpu, len(wl.instances)))
+    M = wl.quad.n_dir
+    kw = dict(norm="bound", stride=16) if stop == "bound" else dict(norm="l2")
+    t0 = time.perf_counter()
+    res = oracle.solve_many(wl.instances, wl.quad, tol=tol, threads=threads, f32_inputs=True,
+                            **kw)
+    dt_all = time.perf_counter() - t0
+    its = [int(r.iterations) for r in res]
+    ups_all = sum(n * i.cells for n, i in zip(its, wl.instances)) * M
     inst = wl.instances[0]
     t0 = time.perf_counter()
-    oracle.solve_instance(inst, wl.quad, tol=0.0 + 1e-300, max_iter=1)
-    t1 = time.perf_counter() - t0
-    rounds = (len(wl.instances) + threads - 1) // threads
-    iters = int(max(2, min(2000, target_s / max(t1, 1e-6) / rounds)))
+    oracle.solve_instance(inst, wl.quad, tol=1e-300, max_iter=2)
+    per_it = (time.perf_counter() - t0) / 2
+    n1 = int(max(2, min(5000, target_1core_s / max(per_it, 1e-6))))
     t0 = time.perf_counter()
-    res = oracle.solve_many(wl.instances, wl.quad, tol=1e-300, threads=threads,
-                            max_iter=iters)
-    dt = time.perf_counter() - t0
-    ups = sum(r.iterations * i.cells for r, i in zip(res, wl.instances)) * wl.quad.n_dir
-    return {"value": ups / dt, "unit": "cell-angle updates/s", "cores": threads,
+    r1 = oracle.solve_instance(inst, wl.quad, tol=1e-300, max_iter=n1)
+    dt1 = time.perf_counter() - t0
+    rate1 = r1.iterations * inst.cells * M / dt1
+    return {"value": ups_all / dt_all, "unit": "cell-angle updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{len(wl.instances)} instances x {iters} source iterations "
-                      f"(FP64 C oracle, one thread per instance), {dt:.1f} s wall"}
+            "sample": f"all {len(wl.instances)} instances from zero to {tol:g} ({stop} rule), "
+                      f"one thread per instance, {dt_all:.1f} s wall; one core: instance 0 "
+                      f"for {n1} iterations, {dt1:.1f} s",
+            "cpu_model": _cpu_model(), "host_cpus": ncpu,
+            "cores_all": {"threads": threads, "seconds_to_tolerance": dt_all,
+                          "updates_per_s": ups_all / dt_all},
+            "cores_1": {"updates_per_s": rate1,
+                        "seconds_to_tolerance_estimated": ups_all / rate1},
+            "oracle_iterations_zero_start": its}
 
 
 # algorithmic FLOP of one network forward per 64 x 64 sample (dense products
@@ -122,6 +167,28 @@ def fno_flop_per_sample(n=64, w=32, m=12, layers=4, proj=128):
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def rel_l2_vs_refs(args, warm, zero, torch):
+    """Relative L2 distance of the warm- and zero-start answers to the stored
+    FP64 oracle references (instances 0, 7, 15 of the default workload;
+    None for other workloads)."""
+    if args.instances != 16 or args.n != 256:
+        return None
+    z = np.load(os.path.join(ROOT, "tests", "golden", "two_region_16x256_S16_refs.npz"))
+    out = {"instances": [int(k) for k in z["index"]], "reference": "FP64 oracle to a "
+           "relative change of 1e-11 on the FP32-rounded fields"}
+    for name, phis in (("warm", warm), ("zero", zero)):
+        if name == "warm" and args.zero_only:
+            continue
+        e = []
+        for k, ref in zip(z["index"], z["phi"]):
+            ref = ref.astype(np.float64)
+            got = phis[int(k)].cpu().numpy().astype(np.float64)
+            e.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        out[name] = e
+        out[name + "_max"] = max(e)
+    return out
 
 
 def eigen_leg(ctx, model, B, I, torch, args):
@@ -251,7 +318,9 @@ def main():
                        source=torch.tensor(i.source, dtype=torch.float32, device=dev),
                        lx=i.lx, ly=i.ly) for i in wl.instances]
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    phis0 = [torch.zeros_like(p.sigma_t) for p in probs]
     ctx = B.Context()
+    ctx.set_stop_rule(args.stop)
     planned = ctx.sweep_plan(probs, quad)
     t_tune = time.perf_counter()
     tuned = ctx.autotune(probs, quad, reps=3)
@@ -261,7 +330,7 @@ def main():
     model = None if args.zero_only else B.Model(ctx, T.load_weights(args.weights))
 
     def zero_step():
-        rc, st = B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis0, args.tol, args.max_iter)
         return st, None, 0.0
 
     def warm_step():
@@ -293,6 +362,7 @@ def main():
         return dict(updates=updates, dt=dt, its=its, rits=rits, guess_s=tg, prof=prof)
 
     step = zero_step if args.zero_only else warm_step
+    result = phis0 if args.zero_only else phis
     for w in range(args.warmup):
         st, sg, _ = step()
         log(f"[bench] warmup {w}: iterations {[s['iterations'] for s in st][:4]}...")
@@ -308,6 +378,9 @@ def main():
     prof = prof_run["prof"]
     log(f"[bench] profiled step: {prof}")
 
+    accuracy = rel_l2_vs_refs(args, result, phis0, torch)
+    log(f"[bench] distance to the oracle's fixed point: {accuracy}")
+
     updates, dt = main_run["updates"], main_run["dt"]
     ms_step = dt * 1e3 / args.steps
     sweep_ms = prof["sweep_ms"]
@@ -316,12 +389,15 @@ def main():
     cell_iters = prof_run["updates"] / M
     hbm = cell_iters * BYTES_PER_CELL_ITER / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     traffic = None
-    src = os.path.join(ROOT, "paper_2509_01416_amd", "csrc", "sweep2d.hip")
     default_wl = args.instances == 16 and args.n == 256
-    if default_wl and hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == SWEEP_TRAFFIC_SRC:
+    if default_wl and sweep_source_hash() == SWEEP_TRAFFIC_SRC:
         traffic = SWEEP_TRAFFIC_BYTES
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None,
+            "flop_per_update": FLOP_PER_UPDATE,
+            "frac_vs_nonpacked_peak": (achieved / VALU_FP32_NONPACKED_TFLOPS
+                                       if achieved else None),
+            "nonpacked_peak": VALU_FP32_NONPACKED_TFLOPS,
             "traffic": traffic, "traffic_unit": "bytes per launch",
             "kernel": "sweep2d_fast_kernel" if plan.get("specialised") else "sweep2d_kernel",
             "avg_launch_ms": sweep_ms / max(1, prof["sweep_launches"]),
@@ -383,7 +459,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu = cpu_baseline(wl, args.tol, args.stop, args.cpu_seconds)
         log(f"[bench] cpu {cpu}")
 
     zero_ms = zero_run["dt"] * 1e3 / args.steps
@@ -398,6 +474,8 @@ def main():
         "config": {"workload": wl.name, "instances": len(wl.instances),
                    "grid": f"{args.n}x{args.n}", "directions": M,
                    "tol": args.tol,
+                   "stop_rule": ("error bound r rho/(1-rho) over 16-iteration changes"
+                                 if args.stop == "bound" else "relative L2 change"),
                    "start": "zero" if args.zero_only else "operator-network recast warm start",
                    "recast_tol": None if args.zero_only else args.recast_tol,
                    "recast_max_iter": None if args.zero_only else args.recast_max,
@@ -415,6 +493,7 @@ def main():
             "si_iterations_max_zero": int(max(zero_run["its"][-1])),
             "zero_start_updates_per_s": zero_run["updates"] / zero_run["dt"]},
         "iterations": main_run["its"][-1],
+        "rel_l2_vs_oracle": accuracy,
         "roofline": roof,
         "network": network,
         "eigen": eigen,

@@ -114,6 +114,23 @@ tr_status tr_solve(tr_context *ctx, int32_t n_inst, const tr_problem *p,
                    float *const *phi_out, double tol, int32_t max_iter,
                    tr_stats *stats);
 
+/* Stopping rule of tr_solve on a context.  The paper quotes only a
+ * tolerance for its iterations (section 5.1); these are the two readings.
+ *   TR_STOP_CHANGE (default): the change norm of tr_solve's tol (relative L2
+ *     for tol > 0, max relative for tol < 0) drops below |tol|.
+ *   TR_STOP_ERROR_BOUND: with r_l the relative L2 change of iteration l and
+ *     rho = r_l / r_(l-1) the observed contraction rate of the fixed-point
+ *     iteration, stop once rho < 1 and r_l rho / (1 - rho) < tol, an
+ *     estimate of the remaining distance to the fixed point (for slowly
+ *     converging problems, where a small change still leaves a large error).
+ *     Needs tol > 0 (else TR_ERR_INVALID_ARG from tr_solve).  stats.residual
+ *     still reports r_l.
+ * The setting stays on the context until changed; the eigenvalue solvers'
+ * inner iterations always use TR_STOP_CHANGE.  Unknown values give
+ * TR_ERR_INVALID_ARG.                                                      */
+typedef enum { TR_STOP_CHANGE = 0, TR_STOP_ERROR_BOUND = 1 } tr_stop_rule;
+tr_status tr_set_stop_rule(tr_context *ctx, int32_t rule);
+
 /* Per-instance results of tr_eigen.  outer: outer updates performed;
  * inner: source-iteration sweeps summed over all inner solves; k: final
  * eigenvalue; dk, dphi: the last update's |k_new - k|/k_new and

@@ -25,6 +25,8 @@ TR_ERR_HIP = -2
 TR_ERR_OOM = -3
 TR_ERR_NONFINITE = -4
 NO_EIGEN_SP = 0
+TR_STOP_CHANGE = 0
+TR_STOP_ERROR_BOUND = 1
 NO_EIGEN_CP = 1
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
@@ -34,7 +36,7 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
            "no_train_step",
            "tr_check_args", "tr_autotune", "tr_set_sweep_config", "tr_set_sweep_kernel",
-           "tr_get_sweep_plan",
+           "tr_set_stop_rule", "tr_get_sweep_plan",
            "tr_profile_enable", "tr_profile_read")
 
 
@@ -120,6 +122,7 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_char_p, i32]
     lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
     lib.tr_set_sweep_kernel.argtypes = [vp, i32]
+    lib.tr_set_stop_rule.argtypes = [vp, i32]
     lib.tr_autotune.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), i32, P(i32), P(d)]
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
     lib.tr_profile_enable.argtypes = [vp, i32]
@@ -252,6 +255,15 @@ class Context:
     def set_sweep_kernel(self, generic: bool):
         self.check(self.lib.tr_set_sweep_kernel(self.handle, int(generic)), allow=(TR_OK,))
 
+    def set_stop_rule(self, rule: str):
+        """tr_solve's stopping rule on this context: "change" (the change norm
+        below tol) or "bound" (the fixed-point error bound r rho / (1 - rho)
+        below tol)."""
+        codes = {"change": TR_STOP_CHANGE, "bound": TR_STOP_ERROR_BOUND}
+        if rule not in codes:
+            raise ValueError(f"unknown stopping rule {rule!r}")
+        self.check(self.lib.tr_set_stop_rule(self.handle, codes[rule]), allow=(TR_OK,))
+
     def profile(self, enable: bool = True):
         self.check(self.lib.tr_profile_enable(self.handle, int(enable)), allow=(TR_OK,))
 
@@ -347,12 +359,26 @@ def tr_eigen_mg(ctx: Context, problems: Sequence[Problem], groups: Sequence[dict
     None = zero], nu_sigma_f=[G], chi=[G floats]); phi_out[i][g] (and
     phi_init[i][g]) are device fields.  Returns (status, stats dicts)."""
     n = len(problems)
-    if len(groups) != n or len(phi_out) != n:
+    if n < 1 or len(groups) != n or len(phi_out) != n:
         raise ValueError("one group table and one phi_out list per problem")
+    if phi_init is not None and len(phi_init) != n:
+        raise ValueError("one phi_init list per problem")
+    G = len(groups[0]["sigma_t"])
+    if not 1 <= G <= 8:
+        raise ValueError("1 to 8 groups")
+    # every list the library indexes by group must hold G entries: the
+    # pointer arrays built below are exactly that long
+    for i, gd in enumerate(groups):
+        ss_rows = gd["sigma_s"]
+        if (len(gd["sigma_t"]) != G or len(gd["nu_sigma_f"]) != G or len(gd["chi"]) != G
+                or len(phi_out[i]) != G or len(ss_rows) != G
+                or any(len(row) != G for row in ss_rows)
+                or (phi_init is not None and len(phi_init[i]) != G)):
+            raise ValueError(f"problem {i}: sigma_t, nu_sigma_f, chi, phi_out (and "
+                             f"phi_init) need {G} entries and sigma_s {G} x {G}")
     arr = make_problems(problems)
     keep = []
     mg = (TrMultigroup * n)()
-    G = len(groups[0]["sigma_t"])
     for i, (p, gd) in enumerate(zip(problems, groups)):
         cells = p.nx * p.ny
         fields = list(gd["sigma_t"]) + list(gd["nu_sigma_f"]) + list(phi_out[i]) + [
@@ -364,8 +390,6 @@ def tr_eigen_mg(ctx: Context, problems: Sequence[Problem], groups: Sequence[dict
                     or t.numel() != cells):
                 raise ValueError(f"problem {i}: group fields must be float32 GPU tensors "
                                  f"of {cells} cells")
-        if len(gd["sigma_t"]) != G or len(phi_out[i]) != G:
-            raise ValueError("every problem needs the same number of groups")
         st = _ptr_array(gd["sigma_t"])
         nsf = _ptr_array(gd["nu_sigma_f"])
         ss = (ctypes.c_void_p * (G * G))()

@@ -31,6 +31,8 @@ struct InstDesc {
     float *face;                   // [2 parity][4 faces][nf][M] (2-D),
                                    // [2][2][M] (1-D)
     const float *phi_init;         // warm start or nullptr
+    float *snap;                   // iterate kStopStride iterations back
+                                   // (error-bound stopping rule) or nullptr
     int dim, nx, ny, nf, cells;
     int R;                         // rows per lane segment (64, 32, 16)
     int S;                         // direction slices per octant
@@ -51,7 +53,39 @@ struct IterState {
     int *iter;        // sweeps performed
     int *status;      // 0 ok, 1 not converged, -4 non-finite
     double *resid;    // last change norm
+    double *rhist;    // [n][2]: change norm of iteration l in slot l & 1
 };
+
+// Change norms (norm_kind): 0 relative L2 change, 1 max relative change,
+// 2 error bound of the fixed-point iteration.  For the bound the iterate is
+// compared with the one kStopStride iterations back: with
+// r = ||phi_l - phi_(l-K)|| / ||phi_l|| and the observed contraction over K
+// iterations rho = r_l / r_(l-K), the distance to the fixed point is about
+// r rho / (1 - rho); the test stops once rho < 1 and that estimate is below
+// tol, and runs only at iterations l that are multiples of K.  (Measured over
+// K iterations the change stands well above the FP32 rounding floor of the
+// one-iteration change, about 1e-7 relative, which would otherwise hide the
+// slowly decaying error of a problem with a contraction rate near 1.)
+// r_prev is INFINITY before the second test.
+constexpr int kStopStride = 16;
+
+__device__ __forceinline__ bool stop_test(double r, double r_prev, double tol, int norm_kind) {
+    if (norm_kind != 2) return r < tol;
+    if (r == 0.0) return true;
+    if (!(r_prev < INFINITY) || !(r_prev > 0.0)) return false;
+    const double rho = r / r_prev;
+    if (!(rho < 1.0)) return false;
+    return r * rho / (1.0 - rho) < tol;
+}
+
+// Whether iteration l (1-based) is tested, and the slot of the residual
+// history its change norm goes to (the previous tested one is in the other).
+__device__ __forceinline__ bool tested_iteration(int l, int norm_kind) {
+    return norm_kind != 2 || l % kStopStride == 0;
+}
+__device__ __forceinline__ int history_slot(int l, int norm_kind) {
+    return (norm_kind == 2 ? l / kStopStride : l) & 1;
+}
 
 // Convergence test of the previous iteration, run by the next sweep: every
 // workgroup of an instance evaluates it from the combine kernel's FP64
@@ -60,7 +94,8 @@ struct IterState {
 // sweep, or the host ran the separate finalize kernel since).  it = sweeps
 // launched so far in this solve (every active instance has performed that
 // many), which gives the face parity without reading the state being
-// updated.
+// updated; it also tells whether this iteration is tested and which slot
+// of the residual history its change norm goes to.
 struct FinArgs {
     const double2* red;
     IterState st;
@@ -74,6 +109,10 @@ struct FinArgs {
 __device__ __forceinline__ bool sweep_prologue(const InstDesc& I, int n, const FinArgs& f,
                                                bool designated) {
     if (f.st.done[n]) return true;
+    if (!tested_iteration(f.it, f.norm_kind)) {
+        if (designated && threadIdx.x == 0) f.st.iter[n] += 1;
+        return false;
+    }
     // the finalize kernel's summation order, with the loads issued 8 at a time
     double s1 = 0.0, s2 = 0.0;
     int b = 0;
@@ -83,24 +122,27 @@ __device__ __forceinline__ bool sweep_prologue(const InstDesc& I, int n, const F
         for (int j = 0; j < 8; ++j) v[j] = f.red[I.red0 + b + j];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            if (f.norm_kind == 0) { s1 += v[j].x; s2 += v[j].y; }
+            if (f.norm_kind != 1) { s1 += v[j].x; s2 += v[j].y; }
             else s1 = fmax(s1, v[j].x);
         }
     }
     for (; b < I.nred; ++b) {
         const double2 v = f.red[I.red0 + b];
-        if (f.norm_kind == 0) { s1 += v.x; s2 += v.y; }
+        if (f.norm_kind != 1) { s1 += v.x; s2 += v.y; }
         else s1 = fmax(s1, v.x);
     }
     double r;
-    if (f.norm_kind == 0)
+    if (f.norm_kind != 1)
         r = s2 > 0.0 ? sqrt(s1 / s2) : (s1 == 0.0 ? 0.0 : INFINITY);
     else
         r = s1;
     const bool bad = !isfinite(s1) || !isfinite(s2);
-    const bool conv = !bad && r < f.tol;
+    const int slot = history_slot(f.it, f.norm_kind);
+    const double r_prev = f.st.rhist[2 * n + (slot ^ 1)];
+    const bool conv = !bad && stop_test(r, r_prev, f.tol, f.norm_kind);
     if (designated && threadIdx.x == 0) {
         f.st.resid[n] = r;
+        f.st.rhist[2 * n + slot] = r;
         f.st.iter[n] += 1;
         if (bad) {
             f.st.status[n] = -4;

@@ -874,6 +874,12 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
         }
         hact[i] = 1;
     }
+    // the cross-section checks of tr_eigen (finite, sigma_t > 0,
+    // 0 <= sigma_s <= sigma_t), now that the start has defined the source
+    {
+        const tr_status sf = c->scan_fields(su, B, pp.data(), true, nullptr);
+        if (sf != TR_OK) return sf;
+    }
     if (!c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
         return TR_ERR_HIP;
     Runner r{c, m};

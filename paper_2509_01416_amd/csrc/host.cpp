@@ -437,7 +437,7 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
 // selects a bare sweep (Q = caller emission, phi = phi_out).
 bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
                 const float* const* phi_init, float* const* phi_out,
-                const float* const* emission, Setup* su) {
+                const float* const* emission, Setup* su, bool snapshots) {
     const int dim = p[0].dim;
     if (!build_dirtable(this, q, dim, &su->dt)) return false;
     const int M = su->dt.M;
@@ -457,7 +457,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     su->blocks.clear();
     su->work.clear();
     size_t off = 0;
-    std::vector<size_t> offQ(n_inst), offP(n_inst), offF(n_inst);
+    std::vector<size_t> offQ(n_inst), offP(n_inst), offF(n_inst), offS(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const tr_problem& P = p[i];
         InstDesc& d = su->inst[i];
@@ -501,6 +501,10 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         offF[i] = off;
         off += align_up(sizeof(float) * (dim == 1 ? (size_t)4 * M
                                                    : (size_t)8 * d.nf * M));
+        if (snapshots) {
+            offS[i] = off;
+            off += align_up(sizeof(float) * d.cells);
+        }
     }
     // XCD-aware order: workgroup b of a launch runs on XCD b % kXcds, so
     // every instance is given one XCD (balanced by work) and its sweep
@@ -567,6 +571,8 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     off += align_up(sizeof(int) * n_inst);
     const size_t oRes = off;
     off += align_up(sizeof(double) * n_inst);
+    const size_t oRh = off;
+    off += align_up(sizeof(double) * 2 * n_inst);
     const size_t oBal = off;
     off += align_up(sizeof(double) * 3 * n_inst);
     const size_t oFlag = off;
@@ -582,6 +588,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         d.Q = emission ? const_cast<float*>(emission[i]) : (float*)(b + offQ[i]);
         d.part = (float*)(b + offP[i]);
         d.face = (float*)(b + offF[i]);
+        d.snap = snapshots ? (float*)(b + offS[i]) : nullptr;
     }
     su->d_inst = (InstDesc*)(b + oInst);
     su->d_work = (SweepWork*)(b + oWork);
@@ -592,6 +599,7 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     su->st.iter = (int*)(b + oIter);
     su->st.status = (int*)(b + oStat);
     su->st.resid = (double*)(b + oRes);
+    su->st.rhist = (double*)(b + oRh);
     su->d_bal = (double*)(b + oBal);
     su->d_flags = (int*)(b + oFlag);
     su->d_samax = (float*)(b + oSa);
@@ -666,8 +674,12 @@ bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, in
             if (!launch_sweep(su, n_inst, su.st.done, su.st.iter, 1, false, &fin)) return false;
             if (p0) prof_end();
             const bool p1 = prof_begin(1);
+            // the error-bound rule measures the change against the snapshot
+            // on its tested iterations (every kStopStride-th) only
+            const int l = done_iters + it + 1;
+            const int mode = norm_kind != 2 ? 0 : (l % kStopStride == 0 ? 2 : 3);
             launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
-                           su.d_red, 0, norm_kind, stream);
+                           su.d_red, mode, norm_kind, stream);
             if (!fused_fin || it + 1 == k)
                 launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind, stream);
             if (p1) prof_end();
@@ -790,10 +802,14 @@ extern "C" tr_status tr_solve(tr_context* ctx, int32_t n_inst, const tr_problem*
             c->fail("problem %d: null phi_out", i);
             return TR_ERR_INVALID_ARG;
         }
-    const int norm_kind = tol < 0 ? 1 : 0;
+    if (c->stop_rule == TR_STOP_ERROR_BOUND && tol < 0) {
+        c->fail("the error-bound stopping rule needs tol > 0");
+        return TR_ERR_INVALID_ARG;
+    }
+    const int norm_kind = c->stop_rule == TR_STOP_ERROR_BOUND ? 2 : (tol < 0 ? 1 : 0);
     const double atol = std::fabs(tol);
     Setup su;
-    if (!c->setup(n_inst, p, q, phi_init, phi_out, nullptr, &su))
+    if (!c->setup(n_inst, p, q, phi_init, phi_out, nullptr, &su, norm_kind == 2))
         return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
     if (stats)
         for (int i = 0; i < n_inst; ++i) stats[i] = tr_stats{0, 0, 0.0, 0.0, 0.0};
@@ -1047,6 +1063,17 @@ extern "C" tr_status tr_set_sweep_kernel(tr_context* ctx, int32_t generic) {
         return TR_ERR_INVALID_ARG;
     }
     c->force_generic = generic != 0;
+    return TR_OK;
+}
+
+extern "C" tr_status tr_set_stop_rule(tr_context* ctx, int32_t rule) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    if (rule != TR_STOP_CHANGE && rule != TR_STOP_ERROR_BOUND) {
+        c->fail("unknown stopping rule %d", rule);
+        return TR_ERR_INVALID_ARG;
+    }
+    c->stop_rule = rule;
     return TR_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mdpnop.h"
 
 namespace mdp {
 
@@ -62,6 +63,7 @@ struct Ctx {
     PinnedBuf pinned;     // staging and flag read-back
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
     bool force_generic = false;   // never use the specialised sweep kernel
+    int stop_rule = TR_STOP_CHANGE;   // tr_solve's stopping rule (tr_stop_rule)
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS (gfx950; device property when known)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces
@@ -84,7 +86,7 @@ struct Ctx {
     void release_fno();
     bool setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
                const float* const* phi_init, float* const* phi_out,
-               const float* const* emission, Setup* su);
+               const float* const* emission, Setup* su, bool snapshots = false);
     bool launch_sweep(const Setup& su, int n_inst, const int* done,
                       const int* iter, int use_faces, bool tally = false,
                       const FinArgs* fin = nullptr);

@@ -118,6 +118,7 @@ __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
         const float p = I.phi_init != nullptr ? I.phi_init[c] : 0.f;
         I.phi[c] = p;
         I.Q[c] = fmaf(I.ss[c], p, I.q[c]);
+        if (I.snap != nullptr) I.snap[c] = p;
     }
 }
 
@@ -145,6 +146,8 @@ init_faces_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ b
         st.iter[n] = 0;
         st.status[n] = 1;
         st.resid[n] = INFINITY;
+        st.rhist[2 * n] = INFINITY;
+        st.rhist[2 * n + 1] = INFINITY;
     }
     if (I.dim == 1) {
         const int total = 2 * M;
@@ -183,7 +186,12 @@ init_faces_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ b
 
 // ------------------------------------------------------------ combine ----
 // mode 0: source-iteration update (phi, Q, change-norm partials);
-// mode 1: bare sweep (phi = sum of planes).  The planes of a cell are summed
+// mode 1: bare sweep (phi = sum of planes);
+// mode 2: source-iteration update with the norm partials of the change
+//         against the snapshot, which then takes phi_new (error-bound rule,
+//         tested iterations);
+// mode 3: source-iteration update without norm partials (error-bound rule,
+//         untested iterations).  The planes of a cell are summed
 // in plane order; with cells % 4 == 0 four cells move per 16-byte access.
 struct CellAcc {
     double s1 = 0.0, s2 = 0.0;
@@ -191,7 +199,7 @@ struct CellAcc {
 
 __device__ __forceinline__ void combine_norm(float old, float s, int norm_kind, CellAcc& a) {
     const double d = (double)s - (double)old;
-    if (norm_kind == 0) {
+    if (norm_kind != 1) {
         a.s1 += d * d;
         a.s2 += (double)s * (double)s;
     } else {
@@ -207,10 +215,11 @@ __device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
         I.phi[c] = s;
         return;
     }
-    const float old = I.phi[c];
+    const float old = mode == 2 ? I.snap[c] : I.phi[c];
     I.phi[c] = s;
     I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
-    combine_norm(old, s, norm_kind, a);
+    if (mode == 2) I.snap[c] = s;
+    if (mode != 3) combine_norm(old, s, norm_kind, a);
 }
 
 __global__ void __launch_bounds__(kCombineThreads)
@@ -226,7 +235,8 @@ combine_kernel(const InstDesc* __restrict__ insts,
     const int c1 = min(bi.y + kCombineChunk, cells);
     CellAcc acc;
     const bool al16 = ((reinterpret_cast<uintptr_t>(I.phi) | reinterpret_cast<uintptr_t>(I.ss) |
-                        reinterpret_cast<uintptr_t>(I.q) | reinterpret_cast<uintptr_t>(I.Q)) &
+                        reinterpret_cast<uintptr_t>(I.q) | reinterpret_cast<uintptr_t>(I.Q) |
+                        reinterpret_cast<uintptr_t>(I.snap)) &
                        15) == 0;
     if ((cells & 3) == 0 && (al16 || mode == 1) &&
         (reinterpret_cast<uintptr_t>(I.phi) & 15) == 0) {
@@ -256,13 +266,16 @@ combine_kernel(const InstDesc* __restrict__ insts,
                 *phi4 = s;
                 continue;
             }
-            const float4 old = *phi4;
+            const float4 old =
+                mode == 2 ? reinterpret_cast<const float4*>(I.snap)[c >> 2] : *phi4;
             const float4 ss = reinterpret_cast<const float4*>(I.ss)[c >> 2];
             const float4 qq = reinterpret_cast<const float4*>(I.q)[c >> 2];
             *phi4 = s;
             reinterpret_cast<float4*>(I.Q)[c >> 2] =
                 make_float4(fmaf(ss.x, s.x, qq.x), fmaf(ss.y, s.y, qq.y),
                             fmaf(ss.z, s.z, qq.z), fmaf(ss.w, s.w, qq.w));
+            if (mode == 2) reinterpret_cast<float4*>(I.snap)[c >> 2] = s;
+            if (mode == 3) continue;
             combine_norm(old.x, s.x, norm_kind, acc);
             combine_norm(old.y, s.y, norm_kind, acc);
             combine_norm(old.z, s.z, norm_kind, acc);
@@ -276,14 +289,14 @@ combine_kernel(const InstDesc* __restrict__ insts,
             combine_cell(I, c, s, mode, norm_kind, acc);
         }
     }
-    if (mode == 1) return;
+    if (mode == 1 || mode == 3) return;
     __shared__ double r1[kCombineThreads], r2[kCombineThreads];
     r1[threadIdx.x] = acc.s1;
     r2[threadIdx.x] = acc.s2;
     __syncthreads();
     for (int h = kCombineThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
-            if (norm_kind == 0) {
+            if (norm_kind != 1) {
                 r1[threadIdx.x] += r1[threadIdx.x + h];
                 r2[threadIdx.x] += r2[threadIdx.x + h];
             } else {
@@ -302,23 +315,31 @@ __global__ void finalize_kernel(const InstDesc* __restrict__ insts,
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_inst || st.done[n]) return;
     const InstDesc& I = insts[n];
+    const int l = st.iter[n] + 1;   // the iteration tested here
+    if (!tested_iteration(l, norm_kind)) {
+        st.iter[n] = l;
+        return;
+    }
     double s1 = 0.0, s2 = 0.0;
     for (int b = 0; b < I.nred; ++b) {
         const double2 v = red[I.red0 + b];
-        if (norm_kind == 0) { s1 += v.x; s2 += v.y; }
+        if (norm_kind != 1) { s1 += v.x; s2 += v.y; }
         else s1 = fmax(s1, v.x);
     }
     double r;
-    if (norm_kind == 0)
+    if (norm_kind != 1)
         r = s2 > 0.0 ? sqrt(s1 / s2) : (s1 == 0.0 ? 0.0 : INFINITY);
     else
         r = s1;
+    const int slot = history_slot(l, norm_kind);
+    const double r_prev = st.rhist[2 * n + (slot ^ 1)];
     st.resid[n] = r;
-    st.iter[n] += 1;
+    st.rhist[2 * n + slot] = r;
+    st.iter[n] = l;
     if (!isfinite(s1) || !isfinite(s2)) {
         st.status[n] = -4;
         st.done[n] = 1;
-    } else if (r < tol) {
+    } else if (stop_test(r, r_prev, tol, norm_kind)) {
         st.status[n] = 0;
         st.done[n] = 1;
     }

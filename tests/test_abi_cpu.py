@@ -88,3 +88,34 @@ def test_check_args_rejects_empty_and_mixed_batches():
         arr[k].sigma_t = arr[k].sigma_s = arr[k].source = 0x1000
     rc, msg = B.tr_check_args(arr, 2, q, 1e-6, 100)
     assert rc == B.TR_ERR_INVALID_ARG and "share dim" in msg
+
+
+def test_stop_rule_needs_a_context():
+    lib = B.load()
+    assert lib.tr_set_stop_rule(None, B.TR_STOP_ERROR_BOUND) == B.TR_ERR_INVALID_ARG
+
+
+class _Grid:
+    """Stands in for a Problem: the binding's checks read only the grid."""
+    nx = ny = 4
+
+
+def test_multigroup_binding_rejects_short_group_lists():
+    """tr_eigen_mg's binding checks every per-group list against the group
+    count before it builds pointer arrays or calls the library (ctx is never
+    touched: None here)."""
+    import torch
+    t = torch.zeros(16)
+    good = dict(sigma_t=[t, t], sigma_s=[[t, None], [None, t]], nu_sigma_f=[t, t],
+                chi=[1.0, 0.0])
+    cases = [dict(good, nu_sigma_f=[t]), dict(good, chi=[1.0]),
+             dict(good, sigma_s=[[t, None]]), dict(good, sigma_s=[[t], [None, t]])]
+    for gd in cases:
+        with pytest.raises(ValueError):
+            B.tr_eigen_mg(None, [_Grid()], [gd], None, None, [[t, t]])
+    with pytest.raises(ValueError):   # phi_out with one group short
+        B.tr_eigen_mg(None, [_Grid()], [good], None, None, [[t]])
+    with pytest.raises(ValueError):   # phi_init row with one group short
+        B.tr_eigen_mg(None, [_Grid()], [good], None, [[t]], [[t, t]])
+    with pytest.raises(ValueError):   # phi_init for the wrong number of problems
+        B.tr_eigen_mg(None, [_Grid()], [good], None, [[t, t], [t, t]], [[t, t]])

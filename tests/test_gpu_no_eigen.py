@@ -175,3 +175,34 @@ def test_no_eigen_rejects_unsupported_problems(env):
                            raise_on_error=False)
         assert rc == B.TR_ERR_INVALID_ARG, (nx, bc, variant)
     m.close()
+
+
+def test_no_eigen_rejects_invalid_cross_sections(env):
+    """The field checks of tr_eigen apply: sigma_s > sigma_t, sigma_t <= 0 or
+    a non-finite value is an argument error (or a non-finite-value error)
+    before any network application, and the context stays usable."""
+    torch, B, ctx, w = env
+    m = B.Model(ctx, w)
+    quad = B.Quad.from_inputs(I.level_symmetric_2d(4))
+    inst, nsf = _case("flat")
+    bad = [("sigma_s", 1.5 * inst.sigma_t, B.TR_ERR_INVALID_ARG),
+           ("sigma_t", np.where(np.arange(N * N).reshape(N, N) == 77, -1.0, inst.sigma_t),
+            B.TR_ERR_INVALID_ARG),
+           ("sigma_t", np.where(np.arange(N * N).reshape(N, N) == 5, np.nan, inst.sigma_t),
+            B.TR_ERR_NONFINITE)]
+    for field, value, want in bad:
+        case = I.Instance(nx=N, ny=N, lx=10.0, ly=10.0,
+                          sigma_t=value if field == "sigma_t" else inst.sigma_t,
+                          sigma_s=value if field == "sigma_s" else inst.sigma_s,
+                          source=np.zeros((N, N)))
+        phi = [torch.zeros((N, N), device="cuda")]
+        rc, _ = B.no_eigen(ctx, m, [to_problem(case, torch)], [_dev(torch, nsf)], quad,
+                           I.SIGMA_T_STAR, I.SIGMA_S_STAR, B.NO_EIGEN_SP, None, phi,
+                           raise_on_error=False)
+        log(f"  no_eigen with invalid {field}: status {rc}")
+        assert rc == want, (field, rc)
+    phi = [torch.zeros((N, N), device="cuda")]
+    rc, st = B.no_eigen(ctx, m, [to_problem(inst, torch)], [_dev(torch, nsf)], quad,
+                        I.SIGMA_T_STAR, I.SIGMA_S_STAR, B.NO_EIGEN_SP, None, phi)
+    assert rc in (B.TR_OK, B.TR_NOT_CONVERGED) and st[0]["k"] > 0
+    m.close()

@@ -2,13 +2,24 @@
 
 Every call goes through the C ABI (libmdpnop.so via the ctypes binding).
 Tolerances:
-  * one sweep in FP32: each cell update is a handful of fused operations
-    (relative rounding <= ~4 eps32 per cell) and a face flux is carried along
-    at most nx + ny cells with gain <= 1 per cell, so the error relative to
-    max|phi| is bounded by ~4 eps32 (nx + ny); the tests use that bound;
-  * converged source iteration: FP32 fixed point within eps32 / (1 - rho)
-    of the FP64 one; the bar is 1e-5 relative L2 (the library's stated
-    accuracy target) against the oracle run to 1e-13.
+  * one sweep in FP32, relative to max|phi|: 2e-6.  A cell update is six
+    rounded operations (two fused multiply-adds, the denominator, the
+    hardware reciprocal of about 1 ulp, the product, the outgoing faces),
+    i.e. at most about 4 eps32 = 2.4e-7 relative; the faces carry it
+    downwind with a diamond-difference gain below 1 per cell, and the
+    scalar flux sums at most a few hundred weighted terms in a fixed order.
+    Rounding errors of different cells do not align, and the worst case
+    seen over every test grid (up to 16 x 256^2 S16 and a 32768-cell row)
+    is 6.5e-7; the bar is three times that.  (The worst case if every
+    rounding did align, 4 eps32 (nx + ny), is 1.2e-4 at 256^2 and would not
+    catch a regression.)
+  * converged source iteration: 1e-5 relative L2 (the library's stated
+    accuracy target) against the oracle run to 1e-12 or tighter.  The FP32
+    fixed point lies within about a few eps32 / (1 - c) of the FP64 one
+    (coherent rounding in smooth regions acts like a bias that the
+    iteration amplifies by 1 / (1 - c)): 3e-6 to 7e-6 at c = 0.99.  Where
+    the plain 1e-6 change rule would stop farther than that from the fixed
+    point (c near 1), the solves use the error-bound rule.
 """
 import numpy as np
 import pytest
@@ -20,6 +31,7 @@ from paper_2509_01416_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 EPS32 = 2.0 ** -24
+SWEEP_BAR = 2e-6
 
 
 @pytest.fixture(scope="module")
@@ -47,9 +59,8 @@ def _sweep_case(env, insts, quad):
                              quad.eta, quad.w, inst.sigma_t.astype(np.float32),
                              q.astype(np.float32))
         e = rel_inf(o.cpu().numpy(), ref)
-        bound = 4 * EPS32 * (inst.nx + inst.ny) + 8 * EPS32
-        log(f"  sweep {inst.nx}x{inst.ny} M={quad.n_dir}: rel_inf={e:.3e} bound={bound:.3e}")
-        assert e <= bound
+        log(f"  sweep {inst.nx}x{inst.ny} M={quad.n_dir}: rel_inf={e:.3e} bar={SWEEP_BAR:.1e}")
+        assert e <= SWEEP_BAR
         worst = max(worst, e)
     return worst
 
@@ -152,14 +163,14 @@ def test_sinusoid_128_full(env):
 
 def test_batched_uneven_256_full(env):
     """The 256-instance uneven batch (sides 32..128, 4x4-block sigma_t,
-    c in [0.5, 0.95], S8) in one batched solve: every instance converges with
-    particle balance < 1e-4, and sampled instances (one per side length, the
-    smallest and the largest side included) match the FP64 oracle run under
-    the same stopping rule (relative change 1e-6) within 1e-5 relative L2,
-    in the same number of iterations (+-2).  Against the oracle run to 1e-12
-    the distance is the stopping error r rho / (1 - rho) of source
-    iteration, which for the slowest instances (c near 0.95, rho near 0.95)
-    reaches ~2e-5; it is bounded here by 20 x the tolerance."""
+    c in [0.5, 0.95], S8) in one batched solve under the error-bound rule
+    (tol 1e-6, tested every 16 iterations): every instance converges with
+    particle balance < 1e-4; sampled instances (one per side length, and
+    the three that need the most iterations) lie within 1e-5 relative L2 of
+    the oracle's fixed point (oracle run to a relative change of 1e-12) and
+    stop within one test stride of the oracle run under the same rule.  The
+    plain 1e-6 change rule would leave the slowest instances about 2e-5 from
+    the fixed point."""
     import time
     torch, B, ctx = env
     wl = I.batched_uneven(256)
@@ -167,32 +178,37 @@ def test_batched_uneven_256_full(env):
     quad = B.Quad.from_inputs(wl.quad)
     phis = [torch.zeros_like(p.sigma_t) for p in probs]
     plan = ctx.sweep_plan(probs, quad)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, st = B.tr_solve(ctx, probs, quad, None, phis, wl.tol, 5000)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    ctx.set_stop_rule("bound")
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis, wl.tol, 5000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        ctx.set_stop_rule("change")
     its = np.array([s["iterations"] for s in st])
     ups = sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * wl.quad.n_dir
     log(f"  256 uneven: plan {plan}, iterations {its.min()}..{its.max()}, {dt*1e3:.1f} ms, "
         f"{ups / dt:.3e} cell-angle updates/s")
     assert rc == B.TR_OK
+    assert np.all(its % 16 == 0)
     assert max(s["balance_rel"] for s in st) < 1e-4
     picked = {}
     for k, inst in enumerate(wl.instances):
         picked.setdefault(inst.nx, k)
-    for n, k in sorted(picked.items()):
+    sample = sorted(set(picked.values()) | set(np.argsort(-its)[:3].tolist()))
+    for k in sample:
         inst = wl.instances[k]
-        same = oracle.solve_instance(inst, wl.quad, tol=wl.tol)
-        tight = oracle.solve_instance(inst, wl.quad, tol=1e-12)
+        same = oracle.solve_instance(inst, wl.quad, tol=wl.tol, norm="bound", stride=16,
+                                     f32_inputs=True)
+        tight = oracle.solve_instance(inst, wl.quad, tol=1e-12, f32_inputs=True)
         got = phis[k].cpu().numpy()
-        e = rel_l2(got, same.phi)
         et = rel_l2(got, tight.phi)
-        log(f"  instance {k} ({n}^2): {its[k]} iterations (oracle {same.iterations}), "
-            f"rel_l2 vs oracle at 1e-6 {e:.2e}, vs oracle at 1e-12 {et:.2e}")
-        assert abs(int(its[k]) - same.iterations) <= 2
-        assert e < 1e-5
-        assert et < 20 * wl.tol
+        log(f"  instance {k} ({inst.nx}^2): {its[k]} iterations (oracle, same rule: "
+            f"{same.iterations}), rel_l2 vs the oracle's fixed point {et:.2e}")
+        assert abs(int(its[k]) - same.iterations) <= 16
+        assert et < 1e-5
 
 
 def test_autotune_picks_a_valid_shape(env):
@@ -330,16 +346,28 @@ def test_not_converged_and_errors(env):
     assert e.value.status == B.TR_ERR_INVALID_ARG
 
 
+def _two_region_refs():
+    """FP64 oracle solutions of instances 0, 7 and 15 of the benchmark batch
+    (fields rounded to FP32, relative change 1e-11), written by
+    tests/golden/make_two_region_refs.py."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "two_region_16x256_S16_refs.npz")
+    z = np.load(path)
+    return [int(k) for k in z["index"]], z["phi"].astype(np.float64), z["iters_1e6"]
+
+
 @pytest.mark.parametrize("W", [9, 10])
 def test_full_batch_in_benchmark_launch_shapes(env, W):
     """The benchmark batch itself (16 instances of 256 x 256, S16, c = 0.99,
     two-region sigma_t) in the launch shapes the autotuner picks for it
     (D = 1, W = 9 or 10 waves, S = 4 slices, 64-row segments, KB = 16): one
     sweep of a seeded emission matches the oracle's sweep in every cell of
-    every instance; a zero-start solve to 1e-6 closes the particle balance of
-    every instance, and sampled instances (first, middle, last) are fixed
-    points of one FP64 oracle sweep to within what the stopping rule
-    leaves."""
+    every instance; a zero-start solve under the error-bound rule (tol 1e-6)
+    closes the particle balance of every instance, and the sampled
+    instances 0, 7 and 15 lie within 1e-5 relative L2 of the oracle's fixed
+    point (the stored tight references).  With the contraction rate near
+    0.985 the plain 1e-6 change rule leaves about 7e-5."""
     torch, B, ctx = env
     log(f"[tr_sweep/tr_solve] benchmark batch 16 x 256^2 S16, W={W}")
     wl = I.hard_two_region(16, 256)
@@ -347,31 +375,43 @@ def test_full_batch_in_benchmark_launch_shapes(env, W):
     probs = [to_problem(i, torch) for i in wl.instances]
     q = B.Quad.from_inputs(quad)
     ctx.set_sweep_config(1, W, 4, 64)
+    ctx.set_stop_rule("bound")
     try:
         plan = ctx.sweep_plan(probs, q)
         assert plan == dict(D=1, W=W, S=4, R=64, KB=16, specialised=1)
         _sweep_case(env, wl.instances, quad)
         phis = [torch.zeros_like(p.sigma_t) for p in probs]
-        rc, st = B.tr_solve(ctx, probs, q, None, phis, 1e-6, 2000)
+        rc, st = B.tr_solve(ctx, probs, q, None, phis, 1e-6, 3000)
         torch.cuda.synchronize()
     finally:
         ctx.set_sweep_config(0, 0, 0, 0)
+        ctx.set_stop_rule("change")
     assert rc == B.TR_OK
     its = [s["iterations"] for s in st]
     worst_bal = max(s["balance_rel"] for s in st)
     log(f"  iterations {min(its)}..{max(its)}, worst balance {worst_bal:.2e}")
     assert worst_bal < 1e-4
-    for k in (0, 7, 15):
-        inst = wl.instances[k]
-        phi = phis[k].cpu().numpy().astype(np.float64)
-        st64 = np.asarray(inst.sigma_t, np.float32).astype(np.float64)
-        ss64 = np.asarray(inst.sigma_s, np.float32).astype(np.float64)
-        q64 = np.asarray(inst.source, np.float32).astype(np.float64)
-        nxt = oracle.sweep2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
-                             st64, ss64 * phi + q64)
-        r = rel_l2(nxt, phi)
-        log(f"  instance {k}: {its[k]} iterations, one FP64 oracle sweep changes it by {r:.2e}")
-        assert r < 5e-6
+    index, refs, _ = _two_region_refs()
+    for k, ref in zip(index, refs):
+        e = rel_l2(phis[k].cpu().numpy(), ref)
+        log(f"  instance {k}: {its[k]} iterations, rel_l2 vs the oracle's fixed point {e:.2e}")
+        assert e < 1e-5
+
+
+def test_full_batch_change_rule_iterations(env):
+    """Zero start under the plain change rule (1e-6) on the benchmark batch:
+    every instance stops within two iterations of the oracle's count under
+    the same rule (stored with the references)."""
+    torch, B, ctx = env
+    wl = I.hard_two_region(16, 256)
+    probs = [to_problem(i, torch) for i in wl.instances]
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    rc, st = B.tr_solve(ctx, probs, B.Quad.from_inputs(wl.quad), None, phis, 1e-6, 3000)
+    _, _, iters = _two_region_refs()
+    its = np.array([s["iterations"] for s in st])
+    log(f"  change rule: GPU {its.tolist()}, oracle {iters.tolist()}")
+    assert rc == B.TR_OK
+    assert np.all(np.abs(its - iters) <= 2)
 
 
 def test_widest_grid_of_the_specialised_kernel(env):
@@ -432,7 +472,7 @@ def _paper_1d_batch():
 
 def test_paper_1d_setting_sweep(env):
     """One batched 1-D sweep of a seeded emission against the oracle's sweep,
-    element by element (bound as for the 2-D sweep with ny = 1)."""
+    element by element (the bar of the 2-D sweep)."""
     torch, B, ctx = env
     insts, quad = _paper_1d_batch()
     probs = [to_problem(i, torch) for i in insts]
@@ -446,9 +486,8 @@ def test_paper_1d_setting_sweep(env):
         ref = oracle.sweep1d(inst.nx, inst.lx, quad.mu, quad.w,
                              inst.sigma_t.astype(np.float32), q.astype(np.float32))
         e = rel_inf(o.cpu().numpy(), ref)
-        bound = 4 * EPS32 * (inst.nx + 1) + 8 * EPS32
-        log(f"  1-D sweep {inst.nx} cells S32: rel_inf={e:.3e} bound={bound:.3e}")
-        assert e <= bound
+        log(f"  1-D sweep {inst.nx} cells S32: rel_inf={e:.3e} bar={SWEEP_BAR:.1e}")
+        assert e <= SWEEP_BAR
 
 
 def test_paper_1d_setting_solve(env):
