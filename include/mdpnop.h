@@ -114,6 +114,27 @@ tr_status tr_solve(tr_context *ctx, int32_t n_inst, const tr_problem *p,
                    float *const *phi_out, double tol, int32_t max_iter,
                    tr_stats *stats);
 
+/*
+ * tr_solve without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Arguments, results, kernels and launch shapes are those of
+ * tr_solve (same answers bit for bit).  Every device workspace of the call
+ * lives in one fixed device array of 128 MiB compiled into the library, of
+ * which each device holds its own copy until the process ends; the host
+ * staging area (2 MiB) is allocated with the context.  The call allocates
+ * nothing, on the device or the host; a problem set whose workspace (about
+ * 4 * (4 * S + 2) * cells bytes per problem plus its boundary faces and
+ * tables; about 90 MB for 16 problems of 256 x 256 at S16) exceeds the array, or
+ * whose tables exceed the staging area, is rejected with
+ * TR_ERR_INVALID_ARG before anything is launched.  All calls on one device
+ * share the array (it keeps the last call's contents; the call initialises
+ * everything it reads): calls that overlap on one device, from any context
+ * or thread, race.  Kernel timing (tr_profile_enable) is not recorded.     */
+tr_status tr_solve_noalloc(tr_context *ctx, int32_t n_inst, const tr_problem *p,
+                           const tr_quadrature *q, const float *const *phi_init,
+                           float *const *phi_out, double tol, int32_t max_iter,
+                           tr_stats *stats);
+
 /* Stopping rule of tr_solve on a context.  The paper quotes only a
  * tolerance for its iterations (section 5.1); these are the two readings.
  *   TR_STOP_CHANGE (default): the change norm of tr_solve's tol (relative L2

@@ -30,7 +30,7 @@ TR_STOP_ERROR_BOUND = 1
 NO_EIGEN_CP = 1
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
-           "tr_sweep", "tr_solve", "tr_eigen", "tr_eigen_mg", "no_recast_guess", "no_eigen",
+           "tr_sweep", "tr_solve", "tr_solve_noalloc", "tr_eigen", "tr_eigen_mg", "no_recast_guess", "no_eigen",
            "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_set_fp32", "no_forward",
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.tr_sweep.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(vp), P(vp)]
     lib.tr_solve.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(vp), P(vp),
                              d, i32, P(TrStats)]
+    lib.tr_solve_noalloc.argtypes = lib.tr_solve.argtypes
     lib.no_recast_guess.argtypes = [vp, vp, i32, P(TrProblem), d, d, d, i32, P(vp),
                                     P(TrStats)]
     lib.no_eigen.argtypes = [vp, vp, i32, P(TrProblem), P(vp), P(TrQuadrature), d, d, i32,
@@ -298,14 +299,16 @@ def tr_sweep(ctx: Context, problems: Sequence[Problem], quad: Quad,
 
 def tr_solve(ctx: Context, problems: Sequence[Problem], quad: Quad,
              phi_init: Optional[Sequence], phi_out: Sequence, tol: float,
-             max_iter: int, raise_on_error: bool = True):
-    """Returns (status, list of per-instance stats dicts)."""
+             max_iter: int, raise_on_error: bool = True, noalloc: bool = False):
+    """Returns (status, list of per-instance stats dicts).  noalloc: call
+    tr_solve_noalloc (workspaces in the library's fixed device scratch)."""
     n = len(problems)
     arr = make_problems(problems)
     stats = (TrStats * n)()
     init = None if phi_init is None else _ptr_array(phi_init)
-    rc = ctx.lib.tr_solve(ctx.handle, n, arr, ctypes.byref(quad.struct), init,
-                          _ptr_array(phi_out), float(tol), int(max_iter), stats)
+    fn = ctx.lib.tr_solve_noalloc if noalloc else ctx.lib.tr_solve
+    rc = fn(ctx.handle, n, arr, ctypes.byref(quad.struct), init,
+            _ptr_array(phi_out), float(tol), int(max_iter), stats)
     if raise_on_error:
         ctx.check(rc)
     return rc, [dict(status=s.status, iterations=s.iterations,

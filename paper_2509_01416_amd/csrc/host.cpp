@@ -69,6 +69,10 @@ bool Ctx::hip_ok(hipError_t e, const char* what) {
 // Grow-only device arena; sub-allocations are 256-byte aligned.
 bool Arena::reserve(Ctx* c, size_t bytes) {
     if (bytes <= cap) return true;
+    if (fixed) {
+        c->fail("workspace of %zu bytes exceeds the fixed scratch of %zu bytes", bytes, cap);
+        return false;
+    }
     if (base) { (void)hipFree(base); base = nullptr; cap = 0; }
     size_t want = std::max(bytes, cap * 3 / 2);
     if (hipMalloc(&base, want) != hipSuccess) {
@@ -87,6 +91,10 @@ bool Arena::reserve(Ctx* c, size_t bytes) {
 
 bool PinnedBuf::reserve(Ctx* c, size_t bytes) {
     if (bytes <= cap) return true;
+    if (fixed) {
+        c->fail("host staging of %zu bytes exceeds the fixed buffer of %zu bytes", bytes, cap);
+        return false;
+    }
     if (ptr) { (void)hipHostFree(ptr); ptr = nullptr; cap = 0; }
     if (hipHostMalloc(&ptr, bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -226,6 +234,17 @@ extern "C" tr_status tr_context_create(tr_context** ctx, void* hip_stream) {
     Ctx* c = new (std::nothrow) Ctx();
     if (!c) return TR_ERR_OOM;
     c->device = dev;
+    c->noalloc_host = new (std::nothrow) char[kNoAllocHostBytes];
+    if (!c->noalloc_host) {
+        delete c;
+        return TR_ERR_OOM;
+    }
+    // the fixed scratch of tr_solve_noalloc: its address on this device
+    if (!noalloc_init(dev)) {
+        delete[] c->noalloc_host;
+        delete c;
+        return TR_ERR_HIP;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
         c->lds_limit = prop.sharedMemPerBlock;
@@ -241,6 +260,7 @@ extern "C" void tr_context_destroy(tr_context* ctx) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     c->release();
+    delete[] c->noalloc_host;
     delete c;
 }
 

@@ -13,17 +13,31 @@ namespace mdp {
 
 struct Ctx;
 
+// Device workspace, grown on demand with hipMalloc; a fixed (external)
+// arena never allocates and refuses requests beyond its size.
 struct Arena {
     void* base = nullptr;
     size_t cap = 0;
+    bool fixed = false;
     bool reserve(Ctx* c, size_t bytes);
 };
 
+// Host staging and read-back buffer: pinned memory grown on demand, or a
+// fixed buffer that never allocates.
 struct PinnedBuf {
     void* ptr = nullptr;
     size_t cap = 0;
+    bool fixed = false;
     bool reserve(Ctx* c, size_t bytes);
 };
+
+// Host staging area of the no-allocation entry point, allocated with the
+// context (ordinary host memory).
+constexpr size_t kNoAllocHostBytes = 2u << 20;
+// Per-device address of the library's fixed device scratch (nullptr if the
+// lookup failed); looked up once per device by noalloc_init.
+bool noalloc_init(int device);
+void* noalloc_scratch(int device, size_t* bytes);
 
 // Launch plan of the 2-D sweep: D directions per lane, W waves per
 // workgroup, per-instance rows per segment R and slices S, LDS block KB.
@@ -61,6 +75,7 @@ struct Ctx {
     Arena arena;          // per-call solver workspace
     Arena eig;            // k-eigenvalue workspace (fission source, last iterate, state)
     PinnedBuf pinned;     // staging and flag read-back
+    char* noalloc_host = nullptr;   // kNoAllocHostBytes, see tr_solve_noalloc
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
     bool force_generic = false;   // never use the specialised sweep kernel
     int stop_rule = TR_STOP_CHANGE;   // tr_solve's stopping rule (tr_stop_rule)
