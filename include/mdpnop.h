@@ -302,6 +302,16 @@ tr_status no_model_get_params(tr_context *ctx, const no_model *m,
  * Adam moments and step count (a new starting point for training).        */
 tr_status no_model_set_params(tr_context *ctx, no_model *m,
                               const float *params_host);
+/* Training checkpoint: the FP32 master parameters, Adam's first and second
+ * moments (each param_count floats, HOST buffers) and the count of Adam
+ * steps taken (its bias corrections depend on it).  Setting a state taken
+ * with no_model_get_state and continuing to train reproduces the
+ * uninterrupted run bit for bit.  set_state rejects a negative step.      */
+tr_status no_model_get_state(tr_context *ctx, const no_model *m, float *params_host,
+                             float *adam_m_host, float *adam_v_host, int64_t *step);
+tr_status no_model_set_state(tr_context *ctx, no_model *m, const float *params_host,
+                             const float *adam_m_host, const float *adam_v_host,
+                             int64_t step);
 /* Operand precision of the matrix-core products: enable = 0 (default)
  * rounds operands to BF16, enable = 1 keeps them FP32
  * (v_mfma_f32_16x16x4f32; slower, for checking against FP64 references).

@@ -29,7 +29,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "si_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libsi_oracle.so")
+# ORACLE_LIB: another build of si_oracle.c (the sanitizer build)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "libsi_oracle.so")
 _lib = None
 _lock = threading.Lock()
 

@@ -15,7 +15,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmdpnop.so")
+# MDPNOP_LIB points the binding at another build of the library (the
+# host-sanitizer build of sanitize.py); it must exist like the default one
+LIB_PATH = os.environ.get("MDPNOP_LIB") or os.path.join(_HERE, "libmdpnop.so")
 
 TR_OK = 0
 TR_NOT_CONVERGED = 1
@@ -33,7 +35,8 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "tr_sweep", "tr_solve", "tr_solve_noalloc", "tr_eigen", "tr_eigen_mg", "no_recast_guess", "no_eigen",
            "no_model_create",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
-           "no_model_set_params", "no_model_set_fp32", "no_forward",
+           "no_model_set_params", "no_model_get_state", "no_model_set_state",
+           "no_model_set_fp32", "no_forward",
            "no_train_step",
            "tr_check_args", "tr_autotune", "tr_set_sweep_config", "tr_set_sweep_kernel",
            "tr_set_stop_rule", "tr_get_sweep_plan",
@@ -116,6 +119,8 @@ def load(path: str = LIB_PATH):
     lib.no_model_param_count.restype = i64
     lib.no_model_get_params.argtypes = [vp, vp, vp]
     lib.no_model_set_params.argtypes = [vp, vp, vp]
+    lib.no_model_get_state.argtypes = [vp, vp, vp, vp, vp, P(i64)]
+    lib.no_model_set_state.argtypes = [vp, vp, vp, vp, vp, i64]
     lib.no_model_set_fp32.argtypes = [vp, i32]
     lib.no_forward.argtypes = [vp, vp, i32, vp, vp]
     lib.no_train_step.argtypes = [vp, vp, i32, vp, vp, d, P(d), vp]
@@ -537,6 +542,24 @@ class Model:
             raise ValueError(f"expected {self.n_params} parameters, got {buf.size}")
         self.ctx.check(self.lib.no_model_set_params(self.ctx.handle, self.handle,
                                                     buf.ctypes.data), allow=(TR_OK,))
+
+    def get_state(self) -> dict:
+        """Training checkpoint: FP32 parameters, Adam moments, step count."""
+        p, m, v = (np.empty(self.n_params, dtype=np.float32) for _ in range(3))
+        step = ctypes.c_int64()
+        self.ctx.check(self.lib.no_model_get_state(self.ctx.handle, self.handle, p.ctypes.data,
+                                                   m.ctypes.data, v.ctypes.data,
+                                                   ctypes.byref(step)), allow=(TR_OK,))
+        return dict(params=p, adam_m=m, adam_v=v, step=int(step.value))
+
+    def set_state(self, state: dict):
+        bufs = [np.ascontiguousarray(state[k], dtype=np.float32)
+                for k in ("params", "adam_m", "adam_v")]
+        if any(b.size != self.n_params for b in bufs):
+            raise ValueError(f"expected {self.n_params} values per array")
+        self.ctx.check(self.lib.no_model_set_state(self.ctx.handle, self.handle,
+                                                   *[b.ctypes.data for b in bufs],
+                                                   int(state["step"])), allow=(TR_OK,))
 
     def forward(self, inp, out=None):
         """inp: float32 GPU tensor (B, grid, grid) -> output tensor (B, grid, grid)."""

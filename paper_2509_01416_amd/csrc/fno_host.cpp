@@ -498,6 +498,54 @@ extern "C" tr_status no_model_set_params(tr_context* ctx, no_model* m, const flo
     return finish(c, "set params");
 }
 
+extern "C" tr_status no_model_get_state(tr_context* ctx, const no_model* m, float* params_host,
+                                        float* adam_m_host, float* adam_v_host,
+                                        int64_t* step) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || !params_host || !adam_m_host || !adam_v_host || !step) {
+        c->fail("null model, buffer or step");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    const size_t pb = 4 * (size_t)m->n_params;
+    if (!c->hip_ok(hipMemcpyAsync(params_host, m->params, pb, hipMemcpyDeviceToHost, c->stream),
+                   "copy") ||
+        !c->hip_ok(hipMemcpyAsync(adam_m_host, m->am, pb, hipMemcpyDeviceToHost, c->stream),
+                   "copy") ||
+        !c->hip_ok(hipMemcpyAsync(adam_v_host, m->av, pb, hipMemcpyDeviceToHost, c->stream),
+                   "copy"))
+        return TR_ERR_HIP;
+    const tr_status st = finish(c, "get state");
+    if (st == TR_OK) *step = m->step;
+    return st;
+}
+
+extern "C" tr_status no_model_set_state(tr_context* ctx, no_model* m, const float* params_host,
+                                        const float* adam_m_host, const float* adam_v_host,
+                                        int64_t step) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!m || !params_host || !adam_m_host || !adam_v_host || step < 0) {
+        c->fail("null model or buffer, or a negative step count");
+        return TR_ERR_INVALID_ARG;
+    }
+    if (!same_device(c, m)) return TR_ERR_INVALID_ARG;
+    const size_t pb = 4 * (size_t)m->n_params;
+    if (!c->hip_ok(hipMemcpyAsync(m->params, params_host, pb, hipMemcpyHostToDevice, c->stream),
+                   "copy") ||
+        !c->hip_ok(hipMemcpyAsync(m->am, adam_m_host, pb, hipMemcpyHostToDevice, c->stream),
+                   "copy") ||
+        !c->hip_ok(hipMemcpyAsync(m->av, adam_v_host, pb, hipMemcpyHostToDevice, c->stream),
+                   "copy"))
+        return TR_ERR_HIP;
+    const tr_status st = finish(c, "set state");
+    if (st == TR_OK) m->step = step;
+    return st;
+}
+
 extern "C" tr_status no_forward(tr_context* ctx, const no_model* m, int32_t batch,
                                 const float* input, float* output) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);

@@ -15,7 +15,13 @@ kernels (no_train_step).  The epoch budget is wall time; the parameters kept
 are those of the best validation error (checked every 5 epochs), since the
 constant learning rate leaves the error oscillating late in training.
 
-Usage: python -m paper_2509_01416_amd.train --out DIR [--minutes M]
+A run can write a checkpoint (parameters, Adam moments and step count,
+the batch-order generator, counters and the best parameters so far) every
+few epochs and resume from it; a resumed run continues the interrupted one
+bit for bit.
+
+Usage: python -m paper_2509_01416_amd.train --out FILE [--minutes M]
+           [--checkpoint FILE [--resume]]
 """
 from __future__ import annotations
 
@@ -77,8 +83,35 @@ def rel_l2_batch(pred, target):
     return (d / target.double().flatten(1).norm(dim=1))
 
 
+def save_checkpoint(path: str, model, rng, epoch: int, steps: int, best, hist) -> None:
+    """Everything a resumed run needs to continue this one bit for bit."""
+    st = model.get_state()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=st["params"], adam_m=st["adam_m"], adam_v=st["adam_v"],
+             step=np.int64(st["step"]), epoch=np.int64(epoch), steps=np.int64(steps),
+             rng=np.array(json.dumps(rng.bit_generator.state)),
+             best_val=np.float64(best[0]), best_epoch=np.int64(best[1]),
+             best_params=(best[2] if best[2] is not None
+                          else np.zeros(0, dtype=np.float32)),
+             hist=np.array(json.dumps(hist)))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str, model, rng):
+    """Restores the model's training state and the generator; returns
+    (epoch, steps, best, hist)."""
+    z = np.load(path, allow_pickle=False)
+    model.set_state(dict(params=z["params"], adam_m=z["adam_m"], adam_v=z["adam_v"],
+                         step=int(z["step"])))
+    rng.bit_generator.state = json.loads(str(z["rng"]))
+    bp = z["best_params"]
+    best = (float(z["best_val"]), int(z["best_epoch"]), bp if bp.size else None)
+    return int(z["epoch"]), int(z["steps"]), best, json.loads(str(z["hist"]))
+
+
 def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 200,
-          batch: int = 32, lr: float = 1e-3, seed: int = 1234, max_epochs: int = 100000):
+          batch: int = 32, lr: float = 1e-3, seed: int = 1234, max_epochs: int = 100000,
+          checkpoint: str = None, checkpoint_every: int = 50, resume: bool = False):
     import torch
     torch.cuda.set_device(0)
     ctx = B.Context()
@@ -98,6 +131,9 @@ def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 2
     t1 = time.time()
     epoch = 0
     steps = 0
+    if resume and checkpoint and os.path.exists(checkpoint):
+        epoch, steps, best, hist = load_checkpoint(checkpoint, model, rng)
+        log(f"resumed from {checkpoint} at epoch {epoch} ({steps} steps)")
     while epoch < max_epochs and (time.time() - t1) < minutes * 60.0:
         perm = torch.tensor(rng.permutation(n_tr), device="cuda")
         tot = 0.0
@@ -121,6 +157,8 @@ def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 2
             if epoch % (10 * eval_every) == 0:
                 log(f"epoch {epoch}: train mse {train_mse:.3e}, validation rel L2 "
                     f"{vm:.3e}, best {best[0]:.3e} at {best[1]} ({time.time() - t1:.0f} s)")
+        if checkpoint and epoch % checkpoint_every == 0:
+            save_checkpoint(checkpoint, model, rng, epoch, steps, best, hist)
     if best[2] is not None:
         model.set_params(best[2])
     pv = model.forward(xva)
@@ -188,8 +226,14 @@ def main(argv=None):
     ap.add_argument("--minutes", type=float, default=3.0)
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--max-epochs", type=int, default=100000)
+    ap.add_argument("--checkpoint", default=None,
+                    help="write the training state here every --checkpoint-every epochs")
+    ap.add_argument("--checkpoint-every", type=int, default=50)
+    ap.add_argument("--resume", action="store_true",
+                    help="continue from --checkpoint if it exists")
     a = ap.parse_args(argv)
-    train(a.out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs)
+    train(a.out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs,
+          checkpoint=a.checkpoint, checkpoint_every=a.checkpoint_every, resume=a.resume)
 
 
 if __name__ == "__main__":

@@ -184,6 +184,41 @@ def test_training_reduces_loss(env):
     m.close()
 
 
+def test_checkpoint_resume_is_bitwise(env):
+    """Training state (parameters, Adam moments, step count) taken after
+    three steps and set on a fresh model continues the run bit for bit:
+    after three more steps the parameters equal those of six uninterrupted
+    steps.  set_params, by contrast, restarts Adam (a different answer)."""
+    torch, B, ctx = env
+    x = torch.tensor(_fields(8, 300).astype(np.float32), device="cuda")
+    y = torch.tensor(_fields(8, 400).astype(np.float32), device="cuda")
+    lr = 1e-3
+    a = B.Model(ctx, _params(21))
+    for _ in range(6):
+        a.train_step(x, y, lr)
+    want = a.get_params()
+    b = B.Model(ctx, _params(21))
+    for _ in range(3):
+        b.train_step(x, y, lr)
+    state = b.get_state()
+    assert state["step"] == 3
+    c = B.Model(ctx, _params(99))
+    c.set_state(state)
+    for _ in range(3):
+        c.train_step(x, y, lr)
+    got = c.get_params()
+    log(f"  resume: max |diff| {np.abs(got - want).max():.1e}")
+    assert np.array_equal(got, want)
+    assert c.get_state()["step"] == 6
+    d = B.Model(ctx, _params(99))
+    d.set_params(state["params"])
+    for _ in range(3):
+        d.train_step(x, y, lr)
+    assert not np.array_equal(d.get_params(), want)
+    for m in (a, b, c, d):
+        m.close()
+
+
 def test_forward_parity_two_row_tiles(env):
     """A batch of 20 spans two 16-row tiles of the per-mode mixing (the
     second one ragged): FP32-operand forward against the FP64 oracle."""
