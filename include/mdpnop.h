@@ -382,6 +382,14 @@ tr_status tr_autotune(tr_context *ctx, int32_t n_inst, const tr_problem *p,
  * their results agree bit for bit.                                        */
 tr_status tr_set_sweep_kernel(tr_context *ctx, int32_t generic);
 
+/* Debugging: with enable = 1 every HIP step of a call on this context
+ * (launch, copy) is followed by a stream synchronisation and an error
+ * check, so a failing kernel is reported, in tr_last_error, at the step
+ * that launched it rather than at the next synchronisation.  Slow; off by
+ * default, or on for every new context when the environment variable
+ * MDPNOP_SYNC_CHECKS is set to a value other than 0.                      */
+tr_status tr_set_sync_checks(tr_context *ctx, int32_t enable);
+
 /* Kernel timing for benchmarks: with enable != 0, tr_solve records HIP
  * events on the context stream around every sweep launch and around every
  * combine+finalize pair (totals reset by each call of this function).    */

@@ -58,11 +58,12 @@ def _load():
             D = ctypes.POINTER(ctypes.c_double)
             I = ctypes.POINTER(ctypes.c_int)
             i, d = ctypes.c_int, ctypes.c_double
-            lib.or_sweep2d.argtypes = [i, i, d, d, i, D, D, D, D, D, I, D, D, D, D]
-            lib.or_si2d.argtypes = [i, i, d, d, i, D, D, D, D, D, D, I, D, d, i,
+            lib.or_sweep2d.argtypes = [i, i, d, d, i, D, D, D, D, D, D, D, I, D, D, D,
+                                       D, D, D]
+            lib.or_si2d.argtypes = [i, i, d, d, i, D, D, D, D, D, D, D, I, D, d, i,
                                     i, i, D, D, D]
-            lib.or_sweep1d.argtypes = [i, d, i, D, D, D, D, I, D, D, D, D]
-            lib.or_si1d.argtypes = [i, d, i, D, D, D, D, D, I, D, d, i, i, i, D, D, D]
+            lib.or_sweep1d.argtypes = [i, d, i, D, D, D, D, D, I, D, D, D, D, D]
+            lib.or_si1d.argtypes = [i, d, i, D, D, D, D, D, D, I, D, d, i, i, i, D, D, D]
             for f in (lib.or_sweep2d, lib.or_si2d, lib.or_sweep1d, lib.or_si1d):
                 f.restype = ctypes.c_int
             _lib = lib
@@ -109,10 +110,14 @@ class SolveResult:
 
 
 def sweep2d(nx, ny, lx, ly, mu, eta, w, sigma_t, emission, bc=(0, 0, 0, 0),
-            face_prev=None, return_faces=False):
-    """One 2-D DD sweep of every direction for emission density Q.
+            face_prev=None, return_faces=False, ex=None, ey=None,
+            return_current=False):
+    """One 2-D DD sweep of every direction for the isotropic emission
+    density Q, plus mu_m ex + eta_m ey per direction when the anisotropic
+    fields are given (P1: ex, ey = 3 sigma_s1 J).
 
-    Returns phi (ny, nx) [and the face array (4, max(nx,ny), M), leakage]."""
+    Returns phi (ny, nx) [and the face array (4, max(nx,ny), M), leakage]
+    [and the current (jx, jy) when return_current]."""
     lib = _load()
     mu, eta, w = _f64(mu), _f64(eta), _f64(w)
     M = mu.shape[0]
@@ -122,33 +127,43 @@ def sweep2d(nx, ny, lx, ly, mu, eta, w, sigma_t, emission, bc=(0, 0, 0, 0),
     phi = np.zeros(nx * ny)
     fo = np.zeros(4 * nf * M)
     fp = None if face_prev is None else _f64(face_prev).reshape(-1)
+    exa = None if ex is None else _f64(ex).reshape(-1)
+    eya = None if ey is None else _f64(ey).reshape(-1)
+    jx = np.zeros(nx * ny) if return_current else None
+    jy = np.zeros(nx * ny) if return_current else None
     leak = ctypes.c_double(0.0)
     rc = lib.or_sweep2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
-                        _dp(Q), _bc(bc), _dp(fp), _dp(fo), _dp(phi),
-                        ctypes.byref(leak))
+                        _dp(Q), _dp(exa), _dp(eya), _bc(bc), _dp(fp), _dp(fo), _dp(phi),
+                        _dp(jx), _dp(jy), ctypes.byref(leak))
     if rc != OK:
         raise ValueError(f"or_sweep2d failed ({rc})")
     phi = phi.reshape(ny, nx)
+    out = (phi,)
     if return_faces:
-        return phi, fo.reshape(4, nf, M), leak.value
-    return phi
+        out += (fo.reshape(4, nf, M), leak.value)
+    if return_current:
+        out += ((jx.reshape(ny, nx), jy.reshape(ny, nx)),)
+    return out[0] if len(out) == 1 else out
 
 
 def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
-         phi0=None, tol=1e-6, max_iter=100000, norm="l2", stride=1) -> SolveResult:
-    """2-D source iteration to tolerance (zero start unless phi0 is given)."""
+         phi0=None, tol=1e-6, max_iter=100000, norm="l2", stride=1,
+         sigma_s1=None) -> SolveResult:
+    """2-D source iteration to tolerance (zero start unless phi0 is given);
+    sigma_s1: first Legendre moment of scattering (P1, Eq. 25), or None."""
     lib = _load()
     mu, eta, w = _f64(mu), _f64(eta), _f64(w)
     M = mu.shape[0]
     st = _f64(sigma_t).reshape(-1)
     ss = _f64(sigma_s).reshape(-1)
+    s1 = None if sigma_s1 is None else _f64(sigma_s1).reshape(-1)
     qq = _f64(q).reshape(-1)
     p0 = None if phi0 is None else _f64(phi0).reshape(-1)
     phi = np.zeros(nx * ny)
     stats = np.zeros(4)
     hist = np.zeros(max_iter)
     rc = lib.or_si2d(nx, ny, lx, ly, M, _dp(mu), _dp(eta), _dp(w), _dp(st),
-                     _dp(ss), _dp(qq), _bc(bc), _dp(p0), float(tol),
+                     _dp(ss), _dp(s1), _dp(qq), _bc(bc), _dp(p0), float(tol),
                      int(max_iter), _norm_kind(norm), int(stride), _dp(phi),
                      _dp(stats), _dp(hist))
     if rc < 0:
@@ -159,7 +174,10 @@ def si2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, q, bc=(0, 0, 0, 0),
 
 
 def sweep1d(nx, lx, mu, w, sigma_t, emission, bc=(0, 0), face_prev=None,
-            return_faces=False):
+            return_faces=False, ex=None, return_current=False):
+    """One 1-D DD sweep for the isotropic emission Q plus mu_m ex per
+    direction (P1: ex = 3 sigma_s1 J).  Returns phi [faces, leakage]
+    [current]."""
     lib = _load()
     mu, w = _f64(mu), _f64(w)
     M = mu.shape[0]
@@ -168,29 +186,35 @@ def sweep1d(nx, lx, mu, w, sigma_t, emission, bc=(0, 0), face_prev=None,
     phi = np.zeros(nx)
     fo = np.zeros(2 * M)
     fp = None if face_prev is None else _f64(face_prev).reshape(-1)
+    exa = None if ex is None else _f64(ex).reshape(-1)
+    jx = np.zeros(nx) if return_current else None
     leak = ctypes.c_double(0.0)
-    rc = lib.or_sweep1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(Q), _bc(bc),
-                        _dp(fp), _dp(fo), _dp(phi), ctypes.byref(leak))
+    rc = lib.or_sweep1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(Q), _dp(exa), _bc(bc),
+                        _dp(fp), _dp(fo), _dp(phi), _dp(jx), ctypes.byref(leak))
     if rc != OK:
         raise ValueError(f"or_sweep1d failed ({rc})")
+    out = (phi,)
     if return_faces:
-        return phi, fo.reshape(2, M), leak.value
-    return phi
+        out += (fo.reshape(2, M), leak.value)
+    if return_current:
+        out += (jx,)
+    return out[0] if len(out) == 1 else out
 
 
 def si1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), phi0=None, tol=1e-8,
-         max_iter=100000, norm="max", stride=1) -> SolveResult:
+         max_iter=100000, norm="max", stride=1, sigma_s1=None) -> SolveResult:
     lib = _load()
     mu, w = _f64(mu), _f64(w)
     M = mu.shape[0]
     st = _f64(sigma_t).reshape(-1)
     ss = _f64(sigma_s).reshape(-1)
+    s1 = None if sigma_s1 is None else _f64(sigma_s1).reshape(-1)
     qq = _f64(q).reshape(-1)
     p0 = None if phi0 is None else _f64(phi0).reshape(-1)
     phi = np.zeros(nx)
     stats = np.zeros(4)
     hist = np.zeros(max_iter)
-    rc = lib.or_si1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(ss), _dp(qq),
+    rc = lib.or_si1d(nx, lx, M, _dp(mu), _dp(w), _dp(st), _dp(ss), _dp(s1), _dp(qq),
                      _bc(bc), _dp(p0), float(tol), int(max_iter),
                      _norm_kind(norm), int(stride), _dp(phi), _dp(stats),
                      _dp(hist))
@@ -217,13 +241,17 @@ def solve_instance(inst, quad, tol, phi0=None, max_iter=100000, norm=None,
         inst.sigma_t = f32_rounded(inst.sigma_t)
         inst.sigma_s = f32_rounded(inst.sigma_s)
         inst.source = f32_rounded(inst.source)
+        if getattr(inst, "sigma_s1", None) is not None:
+            inst.sigma_s1 = f32_rounded(inst.sigma_s1)
     if inst.dim == 1:
         return si1d(inst.nx, inst.lx, quad.mu, quad.w, inst.sigma_t,
                     inst.sigma_s, inst.source, bc=inst.bc[:2], phi0=phi0,
-                    tol=tol, max_iter=max_iter, norm=norm or "max", stride=stride)
+                    tol=tol, max_iter=max_iter, norm=norm or "max", stride=stride,
+                    sigma_s1=getattr(inst, "sigma_s1", None))
     return si2d(inst.nx, inst.ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
                 inst.sigma_t, inst.sigma_s, inst.source, bc=inst.bc,
-                phi0=phi0, tol=tol, max_iter=max_iter, norm=norm or "l2", stride=stride)
+                phi0=phi0, tol=tol, max_iter=max_iter, norm=norm or "l2", stride=stride,
+                sigma_s1=getattr(inst, "sigma_s1", None))
 
 
 def solve_many(insts: Sequence, quad, tol, phi0s=None, threads: int = 1,

@@ -25,6 +25,18 @@
  *     the mirrored direction's outgoing value from the previous sweep, i.e.
  *     lagged one iteration).
  *
+ * Linearly anisotropic (P1) scattering, section 5.1 Eq. 25: with the first
+ * Legendre moment sigma_s1 of the scattering cross section the emission of
+ * direction m becomes
+ *     Q_m = sigma_s phi + 3 sigma_s1 (mu_m J_x + eta_m J_y) + S,
+ *     J = sum_m w_m Omega_m psi_m  (the current; J_y absent in 1-D).
+ * In the paper's normalisation (weights summing to 2, the factors 1/2 and
+ * 3/2 of Eq. 25) the same emission results.  Source iteration lags J like
+ * phi: it comes from the previous sweep (zero before the first).  The P1
+ * term integrates to zero over the directions, so particle balance is
+ * unchanged.  The sweeps take the anisotropic part as per-cell fields
+ * E = 3 sigma_s1 J (NULL: isotropic emission) and return J when asked.
+ *
  * Convergence: norm_kind 0 -> ||phi_new - phi_old||_2 / ||phi_new||_2 < tol,
  *              norm_kind 1 -> max_i |phi_new_i - phi_old_i| / |phi_new_i| < tol,
  *              norm_kind 2 -> error bound of the fixed-point iteration: with
@@ -78,14 +90,17 @@ static int mirror_dir(int M, const double *mu, const double *eta, int m,
  */
 int or_sweep2d(int nx, int ny, double lx, double ly, int M, const double *mu,
                const double *eta, const double *w, const double *sigma_t,
-               const double *emission, const int *bc, const double *face_prev,
-               double *face_out, double *phi, double *leak) {
+               const double *emission, const double *ex, const double *ey,
+               const int *bc, const double *face_prev, double *face_out,
+               double *phi, double *jx, double *jy, double *leak) {
     if (nx <= 0 || ny <= 0 || M <= 0) return OR_BAD_ARG;
     const double dx = lx / nx, dy = ly / ny;
     const int nf = nx > ny ? nx : ny;
     double *ycol = (double *)malloc(sizeof(double) * nx);
     if (!ycol) return OR_BAD_ARG;
     memset(phi, 0, sizeof(double) * nx * ny);
+    if (jx) memset(jx, 0, sizeof(double) * nx * ny);
+    if (jy) memset(jy, 0, sizeof(double) * nx * ny);
     double lk = 0.0;
     for (int m = 0; m < M; ++m) {
         const double a = 2.0 * fabs(mu[m]) / dx;
@@ -113,11 +128,16 @@ int or_sweep2d(int nx, int ny, double lx, double ly, int M, const double *mu,
             for (int ii = 0; ii < nx; ++ii) {
                 const int i = xpos ? ii : nx - 1 - ii;
                 const size_t c = (size_t)j * nx + i;
-                const double psi = (emission[c] + a * xin + b * ycol[i]) /
+                double q = emission[c];
+                if (ex) q += mu[m] * ex[c];
+                if (ey) q += eta[m] * ey[c];
+                const double psi = (q + a * xin + b * ycol[i]) /
                                    (sigma_t[c] + a + b);
                 xin = 2.0 * psi - xin;
                 ycol[i] = 2.0 * psi - ycol[i];
                 phi[c] += w[m] * psi;
+                if (jx) jx[c] += w[m] * mu[m] * psi;
+                if (jy) jy[c] += w[m] * eta[m] * psi;
             }
             if (face_out) face_out[((size_t)fx_out * nf + j) * M + m] = xin;
             lk += w[m] * fabs(mu[m]) * dy * xin;
@@ -180,7 +200,7 @@ static int converged(double r, double r_prev, double tol, int kind) {
  */
 int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
             const double *eta, const double *w, const double *sigma_t,
-            const double *sigma_s, const double *q, const int *bc,
+            const double *sigma_s, const double *sigma_s1, const double *q, const int *bc,
             const double *phi0, double tol, int max_iter, int norm_kind,
             int stride, double *phi, double *stats, double *hist) {
     if (nx <= 0 || ny <= 0 || M <= 0 || max_iter <= 0 || stride <= 0) return OR_BAD_ARG;
@@ -192,8 +212,11 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     double *fa = (double *)calloc(fsz, sizeof(double));
     double *fb = (double *)calloc(fsz, sizeof(double));
     double *snap = (double *)malloc(sizeof(double) * n);
-    if (!Q || !phin || !fa || !fb || !snap) {
-        free(Q); free(phin); free(fa); free(fb); free(snap);
+    /* P1: E = 3 sigma_s1 J of the previous sweep (x, y), the new J */
+    double *ex = sigma_s1 ? (double *)calloc(4 * n, sizeof(double)) : NULL;
+    double *ey = ex ? ex + n : NULL, *jx = ex ? ex + 2 * n : NULL, *jy = ex ? ex + 3 * n : NULL;
+    if (!Q || !phin || !fa || !fb || !snap || (sigma_s1 && !ex)) {
+        free(Q); free(phin); free(fa); free(fb); free(snap); free(ex);
         return OR_BAD_ARG;
     }
     if (norm_kind != 2) stride = 1;
@@ -218,8 +241,13 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     double r = INFINITY, r_prev = INFINITY, r_step = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (size_t c = 0; c < n; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
-        or_sweep2d(nx, ny, lx, ly, M, mu, eta, w, sigma_t, Q, bc, fa, fb,
-                   phin, &leak);
+        or_sweep2d(nx, ny, lx, ly, M, mu, eta, w, sigma_t, Q, ex, ey, bc, fa, fb,
+                   phin, jx, jy, &leak);
+        if (sigma_s1)
+            for (size_t c = 0; c < n; ++c) {
+                ex[c] = 3.0 * sigma_s1[c] * jx[c];
+                ey[c] = 3.0 * sigma_s1[c] * jy[c];
+            }
         r_step = change_norm(n, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (size_t c = 0; c < n; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
@@ -236,7 +264,7 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
     if (stats) {
         stats[0] = it; stats[1] = r; stats[2] = leak; stats[3] = dscat;
     }
-    free(Q); free(phin); free(fa); free(fb); free(snap);
+    free(Q); free(phin); free(fa); free(fb); free(snap); free(ex);
     return status;
 }
 
@@ -244,12 +272,13 @@ int or_si2d(int nx, int ny, double lx, double ly, int M, const double *mu,
 
 /* One 1-D sweep; face layout face[f][m], f = 0 left, 1 right. */
 int or_sweep1d(int nx, double lx, int M, const double *mu, const double *w,
-               const double *sigma_t, const double *emission, const int *bc,
-               const double *face_prev, double *face_out, double *phi,
-               double *leak) {
+               const double *sigma_t, const double *emission, const double *ex,
+               const int *bc, const double *face_prev, double *face_out,
+               double *phi, double *jx, double *leak) {
     if (nx <= 0 || M <= 0) return OR_BAD_ARG;
     const double dx = lx / nx;
     memset(phi, 0, sizeof(double) * nx);
+    if (jx) memset(jx, 0, sizeof(double) * nx);
     double lk = 0.0;
     for (int m = 0; m < M; ++m) {
         const double a = 2.0 * fabs(mu[m]) / dx;
@@ -262,9 +291,11 @@ int or_sweep1d(int nx, double lx, int M, const double *mu, const double *w,
         lk -= w[m] * fabs(mu[m]) * in;
         for (int ii = 0; ii < nx; ++ii) {
             const int i = pos ? ii : nx - 1 - ii;
-            const double psi = (emission[i] + a * in) / (sigma_t[i] + a);
+            const double qm = ex ? emission[i] + mu[m] * ex[i] : emission[i];
+            const double psi = (qm + a * in) / (sigma_t[i] + a);
             in = 2.0 * psi - in;
             phi[i] += w[m] * psi;
+            if (jx) jx[i] += w[m] * mu[m] * psi;
         }
         if (face_out) face_out[fout * M + m] = in;
         lk += w[m] * fabs(mu[m]) * in;
@@ -274,7 +305,8 @@ int or_sweep1d(int nx, double lx, int M, const double *mu, const double *w,
 }
 
 int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
-            const double *sigma_t, const double *sigma_s, const double *q,
+            const double *sigma_t, const double *sigma_s, const double *sigma_s1,
+            const double *q,
             const int *bc, const double *phi0, double tol, int max_iter,
             int norm_kind, int stride, double *phi, double *stats, double *hist) {
     if (nx <= 0 || M <= 0 || max_iter <= 0 || stride <= 0) return OR_BAD_ARG;
@@ -283,8 +315,10 @@ int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
     double *fa = (double *)calloc((size_t)2 * M, sizeof(double));
     double *fb = (double *)calloc((size_t)2 * M, sizeof(double));
     double *snap = (double *)malloc(sizeof(double) * nx);
-    if (!Q || !phin || !fa || !fb || !snap) {
-        free(Q); free(phin); free(fa); free(fb); free(snap);
+    double *ex = sigma_s1 ? (double *)calloc(2 * (size_t)nx, sizeof(double)) : NULL;
+    double *jx = ex ? ex + nx : NULL;
+    if (!Q || !phin || !fa || !fb || !snap || (sigma_s1 && !ex)) {
+        free(Q); free(phin); free(fa); free(fb); free(snap); free(ex);
         return OR_BAD_ARG;
     }
     if (norm_kind != 2) stride = 1;
@@ -303,7 +337,9 @@ int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
     double r = INFINITY, r_prev = INFINITY, r_step = INFINITY, leak = 0.0, dscat = 0.0;
     for (it = 1; it <= max_iter; ++it) {
         for (int c = 0; c < nx; ++c) Q[c] = sigma_s[c] * phi[c] + q[c];
-        or_sweep1d(nx, lx, M, mu, w, sigma_t, Q, bc, fa, fb, phin, &leak);
+        or_sweep1d(nx, lx, M, mu, w, sigma_t, Q, ex, bc, fa, fb, phin, jx, &leak);
+        if (sigma_s1)
+            for (int c = 0; c < nx; ++c) ex[c] = 3.0 * sigma_s1[c] * jx[c];
         r_step = change_norm((size_t)nx, phin, phi, norm_kind == 1);
         dscat = 0.0;
         for (int c = 0; c < nx; ++c) dscat += sigma_s[c] * (phin[c] - phi[c]) * V;
@@ -320,6 +356,6 @@ int or_si1d(int nx, double lx, int M, const double *mu, const double *w,
     if (stats) {
         stats[0] = it; stats[1] = r; stats[2] = leak; stats[3] = dscat;
     }
-    free(Q); free(phin); free(fa); free(fb); free(snap);
+    free(Q); free(phin); free(fa); free(fb); free(snap); free(ex);
     return status;
 }

@@ -39,7 +39,7 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "no_model_set_fp32", "no_forward",
            "no_train_step",
            "tr_check_args", "tr_autotune", "tr_set_sweep_config", "tr_set_sweep_kernel",
-           "tr_set_stop_rule", "tr_get_sweep_plan",
+           "tr_set_stop_rule", "tr_set_sync_checks", "tr_get_sweep_plan",
            "tr_profile_enable", "tr_profile_read")
 
 
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.tr_set_sweep_config.argtypes = [vp, i32, i32, i32, i32]
     lib.tr_set_sweep_kernel.argtypes = [vp, i32]
     lib.tr_set_stop_rule.argtypes = [vp, i32]
+    lib.tr_set_sync_checks.argtypes = [vp, i32]
     lib.tr_autotune.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), i32, P(i32), P(d)]
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
     lib.tr_profile_enable.argtypes = [vp, i32]
@@ -269,6 +270,10 @@ class Context:
         if rule not in codes:
             raise ValueError(f"unknown stopping rule {rule!r}")
         self.check(self.lib.tr_set_stop_rule(self.handle, codes[rule]), allow=(TR_OK,))
+
+    def set_sync_checks(self, enable: bool = True):
+        """Debugging: synchronise and check for errors after every HIP step."""
+        self.check(self.lib.tr_set_sync_checks(self.handle, int(enable)), allow=(TR_OK,))
 
     def profile(self, enable: bool = True):
         self.check(self.lib.tr_profile_enable(self.handle, int(enable)), allow=(TR_OK,))

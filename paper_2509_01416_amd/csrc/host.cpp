@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -61,9 +62,21 @@ void Ctx::fail(const char* fmt, ...) {
 }
 
 bool Ctx::hip_ok(hipError_t e, const char* what) {
-    if (e == hipSuccess) return true;
-    fail("%s: %s", what, hipGetErrorString(e));
-    return false;
+    if (e != hipSuccess) {
+        fail("%s: %s", what, hipGetErrorString(e));
+        return false;
+    }
+    if (sync_checks) {
+        // debugging: wait for the work enqueued so far, so that an error of
+        // an asynchronous launch is reported at the step that caused it
+        hipError_t s = hipStreamSynchronize(stream);
+        if (s == hipSuccess) s = hipGetLastError();
+        if (s != hipSuccess) {
+            fail("%s (synchronous check): %s", what, hipGetErrorString(s));
+            return false;
+        }
+    }
+    return true;
 }
 
 // Grow-only device arena; sub-allocations are 256-byte aligned.
@@ -234,6 +247,10 @@ extern "C" tr_status tr_context_create(tr_context** ctx, void* hip_stream) {
     Ctx* c = new (std::nothrow) Ctx();
     if (!c) return TR_ERR_OOM;
     c->device = dev;
+    {
+        const char* env = std::getenv("MDPNOP_SYNC_CHECKS");
+        c->sync_checks = env != nullptr && env[0] != '\0' && env[0] != '0';
+    }
     c->noalloc_host = new (std::nothrow) char[kNoAllocHostBytes];
     if (!c->noalloc_host) {
         delete c;
@@ -1083,6 +1100,17 @@ extern "C" tr_status tr_set_sweep_kernel(tr_context* ctx, int32_t generic) {
         return TR_ERR_INVALID_ARG;
     }
     c->force_generic = generic != 0;
+    return TR_OK;
+}
+
+extern "C" tr_status tr_set_sync_checks(tr_context* ctx, int32_t enable) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    if (enable != 0 && enable != 1) {
+        c->fail("enable must be 0 or 1");
+        return TR_ERR_INVALID_ARG;
+    }
+    c->sync_checks = enable != 0;
     return TR_OK;
 }
 

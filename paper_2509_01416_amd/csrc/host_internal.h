@@ -79,6 +79,7 @@ struct Ctx {
     int force_D = 0, force_W = 0, force_S = 0, force_R = 0, force_KB = 0;
     bool force_generic = false;   // never use the specialised sweep kernel
     int stop_rule = TR_STOP_CHANGE;   // tr_solve's stopping rule (tr_stop_rule)
+    bool sync_checks = false;         // synchronise and check after every HIP step
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS (gfx950; device property when known)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces

@@ -227,7 +227,8 @@ BC_REFLECTIVE = 1
 
 @dataclass
 class Instance:
-    """One fixed-source problem: sigma_t, sigma_s, source on a uniform grid."""
+    """One fixed-source problem: sigma_t, sigma_s, source on a uniform grid;
+    sigma_s1 (optional) is the first Legendre moment of scattering."""
     nx: int
     ny: int
     lx: float
@@ -237,6 +238,7 @@ class Instance:
     source: np.ndarray
     bc: Tuple[int, int, int, int] = (0, 0, 0, 0)   # x-, x+, y-, y+
     dim: int = 2
+    sigma_s1: Optional[np.ndarray] = None
 
     @property
     def cells(self) -> int:

@@ -13,6 +13,9 @@ Equations per direction m and cell (i, j), signed cosines (mu, eta):
     psiC - (psiX[i+1,j] + psiX[i,j]) / 2 = 0
     psiC - (psiY[i,j+1] + psiY[i,j]) / 2 = 0
 Incoming faces: vacuum -> psi = 0; reflective -> psi_m = psi_mirror(m).
+With linearly anisotropic scattering (sigma_s1, section 5.1 Eq. 25) the
+coupling of direction m to direction k gains 3 sigma_s1 w_k (Omega_m .
+Omega_k), the P1 term written out.
 """
 from __future__ import annotations
 
@@ -32,9 +35,10 @@ def _mirror(mu, eta, m, flip_x):
 
 
 def solve_2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, rhs, bc,
-             coupled=True):
-    """Return phi (ny, nx).  coupled=False solves one sweep for emission rhs
-    (sigma_s ignored, reflective faces get the value 0 instead)."""
+             coupled=True, sigma_s1=None, return_current=False):
+    """Return phi (ny, nx) [and the current (jx, jy)].  coupled=False solves
+    one sweep for emission rhs (sigma_s ignored, reflective faces get the
+    value 0 instead); rhs may also be given per direction, (M, ny, nx)."""
     M = len(mu)
     dx, dy = lx / nx, ly / ny
     nC = nx * ny
@@ -44,7 +48,10 @@ def solve_2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, rhs, bc,
     N = M * per
     st = np.asarray(sigma_t, float).reshape(ny, nx)
     ss = np.asarray(sigma_s, float).reshape(ny, nx)
-    r = np.asarray(rhs, float).reshape(ny, nx)
+    s1 = None if sigma_s1 is None else np.asarray(sigma_s1, float).reshape(ny, nx)
+    r = np.asarray(rhs, float)
+    r = r.reshape(M, ny, nx) if r.size == M * nx * ny else np.broadcast_to(
+        r.reshape(ny, nx), (M, ny, nx))
 
     def C(m, i, j):
         return m * per + j * nx + i
@@ -74,8 +81,11 @@ def solve_2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, rhs, bc,
                 add(eq, C(m, i, j), st[j, i])
                 if coupled:
                     for k in range(M):
-                        add(eq, C(k, i, j), -ss[j, i] * w[k])
-                b[eq] = r[j, i]
+                        g = ss[j, i]
+                        if s1 is not None:
+                            g += 3.0 * s1[j, i] * (mu[m] * mu[k] + eta[m] * eta[k])
+                        add(eq, C(k, i, j), -g * w[k])
+                b[eq] = r[m, j, i]
                 eq += 1
                 add(eq, C(m, i, j), 1.0)
                 add(eq, X(m, i + 1, j), -0.5)
@@ -106,12 +116,17 @@ def solve_2d(nx, ny, lx, ly, mu, eta, w, sigma_t, sigma_s, rhs, bc,
     A = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
     x = spla.spsolve(A.tocsc(), b)
     phi = np.zeros((ny, nx))
+    jx = np.zeros((ny, nx))
+    jy = np.zeros((ny, nx))
     for m in range(M):
-        phi += w[m] * x[m * per:m * per + nC].reshape(ny, nx)
-    return phi
+        psi = x[m * per:m * per + nC].reshape(ny, nx)
+        phi += w[m] * psi
+        jx += w[m] * mu[m] * psi
+        jy += w[m] * eta[m] * psi
+    return (phi, (jx, jy)) if return_current else phi
 
 
-def solve_1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0)):
+def solve_1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0), sigma_s1=None):
     """Coupled 1-D DD system (cell and face fluxes of every direction)."""
     M = len(mu)
     dx = lx / nx
@@ -119,6 +134,7 @@ def solve_1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0)):
     N = M * per
     st = np.asarray(sigma_t, float).reshape(-1)
     ss = np.asarray(sigma_s, float).reshape(-1)
+    s1 = None if sigma_s1 is None else np.asarray(sigma_s1, float).reshape(-1)
     qq = np.asarray(q, float).reshape(-1)
     rows, cols, vals = [], [], []
     b = np.zeros(N)
@@ -137,7 +153,8 @@ def solve_1d(nx, lx, mu, w, sigma_t, sigma_s, q, bc=(0, 0)):
             add(eq, F0 + i, -mu[m] / dx)
             add(eq, C0 + i, st[i])
             for k in range(M):
-                add(eq, k * per + i, -ss[i] * w[k])
+                g = ss[i] + (0.0 if s1 is None else 3.0 * s1[i] * mu[m] * mu[k])
+                add(eq, k * per + i, -g * w[k])
             b[eq] = qq[i]
             eq += 1
             add(eq, C0 + i, 1.0)

@@ -211,6 +211,25 @@ def test_batched_uneven_256_full(env):
         assert et < 1e-5
 
 
+def test_sync_checks_change_nothing(env):
+    """The debugging switch (a synchronisation and error check after every
+    HIP step) leaves the results bit for bit as they are."""
+    torch, B, ctx = env
+    insts = [I.random_instance(40, 24, seed=61, bc=(1, 0, 0, 0)),
+             I.random_instance(64, 64, seed=62)]
+    quad = I.level_symmetric_2d(8)
+    rc0, st0, p0 = _solve(env, insts, quad, 1e-7)
+    ctx.set_sync_checks(True)
+    try:
+        rc1, st1, p1 = _solve(env, insts, quad, 1e-7)
+    finally:
+        ctx.set_sync_checks(False)
+    assert rc0 == rc1 == 0
+    assert [s["iterations"] for s in st0] == [s["iterations"] for s in st1]
+    for a, b in zip(p0, p1):
+        assert np.array_equal(a, b)
+
+
 def test_autotune_picks_a_valid_shape(env):
     """The autotuner leaves a measured launch shape on the context; solves
     under it agree with the planner's choice to FP32 rounding."""
