@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--recast-max", type=int, default=30)
     ap.add_argument("--no-eigen", action="store_true",
                     help="skip the k-eigenvalue measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the uneven-batch and network-grid legs")
     ap.add_argument("--weights", default=None,
                     help="trained network parameters (default: the packaged file)")
     return ap.parse_args()
@@ -188,6 +190,91 @@ def rel_l2_vs_refs(args, warm, zero, torch):
             e.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
         out[name] = e
         out[name + "_max"] = max(e)
+    return out
+
+
+def uneven_leg(B, I, torch, args):
+    """The 256-instance uneven batch (sides 32..128, 4 x 4-block sigma_t,
+    c in [0.5, 0.95], S8) solved from zero in one batched call, on its own
+    context (the planner's launch shape): median wall time of three solves,
+    cell-angle updates/s, and the sweep kernel's time per launch."""
+    wl = I.batched_uneven(256)
+    f = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    probs = [B.Problem(sigma_t=f(i.sigma_t), sigma_s=f(i.sigma_s), source=f(i.source),
+                       lx=i.lx, ly=i.ly) for i in wl.instances]
+    quad = B.Quad.from_inputs(wl.quad)
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    ctx = B.Context()
+    ctx.set_stop_rule(args.stop)
+    plan = ctx.sweep_plan(probs, quad)
+    B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)   # warm-up
+    times, ups = [], 0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ups = sum(s["iterations"] * i.cells for s, i in zip(st, wl.instances)) * wl.quad.n_dir
+    ctx.profile(True)
+    B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    med = float(np.median(times))
+    its = [s["iterations"] for s in st]
+    log(f"[bench] uneven batch: {med * 1e3:.1f} ms, {ups / med:.3e} updates/s")
+    return {"workload": wl.name, "ms": med * 1e3, "status": rc,
+            "cell_angle_updates_per_s": ups / med, "iterations_min_max": [min(its), max(its)],
+            "sweep_plan": plan,
+            "sweep_ms_per_launch": prof["sweep_ms"] / max(1, prof["sweep_launches"]),
+            "sweep_launches": prof["sweep_launches"]}
+
+
+def network_grid_leg(model, B, I, torch, args):
+    """Warm start against zero start on the network's own 64 x 64 grid (the
+    sinusoidal and random-line families, 64 instances each, S8): wall time
+    of the whole step (recast guess + source iteration) against the
+    zero-start solve, medians of three, with iteration counts (own context:
+    the planner's launch shape)."""
+    out = {}
+    ctx = B.Context()
+    ctx.set_stop_rule(args.stop)
+    f = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    for family in ("sinusoid", "line"):
+        wl = I.fno_eval_set(family, count=64)
+        probs = [B.Problem(sigma_t=f(i.sigma_t), sigma_s=f(i.sigma_s), source=f(i.source),
+                           lx=i.lx, ly=i.ly) for i in wl.instances]
+        quad = B.Quad.from_inputs(wl.quad)
+        phis = [torch.zeros_like(p.sigma_t) for p in probs]
+
+        def zero():
+            return B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)[1], None
+
+        def warm():
+            _, sg = B.no_recast_guess(ctx, model, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR,
+                                      args.recast_tol, args.recast_max, phis)
+            return B.tr_solve(ctx, probs, quad, phis, phis, args.tol, args.max_iter)[1], sg
+        res = {}
+        for name, fn in (("zero", zero), ("warm", warm)):
+            fn()
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, sg = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[name + "_ms"] = float(np.median(ts)) * 1e3
+            res[name + "_si_iterations_mean"] = float(np.mean([s["iterations"] for s in st]))
+            res[name + "_si_iterations_max"] = int(max(s["iterations"] for s in st))
+            if sg is not None:
+                res["recast_iterations_mean"] = float(np.mean([s["iterations"] for s in sg]))
+        res["time_reduction"] = 1.0 - res["warm_ms"] / res["zero_ms"]
+        out[family] = res
+        log(f"[bench] 64^2 {family}: warm {res['warm_ms']:.1f} ms, zero {res['zero_ms']:.1f} ms")
+    out["workload"] = "fno_eval families, 64 x 64 instances, S8"
+    ctx.close()
     return out
 
 
@@ -448,6 +535,9 @@ def main():
     eigen = None
     if model is not None and not args.no_eigen:
         eigen = eigen_leg(ctx, model, B, I, torch, args)
+    uneven = None if args.no_extra else uneven_leg(B, I, torch, args)
+    netgrid = (None if args.no_extra or model is None
+               else network_grid_leg(model, B, I, torch, args))
 
     if args.calib_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -497,6 +587,8 @@ def main():
         "roofline": roof,
         "network": network,
         "eigen": eigen,
+        "uneven_batch_256": uneven,
+        "warm_vs_zero_64": netgrid,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

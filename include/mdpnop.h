@@ -48,12 +48,24 @@ typedef struct no_model no_model;
  * Uniform cells: dx = lx/nx, dy = ly/ny (ny = 1, ly ignored when dim = 1).
  * Requirements: sigma_t > 0, 0 <= sigma_s <= sigma_t, all values finite;
  * sigma_a = sigma_t - sigma_s must not vanish everywhere unless some face is
- * vacuum.  bc = {x-, x+, y-, y+} (tr_bc); only bc[0..1] are used in 1-D.   */
+ * vacuum.  bc = {x-, x+, y-, y+} (tr_bc); only bc[0..1] are used in 1-D.
+ * sigma_s1: first Legendre moment of the scattering cross section (linearly
+ * anisotropic scattering, section 5.1 Eq. 25), a DEVICE field like
+ * sigma_s with |sigma_s1| <= sigma_s, or NULL for isotropic scattering.  The
+ * emission of direction Omega_m is then
+ *     sigma_s phi + 3 sigma_s1 Omega_m . J + S,  J = sum_m w_m Omega_m psi_m,
+ * with J of the previous sweep (the paper's 1/2 and 3/2 factors belong to
+ * its weights summing to 2).  Read by tr_solve / tr_solve_noalloc (a 2-D
+ * solve with it runs the generic sweep, one direction per lane); not by
+ * tr_sweep (a bare sweep has no current) nor by no_recast_guess (the
+ * network sees only the isotropic problem, Eq. 23); the eigenvalue solvers
+ * reject it.                                                              */
 typedef struct {
     int32_t dim, nx, ny;
     double lx, ly;
     const float *sigma_t, *sigma_s, *source;
     int32_t bc[4];
+    const float *sigma_s1;
 } tr_problem;
 
 /* Discrete ordinates (section 5.1: S_N angular discretisation).  HOST

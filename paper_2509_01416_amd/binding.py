@@ -48,7 +48,7 @@ class TrProblem(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("lx", ctypes.c_double),
                 ("ly", ctypes.c_double), ("sigma_t", ctypes.c_void_p),
                 ("sigma_s", ctypes.c_void_p), ("source", ctypes.c_void_p),
-                ("bc", ctypes.c_int32 * 4)]
+                ("bc", ctypes.c_int32 * 4), ("sigma_s1", ctypes.c_void_p)]
 
 
 class TrQuadrature(ctypes.Structure):
@@ -146,13 +146,15 @@ def load(path: str = LIB_PATH):
 
 @dataclass
 class Problem:
-    """One instance: device tensors sigma_t, sigma_s, source (float32)."""
+    """One instance: device tensors sigma_t, sigma_s, source (float32), and
+    optionally sigma_s1 (linearly anisotropic scattering)."""
     sigma_t: object
     sigma_s: object
     source: object
     lx: float = 10.0
     ly: float = 10.0
     bc: tuple = (0, 0, 0, 0)
+    sigma_s1: object = None
 
     @property
     def dim(self) -> int:
@@ -178,10 +180,12 @@ def _ptr(t) -> Optional[int]:
 def make_problems(problems: Sequence[Problem]):
     arr = (TrProblem * len(problems))()
     for i, p in enumerate(problems):
-        for t in (p.sigma_t, p.sigma_s, p.source):
+        for t in (p.sigma_t, p.sigma_s, p.source, p.sigma_s1):
             if t is not None and (str(t.dtype) != "torch.float32"
                                   or t.device.type != "cuda"):
                 raise ValueError("fields must be float32 GPU tensors")
+        if p.sigma_s1 is not None and p.sigma_s1.numel() != p.nx * p.ny:
+            raise ValueError(f"problem {i}: sigma_s1 must have {p.nx * p.ny} cells")
         arr[i].dim = p.dim
         arr[i].nx = p.nx
         arr[i].ny = p.ny
@@ -190,6 +194,7 @@ def make_problems(problems: Sequence[Problem]):
         arr[i].sigma_t = _ptr(p.sigma_t)
         arr[i].sigma_s = _ptr(p.sigma_s)
         arr[i].source = _ptr(p.source)
+        arr[i].sigma_s1 = _ptr(p.sigma_s1)
         for f in range(4):
             arr[i].bc[f] = int(p.bc[f]) if f < len(p.bc) else 0
     return arr

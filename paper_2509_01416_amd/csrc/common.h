@@ -33,6 +33,10 @@ struct InstDesc {
     const float *phi_init;         // warm start or nullptr
     float *snap;                   // iterate kStopStride iterations back
                                    // (error-bound stopping rule) or nullptr
+    const float *ss1;              // first Legendre moment of scattering
+                                   // (P1) or nullptr (isotropic)
+    float *Ex, *Ey;                // P1 emission fields 3 sigma_s1 J (Ey: 2-D)
+    float *partJ;                  // 2-D P1: current planes [2][P][cells]
     int dim, nx, ny, nf, cells;
     int R;                         // rows per lane segment (64, 32, 16)
     int S;                         // direction slices per octant

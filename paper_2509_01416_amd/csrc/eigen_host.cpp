@@ -296,7 +296,9 @@ extern "C" tr_status tr_eigen(tr_context* ctx, int32_t n_inst, const tr_problem*
         e.phi.push_back(phi_out[i]);
         e.k0.push_back(k_init ? k_init[i] : 1.0);
     }
-    if (!check_problems(c, n_inst, e.pp.data(), true)) return TR_ERR_INVALID_ARG;
+    if (!check_problems(c, n_inst, e.pp.data(), true) ||
+        reject_anisotropic(c, n_inst, e.pp.data(), "tr_eigen"))
+        return TR_ERR_INVALID_ARG;
     return run_eigen(c, e, q, tol_k, tol_phi, tol_inner, max_outer, max_inner, stats, t0);
 }
 
@@ -381,6 +383,8 @@ extern "C" tr_status tr_eigen_mg(tr_context* ctx, int32_t n_inst, const tr_probl
         }
         e.k0.push_back(k_init ? k_init[i] : 1.0);
     }
-    if (!check_problems(c, n_inst * G, e.pp.data(), true)) return TR_ERR_INVALID_ARG;
+    if (!check_problems(c, n_inst * G, e.pp.data(), true) ||
+        reject_anisotropic(c, n_inst * G, e.pp.data(), "tr_eigen_mg"))
+        return TR_ERR_INVALID_ARG;
     return run_eigen(c, e, q, tol_k, tol_phi, tol_inner, max_outer, max_inner, stats, t0);
 }

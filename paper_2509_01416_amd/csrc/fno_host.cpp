@@ -766,7 +766,7 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
 // then the outer update P of eigen.hip (k, normalisation, convergence).
 namespace mdp {
 void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks, const int* done,
-                    double2* red, int mode, int norm_kind, hipStream_t s);
+                    double2* red, int mode, int norm_kind, hipStream_t s, const DirTable* dt);
 }
 
 extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst,
@@ -822,7 +822,8 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
         }
         pp[i].source = P.sigma_t;   // placeholder for the check
     }
-    if (!check_problems(c, B, pp.data(), true)) return TR_ERR_INVALID_ARG;
+    if (!check_problems(c, B, pp.data(), true) || reject_anisotropic(c, B, pp.data(), "no_eigen"))
+        return TR_ERR_INVALID_ARG;
     Ws w;
     if (!workspace(c, m, B, false, &w)) return ws_status(c);
     FnoWork* fw = c->fno;
@@ -939,7 +940,7 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
         if (variant == NO_EIGEN_CP) {
             launch_eig_emission(nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, s);
             if (!c->launch_sweep(su, B, d_done, nullptr, 0)) return TR_ERR_HIP;
-            launch_combine(nblocks, su.d_inst, su.d_blocks, d_done, su.d_red, 1, 0, s);
+            launch_combine(nblocks, su.d_inst, su.d_blocks, d_done, su.d_red, 1, 0, s, su.d_dt);
         }
         launch_eig_update(B, 1, nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, su.d_bpart,
                           su.st, tol_k, tol_phi, outer == max_outer ? 1 : 0, s);

@@ -23,14 +23,16 @@ namespace mdp {
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
                     size_t lds_bytes, const InstDesc* insts,
                     const SweepWork* work, const DirTable* dt, const int* done,
-                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s);
-size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx);
+                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s,
+                    bool p1);
+size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx, bool p1);
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                          const int* done, const int* iter, bool tally, const FinArgs& fin,
                          hipStream_t s);
 size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx);
-int sweep2d_max_kb(int W, int R);
+int sweep2d_max_kb(int W, int R, bool p1);
+bool sweep2d_generic_fits(int W, int KB, int R, bool p1);
 int sweep2d_fast_max_kb(int W);
 int sweep2d_max_w(int D);
 void launch_sweep1d(int n_inst, const InstDesc* insts, const DirTable* dt,
@@ -43,7 +45,7 @@ void launch_init(int n_inst, int nblocks, const InstDesc* insts,
                  const int* skip, hipStream_t s);
 void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     const int* done, double2* red, int mode, int norm_kind,
-                    hipStream_t s);
+                    hipStream_t s, const DirTable* dt);
 void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,
                      IterState st, double tol, int norm_kind, hipStream_t s);
 void launch_balance(int n_inst, int nblocks, const InstDesc* insts, const int4* blocks,
@@ -185,6 +187,16 @@ bool build_dirtable(Ctx* c, const tr_quadrature* q, int dim, DirTable* t) {
 }
 
 // ---------------------------------------------------------- arguments ----
+
+bool reject_anisotropic(Ctx* c, int n_inst, const tr_problem* p, const char* who) {
+    for (int i = 0; i < n_inst; ++i)
+        if (p[i].sigma_s1 != nullptr) {
+            c->fail("problem %d: %s supports isotropic scattering only (sigma_s1 must be NULL)",
+                    i, who);
+            return true;
+        }
+    return false;
+}
 
 bool check_problems(Ctx* c, int n_inst, const tr_problem* p, bool need_xs) {
     if (n_inst <= 0 || !p) {
@@ -358,11 +370,13 @@ int oct_waves(int nd, int R, int D) {
 }
 }  // namespace
 
-Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
+Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool p1) {
     Plan pl;
     int nd = 0;
     for (int o = 0; o < 4; ++o) nd = std::max(nd, dt.count[o]);
-    pl.D = c->force_D > 0 ? c->force_D : 1;
+    // anisotropic (P1) emission: the generic kernel with one direction per lane
+    pl.p1 = p1;
+    pl.D = p1 ? 1 : (c->force_D > 0 ? c->force_D : 1);
     pl.R.assign(n_inst, 1);
     auto model = [&](const std::vector<int>& Rs) {
         double work = 0.0, tmax = 0.0;
@@ -442,14 +456,14 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
     // the specialised kernel: 64-row segments everywhere, vacuum faces only,
     // D <= 4, and nx >= 63 + KB (lane 0's ring column is then always written
     // in an earlier block)
-    bool fast = !c->force_generic && pl.D <= 4;
+    bool fast = !c->force_generic && pl.D <= 4 && !p1;
     int nxmin = 1 << 30;
     for (int i = 0; i < n_inst; ++i) {
         fast = fast && pl.R[i] == 64;
         for (int f = 0; f < 4; ++f) fast = fast && p[i].bc[f] == TR_BC_VACUUM;
         nxmin = std::min(nxmin, p[i].nx);
     }
-    const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax));
+    const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax, p1));
     if (fast) {
         int kb = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_fast_max_kb(W));
         while (kb > 2 && (nxmin < 63 + kb || sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) > c->lds_limit))
@@ -464,9 +478,10 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt) {
     }
     pl.fast = false;
     pl.KB = kb0;
-    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax) > c->lds_limit) pl.KB /= 2;
+    while (pl.KB > 2 && sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax, p1) > c->lds_limit)
+        pl.KB /= 2;
     pl.KB = std::max(pl.KB, 2);
-    pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax);
+    pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax, p1);
     return pl;
 }
 
@@ -478,23 +493,37 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     const int dim = p[0].dim;
     if (!build_dirtable(this, q, dim, &su->dt)) return false;
     const int M = su->dt.M;
+    // linearly anisotropic scattering in a source iteration (a bare sweep
+    // has no current to feed it): every problem of the launch then carries
+    // the emission fields and current planes
+    bool p1 = false;
+    if (!emission)
+        for (int i = 0; i < n_inst; ++i) p1 = p1 || p[i].sigma_s1 != nullptr;
     if (dim == 2) {
         for (int o = 0; o < 4; ++o)
             if (su->dt.count[o] != su->dt.count[0]) {
                 fail("quadrature: octants hold different direction counts");
                 return false;
             }
-        su->plan = make_plan(this, n_inst, p, su->dt);
+        su->plan = make_plan(this, n_inst, p, su->dt, p1);
         if (su->plan.lds > lds_limit) {
             fail("grid too wide for the sweep's LDS ring (nx=%d)", p[0].nx);
             return false;
         }
+        if (!su->plan.fast)
+            for (int i = 0; i < n_inst; ++i)
+                if (!sweep2d_generic_fits(su->plan.W, su->plan.KB, su->plan.R[i], p1)) {
+                    fail("internal: launch shape W=%d KB=%d R=%d exceeds the sweep's "
+                         "staging slots", su->plan.W, su->plan.KB, su->plan.R[i]);
+                    return false;
+                }
     }
     su->inst.resize(n_inst);
     su->blocks.clear();
     su->work.clear();
     size_t off = 0;
-    std::vector<size_t> offQ(n_inst), offP(n_inst), offF(n_inst), offS(n_inst);
+    std::vector<size_t> offQ(n_inst), offP(n_inst), offF(n_inst), offS(n_inst), offE(n_inst),
+        offJ(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const tr_problem& P = p[i];
         InstDesc& d = su->inst[i];
@@ -541,6 +570,15 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         if (snapshots) {
             offS[i] = off;
             off += align_up(sizeof(float) * d.cells);
+        }
+        if (p1) {
+            d.ss1 = P.sigma_s1;
+            offE[i] = off;   // Ex (and Ey in 2-D)
+            off += align_up(sizeof(float) * (size_t)(dim == 1 ? 1 : 2) * d.cells);
+            if (dim == 2) {
+                offJ[i] = off;
+                off += align_up(sizeof(float) * (size_t)2 * d.P * d.cells);
+            }
         }
     }
     // XCD-aware order: workgroup b of a launch runs on XCD b % kXcds, so
@@ -626,6 +664,9 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
         d.part = (float*)(b + offP[i]);
         d.face = (float*)(b + offF[i]);
         d.snap = snapshots ? (float*)(b + offS[i]) : nullptr;
+        d.Ex = p1 ? (float*)(b + offE[i]) : nullptr;
+        d.Ey = p1 && d.dim == 2 ? d.Ex + d.cells : nullptr;
+        d.partJ = p1 && d.dim == 2 ? (float*)(b + offJ[i]) : nullptr;
     }
     su->d_inst = (InstDesc*)(b + oInst);
     su->d_work = (SweepWork*)(b + oWork);
@@ -677,7 +718,7 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
                                       tally, fa, stream)
                 : launch_sweep2d(su.plan.D, refl && use_faces, (int)su.work.size(),
                                  su.plan.W, su.plan.KB, su.plan.lds, su.d_inst, su.d_work,
-                                 su.d_dt, done, iter, use_faces, fa, stream);
+                                 su.d_dt, done, iter, use_faces, fa, stream, su.plan.p1);
         if (!ok) {
             fail("unsupported directions-per-lane D=%d", su.plan.D);
             return false;
@@ -716,7 +757,7 @@ bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, in
             const int l = done_iters + it + 1;
             const int mode = norm_kind != 2 ? 0 : (l % kStopStride == 0 ? 2 : 3);
             launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, su.st.done,
-                           su.d_red, mode, norm_kind, stream);
+                           su.d_red, mode, norm_kind, stream, su.d_dt);
             if (!fused_fin || it + 1 == k)
                 launch_finalize(n_inst, su.d_inst, su.d_red, su.st, atol, norm_kind, stream);
             if (p1) prof_end();
@@ -815,7 +856,7 @@ extern "C" tr_status tr_sweep(tr_context* ctx, int32_t n_inst, const tr_problem*
         return c->err.rfind("out of", 0) == 0 ? TR_ERR_OOM : TR_ERR_INVALID_ARG;
     if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return TR_ERR_HIP;
     launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, nullptr,
-                   su.d_red, 1, 0, c->stream);
+                   su.d_red, 1, 0, c->stream, su.d_dt);
     if (!c->hip_ok(hipGetLastError(), "combine launch")) return TR_ERR_HIP;
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "sync")) return TR_ERR_HIP;
     return TR_OK;
@@ -1138,7 +1179,9 @@ extern "C" tr_status tr_get_sweep_plan(tr_context* ctx, int32_t n_inst,
         delete dt;
         return TR_ERR_INVALID_ARG;
     }
-    Plan pl = make_plan(c, n_inst, p, *dt);
+    bool p1 = false;
+    for (int i = 0; i < n_inst; ++i) p1 = p1 || p[i].sigma_s1 != nullptr;
+    Plan pl = make_plan(c, n_inst, p, *dt, p1);
     delete dt;
     out6[0] = pl.D;
     out6[1] = pl.W;

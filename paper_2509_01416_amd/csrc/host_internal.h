@@ -44,6 +44,7 @@ void* noalloc_scratch(int device, size_t* bytes);
 struct Plan {
     int D = 1, W = 1, KB = 16;
     bool fast = false;   // specialised kernel (R = 64 everywhere, vacuum faces)
+    bool p1 = false;     // anisotropic (P1) emission: generic kernel, D = 1
     size_t lds = 0;
     std::vector<int> R, S;
 };
@@ -116,6 +117,9 @@ struct Ctx {
 size_t align_up(size_t x);
 bool build_dirtable(Ctx* c, const tr_quadrature* q, int dim, DirTable* t);
 bool check_problems(Ctx* c, int n_inst, const tr_problem* p, bool need_xs);
-Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt);
+// true (with the message set) if a problem carries P1 scattering
+bool reject_anisotropic(Ctx* c, int n_inst, const tr_problem* p, const char* who);
+Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt,
+               bool p1 = false);
 
 }  // namespace mdp

@@ -37,9 +37,11 @@ __global__ void sweep1d_kernel(const InstDesc* __restrict__ insts,
         float in = (use_faces && I.bc[fin] == 1) ? fprev[fin * M + dt->mirx[m]] : 0.f;
         float* part = I.part + (size_t)m * I.cells;
         const int nx = I.nx;
+        const float* Ex = I.Ex;   // P1 emission 3 sigma_s1 J, or none
         for (int ii = 0; ii < nx; ++ii) {
             const int i = pos ? ii : nx - 1 - ii;
-            const float psi = fmaf(a, in, I.Q[i]) * __builtin_amdgcn_rcpf(I.st[i] + a);
+            const float qm = Ex != nullptr ? fmaf(mu, Ex[i], I.Q[i]) : I.Q[i];
+            const float psi = fmaf(a, in, qm) * __builtin_amdgcn_rcpf(I.st[i] + a);
             in = psi + psi - in;
             part[i] = wm * psi;
         }
@@ -68,6 +70,11 @@ scan_part_kernel(const InstDesc* __restrict__ insts, const int4* __restrict__ bl
         if (!isfinite(st) || !isfinite(ss) || !isfinite(q)) bad |= 1;
         if (I.phi_init != nullptr && !isfinite(I.phi_init[c])) bad |= 1;
         if (!(st > 0.f) || ss < 0.f || ss > st) bad |= 2;
+        if (I.ss1 != nullptr) {   // P1: |sigma_s1| <= sigma_s (mean cosine in [-1, 1])
+            const float s1 = I.ss1[c];
+            if (!isfinite(s1)) bad |= 1;
+            else if (fabsf(s1) > ss) bad |= 2;
+        }
         mx = fmaxf(mx, st - ss);
     }
     __shared__ int sbad[256];
@@ -119,6 +126,8 @@ __global__ void init_cells_kernel(const InstDesc* __restrict__ insts,
         I.phi[c] = p;
         I.Q[c] = fmaf(I.ss[c], p, I.q[c]);
         if (I.snap != nullptr) I.snap[c] = p;
+        if (I.Ex != nullptr) I.Ex[c] = 0.f;   // no current before the first sweep
+        if (I.Ey != nullptr) I.Ey[c] = 0.f;
     }
 }
 
@@ -209,6 +218,29 @@ __device__ __forceinline__ void combine_norm(float old, float s, int norm_kind, 
     }
 }
 
+// P1 emission of the next sweep from the current of this one: the 1-D
+// planes are per direction (w psi), so J = sum_m mu_m plane_m; the 2-D
+// sweep writes current planes beside the flux planes.  Fixed order.
+__device__ __forceinline__ void combine_p1(const InstDesc& I, int c, const DirTable* dt) {
+    if (I.dim == 1) {
+        const float* pp = I.part + c;
+        float j = 0.f;
+        for (int p = 0; p < I.P; ++p) j = fmaf(dt->mu[p], pp[(size_t)p * I.cells], j);
+        I.Ex[c] = I.ss1 != nullptr ? 3.0f * I.ss1[c] * j : 0.f;
+        return;
+    }
+    const float* px = I.partJ + c;
+    const float* py = I.partJ + (size_t)I.P * I.cells + c;
+    float jx = 0.f, jy = 0.f;
+    for (int p = 0; p < I.P; ++p) {
+        jx += px[(size_t)p * I.cells];
+        jy += py[(size_t)p * I.cells];
+    }
+    const float k = I.ss1 != nullptr ? 3.0f * I.ss1[c] : 0.f;
+    I.Ex[c] = k * jx;
+    I.Ey[c] = k * jy;
+}
+
 __device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
                                              int mode, int norm_kind, CellAcc& a) {
     if (mode == 1) {
@@ -225,7 +257,8 @@ __device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
 __global__ void __launch_bounds__(kCombineThreads)
 combine_kernel(const InstDesc* __restrict__ insts,
                const int4* __restrict__ blocks, const int* __restrict__ done,
-               double2* __restrict__ red, int mode, int norm_kind) {
+               double2* __restrict__ red, int mode, int norm_kind,
+               const DirTable* __restrict__ dt) {
     const int4 bi = blocks[blockIdx.x];
     const int n = bi.x;
     if (n < 0) return;
@@ -238,7 +271,8 @@ combine_kernel(const InstDesc* __restrict__ insts,
                         reinterpret_cast<uintptr_t>(I.q) | reinterpret_cast<uintptr_t>(I.Q) |
                         reinterpret_cast<uintptr_t>(I.snap)) &
                        15) == 0;
-    if ((cells & 3) == 0 && (al16 || mode == 1) &&
+    const bool p1 = I.Ex != nullptr && mode != 1;
+    if ((cells & 3) == 0 && (al16 || mode == 1) && !p1 &&
         (reinterpret_cast<uintptr_t>(I.phi) & 15) == 0) {
         // four cells per thread: every plane load of a thread in flight at
         // once (8 at a time), the cell fields read and written as float4
@@ -287,6 +321,7 @@ combine_kernel(const InstDesc* __restrict__ insts,
             float s = 0.f;
             for (int p = 0; p < P; ++p) s += pp[(size_t)p * cells];
             combine_cell(I, c, s, mode, norm_kind, acc);
+            if (p1) combine_p1(I, c, dt);
         }
     }
     if (mode == 1 || mode == 3) return;
@@ -479,9 +514,9 @@ void launch_init(int n_inst, int nblocks, const InstDesc* insts,
 
 void launch_combine(int nblocks, const InstDesc* insts, const int4* blocks,
                     const int* done, double2* red, int mode, int norm_kind,
-                    hipStream_t s) {
+                    hipStream_t s, const DirTable* dt) {
     hipLaunchKernelGGL(combine_kernel, dim3(nblocks), dim3(kCombineThreads), 0, s,
-                       insts, blocks, done, red, mode, norm_kind);
+                       insts, blocks, done, red, mode, norm_kind, dt);
 }
 
 void launch_finalize(int n_inst, const InstDesc* insts, const double2* red,

@@ -32,6 +32,10 @@
 //     reproducible (no floating-point atomics);
 //   * angular fluxes never leave the chip except on boundary faces, which are
 //     stored for reflective inflow (lagged one iteration) and leakage.
+//   * linearly anisotropic scattering (P1, section 5.1 Eq. 25; generic
+//     kernel, one direction per lane): the emission of direction m is
+//     Q + mu_m Ex + eta_m Ey with Ex, Ey = 3 sigma_s1 J staged like Q, and
+//     the waves also sum w mu psi and w eta psi into current planes.
 #include "common.h"
 
 namespace mdp {
@@ -85,7 +89,7 @@ __device__ __forceinline__ int cursor_cell(Cursor c, int rr, int R, int nx,
 // REFL: some inflow face of this launch is reflective (face loads inside the
 // step loop); the vacuum instance has no global loads in the loop at all.
 // KB: steps per block (a power of two); the step loop is fully unrolled.
-template <int D, bool REFL, int KB>
+template <int D, bool REFL, int KB, bool P1 = false>
 __global__ void __launch_bounds__(SweepBounds<D>::threads)
 sweep2d_kernel(const InstDesc* __restrict__ insts,
                const SweepWork* __restrict__ work,
@@ -122,7 +126,11 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     const bool rx = REFL && use_faces && I.bc[fxin] == 1;
     const bool ry = REFL && use_faces && I.bc[fyin] == 1;
 
-    float a[D], b[D], c[D], w[D];
+    static_assert(!P1 || D == 1, "anisotropic emission: one direction per lane");
+    constexpr int NF = P1 ? 4 : 2;    // staged fields: sigma_t, Q (, Ex, Ey)
+    constexpr int NPB = P1 ? 3 : 1;   // partial sums: phi (, Jx, Jy)
+    constexpr int MPF = P1 ? 2 * kMaxPrefetch : kMaxPrefetch;   // staging slots per thread
+    float a[D], b[D], c[D], w[D], smu[D], seta[D];
     int mi[D], mxr[D], myr[D];
     const int nd = dt->count[o];
     const int base = wk.slice * (W * nseg * D) + (wv * nseg + seg) * D;
@@ -134,11 +142,13 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
             a[d] = 2.0f * dt->amu[m] * I.inv_dx;
             b[d] = 2.0f * dt->aeta[m] * I.inv_dy;
             w[d] = dt->w[m];
+            smu[d] = dt->mu[m];
+            seta[d] = dt->eta[m];
             mi[d] = m;
             mxr[d] = dt->mirx[m];
             myr[d] = dt->miry[m];
         } else {
-            a[d] = 0.f; b[d] = 0.f; w[d] = 0.f;
+            a[d] = 0.f; b[d] = 0.f; w[d] = 0.f; smu[d] = 0.f; seta[d] = 0.f;
             mi[d] = -1; mxr[d] = 0; myr[d] = 0;
         }
         c[d] = a[d] + b[d];
@@ -146,7 +156,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     // one direction per wave and one segment per wave (D = 1, R = 64): the
     // direction weight is applied in the cross-wave sums instead of the
     // step, as the specialised kernel does (same operations, same order)
-    const bool fold = D == 1 && nseg == 1;
+    const bool fold = !P1 && D == 1 && nseg == 1;
     const float wm = fold ? 1.0f : w[0];
     __shared__ float wsh[16];   // weight of each wave's direction (W <= 16)
     if (tid < 16) {
@@ -154,31 +164,38 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
         wsh[tid] = tid < W && kk < nd ? dt->w[dt->list[o][kk]] : 0.f;
     }
 
-    // LDS: pbuf[2][KB][W*64+1] | sbuf[2][2][KB][65] | ring[W][nseg][D][nx]
+    // LDS: pbuf[NPB][2][KB][W*64+1] | sbuf[2][NF][KB][65] | ring[W][nseg][D][nx]
     //      | sink[W][D][nx] (target of the ring store of non-writing lanes).
     // The +1 pads make the block-level staging stores and reduction reads,
     // whose consecutive threads step through KB rows, conflict-free.
     const int PSTR = W * 64 + 1;
+    const int PBS = 2 * KB * PSTR;   // one partial-sum buffer
     float* pbuf = smem;
-    float* sbuf = smem + 2 * KB * PSTR;
-    float* rings = sbuf + 4 * KB * 65;
+    float* sbuf = smem + NPB * PBS;
+    float* rings = sbuf + 2 * NF * KB * 65;
     float* ring = rings + (size_t)((wv * nseg + seg) * D) * nx;
     float* sink = rings + (size_t)W * nseg * D * nx + (size_t)wv * D * nx;
     const int nblk = (ny + R - 1) >> lr;
     const int T = nblk * nx + R - 1;
     cgfloat* __restrict__ St = (cgfloat*)I.st;
     cgfloat* __restrict__ Qb = (cgfloat*)I.Q;
+    cgfloat* __restrict__ Exb = (cgfloat*)I.Ex;
+    cgfloat* __restrict__ Eyb = (cgfloat*)I.Ey;
     gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
+    gfloat* __restrict__ partx =
+        P1 ? (gfloat*)(I.partJ + (size_t)(o * I.S + wk.slice) * I.cells) : nullptr;
+    gfloat* __restrict__ party =
+        P1 ? (gfloat*)(I.partJ + (size_t)(I.P + o * I.S + wk.slice) * I.cells) : nullptr;
 
     // Staging slots of this thread: element e = (field, row, step) packed as
     // f << (lr+lkb) | rr << lkb | t2; each keeps a cursor for its (step, row).
-    const int nstage = 2 * KB * R;
+    const int nstage = NF * KB * R;
     const int npf = (nstage + nthreads - 1) / nthreads;   // slots in use
-    float pf[kMaxPrefetch];
-    bool pv[kMaxPrefetch];
-    Cursor sc[kMaxPrefetch];
+    float pf[MPF];
+    bool pv[MPF];
+    Cursor sc[MPF];
 #pragma unroll
-    for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+    for (int jx = 0; jx < MPF; ++jx) {
         const int e = tid + jx * nthreads;
         sc[jx].ip = (e & (KB - 1)) - ((e >> lkb) & (R - 1));
         sc[jx].kk = 0;
@@ -187,9 +204,9 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
     // all addresses first, then unconditional loads back to back (an empty
     // slot reads cell 0); the per-slot default is applied at store time
     auto stage_load = [&]() {
-        int cells[kMaxPrefetch];
+        int cells[MPF];
 #pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+        for (int jx = 0; jx < MPF; ++jx) {
             if (jx >= npf) break;
             const int e = tid + jx * nthreads;
             const int rr = (e >> lkb) & (R - 1);
@@ -199,16 +216,21 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
             sc[jx].advance(KB, nx);
         }
 #pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+        for (int jx = 0; jx < MPF; ++jx) {
             if (jx >= npf) break;
             const int e = tid + jx * nthreads;
-            cgfloat* src = (e >> (lkb + lr)) == 0 ? St : Qb;
+            // field of the slot; padding slots (e >= nstage, f >= NF) read
+            // cell 0 of a field that exists (Ex and Ey only with P1)
+            const int f = e >> (lkb + lr);
+            cgfloat* src = St;
+            if (f == 1) src = Qb;
+            else if (f >= 2) src = P1 ? (f == 2 ? Exb : Eyb) : Qb;
             pf[jx] = src[cells[jx]];
         }
     };
     auto stage_store = [&](int h) {
 #pragma unroll
-        for (int jx = 0; jx < kMaxPrefetch; ++jx) {
+        for (int jx = 0; jx < MPF; ++jx) {
             if (jx >= npf) break;
             const int e = tid + jx * nthreads;
             if (e < nstage) {
@@ -216,7 +238,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
                 const int rr = (e >> lkb) & (R - 1);
                 const int t2 = e & (KB - 1);
                 const float def = f == 0 ? 1.f : 0.f;
-                sbuf[((h * 2 + f) * KB + t2) * 65 + rr] = pv[jx] ? pf[jx] : def;
+                sbuf[((h * NF + f) * KB + t2) * 65 + rr] = pv[jx] ? pf[jx] : def;
             }
         }
     };
@@ -269,6 +291,8 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
         if (ld) stage_load();
         const float st = sp[tt * 65];
         const float q = sp[(KB + tt) * 65];
+        const float ex = P1 ? sp[(2 * KB + tt) * 65] : 0.f;
+        const float ey = P1 ? sp[(3 * KB + tt) * 65] : 0.f;
         // the first lane of every segment sits at the same (step, row 0)
         // position, so its ring column is uniform across the wave
         const int ip0 = __builtin_amdgcn_readfirstlane(ip);
@@ -292,17 +316,32 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 #pragma unroll
             for (int d = 0; d < D; ++d) xin[d] = rowstart ? 0.f : xin[d];
         }
-        float acc = 0.f;
+        float acc = 0.f, accx = 0.f, accy = 0.f;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
+            const float qd = P1 ? fmaf(seta[d], ey, fmaf(smu[d], ex, q)) : q;
             const float rcp = __builtin_amdgcn_rcpf(st + c[d]);
-            const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], q)) * rcp;
+            const float psi = fmaf(a[d], xin[d], fmaf(b[d], yi[d], qd)) * rcp;
             xin[d] = fmaf(psi, 2.0f, -xin[d]);
             yo[d] = fmaf(psi, 2.0f, -yi[d]);
             acc = fmaf(D == 1 ? wm : w[d], psi, acc);
+            if constexpr (P1) {
+                accx = fmaf(w[d] * smu[d], psi, accx);
+                accy = fmaf(w[d] * seta[d], psi, accy);
+            }
         }
-        for (int off = R; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        for (int off = R; off < 64; off <<= 1) {
+            acc += __shfl_xor(acc, off, 64);
+            if constexpr (P1) {
+                accx += __shfl_xor(accx, off, 64);
+                accy += __shfl_xor(accy, off, 64);
+            }
+        }
         pw[tt * PSTR] = acc;   // lanes of later segments land in unread slots
+        if constexpr (P1) {
+            pw[PBS + tt * PSTR] = accx;
+            pw[2 * PBS + tt * PSTR] = accy;
+        }
         // top row of the block hands its y flux to the ring
         float* wdst = wbase + max(ip, 0);
 #pragma unroll
@@ -324,7 +363,7 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
         const int half = blkno & 1;
         const int tend = min(KB, T - t0);
         const bool more = t0 + KB < T;
-        const float* sp = sbuf + half * 2 * KB * 65 + r;
+        const float* sp = sbuf + half * NF * KB * 65 + r;
         float* pw = pbuf + half * KB * PSTR + wv * 64 + lane;
         if (tend == KB) {
 #pragma unroll
@@ -352,6 +391,15 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
                         for (int v = 0; v < W; ++v) s += pb[v * 64];
                     }
                     part[cell] = s;
+                    if constexpr (P1) {
+                        float sx = 0.f, sy = 0.f;
+                        for (int v = 0; v < W; ++v) {
+                            sx += pb[PBS + v * 64];
+                            sy += pb[2 * PBS + v * 64];
+                        }
+                        partx[cell] = sx;
+                        party[cell] = sy;
+                    }
                 }
                 rc_[jx].advance(KB, nx);
             }
@@ -797,29 +845,29 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
 }
 
 // Host launcher; returns false for an unsupported (D, KB).
-template <int D, int KB>
+template <int D, int KB, bool P1 = false>
 static void launch_dk(bool refl, dim3 grid, dim3 block, size_t lds,
                       hipStream_t s, const InstDesc* insts,
                       const SweepWork* work, const DirTable* dt,
                       const int* done, const int* iter, int use_faces, const FinArgs& fin) {
     if (refl)
-        hipLaunchKernelGGL((sweep2d_kernel<D, true, KB>), grid, block, lds, s,
+        hipLaunchKernelGGL((sweep2d_kernel<D, true, KB, P1>), grid, block, lds, s,
                            insts, work, dt, done, iter, use_faces, fin);
     else
-        hipLaunchKernelGGL((sweep2d_kernel<D, false, KB>), grid, block, lds, s,
+        hipLaunchKernelGGL((sweep2d_kernel<D, false, KB, P1>), grid, block, lds, s,
                            insts, work, dt, done, iter, use_faces, fin);
 }
 
-template <int D>
+template <int D, bool P1 = false>
 static bool launch_d(int KB, bool refl, dim3 grid, dim3 block, size_t lds,
                      hipStream_t s, const InstDesc* insts,
                      const SweepWork* work, const DirTable* dt,
                      const int* done, const int* iter, int use_faces, const FinArgs& fin) {
     switch (KB) {
-        case 16: launch_dk<D, 16>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
-        case 8: launch_dk<D, 8>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
-        case 4: launch_dk<D, 4>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
-        case 2: launch_dk<D, 2>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 16: launch_dk<D, 16, P1>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 8: launch_dk<D, 8, P1>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 4: launch_dk<D, 4, P1>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
+        case 2: launch_dk<D, 2, P1>(refl, grid, block, lds, s, insts, work, dt, done, iter, use_faces, fin); return true;
         default: return false;
     }
 }
@@ -881,8 +929,12 @@ size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx) {
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
                     size_t lds_bytes, const InstDesc* insts,
                     const SweepWork* work, const DirTable* dt, const int* done,
-                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s) {
+                    const int* iter, int use_faces, const FinArgs& fin, hipStream_t s,
+                    bool p1) {
     dim3 grid(nwork), block(64 * W);
+    if (p1)
+        return D == 1 && launch_d<1, true>(KB, refl, grid, block, lds_bytes, s, insts, work, dt,
+                                           done, iter, use_faces, fin);
     switch (D) {
         case 1: return launch_d<1>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
         case 2: return launch_d<2>(KB, refl, grid, block, lds_bytes, s, insts, work, dt, done, iter, use_faces, fin);
@@ -894,17 +946,26 @@ bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,
     }
 }
 
-size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx) {
+size_t sweep2d_lds_bytes(int W, int KB, int D, int max_nseg_nx, int max_nx, bool p1) {
     // + 16: the kernel's static table of wave weights
-    return sizeof(float) * ((size_t)2 * KB * (W * 64 + 1) + (size_t)4 * KB * 65 +
+    const size_t npb = p1 ? 3 : 1, nf = p1 ? 4 : 2;
+    return sizeof(float) * (npb * 2 * KB * (W * 64 + 1) + 2 * nf * KB * 65 +
                             (size_t)W * D * max_nseg_nx + (size_t)W * D * max_nx + 16);
+}
+
+// Whether the generic kernel's per-thread staging and reduction slots hold
+// a block of KB steps of R rows with W waves (checked before every launch).
+bool sweep2d_generic_fits(int W, int KB, int R, bool p1) {
+    const int nf = p1 ? 4 : 2, mpf = p1 ? 2 * kMaxPrefetch : kMaxPrefetch;
+    return nf * KB * R <= mpf * 64 * W && KB * R <= kMaxRed * 64 * W;
 }
 
 // Largest block size whose staging fits kMaxPrefetch values and whose
 // reduction fits kMaxRed outputs per thread.
-int sweep2d_max_kb(int W, int R) {
+int sweep2d_max_kb(int W, int R, bool p1) {
+    const int nf = p1 ? 4 : 2, mpf = p1 ? 2 * kMaxPrefetch : kMaxPrefetch;
     int kb = 16;
-    while (kb > 1 && (2 * kb * R > kMaxPrefetch * 64 * W || kb * R > kMaxRed * 64 * W))
+    while (kb > 1 && (nf * kb * R > mpf * 64 * W || kb * R > kMaxRed * 64 * W))
         kb >>= 1;
     return kb;
 }

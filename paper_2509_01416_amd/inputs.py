@@ -348,6 +348,46 @@ def fno_eval_set(family: str, count: int = 64, n: int = 64,
                     level_symmetric_2d(8), tol=1e-6)
 
 
+def paper_slab_p1(case: int, seed: int = 43000) -> Workload:
+    """The paper's 1-D fixed-source setting with linearly anisotropic
+    scattering (section 5.1, Eq. 25): 100 cells over 10 cm, S32
+    Gauss-Legendre, vacuum faces, sigma_s1 = 0.3, a GRF source (mean 0.07,
+    variance 3e-4, correlation length 1.2 cm).  case 2: sigma_t = 1.2,
+    sigma_s0 = 0.8; case 3: sinusoidal sigma_t and sigma_s0 (the paper gives
+    their shapes only in a figure; sigma_t = 1 + 0.2 sin(2 pi x / 5),
+    sigma_s0 = 0.6 + 0.15 sin(2 pi x / 5) stand in)."""
+    n, L = 100, 10.0
+    x = cell_centres(n, L)
+    if case == 2:
+        st, ss = np.full(n, 1.2), np.full(n, 0.8)
+    elif case == 3:
+        st = 1.0 + 0.2 * np.sin(2 * np.pi * x / 5.0)
+        ss = 0.6 + 0.15 * np.sin(2 * np.pi * x / 5.0)
+    else:
+        raise ValueError(case)
+    q = grf_1d(n, L, seed=seed + case, mean=0.07, std=3e-4 ** 0.5, scale=1.2)
+    inst = Instance(nx=n, ny=1, lx=L, ly=1.0, sigma_t=st.reshape(1, n),
+                    sigma_s=ss.reshape(1, n), source=q.reshape(1, n), dim=1,
+                    sigma_s1=np.full((1, n), 0.3))
+    return Workload(f"paper_slab_case{case}_p1", [inst], gauss_legendre(32), tol=1e-6,
+                    description="1-D slab with P1 scattering")
+
+
+def p1_eval_set(count: int = 8, n: int = 64, seed0: int = 42000) -> Workload:
+    """x-y analogue of the paper's Case 2 on the network grid: sigma_t = 1.1,
+    sigma_s0 = 0.85 (sigma_a = 0.25, inside the recast's convergence range
+    around sigma_a* = 0.2), sigma_s1 = 0.3, a GRF source per instance,
+    10 x 10 mfp, vacuum faces, S8."""
+    insts = []
+    for j in range(count):
+        q = grf_2d(n, 10.0, seed=seed0 + j)
+        insts.append(Instance(nx=n, ny=n, lx=10.0, ly=10.0, sigma_t=np.full((n, n), 1.1),
+                              sigma_s=np.full((n, n), 0.85), source=q,
+                              sigma_s1=np.full((n, n), 0.3)))
+    return Workload(f"p1_eval_{count}_{n}", insts, level_symmetric_2d(8), tol=1e-6,
+                    description="Case 2 analogue with P1 scattering")
+
+
 def hard_two_region(count: int = 16, n: int = 256) -> Workload:
     """`count` instances of n^2 cells, LQ S16, sigma_t in {1, 5} split by a
     seeded random line (seed 5000+i), c = 0.99, GRF source, vacuum."""

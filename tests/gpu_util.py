@@ -16,9 +16,10 @@ def to_problem(inst, torch):
     dev = "cuda"
     f = lambda a: torch.tensor(np.asarray(a, dtype=np.float32).reshape(
         (inst.nx,) if inst.dim == 1 else (inst.ny, inst.nx)), device=dev)
+    s1 = getattr(inst, "sigma_s1", None)
     return B.Problem(sigma_t=f(inst.sigma_t), sigma_s=f(inst.sigma_s),
                      source=f(inst.source), lx=inst.lx, ly=inst.ly,
-                     bc=tuple(inst.bc))
+                     bc=tuple(inst.bc), sigma_s1=None if s1 is None else f(s1))
 
 
 def rel_l2(a, b):
