@@ -12,6 +12,8 @@ Contents
     solution operator (the exact transport operator at p* for the closed-form
     check, or a network);
   * ``fno``: FP64 forward/backward of the Fourier neural operator and Adam;
+  * ``deeponet``: FP64 forward/backward of the deep operator network
+    (section 4.1 Eq. 11, Appendix A1);
   * ``eigen``: the k-eigenvalue power iteration (one group: section 5.2
     Eq. 26, Appendix A2 Eq. A1-A4, with the SP/CP variants; three groups
     with downscatter: section 5.3 Eq. 27-29) around the source iteration.
