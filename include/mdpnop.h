@@ -305,6 +305,24 @@ tr_status no_eigen(tr_context *ctx, const no_model *m, int32_t n_inst,
 tr_status no_model_create(tr_context *ctx, no_model **m, int32_t width,
                           int32_t modes, int32_t layers, int32_t grid,
                           const float *params_host);
+/* Deep operator network (section 4.1, Eq. 11; Appendix A1 carried to the
+ * x-y grid): a branch net maps the input field sampled at the grid's
+ * grid*grid cells to `basis` coefficients through layers of `hidden`
+ * units, a trunk net maps each cell centre (x/lx, y/ly) to `basis` values,
+ * and the output at a cell is their inner product.  Both nets are fully
+ * connected with ReLU between layers and linear last layers; no bias on
+ * the inner product.  Supported shape: grid 64, hidden 200, basis 100 (the
+ * paper's hidden sizes; 940,600 parameters).  Parameters (flat FP32, input
+ * index first in every weight matrix):
+ *   W1[P][h], b1[h], W2[h][h], b2[h], W3[h][k], b3[k],   branch (P = grid^2)
+ *   V1[2][h], c1[h], V2[h][h], c2[h], V3[h][k], c3[k]    trunk
+ * The model handle is used like the Fourier operator's by no_forward,
+ * no_train_step, no_recast_guess, no_eigen and the parameter / state calls;
+ * operands are rounded to BF16 on the matrix cores (FP32 with
+ * no_model_set_fp32).  The trunk's basis is kept on the device and
+ * recomputed when the parameters change.                                  */
+tr_status no_model_create_deeponet(tr_context *ctx, no_model **m, int32_t grid,
+                                   int32_t hidden, int32_t basis, const float *params_host);
 void no_model_destroy(no_model *m);
 int64_t no_model_param_count(const no_model *m);
 /* Copy the FP32 master parameters to host memory (param_count floats).   */

@@ -106,8 +106,11 @@ def forward(p: np.ndarray, u: np.ndarray, y: np.ndarray, L: Layout):
     return out, cache
 
 
-def backward(p: np.ndarray, cache: dict, gout: np.ndarray, L: Layout) -> np.ndarray:
-    """Gradient of sum(gout * out) with respect to the flat parameters."""
+def backward(p: np.ndarray, cache: dict, gout: np.ndarray, L: Layout,
+             parts: dict = None) -> np.ndarray:
+    """Gradient of sum(gout * out) with respect to the flat parameters;
+    `parts` (optional dict) also receives the gradients of the
+    pre-activations (gz1, gz2, gt1, gt2) and of coef and basis."""
     q = unpack(p, L)
     g = {}
     gcoef = gout @ cache["basis"]                  # (B, k)
@@ -130,4 +133,6 @@ def backward(p: np.ndarray, cache: dict, gout: np.ndarray, L: Layout) -> np.ndar
     gt1 = (gt2 @ q["V2"].T) * (cache["t1"] > 0)
     g["V1"] = cache["y"].T @ gt1
     g["c1"] = gt1.sum(axis=0)
+    if parts is not None:
+        parts.update(gz1=gz1, gz2=gz2, gt1=gt1, gt2=gt2, gcoef=gcoef, gbasis=gbasis)
     return pack(g, L)

@@ -33,7 +33,7 @@ NO_EIGEN_CP = 1
 
 EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "tr_sweep", "tr_solve", "tr_solve_noalloc", "tr_eigen", "tr_eigen_mg", "no_recast_guess", "no_eigen",
-           "no_model_create",
+           "no_model_create", "no_model_create_deeponet",
            "no_model_destroy", "no_model_param_count", "no_model_get_params",
            "no_model_set_params", "no_model_get_state", "no_model_set_state",
            "no_model_set_fp32", "no_forward",
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
     lib.tr_eigen.argtypes = [vp, i32, P(TrProblem), P(vp), P(TrQuadrature), P(vp), P(vp),
                              P(d), d, d, d, i32, i32, P(TrEigenStats)]
     lib.no_model_create.argtypes = [vp, P(vp), i32, i32, i32, i32, vp]
+    lib.no_model_create_deeponet.argtypes = [vp, P(vp), i32, i32, i32, vp]
     lib.no_model_destroy.argtypes = [vp]
     lib.no_model_destroy.restype = None
     lib.no_model_param_count.argtypes = [vp]
@@ -505,20 +506,30 @@ def sweep_plan(problems_struct, n: int, quad: Quad, handle=None) -> dict:
 # ---------------------------------------------------------------- network
 
 class Model:
-    """no_model handle: the 2-D FNO (width 32, modes 12, 4 layers, 64 x 64)."""
+    """no_model handle: the 2-D FNO (arch "fno": width 32, modes 12, 4
+    layers, 64 x 64) or the DeepONet (arch "deeponet": 64 x 64 sensors,
+    hidden 200, basis 100)."""
 
     def __init__(self, ctx: Context, params: Optional[np.ndarray] = None,
-                 width: int = 32, modes: int = 12, layers: int = 4, grid: int = 64):
+                 width: int = 32, modes: int = 12, layers: int = 4, grid: int = 64,
+                 arch: str = "fno"):
         self.ctx = ctx
         self.lib = ctx.lib
         self.grid = grid
+        self.arch = arch
         h = ctypes.c_void_p()
         buf = None
         if params is not None:
             buf = np.ascontiguousarray(params, dtype=np.float32)
-        rc = self.lib.no_model_create(ctx.handle, ctypes.byref(h), width, modes,
-                                      layers, grid,
-                                      None if buf is None else buf.ctypes.data)
+        ptr = None if buf is None else buf.ctypes.data
+        if arch == "fno":
+            rc = self.lib.no_model_create(ctx.handle, ctypes.byref(h), width, modes,
+                                          layers, grid, ptr)
+        elif arch == "deeponet":
+            rc = self.lib.no_model_create_deeponet(ctx.handle, ctypes.byref(h), grid, 200, 100,
+                                                   ptr)
+        else:
+            raise ValueError(f"unknown network {arch!r}")
         ctx.check(rc, allow=(TR_OK,))
         self.handle = h
         self.n_params = int(self.lib.no_model_param_count(h))

@@ -168,6 +168,7 @@ gemm_kernel(GemmArgs a) {
                     if (a.bias_col) r += a.bias_col[n];
                     a.C.p[oc] = r;
                     if (a.gelu_out) a.gelu_out[oc] = gelu_dev(r);
+                    if (a.relu_out) a.relu_out[oc] = fmaxf(r, 0.f);
                 }
             }
 }
@@ -204,6 +205,7 @@ __global__ void __launch_bounds__(64 * kRedWaves) gemm_reduce_kernel(GemmArgs a)
     if (a.bias_col) r += a.bias_col[n];
     *pc = r;
     if (a.gelu_out) a.gelu_out[pc - a.C.p] = gelu_dev(r);
+    if (a.relu_out) a.relu_out[pc - a.C.p] = fmaxf(r, 0.f);
 }
 
 static long long hidx(int i, int ls, long long hi, long long lo) {

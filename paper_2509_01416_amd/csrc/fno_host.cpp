@@ -1,7 +1,8 @@
 // fno_host.cpp -- the network half of the C ABI: the 2-D Fourier neural
-// operator of section 4.2 / Appendix A1 (model state, forward, hand-written
-// backward, MSE + Adam training step) and the equation-recast loop of Eq. 24
-// that turns the trained network into an initial guess for source iteration.
+// operator of section 4.2 / Appendix A1 and the deep operator network of
+// section 4.1 (model state, forward, hand-written backward, MSE + Adam
+// training step) and the equation-recast loop of Eq. 24 that turns a
+// trained network into an initial guess for source iteration.
 //
 // Every dense contraction goes through one batched matrix-core GEMM with
 // strided views (launch_gemm).  The truncated 2-D real DFT of a 64 x 64
@@ -47,9 +48,22 @@ struct FnoWork {
 
 using namespace mdp;
 
+// DeepONet shape (section 4.1, Appendix A1 carried to x-y): the 64 x 64
+// grid as sensors, hidden width and basis size of the paper's networks.
+constexpr int kDonHidden = 200, kDonBasis = 100;
+
 struct no_model {
     int device = 0;
+    int kind = 0;              // 0 Fourier neural operator, 1 DeepONet
     int width = 0, modes = 0, layers = 0, grid = 0;
+    // DeepONet: parameter offsets, trunk input (cell centres [P][2]) and the
+    // trunk activations t1, g1, t2, g2 [P][h] and basis [P][k], valid while
+    // trunk_ver == param_ver (the basis depends on the parameters only)
+    long long oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+    long long oV1 = 0, oq1 = 0, oV2 = 0, oq2 = 0, oV3 = 0, oq3 = 0;
+    float *coords = nullptr, *t1 = nullptr, *g1 = nullptr, *t2 = nullptr, *g2 = nullptr,
+          *basis = nullptr;
+    long long param_ver = 0, trunk_ver = -1;
     long long n_params = 0;
     long long oW0 = 0, ob0 = 0, oP1 = 0, oc1 = 0, oP2 = 0, oc2 = 0;
     std::vector<long long> oR, oW, ob;
@@ -76,12 +90,59 @@ struct Ws {
     float *gv = nullptr, *gv2 = nullptr, *gz = nullptr, *gh = nullptr;
     float *out = nullptr, *gout = nullptr, *partial = nullptr, *rpart = nullptr;
     double* mse = nullptr;
+    // DeepONet: branch pre-activations and activations [B][h], coefficients
+    // [B][k]; training: their gradients, the basis gradient [P][k], trunk
+    // gradients [P][h] and column-sum partials
+    float *z1 = nullptr, *a1 = nullptr, *z2 = nullptr, *a2 = nullptr, *coef = nullptr;
+    float *gcoef = nullptr, *gb = nullptr, *gz1 = nullptr, *gz2 = nullptr;
+    float *gbasis = nullptr, *gtt = nullptr, *gt1 = nullptr, *gt2 = nullptr, *cpart = nullptr;
 };
 
 constexpr int kMaxKsplit = 1024;
 constexpr int kMsePartials = 256;
 
+// split-K partial buffer of the DeepONet's long contractions: K = P split
+// in slices of 256 (16), times the largest M x N (a 200 x 200 weight, or a
+// branch layer of at most kDonSplitBatch samples)
+constexpr int kDonSplitBatch = 256;
+constexpr long long kDonPartial = (long long)(kP / 256) *
+                                  std::max(kDonHidden * kDonHidden, kDonSplitBatch * kDonHidden);
+
+size_t carve_don(int B, bool train, char* base, Ws* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t bh = 4 * (size_t)B * kDonHidden, bk = 4 * (size_t)B * kDonBasis;
+    w->B = B;
+    w->z1 = (float*)take(bh);
+    w->a1 = (float*)take(bh);
+    w->z2 = (float*)take(bh);
+    w->a2 = (float*)take(bh);
+    w->coef = (float*)take(bk);
+    w->partial = (float*)take(4 * (size_t)kDonPartial);
+    if (train) {
+        w->gcoef = (float*)take(bk);
+        w->gb = (float*)take(bh);
+        w->gz1 = (float*)take(bh);
+        w->gz2 = (float*)take(bh);
+        w->gbasis = (float*)take(4 * (size_t)kP * kDonBasis);
+        w->gtt = (float*)take(4 * (size_t)kP * kDonHidden);
+        w->gt1 = (float*)take(4 * (size_t)kP * kDonHidden);
+        w->gt2 = (float*)take(4 * (size_t)kP * kDonHidden);
+        w->cpart = (float*)take(4 * (size_t)((std::max(kP, B) + kColChunk - 1) / kColChunk) *
+                                kDonHidden);
+        w->out = (float*)take(4 * (size_t)B * kP);
+        w->gout = (float*)take(4 * (size_t)B * kP);
+        w->mse = (double*)take(8 * kMsePartials);
+    }
+    return off;
+}
+
 size_t carve(const no_model* m, int B, bool train, char* base, Ws* w) {
+    if (m->kind == 1) return carve_don(B, train, base, w);
     const long long C = m->width, L = m->layers, mm = m->modes;
     const long long act = (long long)B * C * kP;
     const long long modes = (long long)B * C * 2 * 2 * mm * mm;
@@ -177,8 +238,11 @@ struct Runner {
 
     bool gemm(int M, int N, int K, int G, View A, View B, View C, int acc = 0,
               const float* bias_row = nullptr, float* partial = nullptr,
-              float* gelu_out = nullptr) {
+              float* gelu_out = nullptr, const float* bias_col = nullptr,
+              float* relu_out = nullptr) {
         GemmArgs a;
+        a.bias_col = bias_col;
+        a.relu_out = relu_out;
         a.M = M;
         a.N = N;
         a.K = K;
@@ -201,9 +265,80 @@ struct Runner {
         return ok;
     }
 
+    // DeepONet (section 4.1, Eq. 11).  Trunk on the P cell centres (kept on
+    // the model until the parameters change), branch on the B sampled
+    // inputs, then out[b][p] = sum_k coef[b][k] basis[p][k].
+    void don_trunk() {
+        const float* P = m->params;
+        const int h = kDonHidden, k = kDonBasis;
+        gemm(kP, h, 2, 1, mat(m->coords, 2, 1), mat(P + m->oV1, h, 1), mat(m->t1, h, 1), 0,
+             nullptr, nullptr, nullptr, P + m->oq1, m->g1);
+        gemm(kP, h, h, 1, mat(m->g1, h, 1), mat(P + m->oV2, h, 1), mat(m->t2, h, 1), 0,
+             nullptr, nullptr, nullptr, P + m->oq2, m->g2);
+        gemm(kP, k, h, 1, mat(m->g2, h, 1), mat(P + m->oV3, k, 1), mat(m->basis, k, 1), 0,
+             nullptr, nullptr, nullptr, P + m->oq3);
+    }
+
+    void don_forward(const float* in, float* out, Ws& w, bool train) {
+        const float* P = m->params;
+        const int h = kDonHidden, k = kDonBasis, B = w.B;
+        if (train || const_cast<no_model*>(m)->trunk_ver != m->param_ver) {
+            don_trunk();
+            const_cast<no_model*>(m)->trunk_ver = m->param_ver;
+        }
+        float* split = B <= kDonSplitBatch ? w.partial : nullptr;
+        gemm(B, h, kP, 1, mat(in, kP, 1), mat(P + m->oW1, h, 1), mat(w.z1, h, 1), 0, nullptr,
+             split, nullptr, P + m->ob1, w.a1);
+        gemm(B, h, h, 1, mat(w.a1, h, 1), mat(P + m->oW2, h, 1), mat(w.z2, h, 1), 0, nullptr,
+             nullptr, nullptr, P + m->ob2, w.a2);
+        gemm(B, k, h, 1, mat(w.a2, h, 1), mat(P + m->oW3, k, 1), mat(w.coef, k, 1), 0, nullptr,
+             nullptr, nullptr, P + m->ob3);
+        gemm(B, kP, k, 1, mat(w.coef, k, 1), mat(m->basis, 1, k), mat(out, kP, 1));
+    }
+
+    // Gradient of sum(gout * out) into m->grad (every entry written).
+    void don_backward(const float* in, const float* gout, Ws& w) {
+        const float* P = m->params;
+        float* g = m->grad;
+        const int h = kDonHidden, k = kDonBasis, B = w.B;
+        float* split = B <= kDonSplitBatch ? w.partial : nullptr;
+        gemm(B, k, kP, 1, mat(gout, kP, 1), mat(m->basis, k, 1), mat(w.gcoef, k, 1), 0, nullptr,
+             split);
+        gemm(kP, k, B, 1, mat(gout, 1, kP), mat(w.coef, k, 1), mat(w.gbasis, k, 1));
+        // branch
+        gemm(h, k, B, 1, mat(w.a2, 1, h), mat(w.gcoef, k, 1), mat(g + m->oW3, k, 1));
+        launch_col_sum(w.gcoef, g + m->ob3, B, k, w.cpart, c->stream);
+        gemm(B, h, k, 1, mat(w.gcoef, k, 1), mat(P + m->oW3, 1, k), mat(w.gb, h, 1));
+        launch_relu_back(w.z2, w.gb, w.gz2, (long long)B * h, c->stream);
+        gemm(h, h, B, 1, mat(w.a1, 1, h), mat(w.gz2, h, 1), mat(g + m->oW2, h, 1));
+        launch_col_sum(w.gz2, g + m->ob2, B, h, w.cpart, c->stream);
+        gemm(B, h, h, 1, mat(w.gz2, h, 1), mat(P + m->oW2, 1, h), mat(w.gb, h, 1));
+        launch_relu_back(w.z1, w.gb, w.gz1, (long long)B * h, c->stream);
+        gemm(kP, h, B, 1, mat(in, 1, kP), mat(w.gz1, h, 1), mat(g + m->oW1, h, 1));
+        launch_col_sum(w.gz1, g + m->ob1, B, h, w.cpart, c->stream);
+        // trunk
+        gemm(h, k, kP, 1, mat(m->g2, 1, h), mat(w.gbasis, k, 1), mat(g + m->oV3, k, 1), 0,
+             nullptr, w.partial);
+        launch_col_sum(w.gbasis, g + m->oq3, kP, k, w.cpart, c->stream);
+        gemm(kP, h, k, 1, mat(w.gbasis, k, 1), mat(P + m->oV3, 1, k), mat(w.gtt, h, 1));
+        launch_relu_back(m->t2, w.gtt, w.gt2, (long long)kP * h, c->stream);
+        gemm(h, h, kP, 1, mat(m->g1, 1, h), mat(w.gt2, h, 1), mat(g + m->oV2, h, 1), 0, nullptr,
+             w.partial);
+        launch_col_sum(w.gt2, g + m->oq2, kP, h, w.cpart, c->stream);
+        gemm(kP, h, h, 1, mat(w.gt2, h, 1), mat(P + m->oV2, 1, h), mat(w.gtt, h, 1));
+        launch_relu_back(m->t1, w.gtt, w.gt1, (long long)kP * h, c->stream);
+        gemm(2, h, kP, 1, mat(m->coords, 1, 2), mat(w.gt1, h, 1), mat(g + m->oV1, h, 1), 0,
+             nullptr, w.partial);
+        launch_col_sum(w.gt1, g + m->oq1, kP, h, w.cpart, c->stream);
+    }
+
     // Forward of `B` fields in[b] ([B][P]) -> out ([B][P]); activations kept
     // in w for a following backward.
     void forward(const float* in, float* out, Ws& w, bool keep_h = false) {
+        if (m->kind == 1) {
+            don_forward(in, out, w, keep_h);
+            return;
+        }
         const int C = m->width, L = m->layers, mm = m->modes, B = w.B;
         const float* P = m->params;
         const int G = B * C;
@@ -246,6 +381,10 @@ struct Runner {
 
     // Gradient of sum(gout * out) into m->grad (every entry written).
     void backward(const float* in, const float* gout, Ws& w) {
+        if (m->kind == 1) {
+            don_backward(in, gout, w);
+            return;
+        }
         const int C = m->width, L = m->layers, mm = m->modes, B = w.B;
         const float* P = m->params;
         float* g = m->grad;
@@ -334,7 +473,8 @@ void dft_matrices(int mm, std::vector<float>& FxT, std::vector<float>& Fy,
 }
 
 void free_model(no_model* m) {
-    float* bufs[] = {m->params, m->grad, m->am, m->av, m->FxT, m->Fy, m->Gy, m->Gx};
+    float* bufs[] = {m->params, m->grad, m->am, m->av, m->FxT, m->Fy, m->Gy, m->Gx,
+                     m->coords, m->t1, m->g1, m->t2, m->g2, m->basis};
     for (float* b : bufs)
         if (b) (void)hipFree(b);
     if (m->spec_img) (void)hipFree(m->spec_img);
@@ -445,6 +585,75 @@ extern "C" tr_status no_model_create(tr_context* ctx, no_model** out, int32_t wi
     return TR_OK;
 }
 
+extern "C" tr_status no_model_create_deeponet(tr_context* ctx, no_model** out, int32_t grid,
+                                              int32_t hidden, int32_t basis,
+                                              const float* params_host) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c || !out) return TR_ERR_INVALID_ARG;
+    c->err.clear();
+    *out = nullptr;
+    if (grid != kGrid || hidden != kDonHidden || basis != kDonBasis) {
+        c->fail("unsupported DeepONet shape (grid %d, hidden %d, basis %d); supported: "
+                "%d, %d, %d", grid, hidden, basis, kGrid, kDonHidden, kDonBasis);
+        return TR_ERR_INVALID_ARG;
+    }
+    no_model* m = new (std::nothrow) no_model();
+    if (!m) return TR_ERR_OOM;
+    m->device = c->device;
+    m->kind = 1;
+    m->grid = grid;
+    const long long s_ = kP, d = 2, h = hidden, k = basis;
+    long long o = 0;
+    m->oW1 = o; o += s_ * h;
+    m->ob1 = o; o += h;
+    m->oW2 = o; o += h * h;
+    m->ob2 = o; o += h;
+    m->oW3 = o; o += h * k;
+    m->ob3 = o; o += k;
+    m->oV1 = o; o += d * h;
+    m->oq1 = o; o += h;
+    m->oV2 = o; o += h * h;
+    m->oq2 = o; o += h;
+    m->oV3 = o; o += h * k;
+    m->oq3 = o; o += k;
+    m->n_params = o;
+    const size_t pb = sizeof(float) * (size_t)o;
+    const size_t th = sizeof(float) * (size_t)kP * h;
+    bool good = c->hip_ok(hipMalloc(&m->params, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->grad, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->am, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->av, pb), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->coords, sizeof(float) * 2 * kP), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->t1, th), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->g1, th), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->t2, th), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->g2, th), "hipMalloc") &&
+                c->hip_ok(hipMalloc(&m->basis, sizeof(float) * (size_t)kP * k), "hipMalloc");
+    if (good) {
+        hipStream_t s = c->stream;
+        good = (params_host
+                    ? c->hip_ok(hipMemcpyAsync(m->params, params_host, pb, hipMemcpyHostToDevice, s),
+                                "copy")
+                    : c->hip_ok(hipMemsetAsync(m->params, 0, pb, s), "memset")) &&
+               c->hip_ok(hipMemsetAsync(m->grad, 0, pb, s), "memset") &&
+               c->hip_ok(hipMemsetAsync(m->am, 0, pb, s), "memset") &&
+               c->hip_ok(hipMemsetAsync(m->av, 0, pb, s), "memset");
+        if (good) {
+            launch_grid_coords(m->coords, kGrid, s);
+            good = c->hip_ok(hipGetLastError(), "coords launch");
+        }
+        good = good && c->hip_ok(hipStreamSynchronize(s), "sync");
+    }
+    if (!good) {
+        (void)hipGetLastError();
+        free_model(m);
+        delete m;
+        return TR_ERR_HIP;
+    }
+    *out = m;
+    return TR_OK;
+}
+
 extern "C" void no_model_destroy(no_model* m) {
     if (!m) return;
     int cur = 0;
@@ -495,6 +704,7 @@ extern "C" tr_status no_model_set_params(tr_context* ctx, no_model* m, const flo
         !c->hip_ok(hipMemsetAsync(m->av, 0, pb, c->stream), "memset"))
         return TR_ERR_HIP;
     m->step = 0;
+    m->param_ver += 1;
     return finish(c, "set params");
 }
 
@@ -541,6 +751,7 @@ extern "C" tr_status no_model_set_state(tr_context* ctx, no_model* m, const floa
         !c->hip_ok(hipMemcpyAsync(m->av, adam_v_host, pb, hipMemcpyHostToDevice, c->stream),
                    "copy"))
         return TR_ERR_HIP;
+    m->param_ver += 1;
     const tr_status st = finish(c, "set state");
     if (st == TR_OK) m->step = step;
     return st;
@@ -597,6 +808,7 @@ extern "C" tr_status no_train_step(tr_context* ctx, no_model* m, int32_t batch,
         const float c2 = (float)(1.0 - std::pow(b2, (double)m->step));
         launch_adam(m->params, m->grad, m->am, m->av, m->n_params, (float)lr, (float)b1,
                     (float)b2, 1e-8f, c1, c2, c->stream);
+        m->param_ver += 1;
     }
     double* hp = (double*)c->fno->host.ptr;
     if (!c->hip_ok(hipMemcpyAsync(hp, w.mse, sizeof(double) * nb, hipMemcpyDeviceToHost,

@@ -32,6 +32,7 @@ struct GemmArgs {
     float* partial = nullptr;          // [ksplit][G][M][N] when ksplit > 1
     int f32 = 0;                       // FP32 operands instead of BF16
     float* gelu_out = nullptr;         // also write gelu(C) at C's offsets
+    float* relu_out = nullptr;         // also write max(C, 0) at C's offsets
 };
 
 bool launch_gemm(const GemmArgs& a, hipStream_t s);
@@ -85,5 +86,13 @@ void launch_recast_average(const ResampleDesc* d, int B, int nc, float* S, float
                            hipStream_t s);
 void launch_recast_output(const ResampleDesc* d, int B, int nc, long long max_cells,
                           const float* phi, hipStream_t s);
+
+// DeepONet helpers: g * (z > 0) elementwise, and column sums of an
+// [R][C] row-major matrix in a fixed order (chunks of rows, then chunks in
+// order; scratch holds ceil(R / kColChunk) * C floats).
+constexpr int kColChunk = 128;
+void launch_relu_back(const float* z, const float* g, float* out, long long n, hipStream_t s);
+void launch_col_sum(const float* x, float* out, int R, int C, float* scratch, hipStream_t s);
+void launch_grid_coords(float* xy, int n, hipStream_t s);
 
 }  // namespace mdp

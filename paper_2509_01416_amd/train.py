@@ -36,8 +36,9 @@ from . import binding as B
 from . import inputs as I
 
 GRID = 64
-DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                               "fno2d_w32_m12_l4_g64.npy")
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "fno2d_w32_m12_l4_g64.npy")
+DEEPONET_WEIGHTS = os.path.join(WEIGHTS_DIR, "deeponet2d_h200_k100_g64.npy")
 
 
 def log(msg: str):
@@ -111,7 +112,8 @@ def load_checkpoint(path: str, model, rng):
 
 def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 200,
           batch: int = 32, lr: float = 1e-3, seed: int = 1234, max_epochs: int = 100000,
-          checkpoint: str = None, checkpoint_every: int = 50, resume: bool = False):
+          checkpoint: str = None, checkpoint_every: int = 50, resume: bool = False,
+          arch: str = "fno"):
     import torch
     torch.cuda.set_device(0)
     ctx = B.Context()
@@ -122,8 +124,8 @@ def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 2
     t_data = time.time() - t0
     n_tr = count - n_val
     xtr, ytr, xva, yva = x[:n_tr], y[:n_tr], x[n_tr:], y[n_tr:]
-    init = _init_params(seed)
-    model = B.Model(ctx, init)
+    init = _init_params(seed) if arch == "fno" else _init_deeponet(seed)
+    model = B.Model(ctx, init, arch=arch)
     rng = np.random.Generator(np.random.PCG64(seed))
     hist = []
     best = (float("inf"), 0, None)   # (validation rel L2, epoch, parameters)
@@ -166,7 +168,11 @@ def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 2
     params = model.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(out_path)), exist_ok=True)
     np.save(out_path, params)
-    meta = dict(layout=dict(width=32, modes=12, layers=4, grid=GRID, params=int(params.size)),
+    layout = (dict(arch="fno", width=32, modes=12, layers=4, grid=GRID, params=int(params.size))
+              if arch == "fno" else
+              dict(arch="deeponet", sensors=GRID * GRID, hidden=200, basis=100, grid=GRID,
+                   params=int(params.size)))
+    meta = dict(layout=layout,
                 training=dict(count=count, n_train=n_tr, n_val=n_val, batch=batch, lr=lr,
                               optimizer="Adam(0.9, 0.999, 1e-8)", epochs=epoch, steps=steps,
                               seed=seed, source_seeds=f"40000..{40000 + count - 1}",
@@ -207,10 +213,23 @@ def _init_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def load_weights(path=None) -> np.ndarray:
+def _init_deeponet(seed: int) -> np.ndarray:
+    """Seeded initialisation of the DeepONet (branch [4096, 200, 200, 100],
+    trunk [2, 200, 200, 100]): every weight and bias U(-1/sqrt(fan_in),
+    +1/sqrt(fan_in)), fan_in the input width of its layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fi, fo in ((GRID * GRID, 200), (200, 200), (200, 100), (2, 200), (200, 200), (200, 100)):
+        k = 1.0 / np.sqrt(fi)
+        parts += [rng.uniform(-k, k, size=fi * fo), rng.uniform(-k, k, size=fo)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def load_weights(path=None, arch: str = "fno") -> np.ndarray:
     """Trained parameters (float32 vector) written by train(); the packaged
-    file when path is None."""
-    path = DEFAULT_WEIGHTS if path is None else path
+    file of the network `arch` ("fno" or "deeponet") when path is None."""
+    if path is None:
+        path = DEFAULT_WEIGHTS if arch == "fno" else DEEPONET_WEIGHTS
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path}: no trained network (run "
                                 "`python -m paper_2509_01416_amd.train`)")
@@ -222,7 +241,9 @@ def load_weights(path=None) -> np.ndarray:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--arch", choices=("fno", "deeponet"), default="fno")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--minutes", type=float, default=3.0)
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--max-epochs", type=int, default=100000)
@@ -232,8 +253,10 @@ def main(argv=None):
     ap.add_argument("--resume", action="store_true",
                     help="continue from --checkpoint if it exists")
     a = ap.parse_args(argv)
-    train(a.out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs,
-          checkpoint=a.checkpoint, checkpoint_every=a.checkpoint_every, resume=a.resume)
+    out = a.out or (DEFAULT_WEIGHTS if a.arch == "fno" else DEEPONET_WEIGHTS)
+    train(out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs, lr=a.lr,
+          checkpoint=a.checkpoint, checkpoint_every=a.checkpoint_every, resume=a.resume,
+          arch=a.arch)
 
 
 if __name__ == "__main__":
