@@ -212,7 +212,10 @@ tr_status tr_eigen(tr_context *ctx, int32_t n_inst, const tr_problem *p,
  * Problems must be 2-D.  A problem whose grid differs from the network's
  * (a multiple of it) is block-averaged onto the network grid for the loop
  * and the result is bilinearly interpolated back (cell-centred, edges
- * clamped).  On divergence (non-finite change, or an absolute change that
+ * clamped).  An instance also stops (status TR_OK) when it has stalled
+ * close to the tolerance: the relative change is below 10 tol but no lower
+ * than 0.9 times its value three updates earlier (the network's rounding
+ * floor).  On divergence (non-finite change, or an absolute change that
  * grew three times running past the first update's) phi_guess[i] is zeroed
  * and status TR_RECAST_DIVERGED reported, so that a following tr_solve
  * falls back to the zero start.  Per-instance stats: status (TR_OK,

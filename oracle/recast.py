@@ -19,7 +19,12 @@ universal tolerance) or after max_iter (default 30) updates; declare
 divergence when the change is non-finite, or when the absolute change
 ||phi^(k+1) - phi^(k)||_2 has grown for three consecutive updates and exceeds
 the first update's (a geometric divergence keeps the relative change near the
-constant 1 - 1/gain, so the absolute change is the one that grows).
+constant 1 - 1/gain, so the absolute change is the one that grows); and
+accept as converged a loop that has stalled close to the tolerance: the
+relative change is below 10 tol but no lower than 0.9 times its value three
+updates earlier (a network evaluated in BF16 has a rounding floor of its
+own, about 3e-4 to 2e-3 relative, that a tight tolerance cannot pass; the
+guess is then as good as the network makes it).
 """
 from __future__ import annotations
 
@@ -35,6 +40,11 @@ DIVERGED = 2
 def recast_source(S, sigma_a, sigma_a_star, phi):
     """Eq. 24 right-hand side: S + (sigma_a* - sigma_a) phi."""
     return S + (sigma_a_star - sigma_a) * phi
+
+
+STALL_FACTOR = 10.0     # stall only below this multiple of tol
+STALL_DROP = 0.9        # ... when the change fell by less than this
+STALL_LAG = 3           # ... over this many updates
 
 
 def recast_loop(S: np.ndarray, sigma_a: np.ndarray, sigma_a_star: float,
@@ -58,6 +68,9 @@ def recast_loop(S: np.ndarray, sigma_a: np.ndarray, sigma_a_star: float,
         if not (np.isfinite(d) and np.isfinite(num)):
             return np.zeros_like(phi), DIVERGED, k + 1, hist
         if d < tol:
+            return phi, CONVERGED, k + 1, hist
+        if (k >= STALL_LAG and d < STALL_FACTOR * tol
+                and d > STALL_DROP * hist[k - STALL_LAG]):
             return phi, CONVERGED, k + 1, hist
         grow = grow + 1 if (k >= 1 and num > absd[-2]) else 0
         if grow >= grow_limit and num > absd[0]:

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -907,6 +908,7 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
         return TR_ERR_HIP;
     std::vector<int> status(B, TR_NOT_CONVERGED), iters(B, 0), grow(B, 0);
     std::vector<double> resid(B, 0.0), first(B, 0.0), prev(B, 0.0);
+    std::vector<std::array<double, 4>> dh(B);
     int live = B;
     Runner r{c, m};
     for (int k = 0; k < max_iter && live > 0; ++k) {
@@ -926,9 +928,14 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
             iters[b] = k + 1;
             resid[b] = d;
             int done = -1;
+            dh[b][k % 4] = d;   // relative changes of the last four updates
             if (!std::isfinite(d) || !std::isfinite(num)) {
                 done = TR_RECAST_DIVERGED;
             } else if (d < tol) {
+                done = TR_OK;
+            } else if (k >= 3 && d < 10.0 * tol && d > 0.9 * dh[b][(k - 3) % 4]) {
+                // stalled close to the tolerance: the network's rounding
+                // floor, which a tight tolerance cannot pass
                 done = TR_OK;
             } else {
                 grow[b] = (k >= 1 && num > prev[b]) ? grow[b] + 1 : 0;

@@ -183,7 +183,7 @@ def train(out_path: str, minutes: float = 3.0, count: int = 2000, n_val: int = 2
                 seconds=dict(data=t_data, train=time.time() - t1),
                 validation=dict(rel_l2_mean=float(val.mean()), rel_l2_max=float(val.max()),
                                 rel_l2_median=float(val.median())),
-                history=hist)
+                history=hist[::max(1, len(hist) // 400)])
     with open(os.path.splitext(out_path)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     log(f"saved {out_path}: {epoch} epochs, {steps} steps, validation rel L2 mean "
@@ -244,6 +244,7 @@ def main(argv=None):
     ap.add_argument("--arch", choices=("fno", "deeponet"), default="fno")
     ap.add_argument("--out", default=None)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--minutes", type=float, default=3.0)
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--max-epochs", type=int, default=100000)
@@ -254,7 +255,7 @@ def main(argv=None):
                     help="continue from --checkpoint if it exists")
     a = ap.parse_args(argv)
     out = a.out or (DEFAULT_WEIGHTS if a.arch == "fno" else DEEPONET_WEIGHTS)
-    train(out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs, lr=a.lr,
+    train(out, minutes=a.minutes, count=a.count, max_epochs=a.max_epochs, lr=a.lr, batch=a.batch,
           checkpoint=a.checkpoint, checkpoint_every=a.checkpoint_every, resume=a.resume,
           arch=a.arch)
 

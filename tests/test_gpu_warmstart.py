@@ -160,3 +160,24 @@ def test_pipeline_bitwise_reproducible(env):
         assert np.array_equal(a, b)
     for a, b in zip(p0, p1):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("family", ["sinusoid", "line"])
+def test_trained_deeponet_gain(env, family):
+    """The packaged DeepONet (validation error 1.2e-2 at p*) as the recast
+    operator: the guess cuts the source iterations to 1e-6 against zero
+    start and the answer still reaches the zero-start one (the iteration
+    removes the network's error)."""
+    torch, B, ctx, _ = env
+    from paper_2509_01416_amd import train as T
+    don = B.Model(ctx, T.load_weights(arch="deeponet"), arch="deeponet")
+    wl = I.fno_eval_set(family, count=16)
+    _, zero, warm, iz, iw, sg, ge = _solve_pair(env, wl, model=don)
+    ratio = iw.mean() / iz.mean()
+    log(f"  DeepONet {family}: SI iterations zero {iz.mean():.1f} warm {iw.mean():.1f} "
+        f"(ratio {ratio:.2f}); recast iterations "
+        f"{np.mean([s['iterations'] for s in sg]):.1f}; guess rel L2 median {np.median(ge):.2e}")
+    assert ratio < 0.9
+    for w, z in zip(warm, zero):
+        assert rel_l2(w.cpu().numpy(), z.cpu().numpy()) < 2e-5
+    don.close()

@@ -85,3 +85,36 @@ def test_recast_contraction_rate():
     ratios = [hist[i + 1] / hist[i] for i in range(2, 8)]
     # relative change ||phi_{k+1}-phi_k|| / ||phi_{k+1}||; tends to (c d)
     assert abs(ratios[-1] - c * d) < 1e-3
+
+
+def test_recast_stall_rule():
+    """A pointwise operator with a rounding-like floor (a fixed pattern of
+    relative size 2e-3 flipping sign every update) stalls with a change near
+    4e-3: below 10 tol at tol 1e-3, so the loop stops as converged once the
+    change has not fallen by 10 % over three updates; at tol 1e-4 the floor
+    lies above 10 tol and the loop runs to max_iter.  A clean contraction at
+    rate 0.95 (change falling 14 % per three updates) is never stopped by
+    the rule and reaches the tolerance."""
+    n = 6
+    S = np.linspace(1.0, 2.0, n * n).reshape(n, n)
+    sa = np.full((n, n), 0.1)
+    pattern = np.where(np.arange(n * n).reshape(n, n) % 2 == 0, 1.0, -1.0)
+    calls = []
+
+    def noisy(s):
+        calls.append(1)
+        sign = 1.0 if len(calls) % 2 else -1.0
+        return (s / 0.2) * (1.0 + 2e-3 * sign * pattern)
+    phi, status, k, hist = RC.recast_loop(S, sa, 0.2, noisy, tol=1e-3, max_iter=30)
+    assert status == RC.CONVERGED and hist[-1] > 1e-3 and k < 30
+    assert hist[-1] > RC.STALL_DROP * hist[-1 - RC.STALL_LAG]
+    calls.clear()
+    _, status, k, hist = RC.recast_loop(S, sa, 0.2, noisy, tol=1e-4, max_iter=30)
+    assert status == RC.NOT_CONVERGED and k == 30
+    # contraction at rate 0.95: sigma_a* - sigma_a = 0.95 sigma_a* for the
+    # exact pointwise operator s / sigma_a*
+    _, status, k, hist = RC.recast_loop(S, np.full((n, n), 0.01), 0.2, lambda s: s / 0.2,
+                                        tol=1e-3, max_iter=400)
+    rates = [hist[i + 1] / hist[i] for i in range(5, len(hist) - 1)]
+    assert status == RC.CONVERGED and hist[-1] < 1e-3
+    assert max(rates) < 0.96
