@@ -454,14 +454,15 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
         nxmax = std::max(nxmax, p[i].nx);
     }
     // the specialised kernel: 64-row segments everywhere, vacuum faces only,
-    // D <= 4, and nx >= 63 + KB (lane 0's ring column is then always written
-    // in an earlier block)
+    // D <= 4, and nx >= 63 + KB wherever a grid has more than one row block
+    // (lane 0's ring column is then always written in an earlier block; with
+    // a single block lane 0 only ever reads the vacuum inflow)
     bool fast = !c->force_generic && pl.D <= 4 && !p1;
     int nxmin = 1 << 30;
     for (int i = 0; i < n_inst; ++i) {
         fast = fast && pl.R[i] == 64;
         for (int f = 0; f < 4; ++f) fast = fast && p[i].bc[f] == TR_BC_VACUUM;
-        nxmin = std::min(nxmin, p[i].nx);
+        if (p[i].ny > 64) nxmin = std::min(nxmin, p[i].nx);
     }
     const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax, p1));
     if (fast) {

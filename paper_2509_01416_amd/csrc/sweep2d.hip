@@ -420,12 +420,16 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 
 // ---------------------------------------------------------------------------
 // Specialisation for the common shape: every instance of the launch has
-// 64-row segments (R = 64: a wave is one segment), 64 | ny, nx >= 63 + KB,
-// and only vacuum inflow faces.  Lane l works on u = t - l = k*nx + ip, so
-// with lane 0 at column ip0 the lane that starts a row on step t is the one
-// with (l - ip0) mod nx == 0, and the y flux lane 0 needs on step t was
-// produced by lane 63 on step t - (nx - 63), at least KB + 1 steps (so in an
-// earlier block) before.  That makes every per-step LDS address an immediate
+// 64-row segments (R = 64: a wave is one segment), 64 | ny, nx >= 63 + KB
+// unless ny = 64, and only vacuum inflow faces.  Lane l works on
+// u = t - l = k*nx + ip, so with lane 0 at column ip0 the lane that starts a
+// row on step t is the one with (l - ip0) mod nx == 0, and the y flux lane 0
+// needs on step t was produced by lane 63 on step t - (nx - 63), at least
+// KB + 1 steps (so in an earlier block) before.  With one row block
+// (ny = 64) lane 0 reads only ring columns that lane 63 writes later (63
+// steps after lane 0's read), so the ring still holds the vacuum inflow
+// there, and lane 0's second restart (step 2 nx) lies past the last step
+// (nx + 62), so the tally's x-outflow capture holds as well.  That makes every per-step LDS address an immediate
 // offset from a per-block base and leaves no scalar bookkeeping in the step:
 //   * lane 0 reads its y inflow from a ring of nx + KB entries (the first KB
 //     mirrored at the end, so a block never wraps) and receives it as the

@@ -295,10 +295,14 @@ def test_determinism_and_batch_equals_single(env):
     ([(128, 64)], 16, (3, 4, 0, 64)),
     ([(96, 64)], 4, (1, 1, 0, 64)),
     ([(80, 128), (79, 192)], 8, (1, 2, 0, 64)),
+    # one row block: any nx >= 64, KB not limited by the width
+    ([(64, 64)], 8, (0, 0, 0, 64)),
+    ([(64, 64), (70, 64), (128, 64)], 16, (1, 10, 0, 64)),
+    ([(64, 64), (80, 128)], 8, (0, 0, 0, 64)),
 ])
 def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
-    """The specialised sweep (64-row segments, vacuum faces, nx >= 63 + KB)
-    performs the generic kernel's operations in the same order: sweeps and
+    """The specialised sweep (64-row segments, vacuum faces, nx >= 63 + KB
+    unless the grid is one row block) performs the generic kernel's operations in the same order: sweeps and
     whole solves agree bit for bit, for several launch shapes, block sizes
     (KB from 2 to 16) and ragged widths; the particle balance from its
     final tally sweep closes as well as the generic one."""
