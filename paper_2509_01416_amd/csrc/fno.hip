@@ -19,14 +19,38 @@ namespace mdp {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Round to nearest even (gfx950's conversion instruction).
 __device__ __forceinline__ unsigned short to_bf16(float f) {
-    unsigned u = __builtin_bit_cast(unsigned, f);
-    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 __device__ __forceinline__ float gelu_dev(float z) {
     return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+// GELU for the BF16-operand path, with erfc from the rational approximation
+// of Abramowitz & Stegun 7.1.26 (Hastings): for a >= 0,
+//   erfc(a) ~= t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-a^2),
+//   t = 1 / (1 + p a),  |error| <= 1.5e-7,
+// so gelu(z) = z (1 + erf(z / sqrt 2)) / 2 = (z + |z| (1 - erfc(|z| / sqrt 2))) / 2
+// to within 1e-7 |z|: about half the instructions of erff, far below the
+// BF16 rounding of the operands it feeds.  The FP32 checking mode keeps erff.
+__device__ __forceinline__ float gelu_fast(float z) {
+    const float h = 0.5f * fabsf(z);
+    const float a = h * 1.41421356237309505f;                 // |z| / sqrt 2
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    q = q * t * __builtin_amdgcn_exp2f(a * (a * -1.44269504088896341f));   // erfc(a)
+    return fmaf(-h, q, h) + 0.5f * z;
+}
+
+template <bool F32>
+__device__ __forceinline__ float gelu_op(float z) {
+    if constexpr (F32) return gelu_dev(z);
+    else return gelu_fast(z);
 }
 
 __device__ __forceinline__ long long vidx(int i, int ls, long long hi, long long lo) {
@@ -86,33 +110,50 @@ gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
-        {
-            const int kk = k0 + ak;
-            const float* pa = a.A.p + voff(a.A, g, m0 + am, kk);
+    // The global values of stage k0 + kTK are loaded into registers while
+    // the matrix cores work on stage k0.  Every load is unconditional (an
+    // element outside the operand reads the view's first element instead and
+    // is replaced by zero), so the 16 loads of a thread go out together.
+    float ra[8], rb[8];
+    auto load_stage = [&](int k0) {
+        const int kk = k0 + ak;
+        const float* pa = a.A.p + voff(a.A, g, m0 + am, kk);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int m = a_kfast ? am + 8 * j : am;
-                const int k = a_kfast ? ak : ak + 4 * j;
-                float va = 0.f;
-                if (m0 + m < a.M && k0 + k < kend) va = pa[j * astep];
-                if constexpr (F32) As[m * kPad + k] = va;
-                else As[m * kPad + k] = to_bf16(va);
-            }
+        for (int j = 0; j < 8; ++j) {
+            const int m = a_kfast ? am + 8 * j : am;
+            const int k = a_kfast ? ak : ak + 4 * j;
+            const bool in = m0 + m < a.M && k0 + k < kend;
+            const float v = *(in ? pa + j * astep : a.A.p);
+            ra[j] = in ? v : 0.f;
         }
-        {
-            const float* pb = a.B.p + voff(a.B, g, k0 + bk, n0 + bn);
+        const float* pb = a.B.p + voff(a.B, g, k0 + bk, n0 + bn);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = b_nfast ? bk + 4 * j : bk;
-                const int n = b_nfast ? bn : bn + 8 * j;
-                float vb = 0.f;
-                if (n0 + n < a.N && k0 + k < kend) vb = pb[j * bstep];
-                if constexpr (F32) Bs[n * kPad + k] = vb;
-                else Bs[n * kPad + k] = to_bf16(vb);
-            }
+        for (int j = 0; j < 8; ++j) {
+            const int k = b_nfast ? bk + 4 * j : bk;
+            const int n = b_nfast ? bn : bn + 8 * j;
+            const bool in = n0 + n < a.N && k0 + k < kend;
+            const float v = *(in ? pb + j * bstep : a.B.p);
+            rb[j] = in ? v : 0.f;
+        }
+    };
+    if (kbeg < kend) load_stage(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int m = a_kfast ? am + 8 * j : am;
+            const int k = a_kfast ? ak : ak + 4 * j;
+            if constexpr (F32) As[m * kPad + k] = ra[j];
+            else As[m * kPad + k] = to_bf16(ra[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = b_nfast ? bk + 4 * j : bk;
+            const int n = b_nfast ? bn : bn + 8 * j;
+            if constexpr (F32) Bs[n * kPad + k] = rb[j];
+            else Bs[n * kPad + k] = to_bf16(rb[j]);
         }
         __syncthreads();
+        if (k0 + kTK < kend) load_stage(k0 + kTK);
         if constexpr (F32) {
 #pragma unroll
             for (int kk = 0; kk < kTK; kk += 4) {
@@ -540,11 +581,47 @@ __global__ void recast_input_kernel(const float* __restrict__ S, const float* __
     }
 }
 
-// phi_new = s * out / sa*; FP64 norms of the change and of phi_new.
+// The recast loop's rules for one instance after update k, from the FP64
+// squared norms of the change (d2) and of the new field (n2): converged when
+// the relative change d falls below tol, or when it has stalled close to it
+// (d < 10 tol and less than 10 % below the change three updates earlier:
+// the network's rounding floor); diverged when the change is not finite, or
+// its norm has grown three updates in a row to above the first update's.
+// Returns true when the instance diverged.
+__device__ bool recast_rules(RecastState& s, double d2, double n2, double tol, int k,
+                             int* active) {
+    const double num = sqrt(d2), den = sqrt(n2);
+    const double d = den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);
+    s.iters = k + 1;
+    s.resid = d;
+    int done = -1;
+    s.dh[k & 3] = d;
+    if (!isfinite(d) || !isfinite(num)) {
+        done = kRecastDiverged;
+    } else if (d < tol) {
+        done = kRecastConverged;
+    } else if (k >= 3 && d < 10.0 * tol && d > 0.9 * s.dh[(k - 3) & 3]) {
+        done = kRecastConverged;
+    } else {
+        s.grow = (k >= 1 && num > s.prev) ? s.grow + 1 : 0;
+        if (k == 0) s.first = num;
+        if (s.grow >= 3 && num > s.first) done = kRecastDiverged;
+    }
+    s.prev = num;
+    if (done >= 0) {
+        s.status = done;
+        *active = 0;
+    }
+    return done == kRecastDiverged;
+}
+
+// phi_new = s * out / sa*; FP64 norms of the change and of phi_new; with a
+// state array, the loop's rules for update k (a diverged instance's field is
+// zeroed: the fallback is the zero start).
 __global__ void recast_update_kernel(const float* __restrict__ out, const float* __restrict__ scale,
                                      float inv_sa_star, float* __restrict__ phi,
-                                     double* __restrict__ norms, const int* __restrict__ active,
-                                     int P) {
+                                     double* __restrict__ norms, int* __restrict__ active,
+                                     RecastState* __restrict__ st, double tol, int k, int P) {
     const int b = blockIdx.x;
     if (!active[b]) return;
     const float sc = scale[b] * inv_sa_star;
@@ -595,10 +672,15 @@ __global__ void recast_update_kernel(const float* __restrict__ out, const float*
         }
         __syncthreads();
     }
+    __shared__ int zero_phi;
     if (threadIdx.x == 0) {
         norms[2 * b] = r1[0];
         norms[2 * b + 1] = r2[0];
+        zero_phi = st != nullptr && recast_rules(st[b], r1[0], r2[0], tol, k, active + b);
     }
+    __syncthreads();
+    if (zero_phi)
+        for (int p = threadIdx.x; p < P; p += blockDim.x) fb[p] = 0.f;
 }
 
 // Block averages of every instance's fields onto the network grid (f x f
@@ -804,7 +886,7 @@ mix_mode_back_w_kernel(const float* __restrict__ X, const float* __restrict__ gY
 // sample): wave w computes hidden units 32w..32w+31 for the 64 pixels with
 // 2 x 4 MFMA tiles, applies c1, GELU and P2, reduces its 32 rows, and the
 // four waves' sums are added in wave order.  h is also stored when h_out is
-// given (training needs it).
+// given (training needs it).  P (pixels per sample) is a multiple of 4.
 template <bool F32>
 __global__ void __launch_bounds__(256)
 proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
@@ -819,16 +901,48 @@ proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int p0 = blockIdx.x * NT, b = blockIdx.y;
     const float* vb = v + (long long)b * C * P;
-    for (int e = tid; e < K * C; e += 256) {          // P1[c][k] -> Ws[k][c]
-        const int c = e / K, k = e - c * K;
-        if constexpr (F32) Ws[k * (C + 4) + c] = P1[e];
-        else Ws[k * (C + 4) + c] = to_bf16(P1[e]);
+    const int km = wv * 32;
+    // every global load of the thread first (P % 4 == 0): P1 (four float4),
+    // the tile of v (two float4), and the c1 / P2 entries of its epilogue
+    float4 pr[K * C / 4 / 256], vr[C * NT / 4 / 256];
+#pragma unroll
+    for (int i = 0; i < K * C / 4 / 256; ++i)
+        pr[i] = reinterpret_cast<const float4*>(P1)[tid + 256 * i];
+#pragma unroll
+    for (int i = 0; i < C * NT / 4 / 256; ++i) {
+        const int e4 = tid + 256 * i, c = e4 / (NT / 4), pp = 4 * (e4 % (NT / 4));
+        const bool in = p0 + pp < P;
+        vr[i] = *reinterpret_cast<const float4*>(vb + (long long)c * P + (in ? p0 + pp : 0));
+        if (!in) vr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (int e = tid; e < C * NT; e += 256) {         // v[c][p] -> Vs[p][c]
-        const int c = e / NT, pp = e - c * NT;
-        const float x = p0 + pp < P ? vb[(long long)c * P + p0 + pp] : 0.f;
-        if constexpr (F32) Vs[pp * (C + 4) + c] = x;
-        else Vs[pp * (C + 4) + c] = to_bf16(x);
+    float ck[2][4], pk[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = km + 16 * i + 4 * (lane >> 4) + q;
+            ck[i][q] = c1[k];
+            pk[i][q] = P2[k];
+        }
+#pragma unroll
+    for (int i = 0; i < K * C / 4 / 256; ++i) {          // P1[c][k] -> Ws[k][c]
+        const int e = 4 * (tid + 256 * i), c = e / K, k = e - c * K;
+        const float x[4] = {pr[i].x, pr[i].y, pr[i].z, pr[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (F32) Ws[(k + j) * (C + 4) + c] = x[j];
+            else Ws[(k + j) * (C + 4) + c] = to_bf16(x[j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < C * NT / 4 / 256; ++i) {         // v[c][p] -> Vs[p][c]
+        const int e4 = tid + 256 * i, c = e4 / (NT / 4), pp = 4 * (e4 % (NT / 4));
+        const float x[4] = {vr[i].x, vr[i].y, vr[i].z, vr[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (F32) Vs[(pp + j) * (C + 4) + c] = x[j];
+            else Vs[(pp + j) * (C + 4) + c] = to_bf16(x[j]);
+        }
     }
     __syncthreads();
     f32x4 acc[2][4];
@@ -836,7 +950,6 @@ proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int km = wv * 32;
     if constexpr (F32) {
 #pragma unroll
         for (int kk = 0; kk < C; kk += 4) {
@@ -873,13 +986,12 @@ proj_fused_kernel(const float* __restrict__ v, const float* __restrict__ P1,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = km + 16 * i + 4 * (lane >> 4) + q;
-            const float ck = c1[k], pk = P2[k];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float hv = acc[i][j][q] + ck;
+                const float hv = acc[i][j][q] + ck[i][q];
                 const int pp = 16 * j + (lane & 15);
                 if (h_out && p0 + pp < P) h_out[((long long)b * K + k) * P + p0 + pp] = hv;
-                s[j] = fmaf(pk, gelu_dev(hv), s[j]);
+                s[j] = fmaf(pk[i][q], gelu_op<F32>(hv), s[j]);
             }
         }
     // reduce over the four row groups of the wave (lanes l, l+16, l+32, l+48)
@@ -978,20 +1090,36 @@ __global__ void stage_spec_kernel(const float* __restrict__ FxT, const float* __
 }
 
 // 16-byte copy of `bytes` (a multiple of 16) from global to LDS by 256 threads
-__device__ __forceinline__ void copy16(void* dst, const void* src, int bytes) {
+// Global -> LDS copy of BYTES (a multiple of 16) by 256 threads: all loads
+// of a thread are issued before its stores (a thread past the end reloads
+// the last chunk and stores nothing).
+template <int BYTES>
+__device__ __forceinline__ void copy16(void* dst, const void* src) {
+    static_assert(BYTES % 16 == 0, "16-byte chunks");
+    constexpr int N = BYTES / 16, IT = (N + 255) / 256;
     const uint4* s = reinterpret_cast<const uint4*>(src);
     uint4* d = reinterpret_cast<uint4*>(dst);
-    for (int e = threadIdx.x; e < bytes / 16; e += 256) d[e] = s[e];
+    uint4 r[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) r[i] = s[min((int)threadIdx.x + 256 * i, N - 1)];
+#pragma unroll
+    for (int i = 0; i < IT; ++i)
+        if ((int)threadIdx.x + 256 * i < N) d[threadIdx.x + 256 * i] = r[i];
 }
 
-// 64 x 64 FP32 field -> LDS [y][LV] in the operand precision (float4 loads)
-template <bool F32>
-__device__ __forceinline__ void stage_field(typename Frag<F32>::T* Vs, const float* vg) {
+// 64 x 64 FP32 field -> registers (four float4 per thread), then -> LDS
+// [y][LV] in the operand precision
+__device__ __forceinline__ void load_field(float4 (&r)[4], const float* vg) {
     const float4* v4 = reinterpret_cast<const float4*>(vg);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = v4[threadIdx.x + 256 * k];
+}
+template <bool F32>
+__device__ __forceinline__ void store_field(typename Frag<F32>::T* Vs, const float4 (&r)[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int e = threadIdx.x + 256 * k;        // float4 index: y = e / 16
-        const float4 v = v4[e];
+        const float4 v = r[k];
         typename Frag<F32>::T* d = Vs + (e >> 4) * kSpLV + 4 * (e & 15);
         if constexpr (F32) {
             *reinterpret_cast<float4*>(d) = v;
@@ -1010,10 +1138,13 @@ __device__ __forceinline__ void zero_lds(typename Frag<F32>::T* p, int elems) {
     for (int e = threadIdx.x; e < n16; e += 256) d[e] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-template <bool F32>
+// A workgroup transforms CH consecutive fields: the DFT images are staged
+// once, and the next field's values are loaded while the current one is on
+// the matrix cores.
+template <bool F32, int CH>
 __global__ void __launch_bounds__(256)
 spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __restrict__ img,
-                float* __restrict__ X) {
+                float* __restrict__ X, int G) {
     typedef typename Frag<F32>::T T;
     constexpr int n = 64, mm = 12, LV = kSpLV, LT = kSpLT;
     __shared__ __attribute__((aligned(16))) T Vs[n * LV];          // [y][x]
@@ -1021,39 +1152,46 @@ spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __rest
     __shared__ __attribute__((aligned(16))) T Fys[48 * LT];        // [(q,kyi)][(p,y)]
     __shared__ __attribute__((aligned(16))) T Ts[16 * LT];         // [kx][(p,y)]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const long long g = blockIdx.x;
-    stage_field<F32>(Vs, v + g * n * n);
-    copy16(Fx, img + kImgFx, 32 * LV * (int)sizeof(T));
-    copy16(Fys, img + kImgFy, 48 * LT * (int)sizeof(T));
-    zero_lds<F32>(Ts, 16 * LT);
-    __syncthreads();
-    // T: wave w owns rows 16w..16w+15, both 16-column tiles
+    const long long g0 = (long long)blockIdx.x * CH;
+    float4 fr[4];
+    load_field(fr, v + g0 * n * n);
+    copy16<32 * LV * (int)sizeof(T)>(Fx, img + kImgFx);
+    copy16<48 * LT * (int)sizeof(T)>(Fys, img + kImgFy);
+    zero_lds<F32>(Ts, 16 * LT);   // rows kx >= 12 stay zero
+    for (int ci = 0; ci < CH; ++ci) {
+        const long long g = g0 + ci;
+        if (g >= G) break;
+        store_field<F32>(Vs, fr);
+        __syncthreads();
+        if (ci + 1 < CH && g + 1 < G) load_field(fr, v + (g + 1) * n * n);
+        // T: wave w owns rows 16w..16w+15, both 16-column tiles
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const f32x4 c = tile_mma<F32>(Vs, LV, Fx, LV, 16 * wv, 16 * t, n, lane);
+        for (int t = 0; t < 2; ++t) {
+            const f32x4 c = tile_mma<F32>(Vs, LV, Fx, LV, 16 * wv, 16 * t, n, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int y = 16 * wv + 4 * (lane >> 4) + q, j = 16 * t + (lane & 15);
-            if (j < 2 * mm) Ts[(j % mm) * LT + (j / mm) * n + y] = Frag<F32>::cvt(c[q]);
+            for (int q = 0; q < 4; ++q) {
+                const int y = 16 * wv + 4 * (lane >> 4) + q, j = 16 * t + (lane & 15);
+                if (j < 2 * mm) Ts[(j % mm) * LT + (j / mm) * n + y] = Frag<F32>::cvt(c[q]);
+            }
         }
-    }
-    __syncthreads();
-    // X: waves 0..2 own rows 16w..16w+15 (48 rows), one 16-column tile
-    if (wv < 3) {
-        const f32x4 c = tile_mma<F32>(Fys, LT, Ts, LT, 16 * wv, 0, 128, lane);
-        float* xg = X + g * 48 * mm;
+        __syncthreads();
+        // X: waves 0..2 own rows 16w..16w+15 (48 rows), one 16-column tile
+        if (wv < 3) {
+            const f32x4 c = tile_mma<F32>(Fys, LT, Ts, LT, 16 * wv, 0, 128, lane);
+            float* xg = X + g * 48 * mm;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = 16 * wv + 4 * (lane >> 4) + q, kx = lane & 15;
-            if (kx < mm) xg[r * mm + kx] = c[q];
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * wv + 4 * (lane >> 4) + q, kx = lane & 15;
+                if (kx < mm) xg[r * mm + kx] = c[q];
+            }
         }
     }
 }
 
-template <bool F32>
+template <bool F32, int CH>
 __global__ void __launch_bounds__(256)
 spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __restrict__ img,
-                float* __restrict__ U) {
+                float* __restrict__ U, int G) {
     typedef typename Frag<F32>::T T;
     constexpr int n = 64, mm = 12, LG = kSpLG, LZ = kSpLZ;
     __shared__ __attribute__((aligned(16))) T Gys[128 * LG];       // [(p,y)][(q,kyi)]
@@ -1061,37 +1199,55 @@ spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __rest
     __shared__ __attribute__((aligned(16))) T Zs[n * LZ];          // [y][(p,kx)], 24 of 32 used
     __shared__ __attribute__((aligned(16))) T Gxs[n * LZ];         // [x][(p,kx)]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const long long g = blockIdx.x;
-    const float* yg = Y + g * 48 * mm;
-    copy16(Gys, img + kImgGy, 128 * LG * (int)sizeof(T));
-    copy16(Gxs, img + kImgGx, n * LZ * (int)sizeof(T));
-    for (int e = tid; e < 16 * 48; e += 256) {                     // Y[r][kx] -> Ys[kx][r]
-        const int kx = e / 48, r = e % 48;
-        Ys[kx * LG + r] = Frag<F32>::cvt(kx < mm ? yg[r * mm + kx] : 0.f);
-    }
-    zero_lds<F32>(Zs, n * LZ);
-    __syncthreads();
-    // Z: wave w owns rows 32w..32w+31 (two 16-row tiles), one column tile
+    const long long g0 = (long long)blockIdx.x * CH;
+    // Y[r][kx] -> Ys[kx][r]: three entries per thread (e = tid + 256 i,
+    // kx = e / 48 < 16); entries with kx >= 12 are zero
+    float yr[3];
+    auto load_y = [&](long long g) {
+        const float* yg = Y + g * 48 * mm;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int m0 = 32 * wv + 16 * t;
-        const f32x4 c = tile_mma<F32>(Gys, LG, Ys, LG, m0, 0, 48, lane);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = m0 + 4 * (lane >> 4) + q, kx = lane & 15;   // r = p*64 + y
-            if (kx < mm) Zs[(r & 63) * LZ + (r >> 6) * mm + kx] = Frag<F32>::cvt(c[q]);
+        for (int i = 0; i < 3; ++i) {
+            const int e = tid + 256 * i, kx = e / 48, r = e % 48;
+            yr[i] = yg[r * mm + min(kx, mm - 1)];
+            if (kx >= mm) yr[i] = 0.f;
         }
-    }
-    __syncthreads();
-    // U: wave w owns rows 16w..16w+15, four column tiles
-    float* ug = U + g * n * n;
+    };
+    load_y(g0);
+    copy16<128 * LG * (int)sizeof(T)>(Gys, img + kImgGy);
+    copy16<n * LZ * (int)sizeof(T)>(Gxs, img + kImgGx);
+    zero_lds<F32>(Zs, n * LZ);    // columns (p,kx) >= 24 stay zero
+    for (int ci = 0; ci < CH; ++ci) {
+        const long long g = g0 + ci;
+        if (g >= G) break;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const f32x4 c = tile_mma<F32>(Zs, LZ, Gxs, LZ, 16 * wv, 16 * t, 32, lane);
+        for (int i = 0; i < 3; ++i) {
+            const int e = tid + 256 * i, kx = e / 48, r = e % 48;
+            Ys[kx * LG + r] = Frag<F32>::cvt(yr[i]);
+        }
+        __syncthreads();
+        if (ci + 1 < CH && g + 1 < G) load_y(g + 1);
+        // Z: wave w owns rows 32w..32w+31 (two 16-row tiles), one column tile
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int y = 16 * wv + 4 * (lane >> 4) + q, x = 16 * t + (lane & 15);
-            ug[y * n + x] = c[q];
+        for (int t = 0; t < 2; ++t) {
+            const int m0 = 32 * wv + 16 * t;
+            const f32x4 c = tile_mma<F32>(Gys, LG, Ys, LG, m0, 0, 48, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = m0 + 4 * (lane >> 4) + q, kx = lane & 15;   // r = p*64 + y
+                if (kx < mm) Zs[(r & 63) * LZ + (r >> 6) * mm + kx] = Frag<F32>::cvt(c[q]);
+            }
+        }
+        __syncthreads();
+        // U: wave w owns rows 16w..16w+15, four column tiles
+        float* ug = U + g * n * n;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 c = tile_mma<F32>(Zs, LZ, Gxs, LZ, 16 * wv, 16 * t, 32, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int y = 16 * wv + 4 * (lane >> 4) + q, x = 16 * t + (lane & 15);
+                ug[y * n + x] = c[q];
+            }
         }
     }
 }
@@ -1101,65 +1257,101 @@ spec_inv_kernel(const float* __restrict__ Y, const typename Frag<F32>::T* __rest
 // one real product on the matrix cores in FP32:
 //   [Yr | Yi] (16 x 64) = [Xr | Xi] (16 x 64) . [[Rr, Ri], [-Ri, Rr]] (64 x 64)
 // X, Y: [B][32][2][2m][m] (modes contiguous); R: [2m][m][Ci][Co][2].
-// Four consecutive modes per workgroup, one per wave; the batch runs in
-// tiles of 16 rows (zero-padded).  X is read and Y written as float4 over the
-// four modes.
+// Four consecutive modes per workgroup, one per wave, and one tile of 16
+// batch rows (zero-padded) per workgroup row of the grid.  X is read and Y
+// written as float4 over the four modes.
 constexpr int kMixLA = 64 + 4;
+// Rr / Ri row pitch: 16 mod 32 words, so the two half-waves of a fragment
+// read (k rows k, k + 1 and k + 2, k + 3) each hit 32 distinct banks
+constexpr int kMixLR = 48;
 __global__ void __launch_bounds__(256)
 mix_mma_kernel(const float* __restrict__ X, const float* __restrict__ R,
                float* __restrict__ Y, int B, int plane) {
-    constexpr int C = 32, LA = kMixLA;
-    __shared__ __attribute__((aligned(16))) float As[4 * 16 * LA];   // [mode][b][k]
-    __shared__ __attribute__((aligned(16))) float Bs[4 * 64 * LA];   // [mode][n][k]
-    __shared__ __attribute__((aligned(16))) float Os[16 * 64 * 4];   // [b][n][mode]
+    constexpr int C = 32, LA = kMixLA, LR = kMixLR;
+    // As: [mode][b][k]; Rs: [mode][part][ci][co] (row pitch LR), which after
+    // the products holds Os: [b][n][mode]
+    __shared__ __attribute__((aligned(16))) float As[4 * 16 * LA];
+    __shared__ __attribute__((aligned(16))) float Rs[4 * 2 * C * LR];
+    float* Os = Rs;
+    static_assert(16 * 64 * 4 <= 4 * 2 * C * LR, "output staging fits the weight buffer");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int md0 = 4 * blockIdx.x, per = 2 * plane;
-    // B operand of the four modes: 2048 complex weights each
-    for (int e = tid; e < 4 * C * C / 2; e += 256) {
-        const int j = e >> 9, cc = (e & 511) * 2;            // two complex weights
-        const float4 w = *reinterpret_cast<const float4*>(R + (size_t)(md0 + j) * C * C * 2 + 2 * cc);
-        float* Bj = Bs + j * 64 * LA;
+    const int b0 = 16 * blockIdx.y;
+    // all global loads of a thread first: 8 x two complex weights (the four
+    // modes' 2048 complex weights each), 4 x four modes of X
+    float4 wr[4 * C * C / 2 / 256], xr[16 * C * 2 / 256];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ci = (cc + h) >> 5, co = (cc + h) & 31;
-            const float rr = h ? w.z : w.x, ri = h ? w.w : w.y;
-            Bj[co * LA + ci] = rr;
-            Bj[(32 + co) * LA + ci] = ri;
-            Bj[co * LA + 32 + ci] = -ri;
-            Bj[(32 + co) * LA + 32 + ci] = rr;
-        }
+    for (int i = 0; i < 4 * C * C / 2 / 256; ++i) {
+        const int e = tid + 256 * i;
+        const int j = e >> 9, cc = (e & 511) * 2;
+        wr[i] = *reinterpret_cast<const float4*>(R + (size_t)(md0 + j) * C * C * 2 + 2 * cc);
     }
-    for (int b0 = 0; b0 < B; b0 += 16) {
-        __syncthreads();
-        for (int e = tid; e < 16 * C * 2; e += 256) {        // (b, c, part)
-            const int bb = e >> 6, c = (e >> 1) & 31, part = e & 1;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (b0 + bb < B)
-                x = *reinterpret_cast<const float4*>(X + ((size_t)(b0 + bb) * C + c) * per +
-                                                    part * plane + md0);
-            const int k = part * 32 + c;
-            As[(0 * 16 + bb) * LA + k] = x.x;
-            As[(1 * 16 + bb) * LA + k] = x.y;
-            As[(2 * 16 + bb) * LA + k] = x.z;
-            As[(3 * 16 + bb) * LA + k] = x.w;
-        }
-        __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16 * C * 2 / 256; ++i) {          // (b, c, part)
+        const int e = tid + 256 * i;
+        const int bb = e >> 6, c = (e >> 1) & 31, part = e & 1;
+        const int bs = min(b0 + bb, B - 1);                 // rows past B load row B-1
+        xr[i] = *reinterpret_cast<const float4*>(X + ((size_t)bs * C + c) * per + part * plane +
+                                                 md0);
+        if (b0 + bb >= B) xr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * C * C / 2 / 256; ++i) {
+        const int e = tid + 256 * i;
+        const int j = e >> 9, cc = (e & 511) * 2;            // two complex weights
+        const int ci = cc >> 5, co = cc & 31;
+        float* Rj = Rs + j * 2 * C * LR;
+        Rj[ci * LR + co] = wr[i].x;
+        Rj[(C + ci) * LR + co] = wr[i].y;
+        Rj[ci * LR + co + 1] = wr[i].z;
+        Rj[(C + ci) * LR + co + 1] = wr[i].w;
+    }
+#pragma unroll
+    for (int i = 0; i < 16 * C * 2 / 256; ++i) {
+        const int e = tid + 256 * i;
+        const int bb = e >> 6, c = (e >> 1) & 31, part = e & 1;
+        const float4 x = xr[i];
+        const int k = part * 32 + c;
+        As[(0 * 16 + bb) * LA + k] = x.x;
+        As[(1 * 16 + bb) * LA + k] = x.y;
+        As[(2 * 16 + bb) * LA + k] = x.z;
+        As[(3 * 16 + bb) * LA + k] = x.w;
+    }
+    __syncthreads();
+    // wave wv: mode md0 + wv; output column tiles n0 = 16 t of the 64 x 64
+    // real operand B[n][k] = [[Rr, Ri], [-Ri, Rr]] (n = part_out * 32 + co,
+    // k = part_in * 32 + ci), read from the compact Rr / Ri planes with the
+    // k order of the other matrix-core products
+    f32x4 acc[4];
+    {
+        const float* Aw = As + wv * 16 * LA + (lane & 15) * LA + (lane >> 4);
+        const float* Rw = Rs + wv * 2 * C * LR;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const f32x4 c = tile_mma<true>(As + wv * 16 * LA, LA, Bs + wv * 64 * LA, LA, 0, 16 * t,
-                                           64, lane);
+            acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                Os[((4 * (lane >> 4) + q) * 64 + 16 * t + (lane & 15)) * 4 + wv] = c[q];
+            for (int kk = 0; kk < 2 * C; kk += 4) {
+                const bool im = (t >= 2) != (kk >= C);           // Ri block
+                const float* rb = Rw + ((im ? C : 0) + (kk & (C - 1)) + (lane >> 4)) * LR +
+                                  16 * (t & 1) + (lane & 15);
+                const float bv = (t < 2 && kk >= C) ? -*rb : *rb;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Aw[kk], bv, acc[t], 0, 0, 0);
+            }
         }
-        __syncthreads();
-        for (int e = tid; e < 16 * 64; e += 256) {           // (b, n = part * 32 + co)
-            const int bb = e >> 6, n = e & 63;
-            if (b0 + bb < B)
-                *reinterpret_cast<float4*>(Y + ((size_t)(b0 + bb) * C + (n & 31)) * per +
-                                           (n >> 5) * plane + md0) =
-                    *reinterpret_cast<const float4*>(Os + e * 4);
-        }
+    }
+    __syncthreads();   // every wave is done with Rs
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            Os[((4 * (lane >> 4) + q) * 64 + 16 * t + (lane & 15)) * 4 + wv] = acc[t][q];
+    __syncthreads();
+    for (int e = tid; e < 16 * 64; e += 256) {               // (b, n = part * 32 + co)
+        const int bb = e >> 6, n = e & 63;
+        if (b0 + bb < B)
+            *reinterpret_cast<float4*>(Y + ((size_t)(b0 + bb) * C + (n & 31)) * per +
+                                       (n >> 5) * plane + md0) =
+                *reinterpret_cast<const float4*>(Os + e * 4);
     }
 }
 
@@ -1210,7 +1402,7 @@ pointwise_kernel(const float* __restrict__ W, const float* __restrict__ v,
             r += z[o];
             r += bias[m];
             if (store_z) z[o] = r;
-            if (vn) vn[o] = gelu_dev(r);
+            if (vn) vn[o] = gelu_op<F32>(r);
         }
     }
 }
@@ -1234,7 +1426,7 @@ void launch_gelu_back(const float* z, const float* gv, float* gz, long long n, h
 }
 void launch_mix(const float* X, const float* R, float* Y, int B, int C, int m, hipStream_t s) {
     if (C == 32 && (2 * m * m) % 4 == 0) {
-        hipLaunchKernelGGL(mix_mma_kernel, dim3(2 * m * m / 4), dim3(256), 0, s, X, R, Y, B,
+        hipLaunchKernelGGL(mix_mma_kernel, dim3(2 * m * m / 4, (B + 15) / 16), dim3(256), 0, s, X, R, Y, B,
                            2 * m * m);
         return;
     }
@@ -1274,21 +1466,44 @@ void launch_pointwise(const float* W, const float* v, const float* bias, float* 
         hipLaunchKernelGGL(pointwise_kernel<false>, grid, dim3(256), 0, s, W, v, bias, z, vn, P,
                            store_z);
 }
+// fields per workgroup: the most (up to 8) that still leave a workgroup per CU
+static int spec_fields_per_wg(int G) {
+    int ch = 8;
+    while (ch > 1 && (G + ch - 1) / ch < 256) ch >>= 1;
+    return ch;
+}
+#define MDP_SPEC_LAUNCH(kern)                                                              \
+    template <bool F32>                                                                    \
+    static void launch_##kern(const float* in, const typename Frag<F32>::T* img, float* o,  \
+                              int G, hipStream_t s) {                                      \
+        const int ch = spec_fields_per_wg(G);                                             \
+        const dim3 grid((unsigned)((G + ch - 1) / ch));                                    \
+        switch (ch) {                                                                      \
+            case 8: hipLaunchKernelGGL((kern<F32, 8>), grid, dim3(256), 0, s, in, img, o, G); break; \
+            case 4: hipLaunchKernelGGL((kern<F32, 4>), grid, dim3(256), 0, s, in, img, o, G); break; \
+            case 2: hipLaunchKernelGGL((kern<F32, 2>), grid, dim3(256), 0, s, in, img, o, G); break; \
+            default: hipLaunchKernelGGL((kern<F32, 1>), grid, dim3(256), 0, s, in, img, o, G); break; \
+        }                                                                                  \
+    }
+MDP_SPEC_LAUNCH(spec_fwd_kernel)
+MDP_SPEC_LAUNCH(spec_inv_kernel)
+#undef MDP_SPEC_LAUNCH
+
 void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s) {
     const float* f = reinterpret_cast<const float*>(img);
     if (f32)
-        hipLaunchKernelGGL(spec_fwd_kernel<true>, dim3(G), dim3(256), 0, s, v, f, X);
+        launch_spec_fwd_kernel<true>(v, f, X, G, s);
     else
-        hipLaunchKernelGGL(spec_fwd_kernel<false>, dim3(G), dim3(256), 0, s, v,
-                           reinterpret_cast<const unsigned short*>(f + kImgElems), X);
+        launch_spec_fwd_kernel<false>(v, reinterpret_cast<const unsigned short*>(f + kImgElems),
+                                      X, G, s);
 }
 void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s) {
     const float* f = reinterpret_cast<const float*>(img);
     if (f32)
-        hipLaunchKernelGGL(spec_inv_kernel<true>, dim3(G), dim3(256), 0, s, Y, f, U);
+        launch_spec_inv_kernel<true>(Y, f, U, G, s);
     else
-        hipLaunchKernelGGL(spec_inv_kernel<false>, dim3(G), dim3(256), 0, s, Y,
-                           reinterpret_cast<const unsigned short*>(f + kImgElems), U);
+        launch_spec_inv_kernel<false>(Y, reinterpret_cast<const unsigned short*>(f + kImgElems),
+                                      U, G, s);
 }
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,
@@ -1350,9 +1565,10 @@ void launch_recast_input(const float* S, const float* sa, const float* phi, floa
                        scale, active, P);
 }
 void launch_recast_update(const float* out, const float* scale, float inv_sa_star, float* phi,
-                          double* norms, const int* active, int B, int P, hipStream_t s) {
+                          double* norms, int* active, RecastState* st, double tol, int k,
+                          int B, int P, hipStream_t s) {
     hipLaunchKernelGGL(recast_update_kernel, dim3(B), dim3(256), 0, s, out, scale, inv_sa_star,
-                       phi, norms, active, P);
+                       phi, norms, active, st, tol, k, P);
 }
 void launch_recast_average(const ResampleDesc* d, int B, int nc, float* S, float* sa,
                            hipStream_t s) {

@@ -869,13 +869,14 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
     if (!workspace(c, m, B, false, &w)) return ws_status(c);
     FnoWork* fw = c->fno;
     // recast fields: S, sigma_a, phi, in, out (B x P), scale (B), norms (2B),
-    // active (B), resampling descriptors (B)
+    // active (B), loop state (B), resampling descriptors (B)
     const size_t fb = align_up(4 * (size_t)B * kP);
     const size_t dsz = align_up(sizeof(ResampleDesc) * (size_t)B);
+    const size_t ssz = align_up(sizeof(RecastState) * (size_t)B);
     const size_t need = 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B) +
-                        align_up(4 * (size_t)B) + dsz;
+                        align_up(4 * (size_t)B) + ssz + dsz;
     const size_t hoff = align_up(16 * (size_t)B + 4 * (size_t)B);
-    if (!fw->rc.reserve(c, need) || !fw->host.reserve(c, hoff + dsz))
+    if (!fw->rc.reserve(c, need) || !fw->host.reserve(c, hoff + ssz + dsz))
         return ws_status(c);
     char* base = (char*)fw->rc.base;
     float* S = (float*)base;
@@ -886,11 +887,13 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
     float* scale = (float*)(base + 5 * fb);
     double* norms = (double*)(base + 5 * fb + align_up(4 * (size_t)B));
     int* active = (int*)(base + 5 * fb + align_up(4 * (size_t)B) + align_up(16 * (size_t)B));
-    ResampleDesc* ddesc = (ResampleDesc*)(base + 5 * fb + align_up(4 * (size_t)B) +
-                                          align_up(16 * (size_t)B) + align_up(4 * (size_t)B));
+    RecastState* dst = (RecastState*)(base + 5 * fb + align_up(4 * (size_t)B) +
+                                      align_up(16 * (size_t)B) + align_up(4 * (size_t)B));
+    ResampleDesc* ddesc = (ResampleDesc*)((char*)dst + ssz);
     double* hn = (double*)fw->host.ptr;
     int* hact = (int*)(hn + 2 * B);
-    ResampleDesc* hdesc = (ResampleDesc*)((char*)fw->host.ptr + hoff);
+    RecastState* hst = (RecastState*)((char*)fw->host.ptr + hoff);
+    ResampleDesc* hdesc = (ResampleDesc*)((char*)hst + ssz);
     hipStream_t s = c->stream;
     long long max_cells = 0;
     for (int i = 0; i < B; ++i) {
@@ -898,64 +901,59 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
                                 p[i].nx, fac[i]};
         max_cells = std::max(max_cells, (long long)p[i].nx * p[i].nx);
         hact[i] = 1;
+        hst[i] = RecastState{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0}, kRecastRunning, 0, 0, 0};
     }
+    static_assert(kRecastConverged == TR_OK && kRecastRunning == TR_NOT_CONVERGED &&
+                      kRecastDiverged == TR_RECAST_DIVERGED,
+                  "recast status codes follow tr_status");
     if (!c->hip_ok(hipMemcpyAsync(ddesc, hdesc, sizeof(ResampleDesc) * (size_t)B,
+                                  hipMemcpyHostToDevice, s), "copy") ||
+        !c->hip_ok(hipMemcpyAsync(dst, hst, sizeof(RecastState) * (size_t)B,
                                   hipMemcpyHostToDevice, s), "copy"))
         return TR_ERR_HIP;
     launch_recast_average(ddesc, B, kGrid, S, sa, s);
     if (!c->hip_ok(hipMemsetAsync(phi, 0, 4 * (size_t)B * kP, s), "memset") ||
         !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
         return TR_ERR_HIP;
-    std::vector<int> status(B, TR_NOT_CONVERGED), iters(B, 0), grow(B, 0);
-    std::vector<double> resid(B, 0.0), first(B, 0.0), prev(B, 0.0);
-    std::vector<std::array<double, 4>> dh(B);
-    int live = B;
+    // The rules run on the device after every update (recast_update_kernel),
+    // so several updates go out between read-backs of the loop state: two
+    // first, then as many as the slowest running instance is predicted to
+    // need from its last two relative changes (at most 8).  Updates enqueued
+    // after every instance has stopped skip the per-instance kernels; only
+    // their network forward is spent.
+    int live = B, k = 0, chunk = 2;
     Runner r{c, m};
-    for (int k = 0; k < max_iter && live > 0; ++k) {
-        launch_recast_input(S, sa, phi, (float)sa_star, in, scale, active, B, kP, s);
-        r.forward(in, out, w);
-        if (!r.ok) return TR_ERR_INVALID_ARG;
-        launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, B, kP, s);
-        if (!c->hip_ok(hipMemcpyAsync(hn, norms, 16 * (size_t)B, hipMemcpyDeviceToHost, s), "copy"))
+    while (k < max_iter && live > 0) {
+        const int n = std::min(chunk, max_iter - k);
+        for (int j = 0; j < n; ++j, ++k) {
+            launch_recast_input(S, sa, phi, (float)sa_star, in, scale, active, B, kP, s);
+            r.forward(in, out, w);
+            if (!r.ok) return TR_ERR_INVALID_ARG;
+            launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, dst,
+                                 tol, k, B, kP, s);
+        }
+        if (!c->hip_ok(hipMemcpyAsync(hst, dst, sizeof(RecastState) * (size_t)B,
+                                      hipMemcpyDeviceToHost, s), "copy") ||
+            !c->hip_ok(hipMemcpyAsync(hact, active, 4 * (size_t)B, hipMemcpyDeviceToHost, s),
+                       "copy"))
             return TR_ERR_HIP;
         const tr_status st = finish(c, "recast launch");
         if (st != TR_OK) return st;
-        bool changed = false;
+        live = 0;
+        int want = 1;
         for (int b = 0; b < B; ++b) {
             if (!hact[b]) continue;
-            const double num = std::sqrt(hn[2 * b]), den = std::sqrt(hn[2 * b + 1]);
-            const double d = den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);
-            iters[b] = k + 1;
-            resid[b] = d;
-            int done = -1;
-            dh[b][k % 4] = d;   // relative changes of the last four updates
-            if (!std::isfinite(d) || !std::isfinite(num)) {
-                done = TR_RECAST_DIVERGED;
-            } else if (d < tol) {
-                done = TR_OK;
-            } else if (k >= 3 && d < 10.0 * tol && d > 0.9 * dh[b][(k - 3) % 4]) {
-                // stalled close to the tolerance: the network's rounding
-                // floor, which a tight tolerance cannot pass
-                done = TR_OK;
-            } else {
-                grow[b] = (k >= 1 && num > prev[b]) ? grow[b] + 1 : 0;
-                if (k == 0) first[b] = num;
-                if (grow[b] >= 3 && num > first[b]) done = TR_RECAST_DIVERGED;
+            ++live;
+            const double d = hst[b].resid;
+            const double d0 = k >= 2 ? hst[b].dh[(k - 2) & 3] : 0.0;
+            int nb = 1;
+            if (d > 0.0 && d0 > d && tol > 0.0) {
+                const double left = std::log(tol / d) / std::log(d / d0);
+                nb = left >= 8.0 ? 8 : std::max(1, (int)std::ceil(left));
             }
-            prev[b] = num;
-            if (done >= 0) {
-                status[b] = done;
-                hact[b] = 0;
-                --live;
-                changed = true;
-                if (done == TR_RECAST_DIVERGED &&
-                    !c->hip_ok(hipMemsetAsync(phi + (size_t)b * kP, 0, 4 * (size_t)kP, s), "memset"))
-                    return TR_ERR_HIP;
-            }
+            want = std::max(want, nb);
         }
-        if (changed && live > 0 &&
-            !c->hip_ok(hipMemcpyAsync(active, hact, 4 * (size_t)B, hipMemcpyHostToDevice, s), "copy"))
-            return TR_ERR_HIP;
+        chunk = want;
     }
     launch_recast_output(ddesc, B, kGrid, max_cells, phi, s);
     const tr_status st = finish(c, "recast output");
@@ -964,11 +962,11 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = TR_OK;
     for (int i = 0; i < B; ++i) {
-        worst = std::max(worst, status[i]);
+        worst = std::max(worst, hst[i].status);
         if (stats) {
-            stats[i].status = status[i];
-            stats[i].iterations = iters[i];
-            stats[i].residual = resid[i];
+            stats[i].status = hst[i].status;
+            stats[i].iterations = hst[i].iters;
+            stats[i].residual = hst[i].resid;
             stats[i].balance_rel = NAN;
             stats[i].seconds = secs;
         }
@@ -1155,7 +1153,8 @@ extern "C" tr_status no_eigen(tr_context* ctx, const no_model* m, int32_t n_inst
         launch_recast_input(Sf, sa, phi, (float)sa_star, in, scale, active, B, kP, s);
         r.forward(in, out, w);
         if (!r.ok) return TR_ERR_INVALID_ARG;
-        launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, B, kP, s);
+        launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, nullptr,
+                             0.0, 0, B, kP, s);
         if (variant == NO_EIGEN_CP) {
             launch_eig_emission(nblocks, su.d_inst, su.d_blocks, d_ed, d_es, d_done, s);
             if (!c->launch_sweep(su, B, d_done, nullptr, 0)) return TR_ERR_HIP;

@@ -73,8 +73,24 @@ void launch_adam(float* p, const float* g, float* m, float* v, long long n, floa
 void launch_recast_input(const float* S, const float* sa, const float* phi, float sa_star,
                          float* in, float* scale, const int* active, int B, int P,
                          hipStream_t s);
+// Per-instance state of the recast loop's stopping and divergence rules,
+// kept on the device so that several updates run between read-backs.
+// status codes: 0 = converged, 1 = running / not converged, 2 = diverged.
+struct RecastState {
+    double resid;     // relative change of the last update
+    double first;     // norm of the first update's change
+    double prev;      // norm of the previous update's change
+    double dh[4];     // relative changes of the last four updates
+    int status, iters, grow, pad;
+};
+constexpr int kRecastConverged = 0, kRecastRunning = 1, kRecastDiverged = 2;
+// phi_new = scale * out / sa*, FP64 norms of the change; with st != nullptr
+// the update also applies the loop's rules for update k (tolerance tol):
+// a stopped instance's active flag is cleared, and a diverged one's field
+// is zeroed.
 void launch_recast_update(const float* out, const float* scale, float inv_sa_star, float* phi,
-                          double* norms, const int* active, int B, int P, hipStream_t s);
+                          double* norms, int* active, RecastState* st, double tol, int k,
+                          int B, int P, hipStream_t s);
 // Per-instance resampling between a problem's grid (nf x nf, f = nf / nc)
 // and the network grid (nc x nc).
 struct ResampleDesc {
