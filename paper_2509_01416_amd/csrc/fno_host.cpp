@@ -108,6 +108,8 @@ constexpr int kMsePartials = 256;
 constexpr int kDonSplitBatch = 256;
 constexpr long long kDonPartial = (long long)(kP / 256) *
                                   std::max(kDonHidden * kDonHidden, kDonSplitBatch * kDonHidden);
+static_assert((kDonHidden + 31) / 32 <= kP / 256,
+              "the split hidden layers fit the partial buffer");
 
 size_t carve_don(int B, bool train, char* base, Ws* w) {
     size_t off = 0;
@@ -240,7 +242,7 @@ struct Runner {
     bool gemm(int M, int N, int K, int G, View A, View B, View C, int acc = 0,
               const float* bias_row = nullptr, float* partial = nullptr,
               float* gelu_out = nullptr, const float* bias_col = nullptr,
-              float* relu_out = nullptr) {
+              float* relu_out = nullptr, int ksplit = 0) {
         GemmArgs a;
         a.bias_col = bias_col;
         a.relu_out = relu_out;
@@ -256,7 +258,7 @@ struct Runner {
         a.gelu_out = gelu_out;
         a.f32 = m->f32;
         if (partial && G == 1) {
-            a.ksplit = std::max(1, std::min(kMaxKsplit, K / 256));
+            a.ksplit = std::max(1, std::min(kMaxKsplit, ksplit > 0 ? ksplit : K / 256));
             a.partial = partial;
         }
         if (!launch_gemm(a, c->stream)) {
@@ -290,10 +292,13 @@ struct Runner {
         float* split = B <= kDonSplitBatch ? w.partial : nullptr;
         gemm(B, h, kP, 1, mat(in, kP, 1), mat(P + m->oW1, h, 1), mat(w.z1, h, 1), 0, nullptr,
              split, nullptr, P + m->ob1, w.a1);
+        // the two 200-deep layers: one 32-wide K stage per workgroup (a
+        // handful of output tiles would otherwise walk seven stages each)
+        const int ks = (h + 31) / 32;
         gemm(B, h, h, 1, mat(w.a1, h, 1), mat(P + m->oW2, h, 1), mat(w.z2, h, 1), 0, nullptr,
-             nullptr, nullptr, P + m->ob2, w.a2);
+             split, nullptr, P + m->ob2, w.a2, ks);
         gemm(B, k, h, 1, mat(w.a2, h, 1), mat(P + m->oW3, k, 1), mat(w.coef, k, 1), 0, nullptr,
-             nullptr, nullptr, P + m->ob3);
+             split, nullptr, P + m->ob3, nullptr, ks);
         gemm(B, kP, k, 1, mat(w.coef, k, 1), mat(m->basis, 1, k), mat(out, kP, 1));
     }
 
