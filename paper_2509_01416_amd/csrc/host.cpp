@@ -618,6 +618,19 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
                 out.pop_back();
             items.swap(out);
         };
+        // within an XCD's queue the longest chains (ceil(ny/R) nx + R - 1
+        // steps) go first: workgroups are handed to the XCD's CUs in turn,
+        // so every CU gets a share of the long ones and none starts one last
+        if (dim == 2) {
+            auto chain = [&](const SweepWork& w) {
+                const InstDesc& d = su->inst[w.inst];
+                return (long long)((d.ny + d.R - 1) / d.R) * d.nx + d.R - 1;
+            };
+            std::stable_sort(su->work.begin(), su->work.end(),
+                             [&](const SweepWork& x, const SweepWork& y) {
+                                 return chain(x) > chain(y);
+                             });
+        }
         if (!su->work.empty())
             interleave(su->work,
                        [&](const SweepWork& w) { return w.inst < 0 ? -1 : bucket[w.inst]; },
