@@ -99,6 +99,8 @@ def parse():
                     help="skip the k-eigenvalue measurements")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the uneven-batch and network-grid legs")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time the networks alone and print their figures (counter runs)")
     ap.add_argument("--weights", default=None,
                     help="trained network parameters (default: the packaged file)")
     return ap.parse_args()
@@ -394,12 +396,77 @@ def eigen_leg(ctx, model, B, I, torch, args):
             "preconditioned_64": small}
 
 
+def _forward_ms(ctx, model, nb, torch, reps=20):
+    """Mean forward time of a batch of nb 64 x 64 fields, HIP events on the
+    library stream."""
+    xin = torch.randn(nb, 64, 64, device="cuda")
+    xout = torch.empty_like(xin)
+    for _ in range(3):
+        model.forward(xin, xout)
+    s = ctx.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        model.forward(xin, xout)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def network_leg(ctx, model, don, nb, torch):
+    """Network forwards on the recast batch (nb fields of 64 x 64) and on 64
+    fields (the 64 x 64 families), for the FNO and the DeepONet, and one FNO
+    training step at batch 32 (forward, MSE, backward, Adam, loss
+    read-back; lr = 0 leaves the parameters as they are)."""
+    fwd_ms = _forward_ms(ctx, model, nb, torch)
+    fl = fno_flop_per_sample() * nb
+    out = {"forward_ms": fwd_ms, "batch": nb, "flop_per_sample": fno_flop_per_sample(),
+           "achieved_TFLOPs": fl / (fwd_ms * 1e-3) / 1e12,
+           "peak_TFLOPs": BF16_MFMA_PEAK_TFLOPS,
+           "frac": fl / (fwd_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+           "dtype": "bf16 operands, fp32 accumulate",
+           "forward_ms_batch64": _forward_ms(ctx, model, 64, torch)}
+    if don is not None:
+        out["deeponet_forward_ms"] = _forward_ms(ctx, don, nb, torch)
+        out["deeponet_forward_ms_batch64"] = _forward_ms(ctx, don, 64, torch)
+    tb = 32
+    tin = torch.randn(tb, 64, 64, device="cuda")
+    tgt = torch.randn(tb, 64, 64, device="cuda")
+    for _ in range(2):
+        model.train_step(tin, tgt, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    treps = 10
+    for _ in range(treps):
+        model.train_step(tin, tgt, 0.0)
+    torch.cuda.synchronize()
+    out["train_step_ms"] = (time.perf_counter() - t0) * 1e3 / treps
+    out["train_batch"] = tb
+    return out
+
+
+def network_only(args):
+    """--network-only: the network leg alone (for counter runs)."""
+    import torch
+    from paper_2509_01416_amd import binding as B
+    from paper_2509_01416_amd import train as T
+    ctx = B.Context()
+    model = B.Model(ctx, T.load_weights(args.weights))
+    don = B.Model(ctx, T.load_weights(arch="deeponet"), arch="deeponet")
+    net = network_leg(ctx, model, don, args.instances, torch)
+    print(json.dumps({"network": net}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this "
               "build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.network_only:
+        network_only(args)
+        return
     import torch
     from paper_2509_01416_amd import binding as B
     from paper_2509_01416_amd import inputs as I
@@ -503,52 +570,14 @@ def main():
             "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None}
 
     network = None
+    don = None if model is None else B.Model(ctx, T.load_weights(arch="deeponet"),
+                                             arch="deeponet")
     if model is not None:
-        # network forward on the recast batch (64 x 64 per instance), timed
-        # with HIP events on the library stream
-        nb = len(probs)
-        xin = torch.randn(nb, 64, 64, device=dev)
-        xout = torch.empty_like(xin)
-        for _ in range(3):
-            model.forward(xin, xout)
-        s = ctx.stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record(s)
-        for _ in range(reps):
-            model.forward(xin, xout)
-        e1.record(s)
-        e1.synchronize()
-        fwd_ms = e0.elapsed_time(e1) / reps
-        fl = fno_flop_per_sample() * nb
-        network = {"forward_ms": fwd_ms, "batch": nb, "flop_per_sample": fno_flop_per_sample(),
-                   "achieved_TFLOPs": fl / (fwd_ms * 1e-3) / 1e12,
-                   "peak_TFLOPs": BF16_MFMA_PEAK_TFLOPS,
-                   "frac": fl / (fwd_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
-                   "dtype": "bf16 operands, fp32 accumulate"}
-        # one training step at the training batch (forward, MSE, backward,
-        # Adam, loss read-back), wall time; lr = 0 leaves the parameters as
-        # they are
-        tb = 32
-        tin = torch.randn(tb, 64, 64, device=dev)
-        tgt = torch.randn(tb, 64, 64, device=dev)
-        for _ in range(2):
-            model.train_step(tin, tgt, 0.0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        treps = 10
-        for _ in range(treps):
-            model.train_step(tin, tgt, 0.0)
-        torch.cuda.synchronize()
-        network["train_step_ms"] = (time.perf_counter() - t0) * 1e3 / treps
-        network["train_batch"] = tb
-
+        network = network_leg(ctx, model, don, len(probs), torch)
     eigen = None
     if model is not None and not args.no_eigen:
         eigen = eigen_leg(ctx, model, B, I, torch, args)
     uneven = None if args.no_extra else uneven_leg(B, I, torch, args)
-    don = None if model is None else B.Model(ctx, T.load_weights(arch="deeponet"),
-                                             arch="deeponet")
     netgrid = (None if args.no_extra or model is None
                else network_grid_leg({"fno": model, "deeponet": don}, B, I, torch, args))
     don_step = None
@@ -566,6 +595,8 @@ def main():
         don_step = {"warm_ms": r["dt"] * 1e3 / args.steps,
                     "recast_ms": r["guess_s"] * 1e3 / args.steps,
                     "recast_iterations_mean": float(np.mean(r["rits"][-1])),
+                    "recast_ms_per_update": r["guess_s"] * 1e3 / args.steps /
+                                            max(1, max(r["rits"][-1])),
                     "si_iterations_mean": float(np.mean(r["its"][-1])),
                     "si_iterations_max": int(max(r["its"][-1])),
                     "updates_per_s": r["updates"] / r["dt"],
@@ -610,6 +641,10 @@ def main():
             "time_reduction": None if args.zero_only else 1.0 - ms_step / zero_ms,
             "recast_ms": None if args.zero_only else main_run["guess_s"] * 1e3 / args.steps,
             "recast_iterations_mean": mean(main_run["rits"]),
+            # the batch's updates run until its slowest instance stops
+            "recast_ms_per_update": (None if args.zero_only else
+                                     main_run["guess_s"] * 1e3 / args.steps /
+                                     max(1, max(main_run["rits"][-1]))),
             "si_iterations_mean_warm": None if args.zero_only else mean(main_run["its"]),
             "si_iterations_mean_zero": mean(zero_run["its"]),
             "si_iterations_max_warm": None if args.zero_only else int(max(main_run["its"][-1])),

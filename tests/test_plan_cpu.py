@@ -32,7 +32,7 @@ def test_benchmark_batch_gets_the_specialised_kernel():
 
 
 @pytest.mark.parametrize("shapes,why", [
-    ([(64, 64)], "nx < 63 + KB"),
+    ([(64, 128)], "nx < 63 + KB with two row blocks"),
     ([(256, 256), (48, 48)], "segment heights differ (48 needs R = 16)"),
     ([(256, 200)], "64 does not divide ny"),
 ])
@@ -47,9 +47,14 @@ def test_reflective_faces_use_the_generic_kernel():
 
 def test_block_size_shrinks_to_fit_narrow_grids():
     # 16 instances at S16 give W = 9 waves, which alone would allow KB = 16;
-    # the specialised kernel needs nx >= 63 + KB
-    p = _plan([(70, 64)] * 16, n=16)    # KB <= 7 -> 4
+    # the specialised kernel needs nx >= 63 + KB where a grid has more than
+    # one row block
+    p = _plan([(70, 128)] * 16, n=16)   # KB <= 7 -> 4
     assert p["specialised"] == 1 and p["KB"] == 4
+    p = _plan([(70, 64)] * 16, n=16)    # one row block: any nx >= 64
+    assert p["specialised"] == 1 and p["KB"] == 16
+    p = _plan([(64, 64)] * 64, n=8)     # the 64 x 64 network-grid batches
+    assert p["specialised"] == 1 and p["KB"] == 16
     p = _plan([(66, 128)] * 16, n=16)   # KB <= 3 -> 2
     assert p["specialised"] == 1 and p["KB"] == 2
     p = _plan([(80, 64)] * 16, n=16)    # KB <= 17 -> 16
