@@ -52,11 +52,11 @@ FLOP_PER_UPDATE = 12
 BYTES_PER_CELL_ITER = 20
 # HBM bytes per sweep launch on the default workload (all 16 instances
 # active) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what the counters
-# read for a 256 MiB copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
+# read for a 256 MiB elementwise copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
 # valid only for the kernel source with this hash prefix (sweep_source_hash),
 # otherwise null
-SWEEP_TRAFFIC_BYTES = 79.76e6
-SWEEP_TRAFFIC_SRC = "85bbd97bb6afe0b9"
+SWEEP_TRAFFIC_BYTES = 79.85e6
+SWEEP_TRAFFIC_SRC = "73c006159697c6d3"
 
 
 def sweep_source_hash() -> str:
@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the one-core oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a 256 MiB device copy (counter calibration)")
+                    help="also run a 256 MiB fill and copy (counter calibration)")
     ap.add_argument("--zero-only", action="store_true",
                     help="time the zero-start source iteration alone")
     ap.add_argument("--max-iter", type=int, default=20000,
@@ -226,11 +226,19 @@ def uneven_leg(B, I, torch, args):
     med = float(np.median(times))
     its = [s["iterations"] for s in st]
     log(f"[bench] uneven batch: {med * 1e3:.1f} ms, {ups / med:.3e} updates/s")
+    # sweep roofline of the profiled solve: its updates (the same iteration
+    # counts) at 12 flop each over the summed sweep kernel time
+    sweep_s = prof["sweep_ms"] * 1e-3
+    achieved = ups * FLOP_PER_UPDATE / sweep_s / 1e12 if sweep_s > 0 else None
     return {"workload": wl.name, "ms": med * 1e3, "status": rc,
             "cell_angle_updates_per_s": ups / med, "iterations_min_max": [min(its), max(its)],
+            "iterations_mean": float(np.mean(its)),
             "sweep_plan": plan,
             "sweep_ms_per_launch": prof["sweep_ms"] / max(1, prof["sweep_launches"]),
-            "sweep_launches": prof["sweep_launches"]}
+            "sweep_launches": prof["sweep_launches"],
+            "sweep_roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                               "unit": "TFLOP/s",
+                               "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None}}
 
 
 def network_grid_leg(models, B, I, torch, args):
@@ -604,9 +612,11 @@ def main():
         log(f"[bench] DeepONet warm step {don_step['warm_ms']:.1f} ms")
 
     if args.calib_copy:
+        # counter calibration: a fill writing 256 MiB, then an elementwise
+        # kernel reading and writing 256 MiB each
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         a.fill_(1.0)
-        b = a.clone()
+        b = a * 1.0
         torch.cuda.synchronize()
         del a, b
 
