@@ -415,6 +415,24 @@ tr_status tr_autotune(tr_context *ctx, int32_t n_inst, const tr_problem *p,
  * their results agree bit for bit.                                        */
 tr_status tr_set_sweep_kernel(tr_context *ctx, int32_t generic);
 
+/* Persistent iteration (enable = 1; off by default): when a 2-D solve runs
+ * the specialised sweep with one direction per lane and 9 or 10 waves per
+ * workgroup, and every workgroup of the launch can be resident at once,
+ * tr_solve and the eigenvalue solvers run each chunk of source iterations
+ * (the batched-launch pattern of the sweeps of section 5.1) as one
+ * cooperative launch: per iteration the workgroups of each instance sweep,
+ * meet at a barrier in device memory, combine their share of the
+ * instance's cells, meet again and evaluate the convergence test.  Results,
+ * iteration counts and statuses equal those of the per-kernel launches
+ * (enable = 0) bit for bit.  spin_limit > 0 bounds the polls of a barrier
+ * wait (0 selects the default, 2^18 polls, far above a normal wait); a
+ * wait that runs out ends every wait of the launch, whose workgroups all
+ * finish, and the call returns TR_ERR_HIP ("barrier wait timed out").
+ * Instances never wait on each other.  On gfx950 it is slower than the
+ * per-kernel launches (each barrier's device-scope release and acquire
+ * write back and invalidate the XCD's L2), hence opt-in.                  */
+tr_status tr_set_persistent(tr_context *ctx, int32_t enable, int32_t spin_limit);
+
 /* Debugging: with enable = 1 every HIP step of a call on this context
  * (launch, copy) is followed by a stream synchronisation and an error
  * check, so a failing kernel is reported, in tr_last_error, at the step
@@ -429,6 +447,10 @@ tr_status tr_set_sync_checks(tr_context *ctx, int32_t enable);
 tr_status tr_profile_enable(tr_context *ctx, int32_t enable);
 /* out4 = {sweep ms, sweep launches, combine+finalize ms, their count}.   */
 tr_status tr_profile_read(tr_context *ctx, double *out4);
+/* out6 = out4 followed by {persistent-iteration ms, its launches} (each
+ * persistent launch runs a chunk of source iterations: sweeps, combines
+ * and convergence tests).                                                 */
+tr_status tr_profile_read_ex(tr_context *ctx, double *out6);
 
 /* The launch shape the next tr_solve / tr_sweep on these problems would
  * use: out6 = {D, W, S of problem 0, R of problem 0, KB, specialised

@@ -39,8 +39,8 @@ EXPORTS = ("tr_context_create", "tr_context_destroy", "tr_last_error",
            "no_model_set_fp32", "no_forward",
            "no_train_step",
            "tr_check_args", "tr_autotune", "tr_set_sweep_config", "tr_set_sweep_kernel",
-           "tr_set_stop_rule", "tr_set_sync_checks", "tr_get_sweep_plan",
-           "tr_profile_enable", "tr_profile_read")
+           "tr_set_stop_rule", "tr_set_sync_checks", "tr_set_persistent", "tr_get_sweep_plan",
+           "tr_profile_enable", "tr_profile_read", "tr_profile_read_ex")
 
 
 class TrProblem(ctypes.Structure):
@@ -135,6 +135,8 @@ def load(path: str = LIB_PATH):
     lib.tr_get_sweep_plan.argtypes = [vp, i32, P(TrProblem), P(TrQuadrature), P(i32)]
     lib.tr_profile_enable.argtypes = [vp, i32]
     lib.tr_profile_read.argtypes = [vp, P(d)]
+    lib.tr_profile_read_ex.argtypes = [vp, P(d)]
+    lib.tr_set_persistent.argtypes = [vp, i32, i32]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:       # default: tr_status
@@ -281,14 +283,22 @@ class Context:
         """Debugging: synchronise and check for errors after every HIP step."""
         self.check(self.lib.tr_set_sync_checks(self.handle, int(enable)), allow=(TR_OK,))
 
+    def set_persistent(self, enable: bool = True, spin_limit: int = 0):
+        """Persistent iteration (several source iterations per cooperative
+        launch) where the launch shape allows it; spin_limit > 0 bounds the
+        polls of its barrier waits (0: the library default)."""
+        self.check(self.lib.tr_set_persistent(self.handle, int(enable), int(spin_limit)),
+                   allow=(TR_OK,))
+
     def profile(self, enable: bool = True):
         self.check(self.lib.tr_profile_enable(self.handle, int(enable)), allow=(TR_OK,))
 
     def profile_read(self) -> dict:
-        out = (ctypes.c_double * 4)()
-        self.check(self.lib.tr_profile_read(self.handle, out), allow=(TR_OK,))
+        out = (ctypes.c_double * 6)()
+        self.check(self.lib.tr_profile_read_ex(self.handle, out), allow=(TR_OK,))
         return dict(sweep_ms=out[0], sweep_launches=int(out[1]),
-                    combine_ms=out[2], combine_launches=int(out[3]))
+                    combine_ms=out[2], combine_launches=int(out[3]),
+                    persistent_ms=out[4], persistent_launches=int(out[5]))
 
     def autotune(self, problems, quad: Quad, reps: int = 3) -> dict:
         """Time the feasible launch shapes on these problems and keep the

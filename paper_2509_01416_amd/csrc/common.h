@@ -159,6 +159,24 @@ __device__ __forceinline__ bool sweep_prologue(const InstDesc& I, int n, const F
     return bad || conv;
 }
 
+// Arguments of the persistent iteration kernel (several source iterations
+// per launch: sweep, combine and convergence test, with a barrier of each
+// instance's workgroups between the phases).  bar[n] counts the barrier
+// arrivals of instance n over the solve (zeroed before its first launch);
+// a wait that exceeds spin_limit polls sets *err and goes on, so every
+// workgroup finishes whatever happens.
+struct PersistArgs {
+    int* bar;
+    int* err;
+    int spin_limit;
+    int it0;          // iterations done before this launch (by every active instance)
+    int k;            // iterations in this launch
+    int norm_kind;
+    double tol;
+    double2* red;
+    IterState st;
+};
+
 constexpr int kCombineThreads = 256;
 constexpr int kCombineChunk = 2048;   // cells per combine block
 constexpr int kXcds = 8;              // accelerator complex dies (L2 domains)

@@ -937,6 +937,9 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
             launch_recast_update(out, scale, (float)(1.0 / sa_star), phi, norms, active, dst,
                                  tol, k, B, kP, s);
         }
+        // the guesses on the problems' grids as they stand: final when this
+        // chunk ends the loop (saves a read-back), rewritten otherwise
+        launch_recast_output(ddesc, B, kGrid, max_cells, phi, s);
         if (!c->hip_ok(hipMemcpyAsync(hst, dst, sizeof(RecastState) * (size_t)B,
                                       hipMemcpyDeviceToHost, s), "copy") ||
             !c->hip_ok(hipMemcpyAsync(hact, active, 4 * (size_t)B, hipMemcpyDeviceToHost, s),
@@ -960,9 +963,6 @@ extern "C" tr_status no_recast_guess(tr_context* ctx, const no_model* m, int32_t
         }
         chunk = want;
     }
-    launch_recast_output(ddesc, B, kGrid, max_cells, phi, s);
-    const tr_status st = finish(c, "recast output");
-    if (st != TR_OK) return st;
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = TR_OK;

@@ -31,6 +31,11 @@ bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
                          const int* done, const int* iter, bool tally, const FinArgs& fin,
                          hipStream_t s);
 size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx);
+bool persistent_supported(int D, int W, int KB);
+bool persistent_fits(int W, int KB, size_t lds, int nwork, int device);
+hipError_t launch_persistent(int W, int KB, size_t lds, int nwork, const InstDesc* insts,
+                             const SweepWork* work, const DirTable* dt, const PersistArgs& pa,
+                             hipStream_t s);
 int sweep2d_max_kb(int W, int R, bool p1);
 bool sweep2d_generic_fits(int W, int KB, int R, bool p1);
 int sweep2d_fast_max_kb(int W);
@@ -670,6 +675,8 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     off += align_up(sizeof(float) * n_inst);
     const size_t oBpart = off;
     off += align_up(sizeof(double) * 3 * std::max<size_t>(1, nslots));
+    const size_t oBar = off;
+    off += align_up(sizeof(int) * (n_inst + 1));
     if (!arena.reserve(this, off)) return false;
     char* b = (char*)arena.base;
     for (int i = 0; i < n_inst; ++i) {
@@ -696,6 +703,14 @@ bool Ctx::setup(int n_inst, const tr_problem* p, const tr_quadrature* q,
     su->d_flags = (int*)(b + oFlag);
     su->d_samax = (float*)(b + oSa);
     su->d_bpart = (double*)(b + oBpart);
+    su->d_bar = (int*)(b + oBar);
+    su->d_err = su->d_bar + n_inst;
+    // source iterations as one cooperative launch per chunk: the specialised
+    // sweep's common shapes, when every workgroup of the launch is resident
+    su->persist = persistent && dim == 2 && !emission && !p1 && su->plan.fast &&
+                  persistent_supported(su->plan.D, su->plan.W, su->plan.KB) &&
+                  persistent_fits(su->plan.W, su->plan.KB, su->plan.lds, (int)su->work.size(),
+                                  device);
     // stage the tables through pinned memory
     const size_t hsz = oRed - oInst;
     if (!pinned.reserve(this, hsz + 4096 + (size_t)n_inst * 64)) return false;
@@ -751,12 +766,29 @@ bool Ctx::launch_sweep(const Setup& su, int n_inst, const int* done,
 bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, int max_iter,
                      int* sweeps, int first_chunk, int* iters_host) {
     int* hdone = (int*)pinned.ptr;
+    // the barrier time-out flag reads back into the last bytes of the
+    // staging buffer (callers keep their own arrays at its start)
+    int* herr = (int*)((char*)pinned.ptr + pinned.cap - 64);
     int done_iters = 0, chunk = std::min(std::max(first_chunk, 1), 64);
     const bool fused_fin = su.inst[0].dim == 2;
     bool all = false;
+    if (su.persist &&
+        !hip_ok(hipMemsetAsync(su.d_bar, 0, sizeof(int) * (n_inst + 1), stream), "memset"))
+        return false;
     while (done_iters < max_iter && !all) {
         const int k = std::min(chunk, max_iter - done_iters);
-        for (int it = 0; it < k; ++it) {
+        if (su.persist) {
+            // k iterations (sweep, combine, test) in one cooperative launch
+            const PersistArgs pa{su.d_bar, su.d_err, persist_spin, done_iters, k, norm_kind,
+                                 atol, su.d_red, su.st};
+            const bool p2 = prof_begin(2);
+            if (!hip_ok(launch_persistent(su.plan.W, su.plan.KB, su.plan.lds,
+                                          (int)su.work.size(), su.d_inst, su.d_work, su.d_dt,
+                                          pa, stream), "persistent launch"))
+                return false;
+            if (p2) prof_end();
+        }
+        for (int it = 0; it < k && !su.persist; ++it) {
             // 2-D: the convergence test of iteration it - 1 runs in the
             // prologue of sweep it (FinArgs); the chunk's last iteration is
             // tested by the finalize kernel before the flags are read back
@@ -780,11 +812,17 @@ bool Ctx::si_iterate(const Setup& su, int n_inst, double atol, int norm_kind, in
         done_iters += k;
         if (!hip_ok(hipMemcpyAsync(hdone, su.st.done, sizeof(int) * n_inst,
                                    hipMemcpyDeviceToHost, stream), "flag copy") ||
+            (su.persist && !hip_ok(hipMemcpyAsync(herr, su.d_err, sizeof(int),
+                                                  hipMemcpyDeviceToHost, stream), "flag copy")) ||
             (iters_host && !hip_ok(hipMemcpyAsync(iters_host, su.st.iter, sizeof(int) * n_inst,
                                                   hipMemcpyDeviceToHost, stream), "copy")) ||
             !hip_ok(hipStreamSynchronize(stream), "sync"))
             return false;
         prof_collect();
+        if (su.persist && *herr) {
+            fail("persistent iteration: an instance barrier wait timed out");
+            return false;
+        }
         all = true;
         for (int i = 0; i < n_inst; ++i) all &= hdone[i] != 0;
         chunk = std::min(chunk * 2, 64);
@@ -1155,6 +1193,28 @@ extern "C" tr_status tr_set_sweep_kernel(tr_context* ctx, int32_t generic) {
         return TR_ERR_INVALID_ARG;
     }
     c->force_generic = generic != 0;
+    return TR_OK;
+}
+
+extern "C" tr_status tr_set_persistent(tr_context* ctx, int32_t enable, int32_t spin_limit) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return TR_ERR_INVALID_ARG;
+    if (enable != 0 && enable != 1) {
+        c->fail("enable must be 0 or 1");
+        return TR_ERR_INVALID_ARG;
+    }
+    c->persistent = enable != 0;
+    c->persist_spin = spin_limit > 0 ? spin_limit : (1 << 18);
+    return TR_OK;
+}
+
+extern "C" tr_status tr_profile_read_ex(tr_context* ctx, double* out6) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c || !out6) return TR_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) {
+        out6[2 * k] = c->prof_ms[k];
+        out6[2 * k + 1] = (double)c->prof_n[k];
+    }
     return TR_OK;
 }
 

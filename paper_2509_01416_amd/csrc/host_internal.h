@@ -65,6 +65,9 @@ struct Setup {
     int* d_flags = nullptr;
     float* d_samax = nullptr;
     double* d_bpart = nullptr;   // balance partials, 3 per reduction block
+    int* d_bar = nullptr;        // persistent iteration: barrier counters (n_inst)
+    int* d_err = nullptr;        // persistent iteration: barrier time-out flag
+    bool persist = false;        // iterations run as one cooperative launch per chunk
 };
 
 struct FnoWork;
@@ -81,6 +84,8 @@ struct Ctx {
     bool force_generic = false;   // never use the specialised sweep kernel
     int stop_rule = TR_STOP_CHANGE;   // tr_solve's stopping rule (tr_stop_rule)
     bool sync_checks = false;         // synchronise and check after every HIP step
+    bool persistent = false;          // persistent iteration where the plan allows it (opt-in)
+    int persist_spin = 1 << 18;       // polls before a persistent barrier wait gives up
     size_t lds_limit = 160 * 1024;  // per-workgroup LDS (gfx950; device property when known)
     int last_sweeps = 0;
     FnoWork* fno = nullptr;   // network workspaces
@@ -91,7 +96,7 @@ struct Ctx {
     hipEvent_t ev[kProfSlots][2] = {};
     int ev_kind[kProfSlots] = {};
     int ev_used = 0;
-    double prof_ms[4] = {0, 0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};   // sweep, combine + finalize, persistent
     long long prof_n[4] = {0, 0, 0, 0};
     bool prof_begin(int kind);      // records the start event; false if full
     void prof_end();

@@ -36,6 +36,7 @@
 //     kernel, one direction per lane): the emission of direction m is
 //     Q + mu_m Ex + eta_m Ey with Ex, Ey = 3 sigma_s1 J staged like Q, and
 //     the waves also sum w mu psi and w eta psi into current planes.
+#include "combine_dev.h"
 #include "common.h"
 
 namespace mdp {
@@ -450,13 +451,13 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 // in which lane 63 restarted (lane 0 restarts only nx - 63 > KB steps
 // later).  The source iteration runs without it and tallies once, after its
 // last iteration.
+// The sweep of one workgroup (instance I, octant and slice of wk) into its
+// partial plane; par = face parity (the tally's face set).  Shared by the
+// sweep kernel and the persistent iteration kernel.
 template <int D, int KB, int WT, bool TALLY>
-__global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<D>::threads)
-sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
-                    const SweepWork* __restrict__ work,
-                    const DirTable* __restrict__ dt, const int* __restrict__ done,
-                    const int* __restrict__ iter, FinArgs fin) {
-    extern __shared__ float smem[];
+__device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork wk,
+                                              const DirTable* __restrict__ dt, int par,
+                                              float* smem) {
     constexpr int lkb = KB >= 16 ? 4 : (KB >= 8 ? 3 : (KB >= 4 ? 2 : (KB >= 2 ? 1 : 0)));
     static_assert((1 << lkb) == KB, "KB must be a power of two <= 16");
     constexpr int R = 64, lr = 6, PST = KB + 1;
@@ -465,19 +466,9 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
     const int wv = tid >> 6;
     const int W = WT > 0 ? WT : (int)(blockDim.x >> 6);
     const int nthreads = W * 64;
-    const SweepWork wk = work[blockIdx.x];
-    const int n = wk.inst;
-    if (n < 0) return;
-    if (fin.pending) {
-        if (sweep_prologue(insts[n], n, fin, wk.oct == 0 && wk.slice == 0)) return;
-    } else if (done != nullptr && done[n]) {
-        return;
-    }
-    const InstDesc& I = insts[n];
     const int o = wk.oct;
     const bool xpos = (o == 0 || o == 3), ypos = (o == 0 || o == 1);
     const int nx = I.nx, ny = I.ny, nf = I.nf, M = dt->M;
-    const int par = (fin.pending ? fin.it : (iter != nullptr ? iter[n] : 0)) & 1;
     const size_t fstride = (size_t)4 * nf * M;
     gfloat* __restrict__ fcur = (gfloat*)(I.face + (size_t)(TALLY ? par : par ^ 1) * fstride);
     const int fxout = xpos ? 1 : 0, fyout = ypos ? 3 : 2;
@@ -846,6 +837,186 @@ sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
             if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ringw[d * RS + ipc];
         }
     }
+}
+
+template <int D, int KB, int WT, bool TALLY>
+__global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<D>::threads)
+sweep2d_fast_kernel(const InstDesc* __restrict__ insts,
+                    const SweepWork* __restrict__ work,
+                    const DirTable* __restrict__ dt, const int* __restrict__ done,
+                    const int* __restrict__ iter, FinArgs fin) {
+    extern __shared__ float smem[];
+    const SweepWork wk = work[blockIdx.x];
+    const int n = wk.inst;
+    if (n < 0) return;
+    if (fin.pending) {
+        if (sweep_prologue(insts[n], n, fin, wk.oct == 0 && wk.slice == 0)) return;
+    } else if (done != nullptr && done[n]) {
+        return;
+    }
+    const int par = (fin.pending ? fin.it : (iter != nullptr ? iter[n] : 0)) & 1;
+    fast_sweep_wg<D, KB, WT, TALLY>(insts[n], wk, dt, par, smem);
+}
+
+// ------------------------------------------------ persistent iteration --
+// Several source iterations in one launch for the specialised sweep with
+// one direction per lane: the workgroups of an
+// instance sweep, meet at a barrier, combine their share of the instance's
+// blocks of cells (combine_dev.h), meet again and evaluate the convergence
+// test of the iteration, exactly as the finalize kernel does; an instance
+// whose test stops it leaves the loop in all its workgroups at once (they
+// read the same partial sums).  The launch is cooperative, so every
+// workgroup is resident; no instance waits on another.  Results, iteration
+// counts and statuses equal those of the sweep / combine / finalize
+// launches.
+
+// Barrier of the G workgroups of instance n: the counter reaches `target`
+// when all of them have arrived `target / G` times.  The wait polls with a
+// short sleep; it gives up after spin_limit polls (setting the flag), or as
+// soon as another workgroup has set it.  Returns false after a time-out
+// anywhere (the caller leaves: every later wait would give up as well).
+__device__ __forceinline__ bool inst_barrier(int* bar, int target, int* err, int spin_limit,
+                                             int* ok_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the workgroup's writes
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0, ok = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > spin_limit) {
+                atomicOr(err, 1);
+                ok = 0;
+                break;
+            }
+            if ((spins & 63) == 0 &&
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the other workgroups' writes
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// The convergence test of iteration l of instance n (the finalize kernel's
+// arithmetic and summation order); the designated workgroup records it.
+// Returns true when the instance stops.
+__device__ __forceinline__ bool persist_test(const InstDesc& I, int n, int l,
+                                             const PersistArgs& pa, bool designated) {
+    const IterState& st = pa.st;
+    if (!tested_iteration(l, pa.norm_kind)) {
+        if (designated && threadIdx.x == 0) st.iter[n] = l;
+        return false;
+    }
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < I.nred; ++b) {
+        const double2 v = pa.red[I.red0 + b];
+        if (pa.norm_kind != 1) { s1 += v.x; s2 += v.y; }
+        else s1 = fmax(s1, v.x);
+    }
+    double r;
+    if (pa.norm_kind != 1)
+        r = s2 > 0.0 ? sqrt(s1 / s2) : (s1 == 0.0 ? 0.0 : INFINITY);
+    else
+        r = s1;
+    const int slot = history_slot(l, pa.norm_kind);
+    const double r_prev = st.rhist[2 * n + (slot ^ 1)];
+    const bool bad = !isfinite(s1) || !isfinite(s2);
+    const bool conv = !bad && stop_test(r, r_prev, pa.tol, pa.norm_kind);
+    if (designated && threadIdx.x == 0) {
+        st.resid[n] = r;
+        st.rhist[2 * n + slot] = r;
+        st.iter[n] = l;
+        if (bad) {
+            st.status[n] = -4;
+            st.done[n] = 1;
+        } else if (conv) {
+            st.status[n] = 0;
+            st.done[n] = 1;
+        }
+    }
+    return bad || conv;
+}
+
+template <int KB, int WT>
+__global__ void __launch_bounds__(WT > 0 ? WT * 64 : SweepBounds<1>::threads)
+si_persistent_kernel(const InstDesc* __restrict__ insts, const SweepWork* __restrict__ work,
+                     const DirTable* __restrict__ dt, PersistArgs pa) {
+    extern __shared__ float smem[];
+    const SweepWork wk = work[blockIdx.x];
+    const int n = wk.inst;
+    if (n < 0 || pa.st.done[n]) return;
+    const InstDesc& I = insts[n];
+    const int G = 4 * I.S;                    // workgroups of the instance
+    const int rank = wk.oct * I.S + wk.slice;
+    double* r1 = reinterpret_cast<double*>(smem);   // combine reduction (after the sweep)
+    double* r2 = r1 + kCombineThreads;
+    __shared__ int ok_lds;
+    int phase = 2 * pa.it0;                   // barrier phases the instance has completed
+    for (int it = 0; it < pa.k; ++it) {
+        const int l = pa.it0 + it + 1;
+        fast_sweep_wg<1, KB, WT, false>(I, wk, dt, 0, smem);
+        if (!inst_barrier(pa.bar + n, G * ++phase, pa.err, pa.spin_limit, &ok_lds)) return;
+        // the error-bound rule measures the change against the snapshot on
+        // its tested iterations only
+        const int mode = pa.norm_kind != 2 ? 0 : (l % kStopStride == 0 ? 2 : 3);
+        for (int j = rank; j < I.nred; j += G)
+            combine_block(I, j * kCombineChunk, I.red0 + j, pa.red, mode, pa.norm_kind, dt,
+                          (int)threadIdx.x, (int)blockDim.x, r1, r2);
+        if (!inst_barrier(pa.bar + n, G * ++phase, pa.err, pa.spin_limit, &ok_lds)) return;
+        if (persist_test(I, n, l, pa, rank == 0)) break;
+    }
+}
+
+bool persistent_supported(int D, int W, int KB) {
+    return D == 1 && W >= 1 && 64 * W <= SweepBounds<1>::threads &&
+           (KB == 16 || KB == 8 || KB == 4 || KB == 2);
+}
+
+template <int KB, int WT>
+static const void* persist_fn() {
+    return reinterpret_cast<const void*>(&si_persistent_kernel<KB, WT>);
+}
+template <int WT>
+static const void* persist_fn_kb(int KB) {
+    switch (KB) {
+        case 16: return persist_fn<16, WT>();
+        case 8: return persist_fn<8, WT>();
+        case 4: return persist_fn<4, WT>();
+        default: return persist_fn<2, WT>();
+    }
+}
+// the fixed wave counts of the sweep kernel (9, 10), any other count through
+// the dynamic variant
+static const void* persist_kernel(int W, int KB) {
+    if (W == 9) return persist_fn_kb<9>(KB);
+    if (W == 10) return persist_fn_kb<10>(KB);
+    return persist_fn_kb<0>(KB);
+}
+
+// Whether nwork workgroups of this shape are resident at once on `device`
+// (the cooperative launch requires it).
+bool persistent_fits(int W, int KB, size_t lds, int nwork, int device) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel(W, KB), 64 * W,
+                                                     lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess)
+        return false;
+    return (long long)per_cu * cus >= nwork;
+}
+
+hipError_t launch_persistent(int W, int KB, size_t lds, int nwork, const InstDesc* insts,
+                             const SweepWork* work, const DirTable* dt, const PersistArgs& pa,
+                             hipStream_t s) {
+    PersistArgs a = pa;
+    void* args[] = {(void*)&insts, (void*)&work, (void*)&dt, (void*)&a};
+    return hipLaunchCooperativeKernel(persist_kernel(W, KB), dim3(nwork), dim3(64 * W), args,
+                                      (unsigned)lds, s);
 }
 
 // Host launcher; returns false for an unsupported (D, KB).

@@ -526,3 +526,68 @@ def test_paper_1d_setting_solve(env):
             f"oracle={ref.iterations} rel_l2={e:.3e} balance={s['balance_rel']:.2e}")
         assert e < 1e-5
         assert s["balance_rel"] < 1e-4
+
+
+@pytest.mark.parametrize("shapes,n,rule", [
+    ([(256, 256)] * 4, 16, "bound"),
+    ([(256, 256)] * 4, 16, "change"),
+    ([(64, 64)] * 64, 8, "change"),
+    ([(64, 64)] * 24 + [(128, 128)] * 4, 8, "bound"),
+    ([(128, 256), (256, 128), (192, 64)], 16, "change"),
+])
+def test_persistent_iteration_matches_kernel_launches(env, shapes, n, rule):
+    """The persistent iteration (a chunk of sweeps, combines and tests per
+    cooperative launch, barriers per instance in device memory) returns the
+    per-kernel launches' answers, iteration counts, statuses and residuals
+    bit for bit, and is the path the solve takes for these shapes."""
+    torch, B, ctx = env
+    quad = B.Quad.from_inputs(I.level_symmetric_2d(n))
+    insts = [I.random_instance(nx, ny, seed=900 + 3 * k + nx, lx=nx / 16.0, ly=ny / 16.0)
+             for k, (nx, ny) in enumerate(shapes)]
+    probs = [to_problem(i, torch) for i in insts]
+    ctx.set_stop_rule(rule)
+    outs = {}
+    try:
+        for pers in (True, False):
+            ctx.set_persistent(pers)
+            phis = [torch.zeros_like(p.sigma_t) for p in probs]
+            ctx.profile(True)
+            rc, st = B.tr_solve(ctx, probs, quad, None, phis, 1e-6, 3000)
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            outs[pers] = (rc, [x.cpu().numpy() for x in phis],
+                          [(s["iterations"], s["status"], s["residual"]) for s in st], prof)
+        log(f"  persistent {len(shapes)} x {shapes[0]} S{n} {rule}: plan "
+            f"{ctx.sweep_plan(probs, quad)}, rc {outs[True][0]}, "
+            f"iterations {sorted(set(x[0] for x in outs[True][2]))}, "
+            f"launches {outs[True][3]['persistent_launches']} vs sweeps "
+            f"{outs[False][3]['sweep_launches']}")
+        assert outs[True][3]["persistent_launches"] > 0
+        assert outs[False][3]["persistent_launches"] == 0
+        assert outs[True][0] == outs[False][0] == B.TR_OK
+        assert outs[True][2] == outs[False][2]
+        for a, b in zip(outs[True][1], outs[False][1]):
+            assert np.array_equal(a, b)
+    finally:
+        ctx.set_persistent(False)
+        ctx.set_stop_rule("change")
+
+
+def test_persistent_barrier_time_out_is_reported(env):
+    """With a barrier wait bounded to one poll the persistent launch still
+    finishes (every wait ends), the solve reports the time-out as an error,
+    and the context then solves normally again."""
+    torch, B, ctx = env
+    quad = B.Quad.from_inputs(I.level_symmetric_2d(16))
+    insts = [I.random_instance(256, 256, seed=950 + k) for k in range(4)]
+    probs = [to_problem(i, torch) for i in insts]
+    phis = [torch.zeros_like(p.sigma_t) for p in probs]
+    try:
+        ctx.set_persistent(True, spin_limit=1)
+        with pytest.raises(B.MdpError, match="timed out"):
+            B.tr_solve(ctx, probs, quad, None, phis, 1e-6, 200)
+        ctx.set_persistent(True)
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis, 1e-6, 3000)
+        assert rc == B.TR_OK
+    finally:
+        ctx.set_persistent(False)
