@@ -47,6 +47,8 @@ VALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # 2 FMA numerator (4), denominator add (1), reciprocal (1), product (1),
 # 2 psi (1), two outgoing faces (2), weighted accumulation FMA (2) = 12 flop
 FLOP_PER_UPDATE = 12
+# a recast tolerance near the networks' own error on the 64 x 64 families
+LOOSE_RECAST_TOL = 3e-2
 # algorithmic HBM bytes per cell per source iteration: read sigma_t, sigma_s,
 # q, phi_old; write phi_new (FP32)
 BYTES_PER_CELL_ITER = 20
@@ -245,8 +247,9 @@ def network_grid_leg(models, B, I, torch, args):
     """Warm start against zero start on the network's own 64 x 64 grid (the
     sinusoidal and random-line families, 64 instances each, S8), for each
     trained network: wall time of the whole step (recast guess + source
-    iteration) against the zero-start solve, medians of three, with
-    iteration counts (own context: the planner's launch shape).  These
+    iteration) against the zero-start solve, medians of five, with
+    iteration counts (own context: the planner's launch shape), at the
+    benchmark's recast tolerance and at a looser one.  These
     families contract at rates up to about 0.9, where the plain change rule
     at 1e-6 stays within about 1e-5 of the fixed point; the error-bound
     rule's 16-iteration test stride would round their 25-65 iterations up
@@ -274,28 +277,50 @@ def _network_grid_arch(ctx, model, B, I, torch, args):
         def zero():
             return B.tr_solve(ctx, probs, quad, None, phis, args.tol, args.max_iter)[1], None
 
-        def warm():
-            _, sg = B.no_recast_guess(ctx, model, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR,
-                                      args.recast_tol, args.recast_max, phis)
-            return B.tr_solve(ctx, probs, quad, phis, phis, args.tol, args.max_iter)[1], sg
-        res = {}
-        for name, fn in (("zero", zero), ("warm", warm)):
+        def warm_at(rtol):
+            def warm():
+                _, sg = B.no_recast_guess(ctx, model, probs, I.SIGMA_T_STAR, I.SIGMA_S_STAR,
+                                          rtol, args.recast_max, phis)
+                return B.tr_solve(ctx, probs, quad, phis, phis, args.tol, args.max_iter)[1], sg
+            return warm
+
+        def run(fn, reps=5):
             fn()
             ts = []
-            for _ in range(3):
+            for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 st, sg = fn()
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
-            res[name + "_ms"] = float(np.median(ts)) * 1e3
-            res[name + "_si_iterations_mean"] = float(np.mean([s["iterations"] for s in st]))
-            res[name + "_si_iterations_max"] = int(max(s["iterations"] for s in st))
+            r = {"ms": float(np.median(ts)) * 1e3,
+                 "si_iterations_mean": float(np.mean([s["iterations"] for s in st])),
+                 "si_iterations_max": int(max(s["iterations"] for s in st))}
             if sg is not None:
-                res["recast_iterations_mean"] = float(np.mean([s["iterations"] for s in sg]))
-        res["time_reduction"] = 1.0 - res["warm_ms"] / res["zero_ms"]
+                r["recast_iterations_mean"] = float(np.mean([s["iterations"] for s in sg]))
+                r["recast_iterations_max"] = int(max(s["iterations"] for s in sg))
+            return r
+        res = {}
+        z = run(zero)
+        w = run(warm_at(args.recast_tol))
+        res["zero_ms"] = z["ms"]
+        res["zero_si_iterations_mean"] = z["si_iterations_mean"]
+        res["zero_si_iterations_max"] = z["si_iterations_max"]
+        res["warm_ms"] = w["ms"]
+        res["warm_si_iterations_mean"] = w["si_iterations_mean"]
+        res["warm_si_iterations_max"] = w["si_iterations_max"]
+        res["recast_iterations_mean"] = w["recast_iterations_mean"]
+        res["recast_iterations_max"] = w["recast_iterations_max"]
+        res["time_reduction"] = 1.0 - w["ms"] / z["ms"]
+        # the guess barely improves below the network's own error on these
+        # families: the same step with a looser recast tolerance
+        loose = run(warm_at(LOOSE_RECAST_TOL))
+        loose["recast_tol"] = LOOSE_RECAST_TOL
+        loose["time_reduction"] = 1.0 - loose["ms"] / z["ms"]
+        res["loose_recast"] = loose
         out[family] = res
-        log(f"[bench] 64^2 {family}: warm {res['warm_ms']:.1f} ms, zero {res['zero_ms']:.1f} ms")
+        log(f"[bench] 64^2 {family}: warm {res['warm_ms']:.2f} ms (tol {LOOSE_RECAST_TOL:g}: "
+            f"{loose['ms']:.2f} ms), zero {res['zero_ms']:.2f} ms")
     return out
 
 
