@@ -354,3 +354,21 @@ def test_recast_rejects_bad_grid(env):
     with pytest.raises(B.MdpError):
         B.no_recast_guess(ctx, m, [prob], 1.0, 0.8, 1e-4, 5, [phi])
     m.close()
+
+
+@pytest.mark.parametrize("arch,batch", [("fno", 8), ("fno", 64), ("deeponet", 8), ("deeponet", 64)])
+def test_forward_repeatable(env, arch, batch):
+    """The BF16 forward gives the same bits on every call (batch 64 takes the
+    DFT kernels' several-fields-per-workgroup path)."""
+    torch, B, ctx = env
+    from paper_2509_01416_amd import train as T
+    m = B.Model(ctx, T.load_weights(arch=arch), arch=arch)
+    x = torch.tensor(_fields(batch, 2600).astype(np.float32), device="cuda")
+    outs = []
+    for _ in range(3):
+        y = torch.empty_like(x)
+        m.forward(x, y)
+        outs.append(y.cpu().numpy())
+    m.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
