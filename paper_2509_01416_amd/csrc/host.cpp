@@ -375,7 +375,9 @@ int oct_waves(int nd, int R, int D) {
 }
 }  // namespace
 
-Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool p1) {
+namespace {
+Plan plan_impl(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool p1,
+               bool try_fast) {
     Plan pl;
     int nd = 0;
     for (int o = 0; o < 4; ++o) nd = std::max(nd, dt.count[o]);
@@ -383,6 +385,19 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
     pl.p1 = p1;
     pl.D = p1 ? 1 : (c->force_D > 0 ? c->force_D : 1);
     pl.R.assign(n_inst, 1);
+    // grids the specialised kernel takes (block size aside): vacuum faces,
+    // 64-row segments (a ragged last row block is fine), and either several
+    // row blocks with nx >= 63 + KB or one row block with nx >= ny - 1
+    bool fast = try_fast && !c->force_generic && pl.D <= 4 && !p1 &&
+                (c->force_R <= 0 || c->force_R == 64);
+    int nxmin = 1 << 30, nxall = 1 << 30;
+    for (int i = 0; i < n_inst && fast; ++i) {
+        for (int f = 0; f < 4; ++f) fast = fast && p[i].bc[f] == TR_BC_VACUUM;
+        nxall = std::min(nxall, p[i].nx);
+        if (p[i].ny > 64) nxmin = std::min(nxmin, p[i].nx);
+        else fast = fast && p[i].nx >= p[i].ny - 1;
+    }
+    fast = fast && nxall >= 2 && nxmin >= 65;
     auto model = [&](const std::vector<int>& Rs) {
         double work = 0.0, tmax = 0.0;
         for (int i = 0; i < n_inst; ++i) {
@@ -413,6 +428,7 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
     if (c->force_R > 0)
         for (int i = 0; i < n_inst; ++i)
             if (feasible(i, c->force_R)) pl.R[i] = c->force_R;
+    if (fast) pl.R.assign(n_inst, 64);
     // W and S: the largest W (fewest partial planes) that still yields at
     // least one workgroup per CU (or every wave in its own slice)
     int vmax = 1;
@@ -458,29 +474,26 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
         Rmax = std::max(Rmax, pl.R[i]);
         nxmax = std::max(nxmax, p[i].nx);
     }
-    // the specialised kernel: 64-row segments everywhere, vacuum faces only,
-    // D <= 4, and nx >= 63 + KB wherever a grid has more than one row block
-    // (lane 0's ring column is then always written in an earlier block; with
-    // a single block lane 0 only ever reads the vacuum inflow)
-    bool fast = !c->force_generic && pl.D <= 4 && !p1;
-    int nxmin = 1 << 30;
-    for (int i = 0; i < n_inst; ++i) {
-        fast = fast && pl.R[i] == 64;
-        for (int f = 0; f < 4; ++f) fast = fast && p[i].bc[f] == TR_BC_VACUUM;
-        if (p[i].ny > 64) nxmin = std::min(nxmin, p[i].nx);
-    }
+    // the specialised kernel's block size: KB <= nx everywhere (a lane
+    // restarts at most once per block) and nx >= 63 + KB wherever a grid
+    // has more than one row block (lane 0's ring column is then always
+    // written in an earlier block); otherwise the generic kernel with its
+    // own segment heights
     const int kb0 = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_max_kb(W, Rmax, p1));
     if (fast) {
         int kb = std::min(c->force_KB > 0 ? c->force_KB : 16, sweep2d_fast_max_kb(W));
-        while (kb > 2 && (nxmin < 63 + kb || sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) > c->lds_limit))
-            kb /= 2;
-        if (kb >= 2 && nxmin >= 63 + kb &&
-            sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax) <= c->lds_limit) {
+        auto kb_ok = [&](int k) {
+            return nxmin >= 63 + k && k <= nxall &&
+                   sweep2d_fast_lds_bytes(W, k, pl.D, nxmax) <= c->lds_limit;
+        };
+        while (kb > 2 && !kb_ok(kb)) kb /= 2;
+        if (kb >= 2 && kb_ok(kb)) {
             pl.fast = true;
             pl.KB = kb;
             pl.lds = sweep2d_fast_lds_bytes(W, kb, pl.D, nxmax);
             return pl;
         }
+        return plan_impl(c, n_inst, p, dt, p1, false);
     }
     pl.fast = false;
     pl.KB = kb0;
@@ -489,6 +502,11 @@ Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
     pl.KB = std::max(pl.KB, 2);
     pl.lds = sweep2d_lds_bytes(W, pl.KB, pl.D, mx, nxmax, p1);
     return pl;
+}
+}  // namespace
+
+Plan make_plan(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool p1) {
+    return plan_impl(c, n_inst, p, dt, p1, true);
 }
 
 // Builds descriptors and workspaces for n_inst problems.  emission != nullptr

@@ -421,22 +421,29 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 
 // ---------------------------------------------------------------------------
 // Specialisation for the common shape: every instance of the launch has
-// 64-row segments (R = 64: a wave is one segment), 64 | ny, nx >= 63 + KB
-// unless ny = 64, and only vacuum inflow faces.  Lane l works on
+// 64-row segments (R = 64: a wave is one segment; the last row block may be
+// ragged), only vacuum inflow faces, KB <= nx, and either several row blocks
+// with nx >= 63 + KB or one row block with nx >= ny - 1.  Lane l works on
 // u = t - l = k*nx + ip, so with lane 0 at column ip0 the lane that starts a
 // row on step t is the one with (l - ip0) mod nx == 0, and the y flux lane 0
 // needs on step t was produced by lane 63 on step t - (nx - 63), at least
-// KB + 1 steps (so in an earlier block) before.  With one row block
-// (ny = 64) lane 0 reads only ring columns that lane 63 writes later (63
-// steps after lane 0's read), so the ring still holds the vacuum inflow
-// there, and lane 0's second restart (step 2 nx) lies past the last step
-// (nx + 62), so the tally's x-outflow capture holds as well.  That makes every per-step LDS address an immediate
-// offset from a per-block base and leaves no scalar bookkeeping in the step:
+// KB + 1 steps (so in an earlier block) before.  With one row block lane 0
+// only ever needs the vacuum inflow, so the ring is not updated at all, and
+// a lane's second restart (step 2 nx + l) lies past the last step (nx + ny - 1), so
+// the tally's x-outflow capture holds as well.  Lanes above the top row rl
+// of a ragged last block compute on the staged defaults (sigma_t = 1,
+// Q = 0); nothing of theirs is stored or flows down (the lane shift moves
+// flux up only, and lane 63's ring values of that block are written after
+// lane 0's last read of the column).  That makes every per-step LDS address
+// an immediate offset from a per-block base and leaves no scalar
+// bookkeeping in the step:
 //   * lane 0 reads its y inflow from a ring of nx + KB entries (the first KB
 //     mirrored at the end, so a block never wraps) and receives it as the
 //     "old" operand of the lane shift (a lane with no source keeps it);
-//   * every lane writes its y outflow to its own [lane][step] slot; after
-//     the block, lane 63's slots are copied into the ring;
+//   * every lane writes its y outflow to a [step] slot row of its own (per
+//     wave, lane 63's and the top row's; the other lanes' rows are a sink
+//     shared by the waves); after the block, lane 63's slots are copied
+//     into the ring;
 //   * a lane resets its x inflow to the vacuum value when it restarts
 //     (restart step e = (l - ip0) mod nx precomputed per block);
 //   * the LDS loads of step tt + kStepAhead are issued before the arithmetic
@@ -449,8 +456,9 @@ sweep2d_kernel(const InstDesc* __restrict__ insts,
 // current parity: a lane captures the x outflow of its finished row when it
 // restarts, and the 64 rows of a block are stored together after the block
 // in which lane 63 restarted (lane 0 restarts only nx - 63 > KB steps
-// later).  The source iteration runs without it and tallies once, after its
-// last iteration.
+// later); the outgoing y face is stored per block from the top row's slots.
+// The source iteration runs without it and tallies once, after its last
+// iteration.
 // The sweep of one workgroup (instance I, octant and slice of wk) into its
 // partial plane; par = face parity (the tally's face set).  Shared by the
 // sweep kernel and the persistent iteration kernel.
@@ -504,7 +512,7 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
 #pragma unroll
     for (int v = 0; v < (WT > 0 ? WT : 1); ++v) wsl[v] = wave_w(v);
     // LDS: pbuf[2][W*64][KB+1] | sbuf[2][KB/2][65 float4] | ring[W][D][nx+KB]
-    //      | yob[W*64][D][KB+1]
+    //      | yob[W][2][D][KB+1] | sink[64][D][KB+1]
     // sbuf holds the (sigma_t, Q) pairs of steps 2k and 2k+1 of a row side
     // by side, one 16-byte read per lane and two steps; its 65-entry rows
     // keep the staging stores (consecutive threads step through a row's KB
@@ -514,11 +522,19 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
     float* pbuf = smem;
     float4* sbuf = reinterpret_cast<float4*>(smem + 2 * W * 64 * PST);
     float* ringw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)(wv * D) * RS;
-    float* yobw = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)W * D * RS +
-                  (size_t)(wv * 64) * D * PST;
-    float* yol = yobw + lane * D * PST;   // this lane's y-outflow slots
-    const int nblk = ny >> lr;
-    const int T = nblk * nx + R - 1;
+    // row blocks; the last one may be ragged: its top row is lane rl, and
+    // the stream ends with that lane's last cell
+    const int nblk = (ny + R - 1) >> lr;
+    const int rl = ny - 1 - (nblk - 1) * R;
+    // y-outflow slots [step]: two rows per wave, lane 63's (the ring's
+    // source) and lane rl's (the tally's y face, when rl < 63); every other
+    // lane writes into a sink row of its own, shared by the waves
+    float* yob0 = smem + 2 * W * 64 * PST + 4 * KB * SROW + (size_t)W * D * RS;
+    float* yobw = yob0 + (size_t)(wv * 2) * D * PST;
+    float* yol = lane == R - 1 ? yobw
+                 : lane == rl  ? yobw + D * PST
+                               : yob0 + (size_t)(W * 2 + lane) * D * PST;
+    const int T = nblk * nx + rl;
     gfloat* __restrict__ part = (gfloat*)(I.part + (size_t)(o * I.S + wk.slice) * I.cells);
 
     // Staging and reduction positions.  A block covers KB steps x 64 rows;
@@ -550,11 +566,10 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
     const int isg = xpos ? 1 : -1, i0 = xpos ? 0 : nx - 1;
     const int jsg = ypos ? 1 : -1, j0 = ypos ? 0 : ny - 1;
     const int dN = 4 * isg * KB, dW = 4 * (jsg * R * nx + isg * (KB - nx));
-    const unsigned U = (unsigned)(nblk * nx);
     const char* __restrict__ Stb = reinterpret_cast<const char*>(I.st);
     const char* __restrict__ Qbb = reinterpret_cast<const char*>(I.Q);
     int cip[kMaxPos], cof[kMaxPos], clo[kMaxPos], rof[kMaxPos];
-    unsigned sad[kMaxPos], rad[kMaxPos];
+    unsigned sad[kMaxPos], rad[kMaxPos], ulim[kMaxPos];
     bool cva[kMaxPos], rva[kMaxPos];
     float pst[kMaxPos], pq[kMaxPos];
 #pragma unroll
@@ -569,7 +584,10 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
         cip[jx] = t2 - rr;
         clo[jx] = rr - t2;
         cof[jx] = 4 * ((j0 + jsg * rr) * nx + i0 + isg * (t2 - rr));
-        cva[jx] = jx < nsl && t2 - rr >= 0;
+        // the position's stream range: rows above rl lie outside the grid
+        // in the last row block
+        ulim[jx] = (unsigned)((rr <= rl ? nblk : nblk - 1) * nx);
+        cva[jx] = jx < nsl && (unsigned)(t2 - rr) < ulim[jx];
         rva[jx] = false;
         rof[jx] = 0;
         sad[jx] = (unsigned)((t2 >> 1) * SROW + rr) * 16u + (unsigned)(t2 & 1) * 8u;
@@ -610,7 +628,7 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
             const bool wrap = ip >= nx;
             cip[jx] = wrap ? ip - nx : ip;
             cof[jx] += wrap ? dW : dN;
-            cva[jx] = (unsigned)(t0n - clo[jx]) < U;
+            cva[jx] = (unsigned)(t0n - clo[jx]) < ulim[jx];
         }
     };
 
@@ -623,14 +641,18 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
     float xin[D], yo[D], xs[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) { xin[d] = 0.f; yo[d] = 0.f; xs[d] = 0.f; }
-    const bool top = lane == R - 1;
     auto flush_x = [&](int kb) {
         const int jp = kb * R + lane;
         const int j = ypos ? jp : ny - 1 - jp;
+        if (jp < ny) {
 #pragma unroll
-        for (int d = 0; d < D; ++d)
-            if (mi[d] >= 0) fcur[((size_t)fxout * nf + j) * M + mi[d]] = xs[d];
+            for (int d = 0; d < D; ++d)
+                if (mi[d] >= 0) fcur[((size_t)fxout * nf + j) * M + mi[d]] = xs[d];
+        }
     };
+    // lane mod nx: a lane's row starts are the steps t with t = lane (mod
+    // nx); equal to lane unless a grid narrower than 64 is one row block
+    const int lmod = lane < nx ? lane : lane % nx;
     int kflush = 0;
 
     // one step: e = this lane's restart step in the block; (st, q, rv) were
@@ -667,7 +689,7 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
         const int half = blkno & 1;
         const int tend = min(KB, T - t0);
         const bool more = t0 + KB < T;
-        int e = lane - ip0b;
+        int e = lmod - ip0b;
         if (e < 0) e += nx;                        // restart step of this lane
         const float4* sp = sbuf + half * (KB / 2) * SROW + lane;   // step pair k: sp[k*SROW]
         float* pw = pbuf + ((size_t)(half * W + wv) * 64 + lane) * PST;
@@ -750,26 +772,41 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
             }
         }
         // lane 63's y outflow of this block into the ring (and its mirror);
-        // its column ip0b + j - 63 lies in [-63, nx - 49]
-        {
+        // its column ip0b + j - 63 lies in [-63, nx - 49].  One row block:
+        // nothing reads the ring again.
+        if (nblk > 1) {
             const int j = lane;
             if (j < tend && t0 + j >= R - 1) {
                 int col = ip0b + j - (R - 1);
                 if (col < 0) col += nx;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const float v = yobw[(size_t)(R - 1) * D * PST + d * PST + j];
+                    const float v = yobw[d * PST + j];
                     ringw[d * RS + col] = v;
                     if (col < KB) ringw[d * RS + nx + col] = v;
                 }
             }
         }
-        // lane 63 restarted in this block: the x outflow of the previous row
-        // block is complete (lane 0 restarts nx - 63 > KB steps later)
         if constexpr (TALLY) {
+            // lane 63 restarted in this block: the x outflow of the previous
+            // row block is complete (lane 0 restarts nx - 63 > KB steps
+            // later).  Only grids of several row blocks (nx >= 63 + KB) get
+            // here: lane 63 restarts at step nx + 63 at the earliest.
             int e63 = (R - 1) - ip0b;
             if (e63 < 0) e63 += nx;
-            if (e63 < tend && t0 + e63 >= nx) flush_x(kflush++);
+            if (e63 < tend && t0 + e63 >= nx + R - 1) flush_x(kflush++);
+            // the grid's outgoing y face: lane rl's y outflow in the last
+            // row block
+            const int j = lane;
+            const int col = t0 + j - rl - (nblk - 1) * nx;
+            if (j < tend && col >= 0 && col < nx) {
+                const int i = xpos ? col : nx - 1 - col;
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    if (mi[d] >= 0)
+                        fcur[((size_t)fyout * nf + i) * M + mi[d]] =
+                            yobw[(rl == R - 1 ? 0 : D * PST) + d * PST + j];
+            }
         }
         ip0b += KB;
         if (ip0b >= nx) ip0b -= nx;
@@ -821,21 +858,12 @@ __device__ __forceinline__ void fast_sweep_wg(const InstDesc& I, const SweepWork
         }
     }
     if constexpr (TALLY) {
-        // lane 63 never restarts after its last row: capture, then store the
-        // x outflow of the last row block
+        // the top lane rl ends the stream and never restarts after its last
+        // row (the lanes below it restarted after theirs): capture, then
+        // store the x outflow of the last row block
 #pragma unroll
-        for (int d = 0; d < D; ++d) xs[d] = top ? xin[d] : xs[d];
+        for (int d = 0; d < D; ++d) xs[d] = lane == rl ? xin[d] : xs[d];
         flush_x(nblk - 1);
-        // the ring holds the grid's outgoing y face of every column
-        for (int e = lane; e < D * nx; e += 64) {
-            const int d = e / nx, ipc = e - d * nx;
-            const int i = xpos ? ipc : nx - 1 - ipc;
-            int m = -1;
-#pragma unroll
-            for (int dd = 0; dd < D; ++dd)
-                if (dd == d) m = mi[dd];
-            if (m >= 0) fcur[((size_t)fyout * nf + i) * M + m] = ringw[d * RS + ipc];
-        }
     }
 }
 
@@ -1098,7 +1126,7 @@ bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,
 
 size_t sweep2d_fast_lds_bytes(int W, int KB, int D, int max_nx) {
     return sizeof(float) * ((size_t)2 * W * 64 * (KB + 1) + (size_t)4 * KB * 65 +
-                            (size_t)W * D * (max_nx + KB) + (size_t)W * 64 * D * (KB + 1));
+                            (size_t)W * D * (max_nx + KB) + (size_t)(2 * W + 64) * D * (KB + 1));
 }
 
 bool launch_sweep2d(int D, bool refl, int nwork, int W, int KB,

@@ -344,6 +344,82 @@ def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
         ctx.set_sweep_config(0, 0, 0, 0)
 
 
+@pytest.mark.parametrize("nx,ny,n,cfg", [
+    (96, 96, 8, (1, 10, 1, 64)),
+    (80, 200, 16, (1, 9, 4, 64)),
+    (70, 65, 8, (2, 5, 1, 64)),    # one row in the last block, KB = 4
+    (128, 1, 4, (1, 3, 1, 64)),    # a single row
+    (64, 30, 8, (3, 2, 2, 64)),
+])
+def test_ragged_rows_match_the_padded_grid(env, nx, ny, n, cfg):
+    """A grid whose last row block is ragged (ny not a multiple of 64) is
+    swept by the specialised kernel with the lanes above its top row idle.
+    The same grid padded to whole row blocks, with zero emission in the
+    padding, sweeps to the same flux bit for bit on the real rows: the
+    padding's downward fluxes are exactly zero (vacuum top face, zero
+    emission), so they enter the real rows as the vacuum inflow does, and
+    the launch shape (and so every operation's order) is the same."""
+    torch, B, ctx = env
+    quad = I.level_symmetric_2d(n)
+    nyp = 64 * -(-ny // 64)
+    dx = dy = 0.125   # exact in binary: both grids get identical cell widths
+    inst = I.random_instance(nx, ny, seed=900 + nx + ny, lx=dx * nx, ly=dy * ny)
+    pad = I.random_instance(nx, nyp, seed=1, lx=dx * nx, ly=dy * nyp)
+    pad.sigma_t[:] = 1.0
+    pad.sigma_t[:ny] = inst.sigma_t
+    rng = np.random.Generator(np.random.PCG64(17))
+    q = rng.uniform(0.0, 2.0, (ny, nx)).astype(np.float32)
+    qp = np.zeros((nyp, nx), np.float32)
+    qp[:ny] = q
+    q_ = B.Quad.from_inputs(quad)
+    ctx.set_sweep_config(*cfg)
+    try:
+        outs = []
+        for ins, em in ((inst, q), (pad, qp)):
+            pr = [to_problem(ins, torch)]
+            plan = ctx.sweep_plan(pr, q_)
+            assert plan["specialised"] == 1 and plan["R"] == 64
+            e = [torch.tensor(em, device="cuda")]
+            o = [torch.zeros_like(e[0])]
+            B.tr_sweep(ctx, pr, q_, e, o)
+            torch.cuda.synchronize()
+            outs.append((plan, o[0].cpu().numpy()))
+        log(f"  ragged {nx}x{ny} vs padded {nx}x{nyp} S{n}: plans {outs[0][0]} / {outs[1][0]}")
+        assert outs[0][0] == outs[1][0]
+        assert np.array_equal(outs[0][1], outs[1][1][:ny])
+        ref = oracle.sweep2d(nx, ny, inst.lx, inst.ly, quad.mu, quad.eta, quad.w,
+                             inst.sigma_t.astype(np.float32), q)
+        assert rel_inf(outs[0][1], ref) <= SWEEP_BAR
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("shapes,n", [
+    ([(96, 96), (48, 48), (32, 32), (37, 23), (130, 100)], 8),
+    ([(5, 6), (3, 2), (64, 1), (16, 17)], 4),
+])
+def test_ragged_grids_solve_on_the_specialised_kernel(env, shapes, n):
+    """Uneven grids with ragged or single row blocks (down to 3 x 2 cells
+    and a one-row grid) solve on the specialised kernel to the oracle's
+    fixed point, and its tally sweep's boundary faces close the particle
+    balance."""
+    torch, B, ctx = env
+    quad = I.level_symmetric_2d(n)
+    insts = [I.random_instance(nx, ny, seed=950 + nx * 3 + ny, lx=6.0, ly=5.0)
+             for nx, ny in shapes]
+    plan = ctx.sweep_plan([to_problem(i, torch) for i in insts], B.Quad.from_inputs(quad))
+    assert plan["specialised"] == 1
+    rc, st, phis = _solve(env, insts, quad, 1e-7)
+    assert rc == 0
+    for inst, s, phi in zip(insts, st, phis):
+        ref = oracle.solve_instance(inst, quad, tol=1e-13)
+        e = rel_l2(phi, ref.phi)
+        log(f"  {inst.nx}x{inst.ny} S{n} plan {plan}: iters gpu={s['iterations']} "
+            f"oracle={ref.iterations} rel_l2={e:.3e} balance={s['balance_rel']:.2e}")
+        assert e < 1e-5
+        assert s["balance_rel"] < 1e-5
+
+
 def test_not_converged_and_errors(env):
     torch, B, ctx = env
     log("[tr_solve] status codes")

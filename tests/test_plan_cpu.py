@@ -33,11 +33,29 @@ def test_benchmark_batch_gets_the_specialised_kernel():
 
 @pytest.mark.parametrize("shapes,why", [
     ([(64, 128)], "nx < 63 + KB with two row blocks"),
-    ([(256, 256), (48, 48)], "segment heights differ (48 needs R = 16)"),
-    ([(256, 200)], "64 does not divide ny"),
+    ([(16, 64)], "one row block, nx < ny - 1"),
+    ([(256, 256), (64, 200)], "nx < 63 + KB for the second grid"),
 ])
 def test_generic_kernel_when_the_specialised_one_does_not_apply(shapes, why):
     assert _plan(shapes)["specialised"] == 0, why
+
+
+@pytest.mark.parametrize("shapes,n", [
+    ([(256, 256), (48, 48)], 8),   # ragged single row block beside full ones
+    ([(256, 200)], 8),             # ragged last row block (200 = 3 x 64 + 8)
+    ([(96, 96), (32, 32), (128, 128)], 8),
+    ([(37, 23)], 8),               # one row block narrower than 64
+    ([(4, 4)], 4),
+    ([(5, 6)], 4),
+    ([(96, 96)] * 16, 16),
+    ([(3, 2)] * 16, 16),           # KB <= nx caps the block at 2
+])
+def test_ragged_row_blocks_take_the_specialised_kernel(shapes, n):
+    p = _plan(shapes, n=n)
+    assert p["specialised"] == 1 and p["R"] == 64
+    assert 2 <= p["KB"] <= min(nx for nx, _ in shapes)
+    if len(shapes) == 16 and shapes[0][0] >= 16:
+        assert p["W"] == 9 and p["KB"] == 16
 
 
 def test_reflective_faces_use_the_generic_kernel():
@@ -62,6 +80,9 @@ def test_block_size_shrinks_to_fit_narrow_grids():
 
 
 def test_plan_rows_divide_ny():
+    # the generic kernel's segments divide ny (its ring writer is the last
+    # lane of every segment); reflective faces keep these on it
     for shapes in ([(96, 96)], [(48, 48)], [(100, 40)], [(33, 66)]):
-        p = _plan(shapes)
+        p = _plan(shapes, bc=(1, 0, 0, 0))
+        assert p["specialised"] == 0
         assert shapes[0][1] % p["R"] == 0 and p["R"] <= shapes[0][0]
