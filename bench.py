@@ -58,7 +58,7 @@ BYTES_PER_CELL_ITER = 20
 # valid only for the kernel source with this hash prefix (sweep_source_hash),
 # otherwise null
 SWEEP_TRAFFIC_BYTES = 79.82e6
-SWEEP_TRAFFIC_SRC = "b9473bee02ac30bb"
+SWEEP_TRAFFIC_SRC = "ebb3a49a9194af28"
 
 
 def sweep_source_hash() -> str:
@@ -103,6 +103,8 @@ def parse():
                     help="skip the uneven-batch and network-grid legs")
     ap.add_argument("--network-only", action="store_true",
                     help="time the networks alone and print their figures (counter runs)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run the uneven-batch leg alone and print its figures (counter runs)")
     ap.add_argument("--weights", default=None,
                     help="trained network parameters (default: the packaged file)")
     return ap.parse_args()
@@ -491,12 +493,23 @@ def network_only(args):
     ctx.close()
 
 
+def uneven_only(args):
+    """--uneven-only: the uneven-batch leg alone (for counter runs)."""
+    import torch
+    from paper_2509_01416_amd import binding as B
+    from paper_2509_01416_amd import inputs as I
+    print(json.dumps({"uneven_batch_256": uneven_leg(B, I, torch, args)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this "
               "build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.uneven_only:
+        uneven_only(args)
+        return
     if args.network_only:
         network_only(args)
         return
