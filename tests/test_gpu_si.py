@@ -610,6 +610,7 @@ def test_paper_1d_setting_solve(env):
     ([(64, 64)] * 64, 8, "change"),
     ([(64, 64)] * 24 + [(128, 128)] * 4, 8, "bound"),
     ([(128, 256), (256, 128), (192, 64)], 16, "change"),
+    ([(96, 96), (48, 48), (130, 100), (37, 23)], 8, "change"),   # ragged row blocks
 ])
 def test_persistent_iteration_matches_kernel_launches(env, shapes, n, rule):
     """The persistent iteration (a chunk of sweeps, combines and tests per
