@@ -286,7 +286,11 @@ def test_recast_linear_fixed_point(env):
     log(f"  recast linear: status={rc} iters={st[0]['iterations']} "
         f"phi={got.mean():.6f} exact={exact:.6f}")
     assert rc == B.TR_OK and st[0]["status"] == B.TR_OK
-    assert np.allclose(got, exact, rtol=1e-4)
+    # the loop stops when the relative change is below 1e-6; with contraction
+    # g the distance to the fixed point is then at most 1e-6 g / (1 - g) =
+    # 1e-6, plus the FP32 rounding of the network's products (about 1e-7
+    # relative per DFT product of 64-128 terms)
+    assert np.allclose(got, exact, rtol=1e-5)
     m.close()
 
 
