@@ -394,22 +394,27 @@ def test_ragged_rows_match_the_padded_grid(env, nx, ny, n, cfg):
         ctx.set_sweep_config(0, 0, 0, 0)
 
 
-@pytest.mark.parametrize("shapes,n", [
-    ([(96, 96), (48, 48), (32, 32), (37, 23), (130, 100)], 8),
-    ([(5, 6), (3, 2), (64, 1), (16, 17)], 4),
+@pytest.mark.parametrize("shapes,n,cfg", [
+    ([(96, 96), (48, 48), (32, 32), (37, 23), (130, 100)], 8, (0, 0, 0, 0)),
+    ([(96, 96), (48, 48), (32, 32), (37, 23), (130, 100)], 8, (2, 5, 1, 64)),
+    ([(5, 6), (3, 2), (64, 1), (16, 17)], 4, (0, 0, 0, 0)),
 ])
-def test_ragged_grids_solve_on_the_specialised_kernel(env, shapes, n):
+def test_ragged_grids_solve_on_the_specialised_kernel(env, shapes, n, cfg):
     """Uneven grids with ragged or single row blocks (down to 3 x 2 cells
     and a one-row grid) solve on the specialised kernel to the oracle's
-    fixed point, and its tally sweep's boundary faces close the particle
-    balance."""
+    fixed point, with one or two directions per lane, and its tally sweep's
+    boundary faces close the particle balance."""
     torch, B, ctx = env
     quad = I.level_symmetric_2d(n)
     insts = [I.random_instance(nx, ny, seed=950 + nx * 3 + ny, lx=6.0, ly=5.0)
              for nx, ny in shapes]
-    plan = ctx.sweep_plan([to_problem(i, torch) for i in insts], B.Quad.from_inputs(quad))
-    assert plan["specialised"] == 1
-    rc, st, phis = _solve(env, insts, quad, 1e-7)
+    ctx.set_sweep_config(*cfg)
+    try:
+        plan = ctx.sweep_plan([to_problem(i, torch) for i in insts], B.Quad.from_inputs(quad))
+        assert plan["specialised"] == 1 and (cfg[0] == 0 or plan["D"] == cfg[0])
+        rc, st, phis = _solve(env, insts, quad, 1e-7)
+    finally:
+        ctx.set_sweep_config(0, 0, 0, 0)
     assert rc == 0
     for inst, s, phi in zip(insts, st, phis):
         ref = oracle.solve_instance(inst, quad, tol=1e-13)
