@@ -161,7 +161,24 @@ def cpu_baseline(wl, tol: float, stop: str, target_1core_s: float):
                           "updates_per_s": ups_all / dt_all},
             "cores_1": {"updates_per_s": rate1,
                         "seconds_to_tolerance_estimated": ups_all / rate1},
-            "oracle_iterations_zero_start": its}
+            "oracle_iterations_zero_start": its,
+            "sinusoid_128": cpu_sinusoid(tol, stop)}
+
+
+def cpu_sinusoid(tol: float, stop: str):
+    """The FP64 C oracle on one core for the 128 x 128 sinusoidal problem,
+    from zero to the same tolerance and stopping rule (a fraction of a
+    second of host work)."""
+    import oracle
+    from paper_2509_01416_amd import inputs as I
+    wl = I.sinusoid_128()
+    kw = dict(norm="bound", stride=16) if stop == "bound" else dict(norm="l2")
+    t0 = time.perf_counter()
+    r = oracle.solve_instance(wl.instances[0], wl.quad, tol=tol, f32_inputs=True, **kw)
+    dt = time.perf_counter() - t0
+    ups = r.iterations * wl.instances[0].cells * wl.quad.n_dir
+    return {"threads": 1, "seconds_to_tolerance": dt, "iterations": int(r.iterations),
+            "updates_per_s": ups / dt}
 
 
 # algorithmic FLOP of one network forward per 64 x 64 sample (dense products
@@ -244,6 +261,53 @@ def uneven_leg(B, I, torch, args):
             "sweep_roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
                                "unit": "TFLOP/s",
                                "frac": achieved / VALU_FP32_PEAK_TFLOPS if achieved else None}}
+
+
+def sinusoid_leg(B, I, torch, args):
+    """The 128 x 128 sinusoidal problem (S8, sigma_t = 1 + 0.5 sin sin,
+    c = 0.9, GRF source, vacuum) solved from zero on its own context, launch
+    shape by the autotuner (outside the timing): median wall time of five
+    solves, cell-angle updates/s, iteration count, the sweep's time per
+    launch, and the distance to the stored FP64 oracle reference."""
+    wl = I.sinusoid_128()
+    inst = wl.instances[0]
+    f = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    probs = [B.Problem(sigma_t=f(inst.sigma_t), sigma_s=f(inst.sigma_s), source=f(inst.source),
+                       lx=inst.lx, ly=inst.ly)]
+    quad = B.Quad.from_inputs(wl.quad)
+    phis = [torch.zeros_like(probs[0].sigma_t)]
+    ctx = B.Context()
+    ctx.set_stop_rule(args.stop)
+    tuned = ctx.autotune(probs, quad)
+    B.tr_solve(ctx, probs, quad, None, phis, wl.tol, args.max_iter)   # warm-up
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = B.tr_solve(ctx, probs, quad, None, phis, wl.tol, args.max_iter)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ctx.profile(True)
+    B.tr_solve(ctx, probs, quad, None, phis, wl.tol, args.max_iter)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    med = float(np.median(times))
+    its = int(st[0]["iterations"])
+    ups = its * inst.cells * wl.quad.n_dir
+    z = np.load(os.path.join(ROOT, "tests", "golden", "sinusoid_128_S8_ref.npz"))
+    ref = z["phi"].astype(np.float64)
+    got = phis[0].cpu().numpy().astype(np.float64)
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    log(f"[bench] sinusoid 128^2: {med * 1e3:.2f} ms, {its} iterations, "
+        f"{ups / med:.3e} updates/s, rel L2 vs oracle {e:.2e}")
+    return {"workload": wl.name, "ms": med * 1e3, "status": rc,
+            "cell_angle_updates_per_s": ups / med, "iterations": its,
+            "oracle_iterations_same_rule": int(z["iters_bound"] if args.stop == "bound"
+                                               else z["iters_change"]),
+            "sweep_plan": {k: v for k, v in tuned.items() if k != "ms"},
+            "sweep_ms_per_launch": prof["sweep_ms"] / max(1, prof["sweep_launches"]),
+            "rel_l2_vs_oracle": e}
 
 
 def network_grid_leg(models, B, I, torch, args):
@@ -625,6 +689,7 @@ def main():
     if model is not None and not args.no_eigen:
         eigen = eigen_leg(ctx, model, B, I, torch, args)
     uneven = None if args.no_extra else uneven_leg(B, I, torch, args)
+    sinus = None if args.no_extra else sinusoid_leg(B, I, torch, args)
     netgrid = (None if args.no_extra or model is None
                else network_grid_leg({"fno": model, "deeponet": don}, B, I, torch, args))
     don_step = None
@@ -705,6 +770,7 @@ def main():
         "network": network,
         "eigen": eigen,
         "uneven_batch_256": uneven,
+        "sinusoid_128": sinus,
         "warm_vs_zero_64": netgrid,
         "deeponet_warm_step": don_step,
         "cpu_baseline": cpu,

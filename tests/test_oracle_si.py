@@ -214,3 +214,20 @@ def test_warm_start_reaches_same_fixed_point():
                               phi0=z.phi * (1 + 0.05 * np.sin(np.arange(64)).reshape(8, 8)))
     assert np.abs(z.phi - g.phi).max() < 1e-10 * z.phi.max()
     assert g.iterations < z.iterations
+
+
+def test_stored_sinusoid_reference_is_the_fixed_point():
+    """The stored 128^2 sinusoidal reference (an FP32 copy of the oracle run
+    to a 1e-12 change) is a fixed point of the source iteration: one more
+    iteration from it moves it by about its own FP32 rounding (6e-8
+    relative) times the contraction, and the oracle restarted from it stops
+    at once under a 1e-6 change."""
+    z = np.load(os.path.join(GOLDEN, "sinusoid_128_S8_ref.npz"))
+    wl = I.sinusoid_128()
+    inst, quad = wl.instances[0], wl.quad
+    phi = z["phi"].astype(np.float64)
+    one = oracle.solve_instance(inst, quad, tol=0.0, phi0=phi, max_iter=1, f32_inputs=True)
+    assert np.linalg.norm(one.phi - phi) < 2e-7 * np.linalg.norm(phi)
+    again = oracle.solve_instance(inst, quad, tol=wl.tol, phi0=phi, f32_inputs=True)
+    assert again.iterations <= 2
+    assert int(z["iters_change"]) < int(z["iters_bound"]) < int(z["iters_ref"])
