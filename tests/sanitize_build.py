@@ -5,7 +5,9 @@ both builds (MDPNOP_LIB and ORACLE_LIB select them; the sanitizer runtime is
 preloaded into the interpreter, leak detection is off because the
 interpreter itself keeps memory until exit).
 
-Usage: python -m paper_2509_01416_amd.sanitize [pytest arguments]
+Test infrastructure (it builds and runs the oracle), kept beside the tests.
+
+Usage: python tests/sanitize_build.py [pytest arguments]
 """
 from __future__ import annotations
 
@@ -15,12 +17,14 @@ import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
-from . import build as B
-
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+from paper_2509_01416_amd import build as B  # noqa: E402
+
 OUT = os.path.join(B.CSRC, "_build_asan")
-LIB = os.path.join(HERE, "libmdpnop_asan.so")
+LIB = os.path.join(ROOT, "paper_2509_01416_amd", "libmdpnop_asan.so")
 ORACLE_SRC = os.path.join(ROOT, "oracle", "si_oracle.c")
 ORACLE_LIB = os.path.join(ROOT, "oracle", "libsi_oracle_asan.so")
 CLANG = "/opt/rocm/llvm/bin/clang"
@@ -62,7 +66,10 @@ def runtime() -> str:
 
 def main(argv) -> int:
     build()
-    env = dict(os.environ, MDPNOP_LIB=LIB, ORACLE_LIB=ORACLE_LIB, LD_PRELOAD=runtime(),
+    # the sanitizer runtime goes first in the child's preload list; whatever
+    # the environment already preloads stays after it
+    preload = ":".join(p for p in (runtime(), os.environ.get("LD_PRELOAD", "")) if p)
+    env = dict(os.environ, MDPNOP_LIB=LIB, ORACLE_LIB=ORACLE_LIB, LD_PRELOAD=preload,
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     cmd = [sys.executable, "-m", "pytest", os.path.join(ROOT, "tests"), "-q", "-m", "not gpu",
