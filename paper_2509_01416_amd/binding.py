@@ -16,7 +16,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # MDPNOP_LIB points the binding at another build of the library (the
-# host-sanitizer build of sanitize.py); it must exist like the default one
+# host-sanitizer build of tests/sanitize_build.py); it must exist like the
+# default one
 LIB_PATH = os.environ.get("MDPNOP_LIB") or os.path.join(_HERE, "libmdpnop.so")
 
 TR_OK = 0
