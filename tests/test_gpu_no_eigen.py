@@ -104,6 +104,46 @@ def test_no_eigen_parity_trained_network(env, variant):
     m.close()
 
 
+@pytest.mark.parametrize("variant", ["sp", "cp"])
+def test_no_eigen_parity_trained_deeponet(env, variant):
+    """The trained DeepONet as the eigenvalue loop's network (the paper's
+    DeepONet-SP and CP, Appendix A2): four outer updates in FP32 mode
+    against the oracle loop driving the FP64 DeepONet, same bars as for the
+    FNO."""
+    from oracle import deeponet as D
+    from paper_2509_01416_amd import train as T
+    torch, B, ctx, _ = env
+    w = T.load_weights(arch="deeponet")
+    m = B.Model(ctx, w, arch="deeponet")
+    m.set_fp32(True)
+    inst, nsf = _case("sine")
+    quad = I.level_symmetric_2d(8)
+    v = B.NO_EIGEN_SP if variant == "sp" else B.NO_EIGEN_CP
+    phi = [torch.zeros((N, N), device="cuda")]
+    log(f"no_eigen {variant}: 4 updates, trained DeepONet in FP32 mode, 64x64 S8")
+    rc, st = B.no_eigen(ctx, m, [to_problem(inst, torch)], [_dev(torch, nsf)],
+                        B.Quad.from_inputs(quad), I.SIGMA_T_STAR, I.SIGMA_S_STAR, v,
+                        None, phi, None, 1e-30, 1e-30, 4)
+    torch.cuda.synchronize()
+    lay, coords = D.Layout(), D.grid_coords(N)
+    p64 = np.asarray(w, np.float32).astype(np.float64)
+
+    def net(s):
+        out, _ = D.forward(p64, s.reshape(1, -1), coords, lay)
+        return out[0].reshape(N, N)
+    inst64 = I.Instance(nx=N, ny=N, lx=10.0, ly=10.0, sigma_t=_f32(inst.sigma_t),
+                        sigma_s=_f32(inst.sigma_s), source=np.zeros((N, N)))
+    ref = E.solve_eigen_no(inst64, quad, _f32(nsf), RC.network_inner(net, SA_STAR),
+                           SA_STAR, variant, tol_k=0.0, tol_phi=0.0, max_outer=4)
+    got = phi[0].cpu().numpy().astype(np.float64)
+    e = rel_l2(got, ref.phi)
+    log(f"  k gpu={st[0]['k']:.7f} oracle={ref.k:.7f} rel_l2={e:.2e} outer={st[0]['outer']}")
+    assert rc == B.TR_NOT_CONVERGED and st[0]["outer"] == 4
+    assert abs(st[0]["k"] - ref.k) < 1e-5 * abs(ref.k)
+    assert e < 1e-4
+    m.close()
+
+
 def test_no_eigen_sp_linear_network_closed_form(env):
     from test_gpu_fno import _linear_params
     torch, B, ctx, _ = env
