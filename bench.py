@@ -391,14 +391,15 @@ def _network_grid_arch(ctx, model, B, I, torch, args):
     return out
 
 
-def eigen_leg(ctx, model, B, I, torch, args):
+def eigen_leg(ctx, model, B, I, torch, args, don=None):
     """k-eigenvalue measurements (section 5.2-5.3, Appendix A2), tolerance
     1e-4 on k, the flux and the inner solves (the paper's uniform
     criterion): the model-based power iteration on 16 x 256^2 S16 (the x-y
     eigen Case 1 analogue), the three-group problem of Tables 8-9 on
     16 x 256^2 S16, and on the network's 64 x 64 grid the model-based solve
-    beside SP and CP (network loop, then model-based refinement), as wall
-    times normalised to the model-based one."""
+    beside SP and CP (network loop, then model-based refinement) with the
+    FNO and with the DeepONet, as wall times normalised to the model-based
+    one."""
     dev = "cuda"
     f = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
 
@@ -473,7 +474,13 @@ def eigen_leg(ctx, model, B, I, torch, args):
     cp = lambda: B.eigen_preconditioned(ctx, model, probs, nsf, quad, I.SIGMA_T_STAR,
                                         I.SIGMA_S_STAR, B.NO_EIGEN_CP, phis, tol, tol, tol)
     small = {"workload": wl.name}
-    for name, fn in (("model_based", mb), ("sp", sp), ("cp", cp)):
+    legs = [("model_based", mb), ("sp", sp), ("cp", cp)]
+    if don is not None:
+        legs += [(name, (lambda v: lambda: B.eigen_preconditioned(
+                    ctx, don, probs, nsf, quad, I.SIGMA_T_STAR, I.SIGMA_S_STAR, v, phis,
+                    tol, tol, tol))(v))
+                 for name, v in (("deeponet_sp", B.NO_EIGEN_SP), ("deeponet_cp", B.NO_EIGEN_CP))]
+    for name, fn in legs:
         fn()
         ms, r = wall(fn, 5, name)
         if name == "model_based":
@@ -489,8 +496,9 @@ def eigen_leg(ctx, model, B, I, torch, args):
                            "refine_inner_sweeps_mean": float(np.mean([s["inner"] for s in st]))}
         log(f"[bench] eigen {wl.name} {name}: {ms:.1f} ms")
     base = small["model_based"]["ms"]
-    for name in ("sp", "cp"):
-        small[name]["normalised_time_pct"] = 100.0 * small[name]["ms"] / base
+    for name in small:
+        if name not in ("workload", "model_based"):
+            small[name]["normalised_time_pct"] = 100.0 * small[name]["ms"] / base
     return {"tol": tol, "timing": "median of 5 solves after one warm-up",
             "min_max_ms": spread, "model_based_256": big, "three_group_256": three,
             "preconditioned_64": small}
@@ -687,7 +695,7 @@ def main():
         network = network_leg(ctx, model, don, len(probs), torch)
     eigen = None
     if model is not None and not args.no_eigen:
-        eigen = eigen_leg(ctx, model, B, I, torch, args)
+        eigen = eigen_leg(ctx, model, B, I, torch, args, don)
     uneven = None if args.no_extra else uneven_leg(B, I, torch, args)
     sinus = None if args.no_extra else sinusoid_leg(B, I, torch, args)
     netgrid = (None if args.no_extra or model is None
