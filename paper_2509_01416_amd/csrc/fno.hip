@@ -1407,6 +1407,144 @@ pointwise_kernel(const float* __restrict__ W, const float* __restrict__ v,
     }
 }
 
+// ----------------------------- last pointwise layer + projection head --
+// The last Fourier layer's pointwise path fused with the projection head,
+// for 32 channels and 128 hidden units.  One workgroup per (64-pixel tile,
+// sample), the tiling both kernels use: z = W^T v + (spectral path) + bias
+// for the tile's 32 channels with pointwise_kernel's products, rounding and
+// order; z goes to LDS as the head's operand, rounded as proj_fused_kernel
+// rounds the z it reads; then proj_fused_kernel's products, GELU and
+// fixed-order sums: out = c2 + sum_k P2[k] gelu(P1^T z + c1)[k].  The
+// results are the two kernels' bit for bit.  z (on entry the spectral
+// path) is stored when store_z (a backward pass reads it), h when h_out.
+template <bool F32>
+__global__ void __launch_bounds__(256)
+pointwise_proj_kernel(const float* __restrict__ W, const float* __restrict__ v,
+                      const float* __restrict__ bias, float* __restrict__ z, int store_z,
+                      const float* __restrict__ P1, const float* __restrict__ c1,
+                      const float* __restrict__ P2, const float* __restrict__ c2,
+                      float* __restrict__ out, float* __restrict__ h_out, int P) {
+    typedef typename Frag<F32>::T T;
+    constexpr int C = 32, K = 128, NT = 64, LK = C + 4;
+    __shared__ __attribute__((aligned(16))) T As[C * LK];     // W^T [co][ci]
+    __shared__ __attribute__((aligned(16))) T Bs[NT * LK];    // v [pixel][ci]
+    __shared__ __attribute__((aligned(16))) T Ws[K * LK];     // P1^T [k][c]
+    __shared__ __attribute__((aligned(16))) T Vs[NT * LK];    // z [pixel][c]
+    __shared__ float part[4][NT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int p0 = blockIdx.x * NT, b = blockIdx.y;
+    const size_t base = (size_t)b * C * P;
+    const int km = wv * 32;
+    // global loads first: P1 (four float4), the v tile (two float4), W, and
+    // the c1 / P2 entries of the head's epilogue
+    float4 pr[K * C / 4 / 256];
+#pragma unroll
+    for (int i = 0; i < K * C / 4 / 256; ++i)
+        pr[i] = reinterpret_cast<const float4*>(P1)[tid + 256 * i];
+    const int vci = tid >> 3, vn0 = (tid & 7) * 8;            // 8 pixels of channel vci
+    const float4* vsrc = reinterpret_cast<const float4*>(v + base + (size_t)vci * P + p0 + vn0);
+    const float4 x0 = vsrc[0], x1 = vsrc[1];
+    float wr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wr[k] = W[tid + 256 * k];
+    float ck[2][4], pk[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = km + 16 * i + 4 * (lane >> 4) + q;
+            ck[i][q] = c1[k];
+            pk[i][q] = P2[k];
+        }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = tid + 256 * k;                          // W[ci][co], e = ci * 32 + co
+        As[(e & 31) * LK + (e >> 5)] = Frag<F32>::cvt(wr[k]);
+    }
+    {
+        const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[(vn0 + j) * LK + vci] = Frag<F32>::cvt(xs[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < K * C / 4 / 256; ++i) {           // P1[c][k] -> Ws[k][c]
+        const int e = 4 * (tid + 256 * i), c = e / K, k = e - c * K;
+        const float x[4] = {pr[i].x, pr[i].y, pr[i].z, pr[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Ws[(k + j) * LK + c] = Frag<F32>::cvt(x[j]);
+    }
+    __syncthreads();
+    // pointwise path: wave w, output rows 16 (w & 1) .. +15, pixels
+    // 32 (w >> 1) .. +31 as two 16 x 16 tiles
+    {
+        const int m0 = 16 * (wv & 1);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int n0 = 32 * (wv >> 1) + 16 * t;
+            const f32x4 c = tile_mma<F32>(As, LK, Bs, LK, m0, n0, C, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + 4 * (lane >> 4) + q, pp = n0 + (lane & 15);
+                const size_t o = base + (size_t)m * P + p0 + pp;
+                float r = c[q];
+                r += z[o];
+                r += bias[m];
+                if (store_z) z[o] = r;
+                Vs[pp * LK + m] = Frag<F32>::cvt(r);
+            }
+        }
+    }
+    __syncthreads();
+    // projection head: wave w, hidden units 32w .. 32w+31 for the 64 pixels
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < C; kk += Frag<F32>::KS) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const T* a = Ws + (km + 16 * i + (lane & 15)) * LK + kk;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T* bp = Vs + (16 * j + (lane & 15)) * LK + kk;
+                acc[i][j] = Frag<F32>::mma(a, bp, lane, acc[i][j]);
+            }
+        }
+    }
+    // lane holds rows km + 16i + 4(lane>>4) + q, column 16j + (lane & 15)
+    float sm[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = km + 16 * i + 4 * (lane >> 4) + q;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float hv = acc[i][j][q] + ck[i][q];
+                const int pp = 16 * j + (lane & 15);
+                if (h_out) h_out[((long long)b * K + k) * P + p0 + pp] = hv;
+                sm[j] = fmaf(pk[i][q], gelu_op<F32>(hv), sm[j]);
+            }
+        }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float t = sm[j];
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        sm[j] = t;
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[wv][16 * j + lane] = sm[j];
+    __syncthreads();
+    if (tid < NT) {
+        const float r = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+        out[(long long)b * P + p0 + tid] = r + c2[0];
+    }
+}
+
 // ------------------------------------------------------------- launchers --
 static int blocks_for(long long n) {
     return (int)std::max<long long>(1, std::min<long long>(8192, (n + 255) / 256));
@@ -1517,6 +1655,20 @@ void launch_proj_fused(const float* v, const float* P1, const float* c1, const f
     else
         hipLaunchKernelGGL(proj_fused_kernel<false>, grid, dim3(256), 0, s, v, P1, c1, P2, c2,
                            out, h_out, P);
+}
+// the last pointwise layer fused with the projection head (32 channels,
+// 128 hidden units, P a multiple of 64)
+void launch_pointwise_proj(const float* W, const float* v, const float* bias, float* z,
+                           int store_z, const float* P1, const float* c1, const float* P2,
+                           const float* c2, float* out, float* h_out, int B, int P, int f32,
+                           hipStream_t s) {
+    dim3 grid(P / 64, B);
+    if (f32)
+        hipLaunchKernelGGL(pointwise_proj_kernel<true>, grid, dim3(256), 0, s, W, v, bias, z,
+                           store_z, P1, c1, P2, c2, out, h_out, P);
+    else
+        hipLaunchKernelGGL(pointwise_proj_kernel<false>, grid, dim3(256), 0, s, W, v, bias, z,
+                           store_z, P1, c1, P2, c2, out, h_out, P);
 }
 void launch_proj_back(const float* h, const float* P2, const float* gout, float* gh, int B,
                       int P, int K, hipStream_t s) {

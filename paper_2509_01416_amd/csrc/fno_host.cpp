@@ -369,6 +369,15 @@ struct Runner {
             }
             // pointwise path, bias and (but after the last layer) GELU; the
             // pre-activations are kept for a backward pass and for the head
+            if (C == 32 && l + 1 == L) {
+                // the last layer and the projection head in one kernel
+                static_assert(kProj == 128, "the fused head has 128 hidden units");
+                launch_pointwise_proj(P + m->oW[l], w.v[l], P + m->ob[l], w.z[l],
+                                      keep_h ? 1 : 0, P + m->oP1, P + m->oc1, P + m->oP2,
+                                      P + m->oc2, out, keep_h ? w.h : nullptr, B, kP, m->f32,
+                                      c->stream);
+                return;
+            }
             if (C == 32) {
                 launch_pointwise(P + m->oW[l], w.v[l], P + m->ob[l], w.z[l],
                                  l + 1 < L ? w.v[l + 1] : nullptr, B, kP,

@@ -55,6 +55,13 @@ void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const
 void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s);
 void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s);
 // Projection head in one kernel (width 32, 128 hidden units only).
+// the last pointwise layer and the projection head in one kernel (32
+// channels, 128 hidden units): z (the spectral path on entry) becomes
+// W^T v + z + bias, stored if store_z; out and, if h_out, the hidden layer
+void launch_pointwise_proj(const float* W, const float* v, const float* bias, float* z,
+                           int store_z, const float* P1, const float* c1, const float* P2,
+                           const float* c2, float* out, float* h_out, int B, int P, int f32,
+                           hipStream_t s);
 void launch_proj_fused(const float* v, const float* P1, const float* c1, const float* P2,
                        const float* c2, float* out, float* h_out, int B, int P, int f32,
                        hipStream_t s);
