@@ -1138,13 +1138,22 @@ __device__ __forceinline__ void zero_lds(typename Frag<F32>::T* p, int elems) {
     for (int e = threadIdx.x; e < n16; e += 256) d[e] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// One lifted value (LiftArgs): channel c, input u at cell (ix, iy) of the
+// 64 x 64 grid, with lift_kernel's arithmetic.
+__device__ __forceinline__ float lift_value(const LiftArgs& L, int c, float u, int ix, int iy) {
+    constexpr int C = 32, n = 64;
+    const float x = (ix + 0.5f) / n, y = (iy + 0.5f) / n;
+    return fmaf(L.W0[c], u, fmaf(L.W0[C + c], x, fmaf(L.W0[2 * C + c], y, L.b0[c])));
+}
+
 // A workgroup transforms CH consecutive fields: the DFT images are staged
 // once, and the next field's values are loaded while the current one is on
-// the matrix cores.
+// the matrix cores.  With lift.in the fields are the lift of the network
+// input, formed here (32 channels).
 template <bool F32, int CH>
 __global__ void __launch_bounds__(256)
 spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __restrict__ img,
-                float* __restrict__ X, int G) {
+                float* __restrict__ X, int G, LiftArgs lift) {
     typedef typename Frag<F32>::T T;
     constexpr int n = 64, mm = 12, LV = kSpLV, LT = kSpLT;
     __shared__ __attribute__((aligned(16))) T Vs[n * LV];          // [y][x]
@@ -1154,7 +1163,24 @@ spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __rest
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long g0 = (long long)blockIdx.x * CH;
     float4 fr[4];
-    load_field(fr, v + g0 * n * n);
+    auto load_v = [&](long long g) {
+        if (lift.in == nullptr) {
+            load_field(fr, v + g * n * n);
+            return;
+        }
+        const int c = (int)(g % 32);
+        const float4* in4 = reinterpret_cast<const float4*>(lift.in + (g / 32) * n * n);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + 256 * k, iy = e >> 4, ix = 4 * (e & 15);
+            const float4 u = in4[e];
+            fr[k] = make_float4(lift_value(lift, c, u.x, ix, iy),
+                                lift_value(lift, c, u.y, ix + 1, iy),
+                                lift_value(lift, c, u.z, ix + 2, iy),
+                                lift_value(lift, c, u.w, ix + 3, iy));
+        }
+    };
+    load_v(g0);
     copy16<32 * LV * (int)sizeof(T)>(Fx, img + kImgFx);
     copy16<48 * LT * (int)sizeof(T)>(Fys, img + kImgFy);
     zero_lds<F32>(Ts, 16 * LT);   // rows kx >= 12 stay zero
@@ -1163,7 +1189,7 @@ spec_fwd_kernel(const float* __restrict__ v, const typename Frag<F32>::T* __rest
         if (g >= G) break;
         store_field<F32>(Vs, fr);
         __syncthreads();
-        if (ci + 1 < CH && g + 1 < G) load_field(fr, v + (g + 1) * n * n);
+        if (ci + 1 < CH && g + 1 < G) load_v(g + 1);
         // T: wave w owns rows 16w..16w+15, both 16-column tiles
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -1362,12 +1388,13 @@ mix_mma_kernel(const float* __restrict__ X, const float* __restrict__ R,
 // 16 (w & 1) .. +15 and pixels 32 (w >> 1) .. +31 as two 16 x 16 MFMA tiles,
 // with the batched GEMM's operand rounding and k order (so the results are
 // those of the strided GEMM for this shape).  store_z = 0 leaves z as it is
-// (inference: the next layer reads only gelu(z)).
+// (inference: the next layer reads only gelu(z)).  With lift.in, v is the
+// lift of the network input, formed here.
 template <bool F32>
 __global__ void __launch_bounds__(256)
 pointwise_kernel(const float* __restrict__ W, const float* __restrict__ v,
                  const float* __restrict__ bias, float* __restrict__ z,
-                 float* __restrict__ vn, int P, int store_z) {
+                 float* __restrict__ vn, int P, int store_z, LiftArgs lift) {
     typedef typename Frag<F32>::T T;
     constexpr int C = 32, LK = C + 4;
     __shared__ __attribute__((aligned(16))) T As[C * LK];    // [co][ci]
@@ -1382,9 +1409,19 @@ pointwise_kernel(const float* __restrict__ W, const float* __restrict__ v,
     }
     {
         const int ci = tid >> 3, n0 = (tid & 7) * 8;           // 8 pixels of channel ci
-        const float4* src = reinterpret_cast<const float4*>(v + base + (size_t)ci * P + p0 + n0);
+        const float4* src =
+            lift.in == nullptr
+                ? reinterpret_cast<const float4*>(v + base + (size_t)ci * P + p0 + n0)
+                : reinterpret_cast<const float4*>(lift.in + (size_t)b * P + p0 + n0);
         const float4 x0 = src[0], x1 = src[1];
-        const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        if (lift.in != nullptr) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int p = p0 + n0 + j;
+                xs[j] = lift_value(lift, ci, xs[j], p & 63, p >> 6);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) Bs[(n0 + j) * LK + ci] = Frag<F32>::cvt(xs[j]);
     }
@@ -1595,14 +1632,14 @@ void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const
     hipLaunchKernelGGL(stage_spec_kernel<false>, dim3(64), dim3(256), 0, s, FxT, Fy, Gy, Gx, h);
 }
 void launch_pointwise(const float* W, const float* v, const float* bias, float* z, float* vn,
-                      int B, int P, int store_z, int f32, hipStream_t s) {
+                      int B, int P, int store_z, int f32, hipStream_t s, const LiftArgs& lift) {
     dim3 grid(P / 64, B);
     if (f32)
         hipLaunchKernelGGL(pointwise_kernel<true>, grid, dim3(256), 0, s, W, v, bias, z, vn, P,
-                           store_z);
+                           store_z, lift);
     else
         hipLaunchKernelGGL(pointwise_kernel<false>, grid, dim3(256), 0, s, W, v, bias, z, vn, P,
-                           store_z);
+                           store_z, lift);
 }
 // fields per workgroup: the most (up to 8) that still leave two workgroups
 // per CU (at batch 64 that is 7 % faster per forward than one per CU; at
@@ -1625,17 +1662,30 @@ static int spec_fields_per_wg(int G) {
             default: hipLaunchKernelGGL((kern<F32, 1>), grid, dim3(256), 0, s, in, img, o, G); break; \
         }                                                                                  \
     }
-MDP_SPEC_LAUNCH(spec_fwd_kernel)
 MDP_SPEC_LAUNCH(spec_inv_kernel)
 #undef MDP_SPEC_LAUNCH
 
-void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s) {
+template <bool F32>
+static void launch_spec_fwd_kernel(const float* in, const typename Frag<F32>::T* img, float* o,
+                                   int G, hipStream_t s, const LiftArgs& lift) {
+    const int ch = spec_fields_per_wg(G);
+    const dim3 grid((unsigned)((G + ch - 1) / ch));
+    switch (ch) {
+        case 8: hipLaunchKernelGGL((spec_fwd_kernel<F32, 8>), grid, dim3(256), 0, s, in, img, o, G, lift); break;
+        case 4: hipLaunchKernelGGL((spec_fwd_kernel<F32, 4>), grid, dim3(256), 0, s, in, img, o, G, lift); break;
+        case 2: hipLaunchKernelGGL((spec_fwd_kernel<F32, 2>), grid, dim3(256), 0, s, in, img, o, G, lift); break;
+        default: hipLaunchKernelGGL((spec_fwd_kernel<F32, 1>), grid, dim3(256), 0, s, in, img, o, G, lift); break;
+    }
+}
+
+void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s,
+                     const LiftArgs& lift) {
     const float* f = reinterpret_cast<const float*>(img);
     if (f32)
-        launch_spec_fwd_kernel<true>(v, f, X, G, s);
+        launch_spec_fwd_kernel<true>(v, f, X, G, s, lift);
     else
         launch_spec_fwd_kernel<false>(v, reinterpret_cast<const unsigned short*>(f + kImgElems),
-                                      X, G, s);
+                                      X, G, s, lift);
 }
 void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s) {
     const float* f = reinterpret_cast<const float*>(img);

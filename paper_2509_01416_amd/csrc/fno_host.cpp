@@ -350,10 +350,15 @@ struct Runner {
         const int G = B * C;
         const long long act = (long long)C * kP;
         const long long per = 4LL * mm * mm, tb = (long long)kGrid * 2 * mm;
-        launch_lift(in, P + m->oW0, P + m->ob0, w.v[0], B, kGrid, C, c->stream);
+        // without a backward pass the first layer forms the lift where it
+        // reads it (no stored v[0]); a backward pass needs the stored one
+        const bool late_lift = !keep_h && C == 32 && mm == 12 && L >= 2;
+        const LiftArgs lift0 = late_lift ? LiftArgs{in, P + m->oW0, P + m->ob0} : LiftArgs{};
+        if (!late_lift) launch_lift(in, P + m->oW0, P + m->ob0, w.v[0], B, kGrid, C, c->stream);
         for (int l = 0; l < L && ok; ++l) {
+            const LiftArgs lift = l == 0 ? lift0 : LiftArgs{};
             if (mm == 12) {   // the supported mode window: fused DFT kernels
-                launch_spec_fwd(w.v[l], m->spec_img, w.X[l], G, m->f32, c->stream);
+                launch_spec_fwd(w.v[l], m->spec_img, w.X[l], G, m->f32, c->stream, lift);
                 launch_mix(w.X[l], P + m->oR[l], w.Y, B, C, mm, c->stream);
                 launch_spec_inv(w.Y, m->spec_img, w.z[l], G, m->f32, c->stream);
             } else {
@@ -381,7 +386,7 @@ struct Runner {
             if (C == 32) {
                 launch_pointwise(P + m->oW[l], w.v[l], P + m->ob[l], w.z[l],
                                  l + 1 < L ? w.v[l + 1] : nullptr, B, kP,
-                                 keep_h || l + 1 == L ? 1 : 0, m->f32, c->stream);
+                                 keep_h || l + 1 == L ? 1 : 0, m->f32, c->stream, lift);
             } else {
                 gemm(C, kP, C, B, mat(P + m->oW[l], 1, C), mat(w.v[l], kP, 1, act),
                      mat(w.z[l], kP, 1, act), 1, P + m->ob[l], nullptr,

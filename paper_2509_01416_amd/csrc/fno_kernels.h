@@ -21,6 +21,17 @@ struct View {
     int c_ls = 31;
 };
 
+// The lift evaluated where its output is read (inference): channel c of
+// sample b at cell (ix, iy) of the 64 x 64 grid is W0[c] in + W0[32 + c] x
+// + W0[64 + c] y + b0[c] with x = (ix + 1/2) / 64, y = (iy + 1/2) / 64,
+// exactly as lift_kernel computes and stores it.  in == nullptr: read the
+// stored lift instead.
+struct LiftArgs {
+    const float* in = nullptr;   // [B][64 * 64] network input
+    const float* W0 = nullptr;   // [3][32]
+    const float* b0 = nullptr;   // [32]
+};
+
 struct GemmArgs {
     int M = 0, N = 0, K = 0, G = 1;
     View A, B, C;
@@ -46,13 +57,15 @@ void launch_mix_back_w(const float* X, const float* gY, float* gR, int B, int C,
                        hipStream_t s);
 // Pointwise path of a Fourier layer for C = 32 channels and P % 64 == 0.
 void launch_pointwise(const float* W, const float* v, const float* bias, float* z, float* vn,
-                      int B, int P, int store_z, int f32, hipStream_t s);
+                      int B, int P, int store_z, int f32, hipStream_t s,
+                      const LiftArgs& lift = LiftArgs{});
 // Truncated 2-D DFT of G fields (64 x 64, 12 x 24 retained modes) and its
 // inverse, each in one kernel (layouts as the batched GEMM path).
 size_t spec_image_bytes();   // FP32 + BF16 LDS images of the DFT matrices
 void launch_stage_spec(const float* FxT, const float* Fy, const float* Gy, const float* Gx,
                        void* img, hipStream_t s);
-void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s);
+void launch_spec_fwd(const float* v, const void* img, float* X, int G, int f32, hipStream_t s,
+                     const LiftArgs& lift = LiftArgs{});
 void launch_spec_inv(const float* Y, const void* img, float* U, int G, int f32, hipStream_t s);
 // Projection head in one kernel (width 32, 128 hidden units only).
 // the last pointwise layer and the projection head in one kernel (32
