@@ -66,7 +66,9 @@ __device__ __forceinline__ void combine_cell(const InstDesc& I, int c, float s,
         I.phi[c] = s;
         return;
     }
-    const float old = mode == 2 ? I.snap[c] : I.phi[c];
+    // the previous flux only where a norm is taken (not on untested
+    // iterations of the error-bound rule)
+    const float old = mode == 3 ? 0.f : (mode == 2 ? I.snap[c] : I.phi[c]);
     I.phi[c] = s;
     I.Q[c] = fmaf(I.ss[c], s, I.q[c]);
     if (mode == 2) I.snap[c] = s;
@@ -123,8 +125,10 @@ __device__ __forceinline__ void combine_block(const InstDesc& I, int c0, int z,
                     *phi4 = s;
                     continue;
                 }
-                const float4 old =
-                    mode == 2 ? reinterpret_cast<const float4*>(I.snap)[c >> 2] : *phi4;
+                // the previous flux only where a norm is taken
+                float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (mode != 3)
+                    old = mode == 2 ? reinterpret_cast<const float4*>(I.snap)[c >> 2] : *phi4;
                 const float4 ss = reinterpret_cast<const float4*>(I.ss)[c >> 2];
                 const float4 qq = reinterpret_cast<const float4*>(I.q)[c >> 2];
                 *phi4 = s;
