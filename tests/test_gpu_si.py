@@ -425,6 +425,31 @@ def test_ragged_grids_solve_on_the_specialised_kernel(env, shapes, n, cfg):
         assert s["balance_rel"] < 1e-5
 
 
+def test_random_shapes_sweep_parity(env):
+    """Seeded random grid shapes (sides 1 to 200, batches of three, S4 and
+    S8), each batch swept with whatever kernel the planner picks (specialised
+    with ragged or single row blocks, or generic) and compared cell by cell
+    with the oracle's sweep; the planner must take the specialised kernel
+    for at least a third of the batches."""
+    torch, B, ctx = env
+    rng = np.random.Generator(np.random.PCG64(2024))
+    fast = 0
+    nb = 16
+    for k in range(nb):
+        shapes = [(int(rng.integers(1, 201)), int(rng.integers(1, 201))) for _ in range(3)]
+        if k % 2 == 0:   # every other batch: vacuum grids the specialised kernel takes
+            shapes = [(max(nx, ny - 1 if ny <= 64 else 65), ny) for nx, ny in shapes]
+        n = 4 if k % 3 == 0 else 8
+        insts = [I.random_instance(nx, ny, seed=3000 + 10 * k + j, lx=0.1 * nx, ly=0.1 * ny)
+                 for j, (nx, ny) in enumerate(shapes)]
+        plan = ctx.sweep_plan([to_problem(i, torch) for i in insts],
+                              B.Quad.from_inputs(I.level_symmetric_2d(n)))
+        fast += plan["specialised"]
+        log(f"[tr_sweep] random batch {k}: {shapes} S{n}, plan {plan}")
+        _sweep_case(env, insts, I.level_symmetric_2d(n))
+    assert fast >= nb // 3
+
+
 def test_not_converged_and_errors(env):
     torch, B, ctx = env
     log("[tr_solve] status codes")
