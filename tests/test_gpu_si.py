@@ -9,8 +9,10 @@ Tolerances:
     downwind with a diamond-difference gain below 1 per cell, and the
     scalar flux sums at most a few hundred weighted terms in a fixed order.
     Rounding errors of different cells do not align, and the worst case
-    seen over every test grid (up to 16 x 256^2 S16 and a 32768-cell row)
-    is 6.5e-7; the bar is three times that.  (The worst case if every
+    seen over every test grid (up to 16 x 256^2 S16, a 32768-cell row and
+    seeded random shapes up to 200 cells a side) is 8.8e-7, on a 65 x 180
+    S4 grid (few directions, so little averaging in the scalar flux); the
+    bar is a little over twice that.  (The worst case if every
     rounding did align, 4 eps32 (nx + ny), is 1.2e-4 at 256^2 and would not
     catch a regression.)
   * converged source iteration: 1e-5 relative L2 (the library's stated
