@@ -395,29 +395,34 @@ tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
 /* Autotuner: times every feasible launch shape (D in 1..4 directions per
  * lane, W waves per workgroup, slices and block size then chosen by the
  * planner) with `reps` HIP-event-timed sweeps of these problems (their
- * sources as emission; one untimed sweep first), times the shapes within
+ * sources as emission; one untimed sweep first), each followed by the sum
+ * of its partial scalar-flux planes (their number depends on the shape),
+ * times the shapes within
  * 5 % of the fastest again in three interleaved rounds, and leaves the one
  * with the lowest total forced on the context exactly as
  * tr_set_sweep_config would (reset with
  * tr_set_sweep_config(ctx, 0, 0, 0, 0)).  out6 (may be NULL) receives the
  * chosen plan as tr_get_sweep_plan reports it, best_ms (may be NULL) its
- * time per sweep.  2-D only: for 1-D problems nothing is tuned.  Allocates
+ * time per sweep and plane sum.  2-D only: for 1-D problems nothing is tuned.  Allocates
  * one temporary output array per call.                                    */
 tr_status tr_autotune(tr_context *ctx, int32_t n_inst, const tr_problem *p,
                       const tr_quadrature *q, int32_t reps, int32_t *out6,
                       double *best_ms);
 
 /* Sweep kernel selection on this context: generic = 0 (default) uses the
- * specialised 2-D kernel whenever every problem of a call has 64-row lane
- * segments and only vacuum faces (the generic kernel otherwise);
+ * specialised 2-D kernel whenever every problem of a call has only vacuum
+ * faces and a grid it takes (64-row lane segments, the last row block
+ * possibly ragged: several row blocks with nx >= 63 + KB, or one with
+ * nx >= ny - 1; tr_get_sweep_plan reports the choice), the generic kernel
+ * otherwise;
  * generic = 1 always uses the generic kernel.  Both perform the same
  * floating-point operations in the same order, so for one launch shape
  * their results agree bit for bit.                                        */
 tr_status tr_set_sweep_kernel(tr_context *ctx, int32_t generic);
 
 /* Persistent iteration (enable = 1; off by default): when a 2-D solve runs
- * the specialised sweep with one direction per lane and 9 or 10 waves per
- * workgroup, and every workgroup of the launch can be resident at once,
+ * the specialised sweep with one direction per lane (any wave count), and
+ * every workgroup of the launch can be resident at once,
  * tr_solve and the eigenvalue solvers run each chunk of source iterations
  * (the batched-launch pattern of the sweeps of section 5.1) as one
  * cooperative launch: per iteration the workgroups of each instance sweep,
@@ -429,8 +434,8 @@ tr_status tr_set_sweep_kernel(tr_context *ctx, int32_t generic);
  * wait that runs out ends every wait of the launch, whose workgroups all
  * finish, and the call returns TR_ERR_HIP ("barrier wait timed out").
  * Instances never wait on each other.  On gfx950 it is slower than the
- * per-kernel launches (each barrier's device-scope release and acquire
- * write back and invalidate the XCD's L2), hence opt-in.                  */
+ * per-kernel launches (an instance barrier of its workgroups costs more
+ * than the kernel boundary it replaces), hence opt-in.                    */
 tr_status tr_set_persistent(tr_context *ctx, int32_t enable, int32_t spin_limit);
 
 /* Debugging: with enable = 1 every HIP step of a call on this context

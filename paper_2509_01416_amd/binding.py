@@ -302,8 +302,9 @@ class Context:
                     persistent_ms=out[4], persistent_launches=int(out[5]))
 
     def autotune(self, problems, quad: Quad, reps: int = 3) -> dict:
-        """Time the feasible launch shapes on these problems and keep the
-        fastest on this context; returns its plan and time per sweep."""
+        """Time the feasible launch shapes on these problems (each sweep with
+        its partial-plane sum) and keep the fastest on this context; returns
+        its plan and time per sweep."""
         out = (ctypes.c_int32 * 6)()
         ms = ctypes.c_double()
         self.check(self.lib.tr_autotune(self.handle, len(problems), make_problems(problems),

@@ -1090,9 +1090,10 @@ extern "C" tr_status tr_autotune(tr_context* ctx, int32_t n_inst, const tr_probl
     if (!c->hip_ok(hipEventCreate(&e0), "event") || !c->hip_ok(hipEventCreate(&e1), "event")) {
         rc = TR_ERR_HIP;
     } else if (p[0].dim == 2) {
-        // time one (D, W) shape: one untimed sweep, then `nrep` timed ones;
-        // returns ms per sweep, -1 if the shape is not feasible, -2 on a
-        // HIP error
+        // time one (D, W) shape: one untimed sweep, then `nrep` timed ones,
+        // each with the sum of its partial planes (their number depends on
+        // the shape, and the iteration's combine reads them all); returns
+        // ms per sweep, -1 if the shape is not feasible, -2 on a HIP error
         auto time_shape = [&](int D, int W, int nrep, std::array<int, 5>* key) -> double {
             c->force_D = D;
             c->force_W = W;
@@ -1105,10 +1106,16 @@ extern "C" tr_status tr_autotune(tr_context* ctx, int32_t n_inst, const tr_probl
             }
             if (key)
                 *key = {su.plan.D, su.plan.W, su.plan.S[0], su.plan.KB, su.plan.fast ? 1 : 0};
-            if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return -2.0;
+            auto sweep = [&]() {
+                if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return false;
+                launch_combine((int)su.blocks.size(), su.d_inst, su.d_blocks, nullptr,
+                               su.d_red, 1, 0, c->stream, su.d_dt);
+                return c->hip_ok(hipGetLastError(), "combine launch");
+            };
+            if (!sweep()) return -2.0;
             (void)hipEventRecord(e0, c->stream);
             for (int r = 0; r < nrep; ++r)
-                if (!c->launch_sweep(su, n_inst, nullptr, nullptr, 0)) return -2.0;
+                if (!sweep()) return -2.0;
             (void)hipEventRecord(e1, c->stream);
             if (!c->hip_ok(hipEventSynchronize(e1), "sync")) return -2.0;
             float ms = 0.f;
