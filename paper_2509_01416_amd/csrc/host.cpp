@@ -361,7 +361,8 @@ namespace mdp {
 // (NW = waves the chip keeps busy), trying the widest feasible R for every
 // instance (latency-bound batches) and the R with the fewest lane-steps
 // 4 v T per instance (throughput-bound batches).  W waves per workgroup and
-// S slices per octant then give at least one workgroup per CU.
+// S slices per octant then give at least one workgroup per CU (generic
+// kernel) or the shortest step time (specialised kernel, see below).
 namespace {
 constexpr double kBusyWaves = 2048.0;   // ~2 waves per SIMD on 256 CUs
 constexpr int kCUs = 256;
@@ -443,6 +444,22 @@ Plan plan_impl(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
     int W = std::min(wcap, vmax);
     if (c->force_W > 0) {
         W = std::min(c->force_W, wcap);
+    } else if (fast && pl.D == 1 && c->force_S <= 0) {
+        // specialised kernel: an instance's chain takes T steps whatever
+        // the number of busy CUs, so a batch too small to fill the chip is
+        // bound by the step time, which is shortest near one wave per SIMD
+        // (W = 4, the fewest waves that keep 16-step blocks).  Take the
+        // most slices per octant (W = ceil(nd/S) >= 4) whose workgroups
+        // still find a CU each on the instance's XCD (32 CUs; instances
+        // spread over the 8 XCDs), and one slice once the batch fills it.
+        const int per_xcd = (n_inst + kXcds - 1) / kXcds;
+        int S = 1;
+        for (int s = 2; (nd + s - 1) / s >= 4 && 4LL * per_xcd * s <= kCUs / kXcds; ++s) S = s;
+        W = std::min(wcap, (nd + S - 1) / S);
+        // a wide grid's LDS ring (nx values per wave) may allow fewer waves
+        int nxw = 1;
+        for (int i = 0; i < n_inst; ++i) nxw = std::max(nxw, p[i].nx);
+        while (W > 1 && sweep2d_fast_lds_bytes(W, 2, pl.D, nxw) > c->lds_limit) --W;
     } else {
         for (; W > 1; --W) {
             long long wgs = 0;

@@ -1088,26 +1088,58 @@ static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_
     }
 }
 
-// Fixed wave counts of the common level-symmetric sets with one direction
-// per lane: S16 (36 directions per octant, 4 slices of 9) and S8 (10 per
-// octant, one slice of 10), for the iteration sweeps and the tally sweep.
+// Wave counts compiled as constants (one direction per lane): a constant W
+// unrolls the cross-wave sums and the staging loops, which a runtime W
+// leaves as loops, at about 1.6 times the step time.  Each W = 2..16 is
+// built with the largest block size it allows (16 from W = 4 on, 8 below);
+// other block sizes, the tally sweep at W other than 9 and 10 (one launch
+// per solve) and D > 1 take the runtime-W kernel.
+template <int D, int WT, bool TALLY>
+static bool launch_fast_const(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                              const InstDesc* insts, const SweepWork* work, const DirTable* dt,
+                              const int* done, const int* iter, const FinArgs& fin) {
+    constexpr int kb = WT >= 4 ? 16 : 8;
+    if (KB != kb)
+        return launch_fast_dw<D, 0, TALLY>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+    hipLaunchKernelGGL((sweep2d_fast_kernel<D, kb, WT, TALLY>), grid, block, lds, s, insts, work,
+                       dt, done, iter, fin);
+    return true;
+}
+
 template <int D>
 static bool launch_fast_d(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                           const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                           const int* done, const int* iter, bool tally, const FinArgs& fin) {
     const int W = (int)block.x / 64;
-    if (tally) {
-        if (D == 1 && W == 9)
-            return launch_fast_dw<D, 9, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
-        if (D == 1 && W == 10)
-            return launch_fast_dw<D, 10, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
-        return launch_fast_dw<D, 0, true>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+#define MDP_FAST_ARGS KB, grid, block, lds, s, insts, work, dt, done, iter, fin
+    if constexpr (D == 1) {
+        if (tally) {
+            if (W == 9) return launch_fast_const<D, 9, true>(MDP_FAST_ARGS);
+            if (W == 10) return launch_fast_const<D, 10, true>(MDP_FAST_ARGS);
+        } else {
+            switch (W) {
+                case 2: return launch_fast_const<D, 2, false>(MDP_FAST_ARGS);
+                case 3: return launch_fast_const<D, 3, false>(MDP_FAST_ARGS);
+                case 4: return launch_fast_const<D, 4, false>(MDP_FAST_ARGS);
+                case 5: return launch_fast_const<D, 5, false>(MDP_FAST_ARGS);
+                case 6: return launch_fast_const<D, 6, false>(MDP_FAST_ARGS);
+                case 7: return launch_fast_const<D, 7, false>(MDP_FAST_ARGS);
+                case 8: return launch_fast_const<D, 8, false>(MDP_FAST_ARGS);
+                case 9: return launch_fast_const<D, 9, false>(MDP_FAST_ARGS);
+                case 10: return launch_fast_const<D, 10, false>(MDP_FAST_ARGS);
+                case 11: return launch_fast_const<D, 11, false>(MDP_FAST_ARGS);
+                case 12: return launch_fast_const<D, 12, false>(MDP_FAST_ARGS);
+                case 13: return launch_fast_const<D, 13, false>(MDP_FAST_ARGS);
+                case 14: return launch_fast_const<D, 14, false>(MDP_FAST_ARGS);
+                case 15: return launch_fast_const<D, 15, false>(MDP_FAST_ARGS);
+                case 16: return launch_fast_const<D, 16, false>(MDP_FAST_ARGS);
+                default: break;
+            }
+        }
     }
-    if (D == 1 && W == 9)
-        return launch_fast_dw<D, 9, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
-    if (D == 1 && W == 10)
-        return launch_fast_dw<D, 10, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
-    return launch_fast_dw<D, 0, false>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
+    return tally ? launch_fast_dw<D, 0, true>(MDP_FAST_ARGS)
+                 : launch_fast_dw<D, 0, false>(MDP_FAST_ARGS);
+#undef MDP_FAST_ARGS
 }
 
 bool launch_sweep2d_fast(int D, int nwork, int W, int KB, size_t lds_bytes,

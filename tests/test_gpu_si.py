@@ -304,7 +304,8 @@ def test_determinism_and_batch_equals_single(env):
 ])
 def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
     """The specialised sweep (64-row segments, vacuum faces, nx >= 63 + KB
-    unless the grid is one row block) performs the generic kernel's operations in the same order: sweeps and
+    unless the grid is one row block) performs the generic kernel's operations
+    in the same order: with the same slicing of the octants, sweeps and
     whole solves agree bit for bit, for several launch shapes, block sizes
     (KB from 2 to 16) and ragged widths; the particle balance from its
     final tally sweep closes as well as the generic one."""
@@ -323,6 +324,12 @@ def test_specialised_kernel_matches_generic(env, shapes, n, cfg):
         outs = {}
         for generic in (False, True):
             ctx.set_sweep_kernel(generic)
+            if generic:
+                # the generic kernel in the specialised plan's slicing (its
+                # own planner fills the CUs with more, narrower slices)
+                ctx.set_sweep_config(plan["D"], plan["W"], plan["S"], 64)
+                gp = ctx.sweep_plan(probs, q)
+                assert gp["specialised"] == 0 and (gp["W"], gp["S"]) == (plan["W"], plan["S"])
             o = [torch.zeros_like(e) for e in em]
             B.tr_sweep(ctx, probs, q, em, o)
             phis = [torch.zeros_like(e) for e in em]

@@ -86,3 +86,27 @@ def test_plan_rows_divide_ny():
         p = _plan(shapes, bc=(1, 0, 0, 0))
         assert p["specialised"] == 0
         assert shapes[0][1] % p["R"] == 0 and p["R"] <= shapes[0][0]
+
+
+@pytest.mark.parametrize("count,n,W,S", [
+    (1, 8, 4, 3),      # lone S8 grid: 10 directions in 3 slices of 4 waves
+    (16, 8, 4, 3),     # 2 per XCD: 8 x 3 = 24 workgroups on its 32 CUs
+    (55, 8, 10, 1),    # 7 per XCD: one slice already fills the XCD
+    (256, 8, 10, 1),
+    (1, 16, 5, 8),     # 36 directions, 8 slices: 32 workgroups on 32 CUs
+    (16, 16, 9, 4),
+])
+def test_specialised_plan_slices_small_batches_to_the_step_time(count, n, W, S):
+    # the specialised sweep's step time, not the count of busy CUs, bounds
+    # a batch too small to fill the chip: most slices of >= 4 waves that
+    # still give each workgroup a CU of the instance's XCD
+    p = _plan([(128, 128)] * count, n=n)
+    assert p["specialised"] == 1 and p["KB"] == 16
+    assert (p["W"], p["S"]) == (W, S)
+
+
+def test_wide_grid_plan_sheds_waves_to_fit_the_lds_ring():
+    # 32768 cells per row: the ring holds nx values per wave, so only one
+    # wave per workgroup fits in 160 KB
+    p = _plan([(32768, 64)], n=4)
+    assert p["specialised"] == 1 and p["W"] == 1 and p["S"] == 3
