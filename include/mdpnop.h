@@ -393,8 +393,9 @@ tr_status tr_set_sweep_config(tr_context *ctx, int32_t D, int32_t W, int32_t S,
                               int32_t R);
 
 /* Autotuner: times every feasible launch shape (D in 1..4 directions per
- * lane, W waves per workgroup, slices and block size then chosen by the
- * planner) with `reps` HIP-event-timed sweeps of these problems (their
+ * lane, W waves per workgroup from a fixed set plus, for one direction per
+ * lane, every ceil(nd/S) for an octant of nd directions; slices and block
+ * size then chosen by the planner) with `reps` HIP-event-timed sweeps of these problems (their
  * sources as emission; one untimed sweep first), each followed by the sum
  * of its partial scalar-flux planes (their number depends on the shape),
  * times the shapes within

@@ -442,20 +442,23 @@ Plan plan_impl(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
     const long long want = std::min<long long>(kCUs, vsum);
     const int wcap = sweep2d_max_w(pl.D);
     int W = std::min(wcap, vmax);
+    bool step_rule = false;   // W set for the specialised kernel's step time
     if (c->force_W > 0) {
         W = std::min(c->force_W, wcap);
     } else if (fast && pl.D == 1 && c->force_S <= 0) {
         // specialised kernel: an instance's chain takes T steps whatever
         // the number of busy CUs, so a batch too small to fill the chip is
         // bound by the step time, which is shortest near one wave per SIMD
-        // (W = 4, the fewest waves that keep 16-step blocks).  Take the
-        // most slices per octant (W = ceil(nd/S) >= 4) whose workgroups
-        // still find a CU each on the instance's XCD (32 CUs; instances
-        // spread over the 8 XCDs), and one slice once the batch fills it.
+        // (W = 4, the fewest waves that keep 16-step blocks, idle waves
+        // included where an octant has fewer directions).  Take the most
+        // slices per octant, up to ceil(nd/4), whose workgroups still find
+        // a CU each on the instance's XCD (32 CUs; instances spread over
+        // the 8 XCDs), and one slice once the batch fills it.
         const int per_xcd = (n_inst + kXcds - 1) / kXcds;
         int S = 1;
-        for (int s = 2; (nd + s - 1) / s >= 4 && 4LL * per_xcd * s <= kCUs / kXcds; ++s) S = s;
-        W = std::min(wcap, (nd + S - 1) / S);
+        for (int s = 2; s <= (nd + 3) / 4 && 4LL * per_xcd * s <= kCUs / kXcds; ++s) S = s;
+        W = std::min(wcap, std::max(4, (nd + S - 1) / S));
+        step_rule = true;
         // a wide grid's LDS ring (nx values per wave) may allow fewer waves
         int nxw = 1;
         for (int i = 0; i < n_inst; ++i) nxw = std::max(nxw, p[i].nx);
@@ -476,7 +479,7 @@ Plan plan_impl(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
         pl.S[i] = c->force_S > 0 ? std::max(c->force_S, (nd + cap - 1) / cap)
                                  : std::max(1, (nd + cap - 1) / cap);
     }
-    if (c->force_W <= 0) {   // same slice counts with the fewest idle waves
+    if (c->force_W <= 0 && !step_rule) {   // same slice counts, fewest idle waves
         int wmin = 1;
         for (int i = 0; i < n_inst; ++i) {
             const int v = oct_waves(nd, pl.R[i], pl.D);
@@ -1142,9 +1145,24 @@ extern "C" tr_status tr_autotune(tr_context* ctx, int32_t n_inst, const tr_probl
         struct Cand { int D, W; double ms; };
         std::vector<Cand> cands;
         const int Ds[] = {1, 2, 3, 4};
-        const int Ws[] = {0, 4, 6, 8, 9, 10, 12, 16};
+        // wave counts: a fixed set, and for one direction per lane every
+        // W = ceil(nd/S) (the octant's nd directions in S full slices)
+        std::vector<int> Ws = {0, 4, 6, 8, 9, 10, 12, 16};
+        {
+            DirTable dt1;
+            if (build_dirtable(c, q, 2, &dt1)) {
+                const int nd = dt1.count[0];
+                for (int S = 1; S <= nd; ++S) {
+                    const int w = (nd + S - 1) / S;
+                    if (w >= 2 && std::find(Ws.begin(), Ws.end(), w) == Ws.end()) Ws.push_back(w);
+                }
+            }
+            c->err.clear();
+        }
         for (int D : Ds) {
             for (int W : Ws) {
+                if (W != 0 && D > 1 && std::find(Ws.begin(), Ws.begin() + 8, W) == Ws.begin() + 8)
+                    continue;   // the added counts are for D = 1
                 if (W > sweep2d_max_w(D)) continue;
                 std::array<int, 5> key{};
                 // feasibility and the resolved shape first (no launch)

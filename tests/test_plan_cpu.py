@@ -94,12 +94,14 @@ def test_plan_rows_divide_ny():
     (55, 8, 10, 1),    # 7 per XCD: one slice already fills the XCD
     (256, 8, 10, 1),
     (1, 16, 5, 8),     # 36 directions, 8 slices: 32 workgroups on 32 CUs
+    (1, 4, 4, 1),      # 3 directions: one slice of 4 waves (one idle)
+    (1, 6, 4, 2),      # 6 directions: two slices of 4 waves
     (16, 16, 9, 4),
 ])
 def test_specialised_plan_slices_small_batches_to_the_step_time(count, n, W, S):
     # the specialised sweep's step time, not the count of busy CUs, bounds
-    # a batch too small to fill the chip: most slices of >= 4 waves that
-    # still give each workgroup a CU of the instance's XCD
+    # a batch too small to fill the chip: most slices of >= 4 waves (idle
+    # ones included) that still give each workgroup a CU of its XCD
     p = _plan([(128, 128)] * count, n=n)
     assert p["specialised"] == 1 and p["KB"] == 16
     assert (p["W"], p["S"]) == (W, S)
