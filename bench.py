@@ -58,8 +58,8 @@ BYTES_PER_CELL_ITER = 20
 # read for a 256 MiB elementwise copy (profiles/sweep2d_fast_two_region_16x256_S16.md);
 # valid only for the kernel source with this hash prefix (sweep_source_hash),
 # otherwise null
-SWEEP_TRAFFIC_BYTES = 79.75e6
-SWEEP_TRAFFIC_SRC = "8b2913cc5443d5c4"
+SWEEP_TRAFFIC_BYTES = 79.82e6
+SWEEP_TRAFFIC_SRC = "ba5aeb282ea67ddd"
 
 
 def sweep_source_hash() -> str:

@@ -1091,14 +1091,18 @@ static bool launch_fast_dw(int KB, dim3 grid, dim3 block, size_t lds, hipStream_
 // Wave counts compiled as constants (one direction per lane): a constant W
 // unrolls the cross-wave sums and the staging loops, which a runtime W
 // leaves as loops, at about 1.6 times the step time.  Each W = 2..16 is
-// built with the largest block size it allows (16 from W = 4 on, 8 below);
-// other block sizes, the tally sweep at W other than 9 and 10 (one launch
-// per solve) and D > 1 take the runtime-W kernel.
+// built with the largest block size it allows (16 from W = 4 on, 8 below),
+// W = 9 and 10 (full S16 and S8 octants) with every block size; other
+// block sizes, the tally sweep at W other than 9 and 10 (one launch per
+// solve) and D > 1 take the runtime-W kernel.
 template <int D, int WT, bool TALLY>
 static bool launch_fast_const(int KB, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                               const InstDesc* insts, const SweepWork* work, const DirTable* dt,
                               const int* done, const int* iter, const FinArgs& fin) {
     constexpr int kb = WT >= 4 ? 16 : 8;
+    if constexpr (WT == 9 || WT == 10)   // S16 and S8 octants: every block size
+        if (KB != kb)
+            return launch_fast_dw<D, WT, TALLY>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
     if (KB != kb)
         return launch_fast_dw<D, 0, TALLY>(KB, grid, block, lds, s, insts, work, dt, done, iter, fin);
     hipLaunchKernelGGL((sweep2d_fast_kernel<D, kb, WT, TALLY>), grid, block, lds, s, insts, work,
