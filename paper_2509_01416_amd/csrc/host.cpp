@@ -451,12 +451,16 @@ Plan plan_impl(Ctx* c, int n_inst, const tr_problem* p, const DirTable& dt, bool
         // bound by the step time, which is shortest near one wave per SIMD
         // (W = 4, the fewest waves that keep 16-step blocks, idle waves
         // included where an octant has fewer directions).  Take the most
-        // slices per octant, up to ceil(nd/4), whose workgroups still find
-        // a CU each on the instance's XCD (32 CUs; instances spread over
-        // the 8 XCDs), and one slice once the batch fills it.
+        // slices per octant, up to ceil(nd/4) and at most 6 (each slice
+        // adds 4 partial planes to the iteration's sum: on 128^2 S16 grids
+        // 8 slices of 5 waves cost 7 % more per iteration than 6 of 6),
+        // whose workgroups still find a CU each on the instance's XCD
+        // (32 CUs; instances spread over the 8 XCDs), and one slice once
+        // the batch fills it.
         const int per_xcd = (n_inst + kXcds - 1) / kXcds;
+        const int smax = std::min(6, (nd + 3) / 4);
         int S = 1;
-        for (int s = 2; s <= (nd + 3) / 4 && 4LL * per_xcd * s <= kCUs / kXcds; ++s) S = s;
+        for (int s = 2; s <= smax && 4LL * per_xcd * s <= kCUs / kXcds; ++s) S = s;
         W = std::min(wcap, std::max(4, (nd + S - 1) / S));
         step_rule = true;
         // a wide grid's LDS ring (nx values per wave) may allow fewer waves

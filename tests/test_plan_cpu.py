@@ -93,7 +93,7 @@ def test_plan_rows_divide_ny():
     (16, 8, 4, 3),     # 2 per XCD: 8 x 3 = 24 workgroups on its 32 CUs
     (55, 8, 10, 1),    # 7 per XCD: one slice already fills the XCD
     (256, 8, 10, 1),
-    (1, 16, 5, 8),     # 36 directions, 8 slices: 32 workgroups on 32 CUs
+    (1, 16, 6, 6),     # 36 directions: at most 6 slices (partial planes)
     (1, 4, 4, 1),      # 3 directions: one slice of 4 waves (one idle)
     (1, 6, 4, 2),      # 6 directions: two slices of 4 waves
     (16, 16, 9, 4),
