@@ -67,6 +67,22 @@ def _sweep_case(env, insts, quad):
     return worst
 
 
+@pytest.mark.parametrize("n,W", [(4, 4), (6, 4), (12, 4), (16, 6)])
+def test_sweep_parity_small_batch_wave_counts(env, n, W):
+    """Two grids (one with a ragged second row block) get the planner's
+    small-batch shape: slices of 4 waves, idle waves included where an
+    octant's directions do not fill them (S4: 3 of 4, S6: 2 slices for 6
+    directions, S12: 6 slices for 21), and at most 6 slices (S16: 6 of 6);
+    each compiled wave count matches the oracle's sweep."""
+    torch, B, ctx = env
+    quad = I.level_symmetric_2d(n)
+    insts = [I.random_instance(128, 96, seed=900 + n), I.random_instance(80, 64, seed=950 + n)]
+    plan = ctx.sweep_plan([to_problem(i, torch) for i in insts], B.Quad.from_inputs(quad))
+    log(f"[tr_sweep] 128x96 + 80x64 S{n}: plan {plan}")
+    assert plan["specialised"] == 1 and plan["W"] == W and plan["KB"] == 16
+    _sweep_case(env, insts, quad)
+
+
 @pytest.mark.parametrize("shape,n", [((4, 4), 4), ((37, 23), 8), ((64, 64), 8),
                                      ((100, 70), 16), ((17, 130), 8)])
 def test_sweep_parity(env, shape, n):
